@@ -1,0 +1,76 @@
+"""Direct Python models of the three policies (no eBPF), used to pin the
+oracle: access counter and latency histogram have closed forms; the stride
+prefetcher is modelled per event with a dict of per-(stream, region tag)
+state, exactly as the policy is described in prose."""
+
+import math
+
+import numpy as np
+
+
+def access_counter(ev):
+    region = (ev["addr"] >> np.uint64(21)).astype(np.int64)
+    hist = np.bincount(region, minlength=4096).astype(np.uint64)
+    rc = (region & 1).astype(np.uint32)
+    return hist, rc
+
+
+def floor_log2(lat):
+    out = np.zeros(len(lat), dtype=np.int64)
+    nz = lat > 0
+    # exact: bit_length - 1 computed with integer arithmetic
+    out[nz] = np.array([int(x).bit_length() - 1 for x in lat[nz].tolist()], dtype=np.int64)
+    return out
+
+
+def latency_hist(ev, T, kernels=4096):
+    b = floor_log2(ev["lat"])
+    k = ev["kernel_id"].astype(np.int64)
+    hist = np.bincount(k * 64 + b, minlength=kernels * 64).astype(np.uint64).reshape(kernels, 64)
+    sel = ev["lat"] > np.uint64(T)
+    recs = sorted(zip(k[sel].tolist(), b[sel].tolist(), ev["lat"][sel].tolist()))
+    records = [(kk, bb, ll, int(T), 0) for kk, bb, ll in recs]
+    return hist, b.astype(np.uint32), records
+
+
+def stride_prefetch(ev):
+    """Returns (rc, state dict key -> (last_addr, stride, conf), records)."""
+    state = {}
+    rc = np.zeros(len(ev), dtype=np.uint32)
+    records = []
+    M = (1 << 64) - 1
+    for i, (a, s, ts) in enumerate(zip(ev["addr"].tolist(), ev["stream"].tolist(), ev["ts"].tolist())):
+        pg, rg = a >> 12, a >> 21
+        key = (s << 32) | (rg & 31)
+        if key not in state:
+            state[key] = [a, 0, 0]
+            continue
+        v = state[key]
+        if (v[0] >> 21) != rg:
+            state[key] = [a, 0, 0]
+            continue
+        d = pg - (v[0] >> 12)
+        v[0] = a
+        if d == 0:
+            continue
+        if d == v[1]:
+            v[2] = (v[2] + 1) & 0xFFFFFFFF
+        else:
+            v[1], v[2] = d, 0
+        conf = v[2]
+        if conf >= 2 and (conf & 7) == 2 and 1 <= abs(d) <= 16:
+            n = 0
+            for k in range(1, 9):
+                p = pg + k * d
+                if p < 0 or p >= (1 << 18) or (p >> 9) != (pg >> 9):
+                    break
+                n = k
+            if n > 0:
+                records.append((s, n, ((pg + d) << 12) & M, (d << 12) & M, ts))
+                rc[i] = n
+    return rc, {k: (v[0], v[1] & M, v[2]) for k, v in state.items()}, records
+
+
+def percentile_threshold(lat):
+    k = math.ceil(0.99 * len(lat)) - 1
+    return int(np.sort(lat)[k])
