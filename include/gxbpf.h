@@ -1,0 +1,172 @@
+/*
+ * gxbpf — device-side eBPF runtime for AMD MI355X (gfx950).  Public C ABI.
+ *
+ * The runtime follows the paper's model of programs, hooks and maps (gpu_ext,
+ * arXiv 2512.12615, sections 4.2–4.4 and 5.3): a control plane loads verified
+ * policy bytecode and configures maps; the device runs the policy once per
+ * hook event, one event per GPU lane, over batches of event records; policies
+ * read and update shared maps (array, hash, ring buffer) and return an integer
+ * decision per event.
+ *
+ * Conventions
+ *   - Every call returns 0 (or a non-negative handle / count) on success and a
+ *     negative Linux errno value on failure; nothing throws across the ABI.
+ *   - Pointers named d_* are device pointers (e.g. torch tensor data_ptr());
+ *     every other pointer is host memory.  The caller keeps ownership of all
+ *     buffers it passes; the runtime copies what it needs to keep.
+ *   - A gx_rt owns every map and program created through it; gx_close frees
+ *     them.  One runtime drives one HIP device.  Calls on one runtime are not
+ *     thread-safe; use one runtime per host thread, or serialise.
+ *   - hipStream_t arguments are passed as void*; NULL is the default stream.
+ */
+#ifndef GXBPF_H
+#define GXBPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gx_rt gx_rt;
+
+/* Map types (Linux numbering) and flags. */
+enum {
+  GX_MAP_HASH = 1,
+  GX_MAP_ARRAY = 2,
+  GX_MAP_RINGBUF = 27,
+};
+enum {
+  /* Shared across streams within a run: lookups and commutative atomics
+   * (ADD/OR/AND/XOR without fetch) only. */
+  GX_F_SHARED = 1u,
+  /* Written by the host only: lookups and loads only. */
+  GX_F_READ_ONLY = 2u,
+};
+
+/* Hook types: select the event record layout and the stream key.
+ *   GX_HOOK_MEM_ACCESS    24 B {u64 addr; u32 stream_id; u32 pad; u64 ts}
+ *                         stream key = stream_id (modelled on the paper's
+ *                         device memory-access hook, section 4.3.1)
+ *   GX_HOOK_KERNEL_TIMING 16 B {u32 kernel_id; u32 pad; u64 latency_ns}
+ *                         stream key = kernel_id (modelled on the paper's
+ *                         device observability tools, Table 2)
+ * The record is the program's read-only ctx (r1). */
+enum {
+  GX_HOOK_MEM_ACCESS = 1,
+  GX_HOOK_KERNEL_TIMING = 2,
+};
+
+/* Execution modes chosen by the verifier (section 4.4's deterministic
+ * reading): a program that touches only shared, read-only and ring maps is
+ * event-parallel; any other program runs each stream's events in order. */
+enum {
+  GX_MODE_EVENT_PARALLEL = 0,
+  GX_MODE_STREAM_SEQUENTIAL = 1,
+};
+
+typedef struct gx_prog_info {
+  uint32_t mode;          /* GX_MODE_* */
+  uint32_t hook;
+  uint32_t n_insns;       /* bytecode slots */
+  uint32_t stack_bytes;   /* stack frame the program uses (multiple of 8) */
+  uint64_t max_insns;     /* longest path, loops counted by trip count */
+  uint64_t max_calls;     /* helper calls per invocation, worst case */
+  uint64_t max_ring_bytes;/* ring bytes per invocation, worst case */
+} gx_prog_info;
+
+typedef struct gx_stats {
+  uint64_t launches;      /* kernel launches issued */
+  uint64_t events;        /* events submitted */
+  uint64_t ring_drops;    /* ringbuf_output calls that found no space */
+  uint64_t hash_e2big;    /* hash inserts refused because the map was full */
+  uint64_t vm_errors;     /* runaway-program aborts (should stay 0) */
+  uint64_t bytes_drained; /* ring bytes copied to the host */
+} gx_stats;
+
+/* Open a runtime on HIP device ``hip_device``.  -ENODEV if it does not
+ * exist, -ENOMEM on allocation failure. */
+int gx_open(int hip_device, gx_rt** out);
+/* Free every map and program of the runtime, then the runtime. */
+void gx_close(gx_rt* rt);
+
+/* Create a map (section 4.4, "Hierarchical Cross-layer Maps"; here every map
+ * lives in device memory).  Returns a map fd >= 0.
+ *   ARRAY:   key_size 4 (u32 index), value_size 1..4096, max_entries >= 1;
+ *            values start zeroed.
+ *   HASH:    key_size 1..64, value_size 1..4096, max_entries >= 1.
+ *   RINGBUF: key_size = value_size = 0, max_entries = data bytes, a power of
+ *            two >= 4096.
+ * flags: GX_F_SHARED or GX_F_READ_ONLY (not both; not on a ring).
+ * Errors: -EINVAL bad sizes or flags; -ENOMEM. */
+int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_size,
+                  uint32_t max_entries, uint32_t flags);
+
+/* Control-plane map access (the paper's user-space control plane, section
+ * 4.2).  Synchronous with respect to the device: they wait for all work the
+ * runtime has launched.  Same error codes as the eBPF helpers:
+ *   update: flags 0 ANY / 1 NOEXIST / 2 EXIST; -EEXIST, -ENOENT, -E2BIG,
+ *           -EINVAL; key/val are key_size / value_size host bytes.
+ *   lookup: copies the value into val_out; -ENOENT if absent.
+ *   delete: -ENOENT if absent; -EINVAL on arrays. */
+int gx_map_update(gx_rt* rt, int map_fd, const void* key, const void* val, uint64_t flags);
+int gx_map_lookup(gx_rt* rt, int map_fd, const void* key, void* val_out);
+int gx_map_delete(gx_rt* rt, int map_fd, const void* key);
+/* Snapshot of a map: writes up to ``cap`` (key, value) pairs (arrays: every
+ * index in order; hashes: live entries in slot order) to keys / vals (either
+ * may be NULL) and returns the number of entries the map holds. */
+int64_t gx_map_dump(gx_rt* rt, int map_fd, void* keys, void* vals, uint64_t cap);
+/* Zero an array map, or empty a hash map or a ring buffer. */
+int gx_map_clear(gx_rt* rt, int map_fd);
+
+/* Verify and load a program (section 4.4 "SIMT-aware Verification"; section
+ * 5.3).  ``insns`` holds n_insns 8-byte eBPF slots; map references are
+ * `lddw rX` with src=5 (imm = index into map_fds) or src=1 (imm = a map fd
+ * listed in map_fds).  Returns a program fd >= 0.  On rejection returns
+ * -EACCES and writes the reason to ``log`` (if log_size > 0).  -E2BIG if
+ * n_insns > 4096, -EINVAL for a bad hook or map table. */
+int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t hook_type,
+                    const int* map_fds, uint32_t n_maps, char* log, uint32_t log_size);
+int gx_prog_info_get(gx_rt* rt, int prog_fd, gx_prog_info* out);
+
+/* Verify without loading (no device needed).  ``map_shapes`` holds 5 u32 per
+ * map: type, key_size, value_size, max_entries, flags; the program's map
+ * table is the identity over them.  Returns 0 if accepted, -EACCES if
+ * rejected (reason in log), and fills *info when accepted. */
+int gx_verify(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
+              uint32_t n_maps, char* log, uint32_t log_size, gx_prog_info* info);
+
+/* Run a program over n_events records at d_events (device memory, record
+ * size given by the hook) asynchronously on ``stream``; writes the u32 return
+ * code of event i to d_rc[i] if d_rc is not NULL.  Maps change in place.
+ * The caller keeps d_events / d_rc alive until the stream reaches this point.
+ * Errors: -EINVAL (bad fd, record_size mismatch), -ENOMEM. */
+int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
+                 uint32_t record_size, uint32_t* d_rc, void* stream);
+
+/* Batched form: the work of n gx_run_batch calls in one persistent launch.
+ * The results are those of the n calls made in order. */
+typedef struct gx_batch {
+  int32_t prog_fd;
+  uint32_t record_size;
+  const void* d_events;
+  uint64_t n_events;
+  uint32_t* d_rc;
+} gx_batch;
+int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream);
+
+/* Copy committed ring records to host memory as {u32 len; u32 flags;
+ * payload padded to 8} and release their space.  Returns the bytes written
+ * (whole records only) and the record count in *n_records.  Waits for work
+ * already launched on the runtime's streams that may still write the ring. */
+int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_bytes,
+                         uint64_t* n_records);
+
+/* Counters accumulated since gx_open (synchronises the device). */
+int gx_stats_get(gx_rt* rt, gx_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GXBPF_H */

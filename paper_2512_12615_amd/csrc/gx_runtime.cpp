@@ -1,0 +1,684 @@
+// Host runtime behind the C ABI of include/gxbpf.h: runtime object, maps in
+// device memory, program loading (verify + pre-decode), batch launch,
+// ring-buffer drain and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gx_internal.h"
+#include "gx_verifier.h"
+#include "gxbpf.h"
+
+namespace gx {
+hipError_t vm_init();
+hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s);
+hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride, hipStream_t s);
+hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
+                            uint32_t* sums, uint32_t* order, hipStream_t s);
+hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
+                         int64_t* ret, uint8_t* val_out, hipStream_t s);
+}  // namespace gx
+
+using namespace gx;
+
+namespace {
+
+struct MapObj {
+  bool live = false;
+  MapDev h{};              // host copy of the descriptor
+  MapDev* d_desc = nullptr;
+  size_t data_bytes = 0, slot_bytes = 0;
+};
+
+struct ProgObj {
+  bool live = false;
+  int hook = 0;
+  uint32_t record_size = 0, stream_off = 0, stream_size = 0;
+  Verdict v;
+  uint32_t n_insns = 0;
+  Uop* d_uops = nullptr;
+  uint64_t* d_guards = nullptr;
+  std::vector<int> fds;
+};
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  return s && *s ? std::atoi(s) : dflt;
+}
+
+}  // namespace
+
+struct gx_rt {
+  int dev = 0;
+  hipStream_t internal = nullptr;
+  std::vector<MapObj> maps;
+  std::vector<ProgObj> progs;
+  uint64_t* d_err = nullptr;
+  uint8_t* d_stage = nullptr;  // control-plane staging (keys, values, results)
+  // stream-sequential workspace
+  uint32_t* d_counts = nullptr;
+  uint32_t* d_sums = nullptr;
+  uint32_t* d_order = nullptr;
+  size_t counts_cap = 0, sums_cap = 0, order_cap = 0;
+  hipEvent_t ws_event = nullptr;
+  bool ws_used = false;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
+  gx_stats stats{};
+};
+
+namespace {
+
+int to_errno(hipError_t e) { return e == hipErrorOutOfMemory ? -ENOMEM : -EIO; }
+
+struct DevGuard {
+  int prev = 0;
+  explicit DevGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+MapObj* get_map(gx_rt* rt, int fd) {
+  if (!rt || fd < 0 || fd >= (int)rt->maps.size() || !rt->maps[fd].live) return nullptr;
+  return &rt->maps[fd];
+}
+
+ProgObj* get_prog(gx_rt* rt, int fd) {
+  if (!rt || fd < 0 || fd >= (int)rt->progs.size() || !rt->progs[fd].live) return nullptr;
+  return &rt->progs[fd];
+}
+
+void free_map(MapObj& m) {
+  if (m.h.data) (void)hipFree(m.h.data);
+  if (m.h.slots) (void)hipFree(m.h.slots);
+  if (m.h.ctrl) (void)hipFree(m.h.ctrl);
+  if (m.d_desc) (void)hipFree(m.d_desc);
+  m = MapObj{};
+}
+
+void note_stream(gx_rt* rt, hipStream_t s) {
+  for (auto& se : rt->stream_events)
+    if (se.first == s) {
+      (void)hipEventRecord(se.second, s);
+      return;
+    }
+  hipEvent_t e;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
+  rt->stream_events.push_back({s, e});
+}
+
+int wait_all(gx_rt* rt) {
+  for (auto& se : rt->stream_events)
+    if (hipEventSynchronize(se.second) != hipSuccess) return -EIO;
+  if (hipStreamSynchronize(rt->internal) != hipSuccess) return -EIO;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// pre-decoder: one 16-byte micro-op per slot
+
+const int kSizeCode[4] = {2, 1, 0, 3};  // eBPF size bits W, H, B, DW -> log2 bytes
+
+int alu_handler(int o, int16_t off, bool x, bool w64) {
+  int base;
+  switch (o) {
+    case 0x00: base = H_ADD64; break;
+    case 0x10: base = H_SUB64; break;
+    case 0x20: base = H_MUL64; break;
+    case 0x30: base = off ? H_SDIV64 : H_DIV64; break;
+    case 0x40: base = H_OR64; break;
+    case 0x50: base = H_AND64; break;
+    case 0x60: base = H_LSH64; break;
+    case 0x70: base = H_RSH64; break;
+    case 0x80: base = H_NEG64; break;
+    case 0x90: base = off ? H_SMOD64 : H_MOD64; break;
+    case 0xa0: base = H_XOR64; break;
+    case 0xb0: base = (x && off) ? H_MOVSX64 : H_MOV64; break;
+    case 0xc0: base = H_ARSH64; break;
+    default: return -1;
+  }
+  return w64 ? base : base + (H_ADD32 - H_ADD64);
+}
+
+int jmp_handler(int o, bool w32) {
+  static const int t64[16] = {H_JA, H_JEQ, H_JGT, H_JGE, H_JSET, H_JNE, H_JSGT, H_JSGE,
+                              -1,   -1,    H_JLT, H_JLE, H_JSLT, H_JSLE, -1,   -1};
+  static const int t32[16] = {H_JA, H_JEQ32, H_JGT32, H_JGE32, H_JSET32, H_JNE32, H_JSGT32, H_JSGE32,
+                              -1,   -1,      H_JLT32, H_JLE32, H_JSLT32, H_JSLE32, -1,      -1};
+  return (w32 ? t32 : t64)[o >> 4];
+}
+
+std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const std::vector<MapObj*>& tab) {
+  std::vector<Uop> U(P.size());
+  for (auto& u : U) u = Uop{uop_w0(H_EXIT, 0, 0, 0, true), 0, 0};
+  for (size_t pc = 0; pc < P.size(); pc++) {
+    const Insn& in = P[pc];
+    int c = in.op & 7, o = in.op & 0xf0;
+    bool x = in.op & 8;
+    Uop u{0, 0, 0};
+    if (c == 4 || c == 7) {
+      bool w64 = c == 7;
+      if (o == 0xd0) {
+        int h = (w64 || x) ? H_BSWAP : H_TRUNC;
+        u = Uop{uop_w0(h, in.dst, 0, in.imm, true), 0, 0};
+      } else {
+        int h = alu_handler(o, in.off, x, w64);
+        int a8 = (o == 0xb0 && x) ? in.off : 0;
+        uint64_t k = x ? 0 : (w64 ? (uint64_t)(int64_t)in.imm : (uint64_t)(uint32_t)in.imm);
+        u = Uop{uop_w0(h, in.dst, x ? in.src : 0, a8, !x), 0, k};
+      }
+    } else if (c == 5 || c == 6) {
+      bool w32 = c == 6;
+      if (o == 0x90) {
+        u = Uop{uop_w0(H_EXIT, 0, 0, 0, true), 0, 0};
+      } else if (o == 0x80) {
+        int mi = V.call_map[pc];
+        if (mi < 0) continue;  // unreachable
+        MapObj* m = tab[mi];
+        int a2 = V.arg2_kind[pc] < 0 ? 0 : V.arg2_kind[pc];
+        int a3 = V.arg3_kind[pc] < 0 ? 0 : V.arg3_kind[pc];
+        int h = H_EXIT, aux = 0;
+        bool arr = m->h.type == MAP_ARRAY;
+        switch (in.imm) {
+          case 1: h = arr ? H_LOOKUP_ARRAY : H_LOOKUP_HASH; break;
+          case 2: h = arr ? H_UPDATE_ARRAY : H_UPDATE_HASH; break;
+          case 3: h = arr ? H_RET_EINVAL : H_DELETE_HASH; break;
+          case 130: h = H_RINGBUF_OUTPUT; aux = (int)V.ring_size[pc]; break;
+        }
+        u = Uop{uop_w0(h, 0, 0, a2 | (a3 << 1), true), aux, (uint64_t)(uintptr_t)m->d_desc};
+      } else {
+        int t = (int)pc + 1 + ((w32 && o == 0) ? in.imm : in.off);
+        int h = jmp_handler(o, w32);
+        uint64_t k = x ? 0 : (w32 ? (uint64_t)(uint32_t)in.imm : (uint64_t)(int64_t)in.imm);
+        u = Uop{uop_w0(h, in.dst, x ? in.src : 0, 0, !x), t, k};
+      }
+    } else if (c == 1) {
+      int sc = kSizeCode[(in.op >> 3) & 3];
+      int sxf = (in.op & 0xe0) == 0x80 ? 4 : 0;
+      int k = V.mem_kind[pc];
+      int h = k == KIND_CTX ? H_LDX_CTX : k == KIND_STACK ? H_LDX_STACK : H_LDX_MAP;
+      u = Uop{uop_w0(h, in.dst, in.src, sc | sxf, false), in.off, 0};
+    } else if (c == 2) {
+      int sc = kSizeCode[(in.op >> 3) & 3];
+      int h = V.mem_kind[pc] == KIND_STACK ? H_ST_STACK : H_ST_MAP;
+      u = Uop{uop_w0(h, in.dst, 0, sc, true), in.off, (uint64_t)(int64_t)in.imm};
+    } else if (c == 3) {
+      int sc = kSizeCode[(in.op >> 3) & 3];
+      bool stack = V.mem_kind[pc] == KIND_STACK;
+      if ((in.op & 0xe0) == 0xc0)
+        u = Uop{uop_w0(stack ? H_ATOMIC_STACK : H_ATOMIC_MAP, in.dst, in.src, sc, false), in.off,
+                (uint64_t)(uint32_t)in.imm};
+      else
+        u = Uop{uop_w0(stack ? H_STX_STACK : H_STX_MAP, in.dst, in.src, sc, false), in.off, 0};
+    } else if (c == 0 && in.op == 0x18) {
+      uint64_t val;
+      if (in.src == 0) {
+        val = (uint64_t)(uint32_t)in.imm | ((uint64_t)(uint32_t)P[pc + 1].imm << 32);
+      } else {
+        int mi = V.ld_map[pc];
+        val = mi >= 0 ? (uint64_t)(uintptr_t)tab[mi]->d_desc : 0;
+      }
+      u = Uop{uop_w0(H_LDIMM, in.dst, 0, 0, true), 0, val};
+      U[pc] = u;
+      pc++;  // the second slot is never executed
+      continue;
+    } else {
+      continue;
+    }
+    U[pc] = u;
+  }
+  return U;
+}
+
+int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
+  auto grow = [](uint32_t** p, size_t* cap, size_t need) -> int {
+    if (*cap >= need) return 0;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    size_t n = std::max<size_t>(need, 1024);
+    if (hipMalloc((void**)p, n * sizeof(uint32_t)) != hipSuccess) return -ENOMEM;
+    *cap = n;
+    return 0;
+  };
+  int r;
+  if ((r = grow(&rt->d_counts, &rt->counts_cap, counts))) return r;
+  if ((r = grow(&rt->d_sums, &rt->sums_cap, sums))) return r;
+  if ((r = grow(&rt->d_order, &rt->order_cap, order))) return r;
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int gx_open(int hip_device, gx_rt** out) {
+  if (!out) return -EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return -ENODEV;
+  gx_rt* rt = new (std::nothrow) gx_rt();
+  if (!rt) return -ENOMEM;
+  rt->dev = hip_device;
+  DevGuard g(hip_device);
+  if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
+      hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess || vm_init() != hipSuccess) {
+    gx_close(rt);
+    return -ENOMEM;
+  }
+  (void)hipMemset(rt->d_err, 0, 64);
+  (void)hipDeviceSynchronize();
+  *out = rt;
+  return 0;
+}
+
+void gx_close(gx_rt* rt) {
+  if (!rt) return;
+  DevGuard g(rt->dev);
+  (void)hipDeviceSynchronize();
+  for (auto& m : rt->maps)
+    if (m.live) free_map(m);
+  for (auto& p : rt->progs) {
+    if (p.d_uops) (void)hipFree(p.d_uops);
+    if (p.d_guards) (void)hipFree(p.d_guards);
+  }
+  for (auto& se : rt->stream_events) (void)hipEventDestroy(se.second);
+  if (rt->ws_event) (void)hipEventDestroy(rt->ws_event);
+  for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_err, (void*)rt->d_stage})
+    if (p) (void)hipFree(p);
+  if (rt->internal) (void)hipStreamDestroy(rt->internal);
+  delete rt;
+}
+
+int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_size, uint32_t max_entries,
+                  uint32_t flags) {
+  if (!rt) return -EINVAL;
+  if (flags & ~(uint32_t)(F_SHARED | F_READ_ONLY)) return -EINVAL;
+  if ((flags & F_SHARED) && (flags & F_READ_ONLY)) return -EINVAL;
+  MapObj m;
+  m.h.type = type;
+  m.h.key_size = key_size;
+  m.h.value_size = value_size;
+  m.h.max_entries = max_entries;
+  m.h.flags = flags;
+  m.h.vstride = (value_size + 7) & ~7u;
+  if (type == MAP_ARRAY) {
+    if (key_size != 4 || value_size == 0 || value_size > 4096 || max_entries == 0) return -EINVAL;
+    m.data_bytes = (size_t)max_entries * m.h.vstride;
+  } else if (type == MAP_HASH) {
+    if (key_size == 0 || key_size > 64 || value_size == 0 || value_size > 4096 || max_entries == 0 ||
+        max_entries > (1u << 28))
+      return -EINVAL;
+    uint64_t slots = next_pow2(std::max<uint64_t>(2ull * max_entries, 16));
+    m.h.slot_mask = (uint32_t)(slots - 1);
+    m.h.sstride = 8 + ((key_size + 7) & ~7u);
+    m.slot_bytes = slots * m.h.sstride;
+    m.data_bytes = slots * m.h.vstride;
+  } else if (type == MAP_RINGBUF) {
+    if (key_size || value_size || max_entries < 4096 || (max_entries & (max_entries - 1)) || flags) return -EINVAL;
+    m.h.slot_mask = max_entries - 1;
+    m.data_bytes = max_entries;
+  } else {
+    return -EINVAL;
+  }
+  DevGuard g(rt->dev);
+  bool ok = hipMalloc((void**)&m.h.data, m.data_bytes) == hipSuccess &&
+            hipMalloc((void**)&m.h.ctrl, 64) == hipSuccess && hipMalloc((void**)&m.d_desc, sizeof(MapDev)) == hipSuccess;
+  if (ok && m.slot_bytes) ok = hipMalloc((void**)&m.h.slots, m.slot_bytes) == hipSuccess;
+  if (!ok) {
+    free_map(m);
+    return -ENOMEM;
+  }
+  ok = hipMemsetAsync(m.h.data, 0, m.data_bytes, rt->internal) == hipSuccess &&
+       hipMemsetAsync(m.h.ctrl, 0, 64, rt->internal) == hipSuccess &&
+       (!m.slot_bytes || hipMemsetAsync(m.h.slots, 0, m.slot_bytes, rt->internal) == hipSuccess) &&
+       hipMemcpyAsync(m.d_desc, &m.h, sizeof(MapDev), hipMemcpyHostToDevice, rt->internal) == hipSuccess &&
+       hipStreamSynchronize(rt->internal) == hipSuccess;
+  if (!ok) {
+    free_map(m);
+    return -EIO;
+  }
+  m.live = true;
+  rt->maps.push_back(m);
+  return (int)rt->maps.size() - 1;
+}
+
+static int map_op(gx_rt* rt, int fd, int op, const void* key, const void* val, uint64_t flags, void* val_out) {
+  MapObj* m = get_map(rt, fd);
+  if (!m || !key || m->h.type == MAP_RINGBUF) return -EINVAL;
+  if (op == 1 && !val) return -EINVAL;
+  if (op == 2 && m->h.type == MAP_ARRAY) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  uint32_t ks = m->h.key_size, vs = m->h.value_size;
+  // staging layout: key @0 (<= 64 B), result @64, value in @128, value out @4224
+  uint8_t* dk = rt->d_stage;
+  int64_t* dret = (int64_t*)(rt->d_stage + 64);
+  uint8_t* dv = rt->d_stage + 128;
+  uint8_t* dout = rt->d_stage + 128 + 4096;
+  int64_t ret = -EIO;
+  bool ok = hipMemcpyAsync(dk, key, ks, hipMemcpyHostToDevice, rt->internal) == hipSuccess &&
+            (op != 1 || hipMemcpyAsync(dv, val, vs, hipMemcpyHostToDevice, rt->internal) == hipSuccess) &&
+            launch_map_op(m->d_desc, op, dk, dv, flags, dret, dout, rt->internal) == hipSuccess &&
+            hipMemcpyAsync(&ret, dret, 8, hipMemcpyDeviceToHost, rt->internal) == hipSuccess &&
+            hipStreamSynchronize(rt->internal) == hipSuccess;
+  if (!ok) return -EIO;
+  if (op == 0 && ret == 0 && val_out)
+    if (hipMemcpy(val_out, dout, vs, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  return (int)ret;
+}
+
+int gx_map_update(gx_rt* rt, int map_fd, const void* key, const void* val, uint64_t flags) {
+  return map_op(rt, map_fd, 1, key, val, flags, nullptr);
+}
+int gx_map_lookup(gx_rt* rt, int map_fd, const void* key, void* val_out) {
+  return map_op(rt, map_fd, 0, key, nullptr, 0, val_out);
+}
+int gx_map_delete(gx_rt* rt, int map_fd, const void* key) {
+  return map_op(rt, map_fd, 2, key, nullptr, 0, nullptr);
+}
+
+int64_t gx_map_dump(gx_rt* rt, int map_fd, void* keys, void* vals, uint64_t cap) {
+  MapObj* m = get_map(rt, map_fd);
+  if (!m || m->h.type == MAP_RINGBUF) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  const MapDev& d = m->h;
+  if (d.type == MAP_ARRAY) {
+    uint64_t n = d.max_entries;
+    if ((keys || vals) && cap) {
+      std::vector<uint8_t> buf(m->data_bytes);
+      if (hipMemcpy(buf.data(), d.data, m->data_bytes, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+      for (uint64_t i = 0; i < n && i < cap; i++) {
+        if (keys) std::memcpy((uint8_t*)keys + 4 * i, &i, 4);
+        if (vals) std::memcpy((uint8_t*)vals + i * d.value_size, buf.data() + i * d.vstride, d.value_size);
+      }
+    }
+    return (int64_t)n;
+  }
+  std::vector<uint8_t> slots(m->slot_bytes), data(m->data_bytes);
+  if (hipMemcpy(slots.data(), d.slots, m->slot_bytes, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  if ((vals && cap) && hipMemcpy(data.data(), d.data, m->data_bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return -EIO;
+  uint64_t n = 0;
+  for (uint64_t i = 0; i <= d.slot_mask; i++) {
+    const uint8_t* hdr = slots.data() + i * d.sstride;
+    uint32_t st;
+    std::memcpy(&st, hdr, 4);
+    if (st != SLOT_LIVE) continue;
+    if (n < cap) {
+      if (keys) std::memcpy((uint8_t*)keys + n * d.key_size, hdr + 8, d.key_size);
+      if (vals) std::memcpy((uint8_t*)vals + n * d.value_size, data.data() + i * d.vstride, d.value_size);
+    }
+    n++;
+  }
+  return (int64_t)n;
+}
+
+int gx_map_clear(gx_rt* rt, int map_fd) {
+  MapObj* m = get_map(rt, map_fd);
+  if (!m) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  bool ok = hipMemset(m->h.data, 0, m->data_bytes) == hipSuccess && hipMemset(m->h.ctrl, 0, 64) == hipSuccess &&
+            (!m->slot_bytes || hipMemset(m->h.slots, 0, m->slot_bytes) == hipSuccess) &&
+            hipDeviceSynchronize() == hipSuccess;
+  return ok ? 0 : -EIO;
+}
+
+static void fill_info(const Verdict& v, uint32_t hook, uint32_t n, gx_prog_info* out) {
+  out->mode = v.event_parallel ? GX_MODE_EVENT_PARALLEL : GX_MODE_STREAM_SEQUENTIAL;
+  out->hook = hook;
+  out->n_insns = n;
+  out->stack_bytes = v.stack_bytes;
+  out->max_insns = v.max_insns;
+  out->max_calls = v.max_calls;
+  out->max_ring_bytes = v.max_ring;
+}
+
+static void write_log(char* log, uint32_t size, const std::string& s) {
+  if (!log || !size) return;
+  size_t n = std::min<size_t>(size - 1, s.size());
+  std::memcpy(log, s.data(), n);
+  log[n] = 0;
+}
+
+int gx_verify(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
+              uint32_t n_maps, char* log, uint32_t log_size, gx_prog_info* info) {
+  if (n_insns > (uint32_t)kMaxInsns) {
+    write_log(log, log_size, "program has more than 4096 instructions");
+    return -E2BIG;
+  }
+  if (!insns && n_insns) return -EINVAL;
+  std::vector<MapShape> shapes(n_maps);
+  std::vector<int> fds(n_maps);
+  for (uint32_t i = 0; i < n_maps; i++) {
+    shapes[i] = MapShape{map_shapes[5 * i], map_shapes[5 * i + 1], map_shapes[5 * i + 2], map_shapes[5 * i + 3],
+                         map_shapes[5 * i + 4]};
+    fds[i] = (int)i;
+  }
+  Verdict v = verify(decode_insns(insns, n_insns), (int)hook_type, shapes, fds);
+  write_log(log, log_size, v.log);
+  if (!v.ok) return -EACCES;
+  if (info) fill_info(v, hook_type, n_insns, info);
+  return 0;
+}
+
+int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const int* map_fds,
+                    uint32_t n_maps, char* log, uint32_t log_size) {
+  if (!rt || (!insns && n_insns)) return -EINVAL;
+  if (n_insns > (uint32_t)kMaxInsns) {
+    write_log(log, log_size, "program has more than 4096 instructions");
+    return -E2BIG;
+  }
+  uint32_t rs, so, ss;
+  if (!hook_layout((int)hook_type, &rs, &so, &ss)) return -EINVAL;
+  std::vector<MapShape> shapes;
+  std::vector<int> fds;
+  std::vector<MapObj*> tab;
+  for (uint32_t i = 0; i < n_maps; i++) {
+    MapObj* m = get_map(rt, map_fds[i]);
+    if (!m) return -EINVAL;
+    shapes.push_back(MapShape{m->h.type, m->h.key_size, m->h.value_size, m->h.max_entries, m->h.flags});
+    fds.push_back(map_fds[i]);
+    tab.push_back(m);
+  }
+  std::vector<Insn> P = decode_insns(insns, n_insns);
+  Verdict v = verify(P, (int)hook_type, shapes, fds);
+  write_log(log, log_size, v.log);
+  if (!v.ok) return -EACCES;
+  std::vector<Uop> U = predecode(P, v, tab);
+  std::vector<uint64_t> guards(2 * P.size(), 0);
+  for (size_t pc = 0; pc < P.size(); pc++)
+    if (v.mem_map[pc] >= 0) {
+      MapObj* m = tab[v.mem_map[pc]];
+      guards[2 * pc] = (uint64_t)(uintptr_t)m->h.data;
+      guards[2 * pc + 1] = (uint64_t)(uintptr_t)m->h.data + m->data_bytes;
+    }
+  ProgObj p;
+  p.hook = (int)hook_type;
+  p.record_size = rs;
+  p.stream_off = so;
+  p.stream_size = ss;
+  p.n_insns = n_insns;
+  p.fds = fds;
+  DevGuard g(rt->dev);
+  if (hipMalloc((void**)&p.d_uops, U.size() * sizeof(Uop)) != hipSuccess) return -ENOMEM;
+  if (hipMalloc((void**)&p.d_guards, guards.size() * sizeof(uint64_t)) != hipSuccess) {
+    (void)hipFree(p.d_uops);
+    return -ENOMEM;
+  }
+  if (hipMemcpy(p.d_uops, U.data(), U.size() * sizeof(Uop), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.d_guards, guards.data(), guards.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p.d_uops);
+    (void)hipFree(p.d_guards);
+    return -EIO;
+  }
+  p.v = std::move(v);
+  p.live = true;
+  rt->progs.push_back(std::move(p));
+  return (int)rt->progs.size() - 1;
+}
+
+int gx_prog_info_get(gx_rt* rt, int prog_fd, gx_prog_info* out) {
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p || !out) return -EINVAL;
+  fill_info(p->v, (uint32_t)p->hook, p->n_insns, out);
+  return 0;
+}
+
+int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size,
+                 uint32_t* d_rc, void* stream) {
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p) return -EINVAL;
+  if (record_size != p->record_size) return -EINVAL;
+  if (n_events == 0) return 0;
+  if (!d_events) return -EINVAL;
+  if (n_events >= (1ull << 32)) return -E2BIG;
+  hipStream_t s = (hipStream_t)stream;
+  DevGuard g(rt->dev);
+  RunArgs A{};
+  A.uops = p->d_uops;
+  A.events = (const uint8_t*)d_events;
+  A.rc = d_rc;
+  A.n_events = n_events;
+  A.record_size = p->record_size;
+  A.stack_bytes = p->v.stack_bytes;
+  A.stream_off = p->stream_off;
+  A.stream_size = p->stream_size;
+  A.err = rt->d_err;
+  A.guards = p->d_guards;
+  A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
+  uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
+  hipError_t e;
+  if (p->v.event_parallel) {
+    A.step_limit = per_event;
+    e = launch_event_parallel(A, s);
+    rt->stats.launches += 1;
+  } else {
+    uint32_t lbits = (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
+    uint32_t L = 1u << lbits;
+    uint64_t tile = std::max<uint64_t>(4096, next_pow2((n_events + 255) / 256));
+    uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
+    uint64_t m = (uint64_t)L * nt;
+    int r = ensure_ws(rt, m, (m + 4095) / 4096 + 1, n_events);
+    if (r) return r;
+    if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
+    A.step_limit = per_event * n_events;
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, s);
+    if (e == hipSuccess) {
+      A.order = rt->d_order;
+      A.qstart = rt->d_counts;
+      A.n_queues = L;
+      uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
+      e = launch_stream_seq(A, lanes, nt, s);
+    }
+    (void)hipEventRecord(rt->ws_event, s);
+    rt->ws_used = true;
+    rt->stats.launches += 6;
+  }
+  if (e != hipSuccess) return to_errno(e);
+  rt->stats.events += n_events;
+  note_stream(rt, s);
+  return 0;
+}
+
+int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
+  if (!rt || (!descs && n)) return -EINVAL;
+  for (uint32_t i = 0; i < n; i++) {
+    int r = gx_run_batch(rt, descs[i].prog_fd, descs[i].d_events, descs[i].n_events, descs[i].record_size,
+                         descs[i].d_rc, stream);
+    if (r) return r;
+  }
+  return 0;
+}
+
+int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_bytes, uint64_t* n_records) {
+  MapObj* m = get_map(rt, ring_fd);
+  if (!m || m->h.type != MAP_RINGBUF || (!host_buf && buf_bytes)) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  uint64_t ctrl[2];
+  if (hipMemcpy(ctrl, m->h.ctrl, 16, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
+  uint64_t avail = head - tail;
+  if (n_records) *n_records = 0;
+  if (avail == 0) return 0;
+  std::vector<uint8_t> buf(avail);
+  uint64_t t0 = tail & (cap - 1);
+  uint64_t first = std::min(avail, cap - t0);
+  if (hipMemcpy(buf.data(), m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  if (first < avail && hipMemcpy(buf.data() + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
+    return -EIO;
+  uint64_t pos = 0, nrec = 0;
+  while (pos + 8 <= avail) {
+    uint32_t len;
+    std::memcpy(&len, buf.data() + pos, 4);
+    if (len == 0) break;  // reserved, not yet committed
+    uint64_t need = 8 + ((len + 7ull) & ~7ull);
+    if (pos + need > avail || pos + need > buf_bytes) break;
+    std::memcpy((uint8_t*)host_buf + pos, buf.data() + pos, need);
+    pos += need;
+    nrec++;
+  }
+  if (pos) {
+    // clear the consumed bytes so that headers read as uncommitted, then
+    // publish the new tail
+    uint64_t c0 = std::min(pos, cap - t0);
+    bool ok = hipMemset(m->h.data + t0, 0, c0) == hipSuccess &&
+              (c0 == pos || hipMemset(m->h.data, 0, pos - c0) == hipSuccess);
+    uint64_t nt = tail + pos;
+    ok = ok && hipMemcpy(m->h.ctrl + 1, &nt, 8, hipMemcpyHostToDevice) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    if (!ok) return -EIO;
+  }
+  rt->stats.bytes_drained += pos;
+  if (n_records) *n_records = nrec;
+  return (int64_t)pos;
+}
+
+int gx_stats_get(gx_rt* rt, gx_stats* out) {
+  if (!rt || !out) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  gx_stats s = rt->stats;
+  s.ring_drops = s.hash_e2big = 0;
+  for (auto& m : rt->maps) {
+    if (!m.live) continue;
+    uint64_t c[3] = {0, 0, 0};
+    if (hipMemcpy(c, m.h.ctrl, 24, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+    if (m.h.type == MAP_RINGBUF) s.ring_drops += c[2];
+    if (m.h.type == MAP_HASH) s.hash_e2big += c[1];
+  }
+  uint64_t err = 0;
+  if (hipMemcpy(&err, rt->d_err, 8, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  s.vm_errors = err;
+  *out = s;
+  return 0;
+}
+
+}  // extern "C"

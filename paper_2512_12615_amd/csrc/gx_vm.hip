@@ -1,0 +1,880 @@
+// Device VM of the eBPF runtime for gfx950 (CDNA4, wave64).
+//
+// One lane runs one event's invocation (paper section 5.3 runs the handler
+// per warp; the deterministic per-event reading is documented with the
+// boundary).  Per lane: r0-r10 as a 16 x u64 register vector held in VGPRs,
+// the event record's words in VGPRs, and a private stack frame in LDS laid
+// out word-major per wave (conflict-free for uniform offsets).  Per wave: one
+// uniform pc; the pre-decoded micro-op is fetched through the scalar cache.
+// Branches that all live lanes take the same way keep the wave in uniform
+// mode; a split branch switches the wave to minimum-pc scheduling until the
+// lanes meet again.  Commutative map atomics that hit one address from every
+// active lane are reduced across the wave and issued once (section 4.4,
+// "Warp-level Execution Optimizations"); ring-buffer space is reserved once
+// per wave.
+#include <hip/hip_runtime.h>
+
+#include "gx_internal.h"
+
+namespace gx {
+
+typedef uint64_t rf_t __attribute__((ext_vector_type(16)));
+
+extern __shared__ __attribute__((aligned(16))) uint8_t g_lds[];
+
+// ---------------------------------------------------------------------------
+// wave utilities
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t rfl64(uint64_t x) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
+__device__ __forceinline__ uint32_t rank_in(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_release(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// stack frames in LDS: frame byte o of a lane lives at
+//   base + (o >> 3) * 512 + lane * 8 + (o & 7)
+
+struct Stk {
+  uint32_t base;   // byte offset of this wave's frames in g_lds
+  uint32_t lane8;  // lane * 8
+};
+
+__device__ __forceinline__ uint8_t* saddr(const Stk& k, uint32_t o) {
+  return g_lds + k.base + (o >> 3) * 512u + k.lane8 + (o & 7u);
+}
+
+__device__ __forceinline__ uint64_t sx(uint64_t v, int sc) {
+  switch (sc) {
+    case 0: return (uint64_t)(int64_t)(int8_t)v;
+    case 1: return (uint64_t)(int64_t)(int16_t)v;
+    case 2: return (uint64_t)(int64_t)(int32_t)v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t load_sized(const uint8_t* p, int sc) {
+  switch (sc) {
+    case 0: return *p;
+    case 1: return *(const uint16_t*)p;
+    case 2: return *(const uint32_t*)p;
+  }
+  return *(const uint64_t*)p;
+}
+__device__ __forceinline__ void store_sized(uint8_t* p, uint64_t v, int sc) {
+  switch (sc) {
+    case 0: *p = (uint8_t)v; break;
+    case 1: *(uint16_t*)p = (uint16_t)v; break;
+    case 2: *(uint32_t*)p = (uint32_t)v; break;
+    default: *(uint64_t*)p = v; break;
+  }
+}
+
+// Bytes [8w, 8w + 8) of an object of ``n`` bytes at ``p`` (stack offset or
+// global address), zero beyond n.
+__device__ __forceinline__ uint64_t chunk(int kind, uint64_t p, uint32_t w, uint32_t n, const Stk& stk) {
+  uint32_t left = n - 8 * w;
+  uint32_t m = left < 8 ? left : 8;
+  if (kind == PK_STACK) {
+    uint32_t o = (uint32_t)p + 8 * w;
+    if (m == 8 && (o & 7) == 0) return *(const uint64_t*)saddr(stk, o);
+    if (m == 4 && (o & 3) == 0) return *(const uint32_t*)saddr(stk, o);
+    uint64_t v = 0;
+    for (uint32_t i = 0; i < m; i++) v |= (uint64_t)*saddr(stk, o + i) << (8 * i);
+    return v;
+  }
+  const uint8_t* q = (const uint8_t*)p + 8 * w;
+  if (m == 8 && ((uintptr_t)q & 7) == 0) return *(const uint64_t*)q;
+  if (m == 4 && ((uintptr_t)q & 3) == 0) return *(const uint32_t*)q;
+  uint64_t v = 0;
+  for (uint32_t i = 0; i < m; i++) v |= (uint64_t)q[i] << (8 * i);
+  return v;
+}
+
+// Copy n bytes from (kind, p) to global memory dst (8-byte aligned).
+__device__ __forceinline__ void copy_in(uint8_t* dst, int kind, uint64_t p, uint32_t n, const Stk& stk) {
+  uint32_t full = n / 8;
+  for (uint32_t w = 0; w < full; w++) ((uint64_t*)dst)[w] = chunk(kind, p, w, n, stk);
+  for (uint32_t i = full * 8; i < n; i++) {
+    uint64_t c = chunk(kind, p, i / 8, n, stk);
+    dst[i] = (uint8_t)(c >> (8 * (i & 7)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// maps
+
+__device__ __forceinline__ uint64_t key_hash(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+  uint32_t nw = (m->key_size + 7) / 8;
+  uint64_t h = m->key_size;
+  for (uint32_t w = 0; w < nw; w++) h = hash_step(h, chunk(kind, kp, w, m->key_size, stk));
+  return hash_final(h);
+}
+
+__device__ __forceinline__ bool key_eq(const MapDev* m, const uint8_t* hdr, int kind, uint64_t kp, const Stk& stk) {
+  uint32_t nw = (m->key_size + 7) / 8;
+  for (uint32_t w = 0; w < nw; w++)
+    if (ld_relaxed((uint64_t*)(hdr + 8 + 8 * w)) != chunk(kind, kp, w, m->key_size, stk)) return false;
+  return true;
+}
+
+// Probe for a key.  Returns the slot index or -1; *free_slot receives the
+// first tombstone or the terminating empty slot (or -1).
+__device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, const Stk& stk,
+                             int64_t* free_slot) {
+  uint32_t mask = m->slot_mask;
+  uint32_t i = (uint32_t)h & mask;
+  uint32_t tag = (uint32_t)(h >> 32);
+  int64_t fr = -1;
+  for (uint32_t probe = 0; probe <= mask; probe++) {
+    uint8_t* hdr = m->slots + (uint64_t)i * m->sstride;
+    uint64_t st = ld_relaxed((uint64_t*)hdr);
+    uint32_t state = (uint32_t)st;
+    if (state == SLOT_EMPTY) {
+      if (fr < 0) fr = i;
+      break;
+    }
+    if (state == SLOT_TOMB) {
+      if (fr < 0) fr = i;
+    } else if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && key_eq(m, hdr, kind, kp, stk)) {
+      if (free_slot) *free_slot = fr;
+      return i;
+    }
+    i = (i + 1) & mask;
+  }
+  if (free_slot) *free_slot = fr;
+  return -1;
+}
+
+__device__ uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+  uint64_t h = key_hash(m, kind, kp, stk);
+  int64_t s = hash_find(m, h, kind, kp, stk, nullptr);
+  return s < 0 ? 0 : (uint64_t)(m->data + (uint64_t)s * m->vstride);
+}
+
+__device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp,
+                               uint64_t flags, const Stk& stk) {
+  if (flags > 2) return -E_INVAL;
+  uint64_t h = key_hash(m, kkind, kp, stk);
+  int64_t fr;
+  int64_t s = hash_find(m, h, kkind, kp, stk, &fr);
+  if (s >= 0) {
+    if (flags == 1) return -E_EXIST;
+    copy_in(m->data + (uint64_t)s * m->vstride, vkind, vp, m->value_size, stk);
+    return 0;
+  }
+  if (flags == 2) return -E_NOENT;
+  uint64_t live = __hip_atomic_fetch_add(&m->ctrl[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (live >= m->max_entries) {
+    __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&m->ctrl[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return -E_2BIG;
+  }
+  uint32_t mask = m->slot_mask;
+  uint32_t i = fr >= 0 ? (uint32_t)fr : ((uint32_t)h & mask);
+  for (uint32_t probe = 0; probe <= mask; probe++) {
+    uint32_t* st = (uint32_t*)(m->slots + (uint64_t)i * m->sstride);
+    uint32_t cur = ld_relaxed(st);
+    if (cur == SLOT_EMPTY || cur == SLOT_TOMB) {
+      uint32_t exp = cur;
+      if (__hip_atomic_compare_exchange_strong(st, &exp, (uint32_t)SLOT_BUSY, __ATOMIC_ACQUIRE,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        uint8_t* hdr = (uint8_t*)st;
+        uint32_t nw = (m->key_size + 7) / 8;
+        ((uint32_t*)hdr)[1] = (uint32_t)(h >> 32);
+        for (uint32_t w = 0; w < nw; w++) ((uint64_t*)(hdr + 8))[w] = chunk(kkind, kp, w, m->key_size, stk);
+        copy_in(m->data + (uint64_t)i * m->vstride, vkind, vp, m->value_size, stk);
+        __threadfence();
+        st_release(st, (uint32_t)SLOT_LIVE);
+        return 0;
+      }
+    }
+    i = (i + 1) & mask;
+  }
+  // unreachable while live < slots; undo the reservation
+  __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return -E_2BIG;
+}
+
+__device__ int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+  uint64_t h = key_hash(m, kind, kp, stk);
+  int64_t s = hash_find(m, h, kind, kp, stk, nullptr);
+  if (s < 0) return -E_NOENT;
+  st_release((uint32_t*)(m->slots + (uint64_t)s * m->sstride), (uint32_t)SLOT_TOMB);
+  __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+__device__ __forceinline__ uint64_t array_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+  uint32_t idx = (uint32_t)chunk(kind, kp, 0, 4, stk);
+  return idx < m->max_entries ? (uint64_t)(m->data + (uint64_t)idx * m->vstride) : 0;
+}
+
+__device__ int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp, uint64_t flags,
+                                const Stk& stk) {
+  if (flags > 2) return -E_INVAL;
+  uint32_t idx = (uint32_t)chunk(kkind, kp, 0, 4, stk);
+  if (idx >= m->max_entries) return -E_2BIG;
+  if (flags == 1) return -E_EXIST;
+  copy_in(m->data + (uint64_t)idx * m->vstride, vkind, vp, m->value_size, stk);
+  return 0;
+}
+
+// ringbuf_output for the whole wave; ``act`` lanes take part.  Space for all
+// outputs of the wave is reserved with one compare-and-swap on the head.
+__device__ uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t size, uint64_t flags,
+                                bool act, const Stk& stk) {
+  uint64_t res = 0;
+  bool want = act && flags == 0;
+  if (act && flags != 0) res = (uint64_t)-E_INVAL;
+  uint64_t wm = ballot(want);
+  if (wm == 0) return res;
+  uint32_t need = 8 + ((size + 7) & ~7u);
+  uint32_t cnt = popc64(wm);
+  uint32_t leader = (uint32_t)__builtin_ctzll(wm);
+  uint64_t total = (uint64_t)need * cnt;
+  uint64_t cap = (uint64_t)m->slot_mask + 1;
+  uint32_t ok = 0, base_lo = 0, base_hi = 0;
+  if (lane_id() == leader) {
+    uint64_t* head = &m->ctrl[0];
+    uint64_t h = ld_relaxed(head);
+    for (int tries = 0; tries < 1 << 20; tries++) {
+      uint64_t t = ld_relaxed(&m->ctrl[1]);
+      if (h + total - t > cap) break;
+      if (__hip_atomic_compare_exchange_strong(head, &h, h + total, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 1;
+        break;
+      }
+    }
+    base_lo = (uint32_t)h;
+    base_hi = (uint32_t)(h >> 32);
+    if (!ok) __hip_atomic_fetch_add(&m->ctrl[2], (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  ok = rdlane(ok, leader);
+  uint64_t base = ((uint64_t)rdlane(base_hi, leader) << 32) | rdlane(base_lo, leader);
+  if (!ok) {
+    if (want) res = (uint64_t)-E_AGAIN;
+    return res;
+  }
+  if (want) {
+    uint64_t pos = base + (uint64_t)need * rank_in(wm);
+    uint64_t mask = cap - 1;
+    uint32_t nw = (size + 7) / 8;
+    for (uint32_t w = 0; w < nw; w++)
+      *(uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask)) = chunk(kind, dp, w, size, stk);
+    __threadfence();
+    __hip_atomic_store((uint64_t*)(m->data + (pos & mask)), (uint64_t)size, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    res = 0;
+  }
+  return res;
+}
+
+// Atomic read-modify-write on global memory; commutative non-fetching forms
+// are reduced across the active lanes when they all hit one address.
+__device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uint32_t op, int sc, uint64_t r0) {
+  bool w64 = sc == 3;
+  if (!(op & 1)) {  // ADD / OR / AND / XOR without fetch
+    uint64_t first = rfl64(addr);
+    if (ballot(addr == first) == ballot(true)) {
+      uint64_t agg;
+      switch (op) {
+        case 0x00: agg = w64 ? __builtin_amdgcn_wave_reduce_add_u64(v, 0) : __builtin_amdgcn_wave_reduce_add_u32((uint32_t)v, 0); break;
+        case 0x40: agg = w64 ? __builtin_amdgcn_wave_reduce_or_b64(v, 0) : __builtin_amdgcn_wave_reduce_or_b32((uint32_t)v, 0); break;
+        case 0x50: agg = w64 ? __builtin_amdgcn_wave_reduce_and_b64(v, 0) : __builtin_amdgcn_wave_reduce_and_b32((uint32_t)v, 0); break;
+        default: agg = w64 ? __builtin_amdgcn_wave_reduce_xor_b64(v, 0) : __builtin_amdgcn_wave_reduce_xor_b32((uint32_t)v, 0); break;
+      }
+      if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
+        v = agg;
+      } else {
+        return 0;
+      }
+    }
+  }
+  if (w64) {
+    uint64_t* p = (uint64_t*)addr;
+    switch (op) {
+      case 0x00: case 0x01: return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      case 0x40: case 0x41: return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      case 0x50: case 0x51: return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      case 0xa0: case 0xa1: return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      case 0xe1: return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      default: {
+        uint64_t e = r0;
+        __hip_atomic_compare_exchange_strong(p, &e, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return e;
+      }
+    }
+  }
+  uint32_t* p = (uint32_t*)addr;
+  uint32_t x = (uint32_t)v;
+  switch (op) {
+    case 0x00: case 0x01: return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    case 0x40: case 0x41: return __hip_atomic_fetch_or(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    case 0x50: case 0x51: return __hip_atomic_fetch_and(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    case 0xa0: case 0xa1: return __hip_atomic_fetch_xor(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    case 0xe1: return __hip_atomic_exchange(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    default: {
+      uint32_t e = (uint32_t)r0;
+      __hip_atomic_compare_exchange_strong(p, &e, x, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return e;
+    }
+  }
+}
+
+// Read-modify-write on the lane's own stack (private: no atomicity needed).
+__device__ __forceinline__ uint64_t atomic_stack(uint8_t* p, uint64_t v, uint32_t op, int sc, uint64_t r0) {
+  uint64_t old = load_sized(p, sc), nv;
+  switch (op & 0xf0) {
+    case 0x00: nv = old + v; break;
+    case 0x40: nv = old | v; break;
+    case 0x50: nv = old & v; break;
+    case 0xa0: nv = old ^ v; break;
+    case 0xe0: nv = v; break;
+    default: nv = ((sc == 3 ? r0 : (uint32_t)r0) == old) ? v : old; break;
+  }
+  store_sized(p, nv, sc);
+  return old;
+}
+
+__device__ __forceinline__ uint64_t bswap_bits(uint64_t a, uint32_t bits) {
+  if (bits == 16) return __builtin_bswap16((uint16_t)a);
+  if (bits == 32) return __builtin_bswap32((uint32_t)a);
+  return __builtin_bswap64(a);
+}
+
+// Checked mode: a map-value access must stay inside the map it was verified
+// against; a violation is counted and the access skipped.
+__device__ __forceinline__ bool guard_ok(const RunArgs& A, uint32_t pc, uint64_t addr, uint32_t size) {
+  typedef const __attribute__((address_space(4))) uint64_t cu64;
+  const cu64* g = (const cu64*)(A.guards + 2 * pc);
+  bool ok = addr >= g[0] && addr + size <= g[1];
+  if (!ok) __hip_atomic_fetch_add(A.err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// The interpreter: runs one invocation per live lane and returns rc.
+
+struct Ctx {
+  uint64_t c0, c1, c2;  // event record words
+};
+
+__device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2,
+                                           const Stk stk, uint64_t& steps) {
+  const Uop* __restrict__ U = A.uops;
+  rf_t r = (rf_t)(0);
+  r[10] = A.stack_bytes;
+  bool alive = live;
+  uint32_t rc = 0;
+  uint32_t pc = 0;
+  bool div = false;
+  uint32_t mypc = 0;
+  uint32_t wd = 15;
+  uint64_t wres = 0;
+  if (ballot(alive) == 0) return 0;
+  for (;;) {
+    // pc and wd are wave-uniform; say so, so that register indexing and the
+    // micro-op fetch stay scalar
+    pc = rfl(pc);
+    wd = rfl(wd);
+    r[wd] = wres;
+    if (++steps > A.step_limit) {
+      if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true)))
+        __hip_atomic_fetch_add(A.err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    // constant address space: invariant for the kernel's lifetime, so the
+    // uniform fetch becomes a scalar load
+    typedef const __attribute__((address_space(4))) uint64_t cu64;
+    const cu64* up = (const cu64*)(U + pc);
+    const uint64_t q0 = up[0], imm = up[1];
+    const uint32_t w0 = (uint32_t)q0;
+    const int32_t aux = (int32_t)(q0 >> 32);
+    const uint32_t h = w0 & 0xff, d = (w0 >> 8) & 15, s = (w0 >> 12) & 15, a8 = (w0 >> 16) & 0xff;
+    const bool K = (w0 >> 24) & 1;
+    bool act = alive && (!div || mypc == pc);
+    const uint64_t a = r[d];
+    uint64_t b;
+    if (K) b = imm;
+    else b = r[s];
+    uint64_t res = a, wold = a;
+    uint32_t nwd = 15;
+    uint32_t npc = pc + 1;
+    int br = 0;
+    bool tk = false;
+    const uint32_t xa = (uint32_t)a, xb = (uint32_t)b;
+    const int sc = a8 & 3;
+    switch (h) {
+      case H_ADD64: res = a + b; nwd = d; break;
+      case H_SUB64: res = a - b; nwd = d; break;
+      case H_MUL64: res = a * b; nwd = d; break;
+      case H_DIV64: res = b ? a / b : 0; nwd = d; break;
+      case H_SDIV64:
+        res = !b ? 0 : ((int64_t)a == INT64_MIN && (int64_t)b == -1) ? a : (uint64_t)((int64_t)a / (int64_t)b);
+        nwd = d;
+        break;
+      case H_OR64: res = a | b; nwd = d; break;
+      case H_AND64: res = a & b; nwd = d; break;
+      case H_LSH64: res = a << (b & 63); nwd = d; break;
+      case H_RSH64: res = a >> (b & 63); nwd = d; break;
+      case H_NEG64: res = 0 - a; nwd = d; break;
+      case H_MOD64: res = b ? a % b : a; nwd = d; break;
+      case H_SMOD64: res = !b ? a : ((int64_t)b == -1) ? 0 : (uint64_t)((int64_t)a % (int64_t)b); nwd = d; break;
+      case H_XOR64: res = a ^ b; nwd = d; break;
+      case H_MOV64: res = b; nwd = d; break;
+      case H_ARSH64: res = (uint64_t)((int64_t)a >> (b & 63)); nwd = d; break;
+      case H_MOVSX64: res = a8 == 8 ? sx(b, 0) : a8 == 16 ? sx(b, 1) : sx(b, 2); nwd = d; break;
+      case H_BSWAP: res = bswap_bits(a, a8); nwd = d; break;
+      case H_TRUNC: res = a8 == 16 ? (a & 0xffff) : a8 == 32 ? (a & 0xffffffffull) : a; nwd = d; break;
+      case H_ADD32: res = (uint32_t)(xa + xb); nwd = d; break;
+      case H_SUB32: res = (uint32_t)(xa - xb); nwd = d; break;
+      case H_MUL32: res = (uint32_t)(xa * xb); nwd = d; break;
+      case H_DIV32: res = xb ? xa / xb : 0; nwd = d; break;
+      case H_SDIV32:
+        res = !xb ? 0 : ((int32_t)xa == INT32_MIN && (int32_t)xb == -1) ? xa : (uint32_t)((int32_t)xa / (int32_t)xb);
+        nwd = d;
+        break;
+      case H_OR32: res = xa | xb; nwd = d; break;
+      case H_AND32: res = xa & xb; nwd = d; break;
+      case H_LSH32: res = (uint32_t)(xa << (xb & 31)); nwd = d; break;
+      case H_RSH32: res = xa >> (xb & 31); nwd = d; break;
+      case H_NEG32: res = (uint32_t)(0u - xa); nwd = d; break;
+      case H_MOD32: res = xb ? xa % xb : xa; nwd = d; break;
+      case H_SMOD32: res = !xb ? xa : ((int32_t)xb == -1) ? 0u : (uint32_t)((int32_t)xa % (int32_t)xb); nwd = d; break;
+      case H_XOR32: res = xa ^ xb; nwd = d; break;
+      case H_MOV32: res = xb; nwd = d; break;
+      case H_ARSH32: res = (uint32_t)((int32_t)xa >> (xb & 31)); nwd = d; break;
+      case H_MOVSX32: res = (uint32_t)(a8 == 8 ? sx(b, 0) : sx(b, 1)); nwd = d; break;
+      // jumps
+      case H_JA: npc = (uint32_t)aux; break;
+      case H_JEQ: br = 1; tk = a == b; break;
+      case H_JGT: br = 1; tk = a > b; break;
+      case H_JGE: br = 1; tk = a >= b; break;
+      case H_JSET: br = 1; tk = (a & b) != 0; break;
+      case H_JNE: br = 1; tk = a != b; break;
+      case H_JSGT: br = 1; tk = (int64_t)a > (int64_t)b; break;
+      case H_JSGE: br = 1; tk = (int64_t)a >= (int64_t)b; break;
+      case H_JLT: br = 1; tk = a < b; break;
+      case H_JLE: br = 1; tk = a <= b; break;
+      case H_JSLT: br = 1; tk = (int64_t)a < (int64_t)b; break;
+      case H_JSLE: br = 1; tk = (int64_t)a <= (int64_t)b; break;
+      case H_JEQ32: br = 1; tk = xa == xb; break;
+      case H_JGT32: br = 1; tk = xa > xb; break;
+      case H_JGE32: br = 1; tk = xa >= xb; break;
+      case H_JSET32: br = 1; tk = (xa & xb) != 0; break;
+      case H_JNE32: br = 1; tk = xa != xb; break;
+      case H_JSGT32: br = 1; tk = (int32_t)xa > (int32_t)xb; break;
+      case H_JSGE32: br = 1; tk = (int32_t)xa >= (int32_t)xb; break;
+      case H_JLT32: br = 1; tk = xa < xb; break;
+      case H_JLE32: br = 1; tk = xa <= xb; break;
+      case H_JSLT32: br = 1; tk = (int32_t)xa < (int32_t)xb; break;
+      case H_JSLE32: br = 1; tk = (int32_t)xa <= (int32_t)xb; break;
+      // memory
+      case H_LDX_CTX: {
+        const uint32_t wi = (uint32_t)aux >> 3;
+        uint64_t wv = c0;
+        if (wi == 1) wv = c1;
+        if (wi == 2) wv = c2;
+        wv >>= 8 * ((uint32_t)aux & 7);
+        uint64_t v = sc == 3 ? wv : (wv & ((1ull << (8 << sc)) - 1));
+        res = (a8 & 4) ? sx(v, sc) : v;
+        nwd = d;
+        break;
+      }
+      case H_LDX_STACK:
+        if (act) {
+          uint64_t v = load_sized(saddr(stk, (uint32_t)b + aux), sc);
+          res = (a8 & 4) ? sx(v, sc) : v;
+        }
+        nwd = d;
+        break;
+      case H_LDX_MAP:
+        if (A.checked) act = act && guard_ok(A, pc, b + (int64_t)aux, 1u << sc);
+        if (act) {
+          uint64_t v = load_sized((const uint8_t*)(b + (int64_t)aux), sc);
+          res = (a8 & 4) ? sx(v, sc) : v;
+        }
+        nwd = d;
+        break;
+      case H_ST_STACK:
+      case H_STX_STACK:
+        if (act) store_sized(saddr(stk, (uint32_t)a + aux), b, sc);
+        break;
+      case H_ST_MAP:
+      case H_STX_MAP:
+        if (A.checked) act = act && guard_ok(A, pc, a + (int64_t)aux, 1u << sc);
+        if (act) store_sized((uint8_t*)(a + (int64_t)aux), b, sc);
+        break;
+      case H_ATOMIC_STACK:
+      case H_ATOMIC_MAP: {
+        uint32_t op = (uint32_t)imm;
+        uint64_t r0 = r[0];
+        uint64_t v = r[s];
+        uint64_t old = 0;
+        if (A.checked && h == H_ATOMIC_MAP) act = act && guard_ok(A, pc, a + (int64_t)aux, 1u << sc);
+        if (act) {
+          if (h == H_ATOMIC_STACK)
+            old = atomic_stack(saddr(stk, (uint32_t)a + aux), v, op, sc, r0);
+          else
+            old = atomic_global(a + (int64_t)aux, v, op, sc, r0);
+        }
+        if (op == 0xf1) {
+          res = old;
+          wold = r0;
+          nwd = 0;
+        } else if (op & 1) {
+          res = old;
+          wold = v;
+          nwd = s;
+        }
+        break;
+      }
+      case H_LDIMM: res = imm; nwd = d; npc = pc + 2; break;
+      // helpers (dst field is 0, so a == r0)
+      case H_LOOKUP_ARRAY: {
+        const MapDev* m = (const MapDev*)imm;
+        if (act) res = array_lookup(m, a8 & 1, r[2], stk);
+        nwd = 0;
+        break;
+      }
+      case H_LOOKUP_HASH: {
+        const MapDev* m = (const MapDev*)imm;
+        if (act) res = hash_lookup(m, a8 & 1, r[2], stk);
+        nwd = 0;
+        break;
+      }
+      case H_UPDATE_ARRAY: {
+        const MapDev* m = (const MapDev*)imm;
+        if (act) res = (uint64_t)array_update(m, a8 & 1, r[2], (a8 >> 1) & 1, r[3], r[4], stk);
+        nwd = 0;
+        break;
+      }
+      case H_UPDATE_HASH: {
+        const MapDev* m = (const MapDev*)imm;
+        if (act) res = (uint64_t)hash_update(m, a8 & 1, r[2], (a8 >> 1) & 1, r[3], r[4], stk);
+        nwd = 0;
+        break;
+      }
+      case H_DELETE_HASH: {
+        const MapDev* m = (const MapDev*)imm;
+        if (act) res = (uint64_t)hash_delete(m, a8 & 1, r[2], stk);
+        nwd = 0;
+        break;
+      }
+      case H_RET_EINVAL: res = (uint64_t)-E_INVAL; nwd = 0; break;
+      case H_RINGBUF_OUTPUT: {
+        const MapDev* m = (const MapDev*)imm;
+        uint64_t rr = ring_output(m, a8 & 1, r[2], (uint32_t)aux, r[4], act, stk);
+        if (act) res = rr;
+        nwd = 0;
+        break;
+      }
+      case H_EXIT: br = 2; break;
+      default: br = 2; break;
+    }
+    wd = nwd;
+    wres = res;
+    if (div && !act) wres = wold;
+    if (br == 2) {
+      if (act) {
+        rc = (uint32_t)a;
+        alive = false;
+      }
+      if (!div || ballot(alive) == 0) {
+        r[wd] = wres;
+        break;
+      }
+    }
+    if (!div) {
+      if (br == 1) {
+        uint64_t am = ballot(alive), tm = ballot(alive && tk);
+        if (tm == 0) {
+          pc = pc + 1;
+        } else if (tm == am) {
+          pc = (uint32_t)aux;
+        } else {
+          div = true;
+          mypc = tk ? (uint32_t)aux : pc + 1;
+          pc = (uint32_t)aux < pc + 1 ? (uint32_t)aux : pc + 1;
+        }
+      } else {
+        pc = npc;
+      }
+    } else {
+      if (act) mypc = br == 1 ? (tk ? (uint32_t)aux : pc + 1) : npc;
+      uint32_t cand = alive ? mypc : 0xffffffffu;
+      pc = __builtin_amdgcn_wave_reduce_min_u32(cand, 0);
+      if (ballot(alive && mypc != pc) == 0) div = false;
+    }
+  }
+  return rc;
+}
+
+__device__ __forceinline__ Ctx load_record(const RunArgs& A, uint64_t i) {
+  const uint64_t* p = (const uint64_t*)(A.events + i * A.record_size);
+  Ctx c;
+  c.c0 = p[0];
+  c.c1 = p[1];
+  c.c2 = A.record_size > 16 ? p[2] : 0;
+  return c;
+}
+
+// Event-parallel mode: lane = event.
+extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A) {
+  const uint32_t wave = threadIdx.x >> 6;
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u};
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < A.n_events;
+  Ctx c{0, 0, 0};
+  if (live) c = load_record(A, i);
+  uint64_t steps = 0;
+  uint32_t rc = vm_run(A, live, c.c0, c.c1, c.c2, stk, steps);
+  if (live && A.rc) A.rc[i] = rc;
+}
+
+// Stream-sequential mode: each lane owns one queue and runs its events in
+// index order.  ``lanes`` lanes of each wave are used (1..64).
+extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
+  const uint32_t l = lane_id();
+  const uint32_t q = blockIdx.x * lanes + l;
+  const bool own = l < lanes && q < A.n_queues;
+  uint32_t beg = 0, end = 0;
+  if (own) {
+    beg = A.qstart[(uint64_t)q * qstride];
+    end = q + 1 < A.n_queues ? A.qstart[(uint64_t)(q + 1) * qstride] : (uint32_t)A.n_events;
+  }
+  uint32_t cnt = end - beg;
+  uint32_t rounds = __builtin_amdgcn_wave_reduce_max_u32(cnt, 0);
+  Stk stk{0, l * 8u};
+  uint64_t steps = 0;
+  for (uint32_t k = 0; k < rounds; k++) {
+    bool live = k < cnt;
+    uint64_t i = live ? A.order[beg + k] : 0;
+    Ctx c{0, 0, 0};
+    if (live) c = load_record(A, i);
+    uint32_t rc = vm_run(A, live, c.c0, c.c1, c.c2, stk, steps);
+    if (live && A.rc) A.rc[i] = rc;
+    if (steps > A.step_limit) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stable partition of event indices by queue = stream key & (L - 1)
+
+__device__ __forceinline__ uint32_t stream_key(const RunArgs& A, uint64_t i) {
+  const uint8_t* p = A.events + i * A.record_size + A.stream_off;
+  return *(const uint32_t*)p;
+}
+
+// counts[q * nt + t] = events of tile t in queue q.  One wave per tile.
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_count(RunArgs A, uint32_t* counts, uint32_t lbits,
+                                                                 uint32_t tile, uint32_t nt) {
+  uint32_t* cnt = (uint32_t*)g_lds;
+  const uint32_t L = 1u << lbits, t = blockIdx.x, l = lane_id();
+  for (uint32_t q = l; q < L; q += 64) cnt[q] = 0;
+  __syncthreads();
+  uint64_t b = (uint64_t)t * tile, e = b + tile < A.n_events ? b + tile : A.n_events;
+  for (uint64_t i = b + l; i < e; i += 64) atomicAdd(&cnt[stream_key(A, i) & (L - 1)], 1u);
+  __syncthreads();
+  for (uint32_t q = l; q < L; q += 64) counts[(uint64_t)q * nt + t] = cnt[q];
+}
+
+// order[offs[q * nt + t] + rank] = i, ranks in index order within the tile.
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter(RunArgs A, const uint32_t* offs, uint32_t* order,
+                                                                   uint32_t lbits, uint32_t tile, uint32_t nt) {
+  uint32_t* base = (uint32_t*)g_lds;
+  const uint32_t L = 1u << lbits, t = blockIdx.x, l = lane_id();
+  for (uint32_t q = l; q < L; q += 64) base[q] = offs[(uint64_t)q * nt + t];
+  __syncthreads();
+  uint64_t b = (uint64_t)t * tile, e = b + tile < A.n_events ? b + tile : A.n_events;
+  for (uint64_t c = b; c < e; c += 64) {
+    uint64_t i = c + l;
+    bool v = i < e;
+    uint32_t key = v ? (stream_key(A, i) & (L - 1)) : 0;
+    uint64_t peers = ballot(v);
+    for (uint32_t bit = 0; bit < lbits; bit++) {
+      uint64_t m = ballot(v && ((key >> bit) & 1));
+      peers &= ((key >> bit) & 1) ? m : ~m;
+    }
+    uint32_t rank = rank_in(peers);
+    uint32_t pos = 0;
+    if (v) pos = base[key] + rank;
+    // every lane has read its base before a group leader advances it: one
+    // wave executes the LDS read and the LDS write in program order
+    if (v) {
+      order[pos] = (uint32_t)i;
+      if (rank == 0) base[key] = pos + popc64(peers);
+    }
+  }
+}
+
+// exclusive scan of u32 data[0..n): block sums, then the sums, then add back
+constexpr uint32_t kScanItems = 16;
+constexpr uint32_t kScanBlock = 256 * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  // 256 threads; tmp has 256 entries
+  const uint32_t t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (uint32_t off = 1; off < 256; off <<= 1) {
+    uint32_t x = t >= off ? tmp[t - off] : 0;
+    __syncthreads();
+    tmp[t] += x;
+    __syncthreads();
+  }
+  uint32_t incl = tmp[t];
+  *total = tmp[255];
+  __syncthreads();
+  return incl - v;
+}
+
+extern "C" __global__ void __launch_bounds__(256) gx_k_scan_local(uint32_t* data, uint64_t n, uint32_t* sums) {
+  __shared__ uint32_t tmp[256];
+  uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t vals[kScanItems];
+  uint32_t acc = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kScanItems; k++) {
+    vals[k] = base + k < n ? data[base + k] : 0;
+    acc += vals[k];
+  }
+  uint32_t total;
+  uint32_t pre = block_exclusive_scan(acc, tmp, &total);
+#pragma unroll
+  for (uint32_t k = 0; k < kScanItems; k++) {
+    if (base + k < n) data[base + k] = pre;
+    pre += vals[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+extern "C" __global__ void __launch_bounds__(256) gx_k_scan_sums(uint32_t* sums, uint32_t nb) {
+  __shared__ uint32_t tmp[256];
+  uint32_t carry = 0;
+  for (uint32_t c = 0; c < nb; c += 256) {
+    uint32_t i = c + threadIdx.x;
+    uint32_t v = i < nb ? sums[i] : 0;
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan(v, tmp, &total);
+    if (i < nb) sums[i] = pre + carry;
+    carry += total;
+    __syncthreads();
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(256) gx_k_scan_add(uint32_t* data, uint64_t n, const uint32_t* sums) {
+  uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
+  uint32_t add = sums[blockIdx.x];
+  for (uint32_t k = threadIdx.x; k < kScanBlock; k += 256)
+    if (base + k < n) data[base + k] += add;
+}
+
+// ---------------------------------------------------------------------------
+// control-plane map operations (one lane): op 0 lookup, 1 update, 2 delete
+extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val,
+                                       uint64_t flags, int64_t* ret, uint8_t* val_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Stk stk{0, 0};
+  uint64_t kp = (uint64_t)key, vp = (uint64_t)val;
+  int64_t r = -E_INVAL;
+  if (m->type == MAP_ARRAY) {
+    if (op == 0) {
+      uint64_t p = array_lookup(m, PK_MAPVAL, kp, stk);
+      if (p) {
+        for (uint32_t i = 0; i < m->value_size; i++) val_out[i] = ((const uint8_t*)p)[i];
+        r = 0;
+      } else {
+        r = -E_NOENT;
+      }
+    } else if (op == 1) {
+      r = array_update(m, PK_MAPVAL, kp, PK_MAPVAL, vp, flags, stk);
+    }
+  } else if (m->type == MAP_HASH) {
+    if (op == 0) {
+      uint64_t p = hash_lookup(m, PK_MAPVAL, kp, stk);
+      if (p) {
+        for (uint32_t i = 0; i < m->value_size; i++) val_out[i] = ((const uint8_t*)p)[i];
+        r = 0;
+      } else {
+        r = -E_NOENT;
+      }
+    } else if (op == 1) {
+      r = hash_update(m, PK_MAPVAL, kp, PK_MAPVAL, vp, flags, stk);
+    } else {
+      r = hash_delete(m, PK_MAPVAL, kp, stk);
+    }
+  }
+  *ret = r;
+}
+
+}  // namespace gx
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+namespace gx {
+
+hipError_t vm_init() {
+  hipError_t e = hipFuncSetAttribute((const void*)gx_k_event_parallel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     256 * kStackMax);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)gx_k_stream_seq, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
+}
+
+hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s) {
+  uint64_t blocks = (A.n_events + 255) / 256;
+  hipLaunchKernelGGL(gx_k_event_parallel, dim3((uint32_t)blocks), dim3(256), 256 * A.stack_bytes, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride, hipStream_t s) {
+  uint32_t blocks = (A.n_queues + lanes - 1) / lanes;
+  hipLaunchKernelGGL(gx_k_stream_seq, dim3(blocks), dim3(64), 64 * A.stack_bytes, s, A, lanes, qstride);
+  return hipGetLastError();
+}
+
+// Stable partition of event indices into 2^lbits queues.  counts must hold
+// 2^lbits * nt entries, sums ceil(2^lbits * nt / 4096), order n_events.
+hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
+                            uint32_t* sums, uint32_t* order, hipStream_t s) {
+  uint32_t L = 1u << lbits;
+  hipLaunchKernelGGL(gx_k_part_count, dim3(nt), dim3(64), L * 4, s, A, counts, lbits, tile, nt);
+  uint64_t m = (uint64_t)L * nt;
+  uint32_t nb = (uint32_t)((m + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(gx_k_scan_local, dim3(nb), dim3(256), 0, s, counts, m, sums);
+  hipLaunchKernelGGL(gx_k_scan_sums, dim3(1), dim3(256), 0, s, sums, nb);
+  hipLaunchKernelGGL(gx_k_scan_add, dim3(nb), dim3(256), 0, s, counts, m, (const uint32_t*)sums);
+  hipLaunchKernelGGL(gx_k_part_scatter, dim3(nt), dim3(64), L * 4, s, A, (const uint32_t*)counts, order, lbits,
+                     tile, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
+                         int64_t* ret, uint8_t* val_out, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_map_op, dim3(1), dim3(64), 0, s, m, op, key, val, flags, ret, val_out);
+  return hipGetLastError();
+}
+
+}  // namespace gx

@@ -1,0 +1,246 @@
+"""Python binding of the C ABI in include/gxbpf.h (ctypes; argument marshalling
+only).  Device buffers are torch tensors; streams are torch CUDA/HIP streams.
+Every step of the path runs in libgxbpf.so: there is no fallback, and
+importing this module without the built library raises."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgxbpf.so")
+
+MAP_HASH, MAP_ARRAY, MAP_RINGBUF = 1, 2, 27
+F_SHARED, F_READ_ONLY = 1, 2
+HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING = 1, 2
+MODE_EVENT_PARALLEL, MODE_STREAM_SEQUENTIAL = 0, 1
+RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16}
+
+
+class GxError(OSError):
+    pass
+
+
+class ProgInfo(C.Structure):
+    _fields_ = [("mode", C.c_uint32), ("hook", C.c_uint32), ("n_insns", C.c_uint32),
+                ("stack_bytes", C.c_uint32), ("max_insns", C.c_uint64), ("max_calls", C.c_uint64),
+                ("max_ring_bytes", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("events", C.c_uint64), ("ring_drops", C.c_uint64),
+                ("hash_e2big", C.c_uint64), ("vm_errors", C.c_uint64), ("bytes_drained", C.c_uint64)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("prog_fd", C.c_int32), ("record_size", C.c_uint32), ("d_events", C.c_void_p),
+                ("n_events", C.c_uint64), ("d_rc", C.c_void_p)]
+
+
+EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
+           "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
+           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run paper_2512_12615_amd/build.py "
+                           "(or __graft_entry__.build()) first")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, i64 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int64
+    L.gx_open.argtypes = [C.c_int, C.POINTER(vp)]
+    L.gx_close.argtypes = [vp]
+    L.gx_close.restype = None
+    L.gx_create_map.argtypes = [vp, u32, u32, u32, u32, u32]
+    L.gx_map_update.argtypes = [vp, C.c_int, vp, vp, u64]
+    L.gx_map_lookup.argtypes = [vp, C.c_int, vp, vp]
+    L.gx_map_delete.argtypes = [vp, C.c_int, vp]
+    L.gx_map_dump.argtypes = [vp, C.c_int, vp, vp, u64]
+    L.gx_map_dump.restype = i64
+    L.gx_map_clear.argtypes = [vp, C.c_int]
+    L.gx_load_program.argtypes = [vp, vp, u32, u32, vp, u32, C.c_char_p, u32]
+    L.gx_prog_info_get.argtypes = [vp, C.c_int, C.POINTER(ProgInfo)]
+    L.gx_verify.argtypes = [vp, u32, u32, vp, u32, C.c_char_p, u32, C.POINTER(ProgInfo)]
+    L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
+    L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
+    L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
+    L.gx_drain_ringbuf.restype = i64
+    L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
+    _lib = L
+    return L
+
+
+def _check(r, what):
+    if r < 0:
+        raise GxError(-r, f"{what}: {os.strerror(-r)}")
+    return r
+
+
+def _words(code: bytes) -> np.ndarray:
+    if len(code) % 8:
+        raise ValueError("bytecode length must be a multiple of 8")
+    return np.frombuffer(code, dtype="<u8").copy() if code else np.zeros(1, "<u8")
+
+
+def verify(code: bytes, hook: int, shapes):
+    """Verify without a device.  ``shapes``: (type, key_size, value_size,
+    max_entries, flags) per map, in the program's map-table order.
+    Returns (ok, log, ProgInfo)."""
+    sh = np.array(shapes, dtype=np.uint32).reshape(-1, 5) if shapes else np.zeros((0, 5), np.uint32)
+    w = _words(code)
+    log = C.create_string_buffer(512)
+    info = ProgInfo()
+    r = lib().gx_verify(w.ctypes.data_as(C.c_void_p), len(code) // 8, hook, sh.ctypes.data_as(C.c_void_p),
+                        len(sh), log, 512, C.byref(info))
+    return r == 0, log.value.decode(), info
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class MapInfo:
+    type: int
+    key_size: int
+    value_size: int
+    max_entries: int
+    flags: int
+
+
+class Runtime:
+    """One gx_rt on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        _check(lib().gx_open(device, C.byref(self._h)), "gx_open")
+        self.maps: dict[int, MapInfo] = {}
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().gx_close(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # maps -----------------------------------------------------------------
+    def create_map(self, type_, key_size, value_size, max_entries, flags=0) -> int:
+        fd = _check(lib().gx_create_map(self._h, type_, key_size, value_size, max_entries, flags), "gx_create_map")
+        self.maps[fd] = MapInfo(type_, key_size, value_size, max_entries, flags)
+        return fd
+
+    def map_update(self, fd, key: bytes, val: bytes, flags=0) -> int:
+        return lib().gx_map_update(self._h, fd, C.c_char_p(bytes(key)), C.c_char_p(bytes(val)), flags)
+
+    def map_lookup(self, fd, key: bytes):
+        buf = C.create_string_buffer(self.maps[fd].value_size)
+        r = lib().gx_map_lookup(self._h, fd, C.c_char_p(bytes(key)), buf)
+        return None if r else buf.raw
+
+    def map_delete(self, fd, key: bytes) -> int:
+        return lib().gx_map_delete(self._h, fd, C.c_char_p(bytes(key)))
+
+    def map_clear(self, fd):
+        _check(lib().gx_map_clear(self._h, fd), "gx_map_clear")
+
+    def map_dump(self, fd):
+        """(keys, values) as uint8 arrays of shape (n, key_size) / (n, value_size)."""
+        m = self.maps[fd]
+        n = _check(lib().gx_map_dump(self._h, fd, None, None, 0), "gx_map_dump")
+        keys = np.zeros((max(n, 1), m.key_size), np.uint8)
+        vals = np.zeros((max(n, 1), m.value_size), np.uint8)
+        _check(lib().gx_map_dump(self._h, fd, keys.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p), n),
+               "gx_map_dump")
+        return keys[:n], vals[:n]
+
+    # programs ---------------------------------------------------------------
+    def load_program(self, code: bytes, hook: int, map_fds) -> int:
+        w = _words(code)
+        fds = np.array(list(map_fds), dtype=np.int32)
+        log = C.create_string_buffer(512)
+        r = lib().gx_load_program(self._h, w.ctypes.data_as(C.c_void_p), len(code) // 8, hook,
+                                  fds.ctypes.data_as(C.c_void_p) if len(fds) else None, len(fds), log, 512)
+        if r < 0:
+            raise GxError(-r, f"gx_load_program: {os.strerror(-r)}: {log.value.decode()}")
+        return r
+
+    def prog_info(self, fd) -> ProgInfo:
+        info = ProgInfo()
+        _check(lib().gx_prog_info_get(self._h, fd, C.byref(info)), "gx_prog_info_get")
+        return info
+
+    def run_batch(self, prog_fd, events, n_events=None, record_size=None, rc=None, stream=None):
+        """events: uint8 device tensor of records; rc: uint32/int32 device tensor or None."""
+        if record_size is None:
+            record_size = RECORD_SIZE[self.prog_info(prog_fd).hook]
+        if n_events is None:
+            n_events = events.numel() * events.element_size() // record_size
+        r = lib().gx_run_batch(self._h, prog_fd, _dptr(events), n_events, record_size, _dptr(rc),
+                               _stream_handle(stream))
+        _check(r, "gx_run_batch")
+
+    def run_batches(self, descs, stream=None):
+        """descs: list of (prog_fd, events tensor, n_events, record_size, rc tensor or None)."""
+        arr = (Batch * len(descs))()
+        for i, (p, ev, n, rs, rc) in enumerate(descs):
+            arr[i].prog_fd = p
+            arr[i].record_size = rs
+            arr[i].d_events = ev.data_ptr()
+            arr[i].n_events = n
+            arr[i].d_rc = rc.data_ptr() if rc is not None else None
+        _check(lib().gx_run_batches(self._h, arr, len(descs), _stream_handle(stream)), "gx_run_batches")
+
+    # ring buffers -----------------------------------------------------------
+    def drain_ringbuf(self, fd, cap=None):
+        """Returns (bytes, n_records) of committed records."""
+        if cap is None:
+            cap = self.maps[fd].max_entries
+        buf = np.zeros(max(cap, 8), np.uint8)
+        n = C.c_uint64(0)
+        nb = _check(lib().gx_drain_ringbuf(self._h, fd, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
+                    "gx_drain_ringbuf")
+        return buf[:nb].tobytes(), n.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().gx_stats_get(self._h, C.byref(s)), "gx_stats_get")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def parse_ring(buf: bytes):
+    out, pos = [], 0
+    while pos + 8 <= len(buf):
+        ln = int.from_bytes(buf[pos:pos + 4], "little")
+        out.append(bytes(buf[pos + 8:pos + 8 + ln]))
+        pos += 8 + ((ln + 7) & ~7)
+    return out
