@@ -264,6 +264,7 @@ struct Checker {
   CheckResult res;
   int min_stack = STACK_BYTES;
   std::vector<char> map_used;
+  std::vector<int> shared_op;  // per shared map: the one (atomic op, size) it takes, or -1
 
   Checker(const std::vector<Insn>& i, int h, const std::vector<MapShape>& m, const std::vector<int>& t)
       : ins(i), n((int)i.size()), hook(h), maps(m), table(t) {}
@@ -526,6 +527,13 @@ struct Checker {
       if (b.lo != b.hi && b.tz < __builtin_ctz(size)) rej(pc, "possibly misaligned map value access");
       if ((m.flags & F_READ_ONLY) && mode != 0) rej(pc, "write to read-only map");
       if ((m.flags & F_SHARED) && mode != 2) rej(pc, "shared map takes only commutative atomics");
+      if (m.flags & F_SHARED) {
+        // updates commute only if every update of the map is the same
+        // operation at the same width
+        int key = (ins[pc].imm & 0xff) | (size << 8);
+        if (shared_op[b.map] < 0) shared_op[b.map] = key;
+        else if (shared_op[b.map] != key) rej(pc, "shared map updated with different atomic operations");
+      }
       return;
     }
     if (b.k == A_MAPVAL_OR_NULL) rej(pc, "map value access without null check");
@@ -913,6 +921,7 @@ struct Checker {
         if (id < 0 || id >= (int)maps.size()) throw Reject{"bad map table"};
       structure();
       map_used.assign(maps.size(), 0);
+      shared_op.assign(maps.size(), -1);
       AState s;
       s.live = true;
       s.r[1] = AV{A_CTX, 0, 0, 64, -1};

@@ -64,6 +64,7 @@ struct Map {
   // ownership tracking (D-3): slot -> first stream to touch it, written flag
   std::map<Bytes, std::pair<uint64_t, bool>> owner;
   std::map<Bytes, bool> multi;  // slot touched by more than one stream
+  int shared_op = -1;            // shared maps: the one (atomic op, size) they take
 };
 
 struct Stats {

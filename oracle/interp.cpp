@@ -380,6 +380,8 @@ struct Exec {
 
   // Resolve [base + off, base + off + size) to host bytes with all checks.
   // mode: 0 = load, 1 = store, 2 = commutative atomic, 3 = fetching atomic.
+  int atomic_op = 0;  // operation of the atomic being executed (for shared maps)
+
   uint8_t* mem(int base_reg, int64_t off, int size, int mode) {
     const Reg& b = rd(base_reg);
     if (b.k == K_CTX) {
@@ -405,6 +407,11 @@ struct Exec {
       if (o2 < 0 || o2 + size > (int64_t)m.value_size) fault("map value access out of bounds");
       if ((m.flags & F_READ_ONLY) && mode != 0) fault("write to read-only map");
       if ((m.flags & F_SHARED) && mode != 2) fault("non-commutative access to shared map");
+      if (m.flags & F_SHARED) {
+        int key = atomic_op | (size << 8);
+        if (m.shared_op < 0) m.shared_op = key;
+        else if (m.shared_op != key) fault("shared map updated with different atomic operations");
+      }
       touch(b.map, slot_of(b), mode != 0);
       if (m.type == MAP_ARRAY) return &m.array[(size_t)b.slot * m.value_size + o2];
       return refs[b.slot].val->data() + o2;
@@ -641,6 +648,7 @@ struct Exec {
           bool fetch = aop & 1;
           uint64_t v = scalar(in.src);
           uint64_t cmp = aop == 0xf1 ? scalar(0) : 0;
+          atomic_op = aop & 0xff;
           uint8_t* p8 = mem(in.dst, in.off, size, fetch ? 3 : 2);
           uint64_t old = load_le(p8, size), nv = old;
           switch (aop & 0xf0) {

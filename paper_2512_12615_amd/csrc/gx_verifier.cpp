@@ -271,6 +271,7 @@ class Verifier {
       V.ld_map.assign(N, -1);
       V.mem_map.assign(N, -1);
       used_.assign(maps_.size(), 0);
+      shared_op_.assign(maps_.size(), -1);
       seen_.assign(N, 0);
       encodings();
       cfg();
@@ -312,6 +313,7 @@ class Verifier {
   Verdict out_;
   std::vector<char> second_, used_, seen_;
   std::vector<int> back_of_head_;  // loop head -> back-edge slot
+  std::vector<int> shared_op_;     // shared map -> its single (atomic op, size)
   int low_stack_ = kStackMax;
 
   [[noreturn]] void fail(int pc, const std::string& m) {
@@ -539,6 +541,12 @@ class Verifier {
         if (((base.b.v + (uint64_t)off) & al) || (base.b.m & al)) fail(pc, "map value access may be misaligned");
         if ((m.flags & F_READ_ONLY) && mode != 0) fail(pc, "write to a read-only map");
         if ((m.flags & F_SHARED) && mode != 2) fail(pc, "shared maps take only commutative atomics");
+        if (m.flags & F_SHARED) {
+          // different operations (or widths) on one slot do not commute
+          int op = (P[pc].imm & 0xff) | (size << 8);
+          if (shared_op_[base.map] < 0) shared_op_[base.map] = op;
+          if (shared_op_[base.map] != op) fail(pc, "a shared map must take one atomic operation at one width");
+        }
         fact(out_.mem_kind, pc, KIND_MAPVAL, "memory access");
         fact_map(out_.mem_map, pc, base.map);
         return;

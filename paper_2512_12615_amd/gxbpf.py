@@ -55,6 +55,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run paper_2512_12615_amd/build.py "
                            "(or __graft_entry__.build()) first")
+    # Share torch's HIP runtime: torch loads its own libamdhip64 at import, and
+    # our library's libamdhip64.so.7 dependency then binds to that copy
+    # instead of loading a second runtime into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, u32, u64, i64 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int64
     L.gx_open.argtypes = [C.c_int, C.POINTER(vp)]

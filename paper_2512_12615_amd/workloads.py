@@ -459,6 +459,9 @@ class _Gen:
         self.n = 0
         self.label = 0
         self.calls = 0
+        # one commutative operation per shared map (mixed operations on a
+        # slot would not commute across streams)
+        self.shared_op = ["aadd64", "aadd64", "aadd64", "aor64", "aand64", "axor64", "aadd32"][self.below(7)]
 
     def rnd(self) -> int:
         self.x = (self.x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
@@ -623,8 +626,7 @@ class _Gen:
         self.emit(f"jeq r0, 0, {skip}")
         self.emit(f"mov64 r1, {r}")
         self.emit("and64 r1, 0xffff")
-        op = ["aadd64", "aadd64", "aadd64", "aor64", "aand64", "axor64", "aadd32"][self.below(7)]
-        self.emit(f"{op} [r0+0], r1")
+        self.emit(f"{self.shared_op} [r0+0], r1")
         self.emit(f"{skip}:", 0)
         self.calls += 1
 

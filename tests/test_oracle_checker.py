@@ -93,6 +93,8 @@ REJECTS = {
     "shared_xchg": (LOOKUP_M0 + "jeq r0, 0, o\nmov64 r1, 1\naxchg64 [r0+0], r1\no: mov64 r0, 0\nexit", (SHARED,)),
     "shared_cmpxchg": (LOOKUP_M0 + "jeq r0, 0, o\nmov64 r1, 1\nmov64 r9, r0\nmov64 r0, 0\nacmpxchg64 [r9+0], r1\no: mov64 r0, 0\nexit", (SHARED,)),
     "shared_update": ("stw [r10-4], 0\nstdw [r10-16], 0\nlddw r1, map:m\nmov64 r2, r10\nadd64 r2, -4\nmov64 r3, r10\nadd64 r3, -16\nmov64 r4, 0\ncall map_update_elem\nmov64 r0, 0\nexit", (SHARED,)),
+    "shared_mixed_ops": (LOOKUP_M0 + "jeq r0, 0, o\nmov64 r1, 1\naadd64 [r0+0], r1\naor64 [r0+0], r1\no: mov64 r0, 0\nexit", (SHARED,)),
+    "shared_mixed_widths": (LOOKUP_M0 + "jeq r0, 0, o\nmov64 r1, 1\naadd64 [r0+0], r1\naadd32 [r0+0], r1\no: mov64 r0, 0\nexit", (SHARED,)),
     "readonly_store": (LOOKUP_M0 + "jeq r0, 0, o\nstdw [r0+0], 1\no: mov64 r0, 0\nexit", (RO,)),
     "readonly_atomic": (LOOKUP_M0 + "jeq r0, 0, o\nmov64 r1, 1\naadd64 [r0+0], r1\no: mov64 r0, 0\nexit", (RO,)),
     "hash_pointer_after_update": ("stdw [r10-8], 1\nstdw [r10-24], 0\nstdw [r10-16], 0\nlddw r1, map:m\nmov64 r2, r10\nadd64 r2, -8\ncall map_lookup_elem\njeq r0, 0, o\nmov64 r6, r0\nlddw r1, map:m\nmov64 r2, r10\nadd64 r2, -8\nmov64 r3, r10\nadd64 r3, -24\nmov64 r4, 0\ncall map_update_elem\nldxdw r0, [r6+0]\nexit\no: mov64 r0, 0\nexit", (HASH,)),
