@@ -165,6 +165,15 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
 /* Counters accumulated since gx_open (synchronises the device). */
 int gx_stats_get(gx_rt* rt, gx_stats* out);
 
+/* Measurement support.  While enabled, each gx_run_batch brackets its VM
+ * kernel launch with HIP events on the caller's stream (the stable stream
+ * partition of stream-sequential programs is outside the bracket).
+ * gx_profile_read waits for those events, returns the summed VM-kernel time
+ * in milliseconds and the number of bracketed launches since the last read,
+ * and resets both. */
+int gx_profile_enable(gx_rt* rt, int on);
+int gx_profile_read(gx_rt* rt, double* vm_ms, uint64_t* vm_launches);
+
 #ifdef __cplusplus
 }
 #endif

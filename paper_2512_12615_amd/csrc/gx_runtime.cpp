@@ -78,9 +78,24 @@ struct gx_rt {
   bool ws_used = false;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
+  // measurement: event pairs bracketing VM kernels
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_free;
 };
 
 namespace {
+
+std::pair<hipEvent_t, hipEvent_t> prof_pair(gx_rt* rt) {
+  if (!rt->prof_free.empty()) {
+    auto p = rt->prof_free.back();
+    rt->prof_free.pop_back();
+    return p;
+  }
+  std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+  (void)hipEventCreate(&p.first);
+  (void)hipEventCreate(&p.second);
+  return p;
+}
 
 int to_errno(hipError_t e) { return e == hipErrorOutOfMemory ? -ENOMEM : -EIO; }
 
@@ -307,6 +322,11 @@ void gx_close(gx_rt* rt) {
     if (p.d_guards) (void)hipFree(p.d_guards);
   }
   for (auto& se : rt->stream_events) (void)hipEventDestroy(se.second);
+  for (auto* v : {&rt->prof_pending, &rt->prof_free})
+    for (auto& pe : *v) {
+      (void)hipEventDestroy(pe.first);
+      (void)hipEventDestroy(pe.second);
+    }
   if (rt->ws_event) (void)hipEventDestroy(rt->ws_event);
   for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_err, (void*)rt->d_stage})
     if (p) (void)hipFree(p);
@@ -575,9 +595,13 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
   hipError_t e;
+  std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
+  if (rt->profile) pe = prof_pair(rt);
   if (p->v.event_parallel) {
     A.step_limit = per_event;
+    if (pe.first) (void)hipEventRecord(pe.first, s);
     e = launch_event_parallel(A, s);
+    if (pe.second) (void)hipEventRecord(pe.second, s);
     rt->stats.launches += 1;
   } else {
     uint32_t lbits = (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
@@ -595,12 +619,15 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
       A.qstart = rt->d_counts;
       A.n_queues = L;
       uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
+      if (pe.first) (void)hipEventRecord(pe.first, s);
       e = launch_stream_seq(A, lanes, nt, s);
+      if (pe.second) (void)hipEventRecord(pe.second, s);
     }
     (void)hipEventRecord(rt->ws_event, s);
     rt->ws_used = true;
     rt->stats.launches += 6;
   }
+  if (pe.first) rt->prof_pending.push_back(pe);
   if (e != hipSuccess) return to_errno(e);
   rt->stats.events += n_events;
   note_stream(rt, s);
@@ -659,6 +686,31 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   rt->stats.bytes_drained += pos;
   if (n_records) *n_records = nrec;
   return (int64_t)pos;
+}
+
+int gx_profile_enable(gx_rt* rt, int on) {
+  if (!rt) return -EINVAL;
+  rt->profile = on != 0;
+  return 0;
+}
+
+int gx_profile_read(gx_rt* rt, double* vm_ms, uint64_t* vm_launches) {
+  if (!rt) return -EINVAL;
+  DevGuard g(rt->dev);
+  double total = 0;
+  uint64_t n = 0;
+  for (auto& pe : rt->prof_pending) {
+    float ms = 0;
+    if (hipEventSynchronize(pe.second) != hipSuccess || hipEventElapsedTime(&ms, pe.first, pe.second) != hipSuccess)
+      return -EIO;
+    total += ms;
+    n++;
+    rt->prof_free.push_back(pe);
+  }
+  rt->prof_pending.clear();
+  if (vm_ms) *vm_ms = total;
+  if (vm_launches) *vm_launches = n;
+  return 0;
 }
 
 int gx_stats_get(gx_rt* rt, gx_stats* out) {

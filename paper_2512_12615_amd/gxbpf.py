@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get"]
+           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read"]
 
 _lib = None
 
@@ -82,6 +82,8 @@ def lib():
     L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.gx_drain_ringbuf.restype = i64
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
+    L.gx_profile_enable.argtypes = [vp, C.c_int]
+    L.gx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64)]
     _lib = L
     return L
 
@@ -237,6 +239,15 @@ class Runtime:
         nb = _check(lib().gx_drain_ringbuf(self._h, fd, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
                     "gx_drain_ringbuf")
         return buf[:nb].tobytes(), n.value
+
+    def profile_enable(self, on=True):
+        _check(lib().gx_profile_enable(self._h, int(on)), "gx_profile_enable")
+
+    def profile_read(self):
+        """(summed VM-kernel milliseconds, bracketed launches) since the last read."""
+        ms, n = C.c_double(0), C.c_uint64(0)
+        _check(lib().gx_profile_read(self._h, C.byref(ms), C.byref(n)), "gx_profile_read")
+        return ms.value, n.value
 
     def stats(self) -> dict:
         s = Stats()
