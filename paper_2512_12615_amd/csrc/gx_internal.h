@@ -92,6 +92,8 @@ struct RunArgs {
   const uint32_t* qstart;  // n_queues + 1 entries
   uint32_t n_queues;
   uint32_t checked;        // 1: bounds-check map-value accesses against guards
+  uint32_t epoch;          // launch counter (tombstones of this launch stay unclaimed)
+  uint32_t pad2;
   uint64_t* err;           // device error counter
   const uint64_t* guards;  // per slot {lo, hi} of the map data a map-value access may touch
 };

@@ -24,7 +24,7 @@ hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride,
 hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
                             uint32_t* sums, uint32_t* order, hipStream_t s);
 hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
-                         int64_t* ret, uint8_t* val_out, hipStream_t s);
+                         int64_t* ret, uint8_t* val_out, uint32_t epoch, hipStream_t s);
 }  // namespace gx
 
 using namespace gx;
@@ -78,6 +78,7 @@ struct gx_rt {
   bool ws_used = false;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
+  uint32_t epoch = 0;  // launch counter for hash tombstone reuse
   // measurement: event pairs bracketing VM kernels
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_free;
@@ -403,7 +404,7 @@ static int map_op(gx_rt* rt, int fd, int op, const void* key, const void* val, u
   int64_t ret = -EIO;
   bool ok = hipMemcpyAsync(dk, key, ks, hipMemcpyHostToDevice, rt->internal) == hipSuccess &&
             (op != 1 || hipMemcpyAsync(dv, val, vs, hipMemcpyHostToDevice, rt->internal) == hipSuccess) &&
-            launch_map_op(m->d_desc, op, dk, dv, flags, dret, dout, rt->internal) == hipSuccess &&
+            launch_map_op(m->d_desc, op, dk, dv, flags, dret, dout, ++rt->epoch, rt->internal) == hipSuccess &&
             hipMemcpyAsync(&ret, dret, 8, hipMemcpyDeviceToHost, rt->internal) == hipSuccess &&
             hipStreamSynchronize(rt->internal) == hipSuccess;
   if (!ok) return -EIO;
@@ -593,6 +594,7 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   A.err = rt->d_err;
   A.guards = p->d_guards;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
+  A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
   hipError_t e;
   std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};

@@ -45,10 +45,6 @@ template <typename T>
 __device__ __forceinline__ T ld_relaxed(T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-__device__ __forceinline__ void st_release(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ---------------------------------------------------------------------------
 // stack frames in LDS: frame byte o of a lane lives at
@@ -130,7 +126,19 @@ __device__ __forceinline__ uint64_t key_hash(const MapDev* m, int kind, uint64_t
   return hash_final(h);
 }
 
-__device__ __forceinline__ bool key_eq(const MapDev* m, const uint8_t* hdr, int kind, uint64_t kp, const Stk& stk) {
+// Hash slots.  The header word {u8 state, u24 epoch, u32 tag} and the key
+// words are shared between lanes of every XCD, so they are only read and
+// written with device-coherent relaxed atomics (no fences: on a multi-XCD
+// device a release/acquire fence writes back / invalidates the whole L2).
+// Values are written by the one lane that owns the key, with plain accesses.
+// A slot freed in this launch (tombstone with the current epoch) is not
+// reclaimed until a later launch, so no two lanes of one launch ever write
+// the same slot's bytes.
+__device__ __forceinline__ uint64_t hdr_word(uint32_t state, uint32_t epoch, uint32_t tag) {
+  return (uint64_t)state | ((uint64_t)(epoch & 0xffffffu) << 8) | ((uint64_t)tag << 32);
+}
+
+__device__ __forceinline__ bool key_eq(const MapDev* m, uint8_t* hdr, int kind, uint64_t kp, const Stk& stk) {
   uint32_t nw = (m->key_size + 7) / 8;
   for (uint32_t w = 0; w < nw; w++)
     if (ld_relaxed((uint64_t*)(hdr + 8 + 8 * w)) != chunk(kind, kp, w, m->key_size, stk)) return false;
@@ -138,9 +146,9 @@ __device__ __forceinline__ bool key_eq(const MapDev* m, const uint8_t* hdr, int 
 }
 
 // Probe for a key.  Returns the slot index or -1; *free_slot receives the
-// first tombstone or the terminating empty slot (or -1).
+// first slot this launch may claim (or -1).
 __device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, const Stk& stk,
-                             int64_t* free_slot) {
+                             uint32_t epoch, int64_t* free_slot) {
   uint32_t mask = m->slot_mask;
   uint32_t i = (uint32_t)h & mask;
   uint32_t tag = (uint32_t)(h >> 32);
@@ -148,13 +156,13 @@ __device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp,
   for (uint32_t probe = 0; probe <= mask; probe++) {
     uint8_t* hdr = m->slots + (uint64_t)i * m->sstride;
     uint64_t st = ld_relaxed((uint64_t*)hdr);
-    uint32_t state = (uint32_t)st;
+    uint32_t state = (uint32_t)st & 0xff;
     if (state == SLOT_EMPTY) {
       if (fr < 0) fr = i;
       break;
     }
     if (state == SLOT_TOMB) {
-      if (fr < 0) fr = i;
+      if (fr < 0 && ((uint32_t)(st >> 8) & 0xffffffu) != (epoch & 0xffffffu)) fr = i;
     } else if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && key_eq(m, hdr, kind, kp, stk)) {
       if (free_slot) *free_slot = fr;
       return i;
@@ -165,18 +173,18 @@ __device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp,
   return -1;
 }
 
-__device__ uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+__device__ uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
   uint64_t h = key_hash(m, kind, kp, stk);
-  int64_t s = hash_find(m, h, kind, kp, stk, nullptr);
+  int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
   return s < 0 ? 0 : (uint64_t)(m->data + (uint64_t)s * m->vstride);
 }
 
 __device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp,
-                               uint64_t flags, const Stk& stk) {
+                               uint64_t flags, const Stk& stk, uint32_t epoch) {
   if (flags > 2) return -E_INVAL;
   uint64_t h = key_hash(m, kkind, kp, stk);
   int64_t fr;
-  int64_t s = hash_find(m, h, kkind, kp, stk, &fr);
+  int64_t s = hash_find(m, h, kkind, kp, stk, epoch, &fr);
   if (s >= 0) {
     if (flags == 1) return -E_EXIST;
     copy_in(m->data + (uint64_t)s * m->vstride, vkind, vp, m->value_size, stk);
@@ -190,36 +198,41 @@ __device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkin
     return -E_2BIG;
   }
   uint32_t mask = m->slot_mask;
+  uint32_t tag = (uint32_t)(h >> 32);
   uint32_t i = fr >= 0 ? (uint32_t)fr : ((uint32_t)h & mask);
   for (uint32_t probe = 0; probe <= mask; probe++) {
-    uint32_t* st = (uint32_t*)(m->slots + (uint64_t)i * m->sstride);
-    uint32_t cur = ld_relaxed(st);
-    if (cur == SLOT_EMPTY || cur == SLOT_TOMB) {
-      uint32_t exp = cur;
-      if (__hip_atomic_compare_exchange_strong(st, &exp, (uint32_t)SLOT_BUSY, __ATOMIC_ACQUIRE,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        uint8_t* hdr = (uint8_t*)st;
-        uint32_t nw = (m->key_size + 7) / 8;
-        ((uint32_t*)hdr)[1] = (uint32_t)(h >> 32);
-        for (uint32_t w = 0; w < nw; w++) ((uint64_t*)(hdr + 8))[w] = chunk(kkind, kp, w, m->key_size, stk);
-        copy_in(m->data + (uint64_t)i * m->vstride, vkind, vp, m->value_size, stk);
-        __threadfence();
-        st_release(st, (uint32_t)SLOT_LIVE);
-        return 0;
-      }
+    uint64_t* hw = (uint64_t*)(m->slots + (uint64_t)i * m->sstride);
+    uint64_t cur = ld_relaxed(hw);
+    uint32_t state = (uint32_t)cur & 0xff;
+    bool claimable = state == SLOT_EMPTY ||
+                     (state == SLOT_TOMB && ((uint32_t)(cur >> 8) & 0xffffffu) != (epoch & 0xffffffu));
+    if (claimable &&
+        __hip_atomic_compare_exchange_strong(hw, &cur, hdr_word(SLOT_BUSY, epoch, tag), __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      uint32_t nw = (m->key_size + 7) / 8;
+      for (uint32_t w = 0; w < nw; w++)
+        __hip_atomic_store(hw + 1 + w, chunk(kkind, kp, w, m->key_size, stk), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      copy_in(m->data + (uint64_t)i * m->vstride, vkind, vp, m->value_size, stk);
+      // the key words reach the coherence point before the slot turns live
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __hip_atomic_store(hw, hdr_word(SLOT_LIVE, epoch, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0;
     }
     i = (i + 1) & mask;
   }
-  // unreachable while live < slots; undo the reservation
+  // no claimable slot in this launch; undo the reservation
   __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&m->ctrl[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return -E_2BIG;
 }
 
-__device__ int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
+__device__ int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
   uint64_t h = key_hash(m, kind, kp, stk);
-  int64_t s = hash_find(m, h, kind, kp, stk, nullptr);
+  int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
   if (s < 0) return -E_NOENT;
-  st_release((uint32_t*)(m->slots + (uint64_t)s * m->sstride), (uint32_t)SLOT_TOMB);
+  __hip_atomic_store((uint64_t*)(m->slots + (uint64_t)s * m->sstride),
+                     hdr_word(SLOT_TOMB, epoch, (uint32_t)(h >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
@@ -282,9 +295,8 @@ __device__ uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t
     uint32_t nw = (size + 7) / 8;
     for (uint32_t w = 0; w < nw; w++)
       *(uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask)) = chunk(kind, dp, w, size, stk);
-    __threadfence();
-    __hip_atomic_store((uint64_t*)(m->data + (pos & mask)), (uint64_t)size, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    // records are read by the host once the producing launch has completed
+    *(uint64_t*)(m->data + (pos & mask)) = (uint64_t)size;
     res = 0;
   }
   return res;
@@ -361,6 +373,25 @@ __device__ __forceinline__ uint64_t bswap_bits(uint64_t a, uint32_t bits) {
   if (bits == 16) return __builtin_bswap16((uint16_t)a);
   if (bits == 32) return __builtin_bswap32((uint32_t)a);
   return __builtin_bswap64(a);
+}
+
+// Minimum over all 64 lanes (every lane active) with DPP row operations:
+// swap neighbours, swap pairs, mirror halves of 8, mirror rows of 16, then
+// broadcast lane 15 into odd rows and lane 31 into the upper half; lane 63
+// ends with the minimum of the wave.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t x) {
+  uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROW_MASK, 0xf, false);
+  return y < x ? y : x;
+}
+__device__ __forceinline__ uint32_t wave_min_all(uint32_t x) {
+  x = dpp_min<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_min<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_min<0x141, 0xf>(x);  // row_half_mirror
+  x = dpp_min<0x140, 0xf>(x);  // row_mirror
+  x = dpp_min<0x142, 0xa>(x);  // row_bcast:15
+  x = dpp_min<0x143, 0xc>(x);  // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
 // Checked mode: a map-value access must stay inside the map it was verified
@@ -560,7 +591,7 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
       }
       case H_LOOKUP_HASH: {
         const MapDev* m = (const MapDev*)imm;
-        if (act) res = hash_lookup(m, a8 & 1, r[2], stk);
+        if (act) res = hash_lookup(m, a8 & 1, r[2], stk, A.epoch);
         nwd = 0;
         break;
       }
@@ -572,13 +603,13 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
       }
       case H_UPDATE_HASH: {
         const MapDev* m = (const MapDev*)imm;
-        if (act) res = (uint64_t)hash_update(m, a8 & 1, r[2], (a8 >> 1) & 1, r[3], r[4], stk);
+        if (act) res = (uint64_t)hash_update(m, a8 & 1, r[2], (a8 >> 1) & 1, r[3], r[4], stk, A.epoch);
         nwd = 0;
         break;
       }
       case H_DELETE_HASH: {
         const MapDev* m = (const MapDev*)imm;
-        if (act) res = (uint64_t)hash_delete(m, a8 & 1, r[2], stk);
+        if (act) res = (uint64_t)hash_delete(m, a8 & 1, r[2], stk, A.epoch);
         nwd = 0;
         break;
       }
@@ -622,9 +653,27 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
         pc = npc;
       }
     } else {
+      // minimum-pc scheduling.  Lanes not active here wait at pcs above pc,
+      // so when any active lane continues at pc + 1 (or at pc + 2 after an
+      // lddw, whose second slot no lane can wait at) that is the new minimum;
+      // a taken back-edge is below every waiting lane.  Only a forward jump
+      // taken by every active lane, or an exit, needs a reduction.
       if (act) mypc = br == 1 ? (tk ? (uint32_t)aux : pc + 1) : npc;
-      uint32_t cand = alive ? mypc : 0xffffffffu;
-      pc = __builtin_amdgcn_wave_reduce_min_u32(cand, 0);
+      bool known = false;
+      if (br == 1) {
+        uint64_t tm = ballot(act && tk), fm = ballot(act && !tk);
+        if (tm != 0 && (uint32_t)aux <= pc) {
+          pc = (uint32_t)aux;
+          known = true;
+        } else if (fm != 0) {
+          pc = pc + 1;
+          known = true;
+        }
+      } else if (br == 0 && h != H_JA) {
+        pc = npc;
+        known = true;
+      }
+      if (!known) pc = wave_min_all(alive ? mypc : 0xffffffffu);
       if (ballot(alive && mypc != pc) == 0) div = false;
     }
   }
@@ -794,7 +843,7 @@ extern "C" __global__ void __launch_bounds__(256) gx_k_scan_add(uint32_t* data, 
 // ---------------------------------------------------------------------------
 // control-plane map operations (one lane): op 0 lookup, 1 update, 2 delete
 extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val,
-                                       uint64_t flags, int64_t* ret, uint8_t* val_out) {
+                                       uint64_t flags, int64_t* ret, uint8_t* val_out, uint32_t epoch) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Stk stk{0, 0};
   uint64_t kp = (uint64_t)key, vp = (uint64_t)val;
@@ -813,7 +862,7 @@ extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* k
     }
   } else if (m->type == MAP_HASH) {
     if (op == 0) {
-      uint64_t p = hash_lookup(m, PK_MAPVAL, kp, stk);
+      uint64_t p = hash_lookup(m, PK_MAPVAL, kp, stk, epoch);
       if (p) {
         for (uint32_t i = 0; i < m->value_size; i++) val_out[i] = ((const uint8_t*)p)[i];
         r = 0;
@@ -821,9 +870,9 @@ extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* k
         r = -E_NOENT;
       }
     } else if (op == 1) {
-      r = hash_update(m, PK_MAPVAL, kp, PK_MAPVAL, vp, flags, stk);
+      r = hash_update(m, PK_MAPVAL, kp, PK_MAPVAL, vp, flags, stk, epoch);
     } else {
-      r = hash_delete(m, PK_MAPVAL, kp, stk);
+      r = hash_delete(m, PK_MAPVAL, kp, stk, epoch);
     }
   }
   *ret = r;
@@ -872,8 +921,8 @@ hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uin
 }
 
 hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
-                         int64_t* ret, uint8_t* val_out, hipStream_t s) {
-  hipLaunchKernelGGL(gx_k_map_op, dim3(1), dim3(64), 0, s, m, op, key, val, flags, ret, val_out);
+                         int64_t* ret, uint8_t* val_out, uint32_t epoch, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_map_op, dim3(1), dim3(64), 0, s, m, op, key, val, flags, ret, val_out, epoch);
   return hipGetLastError();
 }
 

@@ -203,3 +203,114 @@ def test_stride_prefetch_full_size_sampled_streams(rt):
     # whole-run properties
     assert int(g.rc.max()) <= 8
     assert len(g.maps[0]) <= 1024 * 32
+
+
+DIVERGE = """
+    ldxdw r6, [r1+0]
+    ldxdw r7, [r1+16]
+    mov64 r0, 0
+    mov64 r8, r6
+    and64 r8, 7
+    jeq r8, 0, early          ; 1/8 of the lanes leave at once
+    mov64 r9, 0
+loop:
+    mov64 r2, r6
+    rsh64 r2, 3
+    and64 r2, 15
+    jgt r2, 12, brk            ; data-dependent break out of the counted loop
+    add64 r0, r2
+    jset r6, 0x100, odd
+    add64 r0, 3
+    ja next
+odd:
+    xor64 r0, r7
+next:
+    rsh64 r6, 4
+    add64 r9, 1
+    jlt r9, 6, loop
+brk:
+    jsgt32 r0, 100, big
+    mov64 r0, 1
+    exit
+big:
+    and64 r0, 0xfff
+    exit
+early:
+    mov64 r0, 77
+    exit
+"""
+
+
+@pytest.mark.parametrize("n", [64, 1000, 65536])
+def test_divergence_stress_vs_oracle(rt, n):
+    _log(f"divergence n={n}")
+    pol = W.Policy("diverge", W.HOOK_MEM_ACCESS, DIVERGE, [])
+    ev = W.gen_mem_uniform(n, 31 + n)
+    ev["addr"] = W.splitmix(5, n)
+    g = gpu_run(rt, pol, ev)
+    assert_same(g, oracle_run(pol, ev), "divergence")
+
+
+CHURN = """
+    ldxw r6, [r1+8]           ; stream
+    ldxdw r7, [r1+0]
+    mov64 r8, r6
+    lsh64 r8, 32
+    mov64 r2, r7
+    and64 r2, 3
+    or64 r8, r2               ; key = stream << 32 | (addr & 3)
+    stxdw [r10-8], r8
+    lddw r1, map:h
+    mov64 r2, r10
+    add64 r2, -8
+    call map_lookup_elem
+    jeq r0, 0, insert
+    ldxdw r1, [r0+0]
+    add64 r1, r7
+    stxdw [r0+0], r1
+    jset r7, 0x30, keep
+    lddw r1, map:h            ; delete on a data-dependent quarter of the hits
+    mov64 r2, r10
+    add64 r2, -8
+    call map_delete_elem
+    mov64 r0, 2
+    exit
+keep:
+    mov64 r0, 1
+    exit
+insert:
+    stxdw [r10-16], r7
+    lddw r1, map:h
+    mov64 r2, r10
+    add64 r2, -8
+    mov64 r3, r10
+    add64 r3, -16
+    mov64 r4, 1
+    call map_update_elem
+    exit
+"""
+
+
+def test_hash_churn_across_launches(rt):
+    """Inserts, updates and deletes on per-stream keys over several launches:
+    tombstones of a launch are reclaimed only by later launches."""
+    import torch
+    from gpu_runner import collect, setup, to_device
+    pol = W.Policy("churn", W.HOOK_MEM_ACCESS, CHURN, [W.MapSpec("h", W.MAP_HASH, 8, 8, 512, 0)])
+    fds, prog = setup(rt, pol)
+    from oracle import oracle as O
+    o = O.Oracle()
+    o.create_map(W.MAP_HASH, 8, 8, 512, 0)
+    for b in range(4):
+        ev = W.gen_mem_uniform(20000, 90 + b, streams=128)
+        rc = torch.zeros(len(ev), dtype=torch.int32, device="cuda")
+        rt.run_batch(prog, to_device(ev), n_events=len(ev), record_size=24, rc=rc)
+        torch.cuda.synchronize()
+        orc = o.run(pol.code, pol.hook, ev)
+        assert np.array_equal(rc.cpu().numpy().view(np.uint32), orc), f"launch {b}"
+        g = collect(rt, pol, fds, None)
+        k, v = o.dump(0)
+        from runners import normalise_hash
+        assert g.maps[0] == normalise_hash(k, v), f"launch {b}"
+    st = rt.stats()
+    assert st["hash_e2big"] == 0 and st["vm_errors"] == 0
