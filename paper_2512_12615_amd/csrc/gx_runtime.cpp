@@ -450,7 +450,7 @@ int64_t gx_map_dump(gx_rt* rt, int map_fd, void* keys, void* vals, uint64_t cap)
     const uint8_t* hdr = slots.data() + i * d.sstride;
     uint32_t st;
     std::memcpy(&st, hdr, 4);
-    if (st != SLOT_LIVE) continue;
+    if ((st & 0xff) != SLOT_LIVE) continue;  // header: {u8 state, u24 epoch, u32 tag}
     if (n < cap) {
       if (keys) std::memcpy((uint8_t*)keys + n * d.key_size, hdr + 8, d.key_size);
       if (vals) std::memcpy((uint8_t*)vals + n * d.value_size, data.data() + i * d.vstride, d.value_size);
