@@ -98,6 +98,25 @@ struct RunArgs {
   const uint64_t* guards;  // per slot {lo, hi} of the map data a map-value access may touch
 };
 
+// Batched form: one entry per run in a persistent launch.
+struct BatchDev {
+  RunArgs A;
+  uint32_t mode;       // 0 event-parallel, 1 stream-sequential
+  uint32_t lanes;
+  uint32_t qstride;
+  uint32_t qend_last;  // position after the run's last queue in order[]
+};
+
+// Stable-partition job of one stream-sequential run.
+struct PartJob {
+  const uint8_t* events;
+  uint64_t n_events;
+  uint32_t record_size, stream_off;
+  uint32_t lbits, tile;
+  uint32_t nt, pad;
+  uint64_t cbase;  // offset of this run's counts matrix (L x nt, queue-major)
+};
+
 }  // namespace gx
 
 namespace gx {

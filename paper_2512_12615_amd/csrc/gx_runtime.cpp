@@ -25,6 +25,11 @@ hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uin
                             uint32_t* sums, uint32_t* order, hipStream_t s);
 hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
                          int64_t* ret, uint8_t* val_out, uint32_t epoch, hipStream_t s);
+hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, uint32_t n_tiles, uint32_t max_lbits,
+                                 uint64_t total_counts, uint32_t* counts, uint32_t* sums, uint32_t* order,
+                                 hipStream_t s);
+hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
+                          uint32_t waves, uint32_t stack_max, hipStream_t s);
 }  // namespace gx
 
 using namespace gx;
@@ -76,6 +81,14 @@ struct gx_rt {
   size_t counts_cap = 0, sums_cap = 0, order_cap = 0;
   hipEvent_t ws_event = nullptr;
   bool ws_used = false;
+  // batched form: device tables, their pinned staging copy, the work counter
+  uint8_t* d_tables = nullptr;
+  size_t tables_cap = 0;
+  uint8_t* h_stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_event = nullptr;
+  bool stage_used = false;
+  uint32_t* d_next = nullptr;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
   uint32_t epoch = 0;  // launch counter for hash tombstone reuse
@@ -302,7 +315,9 @@ int gx_open(int hip_device, gx_rt** out) {
   DevGuard g(hip_device);
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
-      hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess || vm_init() != hipSuccess) {
+      hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&rt->stage_event, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc((void**)&rt->d_next, 64) != hipSuccess || vm_init() != hipSuccess) {
     gx_close(rt);
     return -ENOMEM;
   }
@@ -329,6 +344,10 @@ void gx_close(gx_rt* rt) {
       (void)hipEventDestroy(pe.second);
     }
   if (rt->ws_event) (void)hipEventDestroy(rt->ws_event);
+  if (rt->stage_event) (void)hipEventDestroy(rt->stage_event);
+  if (rt->h_stage) (void)hipHostFree(rt->h_stage);
+  if (rt->d_tables) (void)hipFree(rt->d_tables);
+  if (rt->d_next) (void)hipFree(rt->d_next);
   for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_err, (void*)rt->d_stage})
     if (p) (void)hipFree(p);
   if (rt->internal) (void)hipStreamDestroy(rt->internal);
@@ -636,12 +655,193 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint32_t* d_rc) {
+  RunArgs A{};
+  A.uops = p->d_uops;
+  A.events = (const uint8_t*)d_events;
+  A.rc = d_rc;
+  A.n_events = n_events;
+  A.record_size = p->record_size;
+  A.stack_bytes = p->v.stack_bytes;
+  A.stream_off = p->stream_off;
+  A.stream_size = p->stream_size;
+  A.err = rt->d_err;
+  A.guards = p->d_guards;
+  A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
+  A.epoch = ++rt->epoch;
+  uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
+  A.step_limit = p->v.event_parallel ? per_event : per_event * n_events;
+  return A;
+}
+
+bool shares_map(ProgObj* a, ProgObj* b, const std::vector<MapObj>& maps) {
+  for (int x : a->fds)
+    for (int y : b->fds)
+      if (x == y && maps[x].h.type != MAP_RINGBUF) return true;
+  return false;
+}
+
+int ensure_dev(uint8_t** p, size_t* cap, size_t need) {
+  if (*cap >= need) return 0;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t n = std::max<size_t>(need, 1 << 16);
+  if (hipMalloc((void**)p, n) != hipSuccess) return -ENOMEM;
+  *cap = n;
+  return 0;
+}
+
+// One persistent launch (after one combined partition) for runs that share
+// no map, so running them concurrently gives the result of running them in
+// order.
+int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
+  std::vector<BatchDev> B;
+  std::vector<PartJob> J;
+  std::vector<uint2> tiles, items;
+  std::vector<std::pair<uint64_t, uint32_t>> order_by_cost;  // (cost, batch)
+  uint64_t counts_total = 0, order_total = 0;
+  uint32_t stack_max = 0, max_lbits = 0;
+  uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
+  uint32_t qbits = (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
+  for (uint32_t i = 0; i < n; i++) {
+    if (d[i].n_events == 0) continue;
+    ProgObj* p = get_prog(rt, d[i].prog_fd);
+    RunArgs A = make_args(rt, p, d[i].d_events, d[i].n_events, d[i].d_rc);
+    BatchDev bd{};
+    stack_max = std::max(stack_max, p->v.stack_bytes);
+    uint32_t nchunks;
+    if (p->v.event_parallel) {
+      bd.mode = 0;
+      bd.lanes = 64;
+      nchunks = (uint32_t)((d[i].n_events + 63) / 64);
+    } else {
+      uint32_t lbits = qbits;
+      uint32_t L = 1u << lbits;
+      uint64_t tile = std::max<uint64_t>(4096, next_pow2((d[i].n_events + 255) / 256));
+      uint32_t nt = (uint32_t)((d[i].n_events + tile - 1) / tile);
+      PartJob pj{A.events, A.n_events, A.record_size, A.stream_off, lbits, (uint32_t)tile, nt, 0, counts_total};
+      for (uint32_t t = 0; t < nt; t++) tiles.push_back(make_uint2((uint32_t)J.size(), t));
+      J.push_back(pj);
+      max_lbits = std::max(max_lbits, lbits);
+      A.qstart = nullptr;  // patched below once the workspace exists
+      A.n_queues = L;
+      bd.mode = 1;
+      bd.lanes = lanes;
+      bd.qstride = nt;
+      bd.qend_last = (uint32_t)(order_total + d[i].n_events);
+      bd.A.pad2 = 0;
+      // remember where this run's counts start (patched into qstart)
+      A.pad2 = (uint32_t)J.size();  // 1 + job index
+      counts_total += (uint64_t)L * nt;
+      order_total += d[i].n_events;
+      nchunks = (L + lanes - 1) / lanes;
+    }
+    bd.A = A;
+    uint64_t cost = (uint64_t)(p->v.max_insns + 1) * (p->v.event_parallel ? 64 : (d[i].n_events / 64 + 1));
+    order_by_cost.push_back({cost, (uint32_t)B.size()});
+    B.push_back(bd);
+    (void)nchunks;
+  }
+  if (B.empty()) return 0;
+  if (order_total >= (1ull << 32) || counts_total >= (1ull << 32)) return -E2BIG;
+  int r = ensure_ws(rt, counts_total + 1, (counts_total + 4095) / 4096 + 1, order_total + 1);
+  if (r) return r;
+  for (auto& bd : B)
+    if (bd.mode == 1) {
+      const PartJob& pj = J[bd.A.pad2 - 1];
+      bd.A.qstart = rt->d_counts + pj.cbase;
+      bd.A.order = rt->d_order;
+      bd.A.pad2 = 0;
+    }
+  // items, largest runs first
+  std::stable_sort(order_by_cost.begin(), order_by_cost.end(),
+                   [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
+                     return a.first > b.first;
+                   });
+  for (auto& oc : order_by_cost) {
+    const BatchDev& bd = B[oc.second];
+    uint32_t nchunks = bd.mode == 0 ? (uint32_t)((bd.A.n_events + 63) / 64) : (bd.A.n_queues + bd.lanes - 1) / bd.lanes;
+    for (uint32_t c = 0; c < nchunks; c++) items.push_back(make_uint2(oc.second, c));
+  }
+  // pack the tables: batches | items | jobs | tiles (each 64-byte aligned)
+  auto al = [](size_t x) { return (x + 63) & ~(size_t)63; };
+  size_t ob = 0, oi = al(ob + B.size() * sizeof(BatchDev)), oj = al(oi + items.size() * sizeof(uint2)),
+         ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
+  if (rt->stage_used && hipEventSynchronize(rt->stage_event) != hipSuccess) return -EIO;
+  if (rt->stage_cap < total) {
+    if (rt->h_stage) (void)hipHostFree(rt->h_stage);
+    rt->h_stage = nullptr;
+    rt->stage_cap = 0;
+    size_t cap = std::max<size_t>(total, 1 << 16);
+    if (hipHostMalloc((void**)&rt->h_stage, cap, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+    rt->stage_cap = cap;
+  }
+  if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
+  if ((r = ensure_dev(&rt->d_tables, &rt->tables_cap, total))) return r;
+  std::memcpy(rt->h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
+  std::memcpy(rt->h_stage + oi, items.data(), items.size() * sizeof(uint2));
+  if (!J.empty()) std::memcpy(rt->h_stage + oj, J.data(), J.size() * sizeof(PartJob));
+  if (!tiles.empty()) std::memcpy(rt->h_stage + ot, tiles.data(), tiles.size() * sizeof(uint2));
+  if (hipMemcpyAsync(rt->d_tables, rt->h_stage, total, hipMemcpyHostToDevice, s) != hipSuccess) return -EIO;
+  (void)hipEventRecord(rt->stage_event, s);
+  rt->stage_used = true;
+  hipError_t e = hipSuccess;
+  if (!J.empty())
+    e = launch_partition_jobs((const PartJob*)(rt->d_tables + oj), (const uint2*)(rt->d_tables + ot),
+                              (uint32_t)tiles.size(), max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order, s);
+  std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
+  if (rt->profile) pe = prof_pair(rt);
+  if (e == hipSuccess) {
+    uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
+    uint32_t waves = (uint32_t)std::min<size_t>(items.size(), 256 * per_cu);
+    if (pe.first) (void)hipEventRecord(pe.first, s);
+    e = launch_batched((const BatchDev*)(rt->d_tables + ob), (const uint2*)(rt->d_tables + oi), (uint32_t)items.size(),
+                       rt->d_next, waves, stack_max, s);
+    if (pe.second) (void)hipEventRecord(pe.second, s);
+  }
+  if (pe.first) rt->prof_pending.push_back(pe);
+  (void)hipEventRecord(rt->ws_event, s);
+  rt->ws_used = true;
+  if (e != hipSuccess) return to_errno(e);
+  rt->stats.launches += J.empty() ? 2 : 7;
+  for (auto& bd : B) rt->stats.events += bd.A.n_events;
+  note_stream(rt, s);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
   if (!rt || (!descs && n)) return -EINVAL;
   for (uint32_t i = 0; i < n; i++) {
-    int r = gx_run_batch(rt, descs[i].prog_fd, descs[i].d_events, descs[i].n_events, descs[i].record_size,
-                         descs[i].d_rc, stream);
+    ProgObj* p = get_prog(rt, descs[i].prog_fd);
+    if (!p || descs[i].record_size != p->record_size || (descs[i].n_events && !descs[i].d_events)) return -EINVAL;
+    if (descs[i].n_events >= (1ull << 32)) return -E2BIG;
+  }
+  DevGuard g(rt->dev);
+  hipStream_t s = (hipStream_t)stream;
+  // split into phases of runs that share no map (their order then cannot
+  // matter); phases run one after another on the stream
+  uint32_t a = 0;
+  while (a < n) {
+    uint32_t b = a + 1;
+    while (b < n) {
+      bool clash = false;
+      for (uint32_t k = a; k < b && !clash; k++)
+        clash = shares_map(get_prog(rt, descs[k].prog_fd), get_prog(rt, descs[b].prog_fd), rt->maps);
+      if (clash) break;
+      b++;
+    }
+    int r = run_phase(rt, descs + a, b - a, s);
     if (r) return r;
+    a = b;
   }
   return 0;
 }

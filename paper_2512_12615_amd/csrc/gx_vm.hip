@@ -689,34 +689,30 @@ __device__ __forceinline__ Ctx load_record(const RunArgs& A, uint64_t i) {
   return c;
 }
 
-// Event-parallel mode: lane = event.
-extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A) {
-  const uint32_t wave = threadIdx.x >> 6;
-  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u};
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave-tile of an event-parallel run: lane l runs event first + l.
+__device__ __forceinline__ void event_tile(const RunArgs& A, uint64_t first, const Stk& stk, uint64_t& steps) {
+  const uint64_t i = first + lane_id();
   const bool live = i < A.n_events;
   Ctx c{0, 0, 0};
   if (live) c = load_record(A, i);
-  uint64_t steps = 0;
   uint32_t rc = vm_run(A, live, c.c0, c.c1, c.c2, stk, steps);
   if (live && A.rc) A.rc[i] = rc;
 }
 
-// Stream-sequential mode: each lane owns one queue and runs its events in
-// index order.  ``lanes`` lanes of each wave are used (1..64).
-extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
+// One wave of a stream-sequential run: lane l < lanes owns queue q0 + l and
+// runs that queue's events (order[qstart[q] ..]) in index order.
+__device__ __forceinline__ void stream_wave(const RunArgs& A, uint32_t q0, uint32_t lanes, uint32_t qstride,
+                                            uint32_t qend_last, const Stk& stk, uint64_t& steps) {
   const uint32_t l = lane_id();
-  const uint32_t q = blockIdx.x * lanes + l;
+  const uint32_t q = q0 + l;
   const bool own = l < lanes && q < A.n_queues;
   uint32_t beg = 0, end = 0;
   if (own) {
     beg = A.qstart[(uint64_t)q * qstride];
-    end = q + 1 < A.n_queues ? A.qstart[(uint64_t)(q + 1) * qstride] : (uint32_t)A.n_events;
+    end = q + 1 < A.n_queues ? A.qstart[(uint64_t)(q + 1) * qstride] : qend_last;
   }
   uint32_t cnt = end - beg;
   uint32_t rounds = __builtin_amdgcn_wave_reduce_max_u32(cnt, 0);
-  Stk stk{0, l * 8u};
-  uint64_t steps = 0;
   for (uint32_t k = 0; k < rounds; k++) {
     bool live = k < cnt;
     uint64_t i = live ? A.order[beg + k] : 0;
@@ -728,41 +724,92 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint
   }
 }
 
+// Event-parallel mode: lane = event.
+extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A) {
+  const uint32_t wave = threadIdx.x >> 6;
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u};
+  uint64_t steps = 0;
+  event_tile(A, (uint64_t)blockIdx.x * blockDim.x + wave * 64u, stk, steps);
+}
+
+// Stream-sequential mode: ``lanes`` lanes of each one-wave block own queues.
+extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
+  Stk stk{0, lane_id() * 8u};
+  uint64_t steps = 0;
+  stream_wave(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: one persistent launch over work items of many runs.  Each
+// item is (run, chunk): a 64-event tile of an event-parallel run, or a group
+// of ``lanes`` queues of a stream-sequential run.  Waves claim items from a
+// counter in the order the host sorted them (largest first).
+
+extern "C" __global__ void __launch_bounds__(64) gx_k_batched(const BatchDev* B, const uint2* items, uint32_t n_items,
+                                                              uint32_t* next) {
+  typedef const __attribute__((address_space(4))) uint64_t cu64;
+  static_assert(sizeof(BatchDev) % 8 == 0, "BatchDev is loaded as 8-byte words");
+  Stk stk{0, lane_id() * 8u};
+  uint64_t steps = 0;
+  for (;;) {
+    uint32_t it = 0;
+    if (lane_id() == 0) it = atomicAdd(next, 1u);
+    it = rdlane(it, 0);
+    if (it >= n_items) break;
+    // tables are read-only for the launch: scalar loads
+    const uint64_t wv = ((const cu64*)items)[it];
+    const uint32_t run = (uint32_t)wv, chunk = (uint32_t)(wv >> 32);
+    uint64_t words[sizeof(BatchDev) / 8];
+    const cu64* src = (const cu64*)(B + run);
+#pragma unroll
+    for (uint32_t k = 0; k < sizeof(BatchDev) / 8; k++) words[k] = src[k];
+    BatchDev bdv;
+    __builtin_memcpy(&bdv, words, sizeof(BatchDev));
+    const BatchDev* bd = &bdv;
+    const RunArgs& A = bdv.A;
+    steps = 0;
+    if (bd->mode == 0)
+      event_tile(A, (uint64_t)chunk * 64u, stk, steps);
+    else
+      stream_wave(A, chunk * bd->lanes, bd->lanes, bd->qstride, bd->qend_last, stk, steps);
+  }
+}
+
+extern "C" __global__ void gx_k_zero(uint32_t* p, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // stable partition of event indices by queue = stream key & (L - 1)
 
-__device__ __forceinline__ uint32_t stream_key(const RunArgs& A, uint64_t i) {
-  const uint8_t* p = A.events + i * A.record_size + A.stream_off;
-  return *(const uint32_t*)p;
+__device__ __forceinline__ uint32_t stream_key_of(const uint8_t* events, uint32_t rs, uint32_t soff, uint64_t i) {
+  return *(const uint32_t*)(events + i * rs + soff);
 }
 
-// counts[q * nt + t] = events of tile t in queue q.  One wave per tile.
-extern "C" __global__ void __launch_bounds__(64) gx_k_part_count(RunArgs A, uint32_t* counts, uint32_t lbits,
-                                                                 uint32_t tile, uint32_t nt) {
+__device__ __forceinline__ void part_count(const PartJob& J, uint32_t t, uint32_t* counts) {
   uint32_t* cnt = (uint32_t*)g_lds;
-  const uint32_t L = 1u << lbits, t = blockIdx.x, l = lane_id();
+  const uint32_t L = 1u << J.lbits, l = lane_id();
   for (uint32_t q = l; q < L; q += 64) cnt[q] = 0;
   __syncthreads();
-  uint64_t b = (uint64_t)t * tile, e = b + tile < A.n_events ? b + tile : A.n_events;
-  for (uint64_t i = b + l; i < e; i += 64) atomicAdd(&cnt[stream_key(A, i) & (L - 1)], 1u);
+  uint64_t b = (uint64_t)t * J.tile, e = b + J.tile < J.n_events ? b + J.tile : J.n_events;
+  for (uint64_t i = b + l; i < e; i += 64)
+    atomicAdd(&cnt[stream_key_of(J.events, J.record_size, J.stream_off, i) & (L - 1)], 1u);
   __syncthreads();
-  for (uint32_t q = l; q < L; q += 64) counts[(uint64_t)q * nt + t] = cnt[q];
+  for (uint32_t q = l; q < L; q += 64) counts[J.cbase + (uint64_t)q * J.nt + t] = cnt[q];
 }
 
-// order[offs[q * nt + t] + rank] = i, ranks in index order within the tile.
-extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter(RunArgs A, const uint32_t* offs, uint32_t* order,
-                                                                   uint32_t lbits, uint32_t tile, uint32_t nt) {
+__device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const uint32_t* offs, uint32_t* order) {
   uint32_t* base = (uint32_t*)g_lds;
-  const uint32_t L = 1u << lbits, t = blockIdx.x, l = lane_id();
-  for (uint32_t q = l; q < L; q += 64) base[q] = offs[(uint64_t)q * nt + t];
+  const uint32_t L = 1u << J.lbits, l = lane_id();
+  for (uint32_t q = l; q < L; q += 64) base[q] = offs[J.cbase + (uint64_t)q * J.nt + t];
   __syncthreads();
-  uint64_t b = (uint64_t)t * tile, e = b + tile < A.n_events ? b + tile : A.n_events;
+  uint64_t b = (uint64_t)t * J.tile, e = b + J.tile < J.n_events ? b + J.tile : J.n_events;
   for (uint64_t c = b; c < e; c += 64) {
     uint64_t i = c + l;
     bool v = i < e;
-    uint32_t key = v ? (stream_key(A, i) & (L - 1)) : 0;
+    uint32_t key = v ? (stream_key_of(J.events, J.record_size, J.stream_off, i) & (L - 1)) : 0;
     uint64_t peers = ballot(v);
-    for (uint32_t bit = 0; bit < lbits; bit++) {
+    for (uint32_t bit = 0; bit < J.lbits; bit++) {
       uint64_t m = ballot(v && ((key >> bit) & 1));
       peers &= ((key >> bit) & 1) ? m : ~m;
     }
@@ -776,6 +823,30 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter(RunArgs A, co
       if (rank == 0) base[key] = pos + popc64(peers);
     }
   }
+}
+
+// One wave per tile; ``tiles`` maps block -> (job, tile) for batched runs.
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_count(const PartJob* jobs, const uint2* tiles,
+                                                                 uint32_t* counts) {
+  const uint2 jt = tiles[blockIdx.x];
+  const PartJob J = jobs[jt.x];
+  part_count(J, jt.y, counts);
+}
+
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter(const PartJob* jobs, const uint2* tiles,
+                                                                   const uint32_t* offs, uint32_t* order) {
+  const uint2 jt = tiles[blockIdx.x];
+  const PartJob J = jobs[jt.x];
+  part_scatter(J, jt.y, offs, order);
+}
+
+// Single-run forms take the job by value.
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_count1(PartJob J, uint32_t* counts) {
+  part_count(J, blockIdx.x, counts);
+}
+
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter1(PartJob J, const uint32_t* offs, uint32_t* order) {
+  part_scatter(J, blockIdx.x, offs, order);
 }
 
 // exclusive scan of u32 data[0..n): block sums, then the sums, then add back
@@ -889,7 +960,9 @@ hipError_t vm_init() {
   hipError_t e = hipFuncSetAttribute((const void*)gx_k_event_parallel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      256 * kStackMax);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)gx_k_stream_seq, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
+  e = hipFuncSetAttribute((const void*)gx_k_stream_seq, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)gx_k_batched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
 }
 
 hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s) {
@@ -904,19 +977,49 @@ hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride,
   return hipGetLastError();
 }
 
-// Stable partition of event indices into 2^lbits queues.  counts must hold
-// 2^lbits * nt entries, sums ceil(2^lbits * nt / 4096), order n_events.
+// Exclusive scan of u32 data[0..m) in place (sums: ceil(m / 4096) entries).
+hipError_t launch_scan(uint32_t* data, uint64_t m, uint32_t* sums, hipStream_t s) {
+  uint32_t nb = (uint32_t)((m + kScanBlock - 1) / kScanBlock);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(gx_k_scan_local, dim3(nb), dim3(256), 0, s, data, m, sums);
+  hipLaunchKernelGGL(gx_k_scan_sums, dim3(1), dim3(256), 0, s, sums, nb);
+  hipLaunchKernelGGL(gx_k_scan_add, dim3(nb), dim3(256), 0, s, data, m, (const uint32_t*)sums);
+  return hipGetLastError();
+}
+
+// Stable partition of one run's event indices into 2^lbits queues.  counts
+// must hold 2^lbits * nt entries, sums ceil(2^lbits * nt / 4096), order n.
 hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
                             uint32_t* sums, uint32_t* order, hipStream_t s) {
   uint32_t L = 1u << lbits;
-  hipLaunchKernelGGL(gx_k_part_count, dim3(nt), dim3(64), L * 4, s, A, counts, lbits, tile, nt);
-  uint64_t m = (uint64_t)L * nt;
-  uint32_t nb = (uint32_t)((m + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(gx_k_scan_local, dim3(nb), dim3(256), 0, s, counts, m, sums);
-  hipLaunchKernelGGL(gx_k_scan_sums, dim3(1), dim3(256), 0, s, sums, nb);
-  hipLaunchKernelGGL(gx_k_scan_add, dim3(nb), dim3(256), 0, s, counts, m, (const uint32_t*)sums);
-  hipLaunchKernelGGL(gx_k_part_scatter, dim3(nt), dim3(64), L * 4, s, A, (const uint32_t*)counts, order, lbits,
-                     tile, nt);
+  PartJob J{A.events, A.n_events, A.record_size, A.stream_off, lbits, tile, nt, 0, 0};
+  hipLaunchKernelGGL(gx_k_part_count1, dim3(nt), dim3(64), L * 4, s, J, counts);
+  hipError_t e = launch_scan(counts, (uint64_t)L * nt, sums, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gx_k_part_scatter1, dim3(nt), dim3(64), L * 4, s, J, (const uint32_t*)counts, order);
+  return hipGetLastError();
+}
+
+// Combined partition of several runs: jobs/tiles are device tables; counts
+// of all runs are concatenated, so one scan yields positions in one global
+// order array in which run j's events occupy a contiguous range.
+hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, uint32_t n_tiles, uint32_t max_lbits,
+                                 uint64_t total_counts, uint32_t* counts, uint32_t* sums, uint32_t* order,
+                                 hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  uint32_t L = 1u << max_lbits;
+  hipLaunchKernelGGL(gx_k_part_count, dim3(n_tiles), dim3(64), L * 4, s, d_jobs, d_tiles, counts);
+  hipError_t e = launch_scan(counts, total_counts, sums, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gx_k_part_scatter, dim3(n_tiles), dim3(64), L * 4, s, d_jobs, d_tiles,
+                     (const uint32_t*)counts, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
+                          uint32_t waves, uint32_t stack_max, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_zero, dim3(1), dim3(64), 0, s, d_next, 1u);
+  hipLaunchKernelGGL(gx_k_batched, dim3(waves), dim3(64), 64 * stack_max, s, d_batches, d_items, n_items, d_next);
   return hipGetLastError();
 }
 

@@ -1,0 +1,70 @@
+"""GPU parity of the batched form: many programs over their own event batches
+in one persistent launch must give exactly the results of running them one
+after another (checked against the oracle run in that order)."""
+
+import numpy as np
+import pytest
+
+from gpu_runner import collect, setup, to_device
+from runners import assert_same, oracle_run
+
+from paper_2512_12615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def rt():
+    from paper_2512_12615_amd import gxbpf as G
+    r = G.Runtime(0)
+    yield r
+    r.close()
+
+
+def _mixed_runs(k, seed):
+    progs, sizes = W.batched_workload(k, seed=seed, min_log2=6, max_log2=14)
+    runs = [(p, W.gen_mem_uniform(int(n), 300 + i), None) for i, (p, n) in enumerate(zip(progs, sizes))]
+    # event-parallel policies in the same launch
+    runs.append((W.access_counter_policy(), W.gen_mem_uniform(5000, 1), None))
+    ev = W.gen_timing(3000, 2)
+    runs.append((W.latency_hist_policy(), ev, [(1, b"\0\0\0\0", np.uint64(W.p99_threshold(ev["lat"])).tobytes())]))
+    runs.append((W.stride_prefetch_policy(), W.gen_mem_stride(7000, 3, streams=128), None))
+    return runs
+
+
+@pytest.mark.parametrize("k", [1, 24])
+def test_batched_matches_oracle(rt, k):
+    import torch
+    print(f"batched k={k}", flush=True)
+    runs = _mixed_runs(k, 1003 + k)
+    descs, keep = [], []
+    for pol, ev, init in runs:
+        fds, prog = setup(rt, pol, init)
+        dev = to_device(ev)
+        rc = torch.zeros(max(len(ev), 1), dtype=torch.int32, device="cuda")
+        descs.append((prog, dev, len(ev), pol.record_size, rc))
+        keep.append((pol, ev, init, fds, rc))
+    rt.run_batches(descs)
+    torch.cuda.synchronize()
+    for i, (pol, ev, init, fds, rc) in enumerate(keep):
+        g = collect(rt, pol, fds, rc[:len(ev)].cpu().numpy().view(np.uint32))
+        assert_same(g, oracle_run(pol, ev, init), f"run {i} ({pol.name})")
+    assert rt.stats()["vm_errors"] == 0
+
+
+def test_batched_same_program_twice_runs_in_order(rt):
+    """Two batches of one program share its maps: they form two phases and
+    the second sees the first's updates."""
+    import torch
+    pol = W.stride_prefetch_policy()
+    fds, prog = setup(rt, pol)
+    ev1 = W.gen_mem_stride(6000, 11, streams=64)
+    ev2 = W.gen_mem_stride(6000, 12, streams=64)
+    rc1 = torch.zeros(len(ev1), dtype=torch.int32, device="cuda")
+    rc2 = torch.zeros(len(ev2), dtype=torch.int32, device="cuda")
+    rt.run_batches([(prog, to_device(ev1), len(ev1), 24, rc1), (prog, to_device(ev2), len(ev2), 24, rc2)])
+    torch.cuda.synchronize()
+    both = np.concatenate([ev1, ev2])
+    o = oracle_run(pol, both)
+    g = collect(rt, pol, fds, np.concatenate([rc1.cpu().numpy(), rc2.cpu().numpy()]).view(np.uint32))
+    assert_same(g, o, "two phases")
