@@ -174,6 +174,61 @@ int gx_stats_get(gx_rt* rt, gx_stats* out);
 int gx_profile_enable(gx_rt* rt, int on);
 int gx_profile_read(gx_rt* rt, double* vm_ms, uint64_t* vm_launches);
 
+/* ---------------------------------------------------------------------------
+ * Served form: continuous batching of tenant requests (multi-tenant policy
+ * coordination, paper sections 3 and 6.3).  A request is (tenant, program,
+ * host event batch).  Requests of one tenant run one at a time in submission
+ * order (a tenant's programs own its maps); requests of different tenants
+ * are admitted whenever device memory for their buffers (events + return
+ * codes) fits in the budget, and everything admitted at one moment is run as
+ * one batched launch on one of ``streams`` HIP streams, so newly admitted
+ * work overlaps with work already on the device.  GX_SERVE_PER_REQUEST runs
+ * every request as its own plain launch on one stream, in arrival order (the
+ * baseline the continuous mode is compared with).  The server drives the
+ * runtime from its own host thread: while a server exists, make no other
+ * calls on its runtime except map snapshots after gx_server_drain. */
+typedef struct gx_server gx_server;
+enum {
+  GX_SERVE_CONTINUOUS = 0,
+  GX_SERVE_PER_REQUEST = 1,
+};
+typedef struct gx_server_cfg {
+  uint64_t hbm_budget_bytes; /* device bytes for in-flight request buffers */
+  uint32_t streams;          /* launch streams (>= 1; per-request mode uses 1) */
+  uint32_t mode;             /* GX_SERVE_* */
+  uint32_t max_group;        /* most requests per launch (0: no limit) */
+  uint32_t pad;
+} gx_server_cfg;
+typedef struct gx_completion {
+  uint64_t req_id;
+  int32_t tenant;
+  int32_t status;        /* 0, or -errno of the launch */
+  uint64_t n_events;
+  const uint32_t* rc;    /* n_events return codes, valid until gx_server_release */
+  double t_submit;       /* host monotonic seconds */
+  double t_admit;
+  double t_done;
+  void* priv;
+} gx_completion;
+
+/* Create a server on ``rt``.  -EINVAL for a zero budget; -ENOMEM. */
+int gx_server_create(gx_rt* rt, const gx_server_cfg* cfg, gx_server** out);
+/* Queue a request; the events (n_events records of record_size bytes in host
+ * memory) are copied before the call returns.  -E2BIG if the request alone
+ * exceeds the budget, -EINVAL for a bad program or record size. */
+int gx_server_submit(gx_server* srv, int32_t tenant, int prog_fd, const void* host_events, uint64_t n_events,
+                     uint32_t record_size, uint64_t req_id);
+/* Take up to ``max`` completions, waiting up to wait_ms for the first one.
+ * Returns the number written. */
+int gx_server_poll(gx_server* srv, gx_completion* out, uint32_t max, int wait_ms);
+/* Return a completion's return-code buffer to the server. */
+void gx_server_release(gx_server* srv, gx_completion* c);
+/* Wait until every submitted request has completed (they remain to be
+ * polled). */
+int gx_server_drain(gx_server* srv);
+/* Stop the server thread (after draining) and free its buffers. */
+void gx_server_destroy(gx_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgxbpf.so")
-SOURCES = ["gx_vm.hip", "gx_runtime.cpp", "gx_verifier.cpp"]
+SOURCES = ["gx_vm.hip", "gx_runtime.cpp", "gx_verifier.cpp", "gx_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

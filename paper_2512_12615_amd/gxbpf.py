@@ -43,7 +43,21 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read"]
+           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_release", "gx_server_drain",
+           "gx_server_destroy"]
+SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("streams", C.c_uint32), ("mode", C.c_uint32),
+                ("max_group", C.c_uint32), ("pad", C.c_uint32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("tenant", C.c_int32), ("status", C.c_int32), ("n_events", C.c_uint64),
+                ("rc", C.POINTER(C.c_uint32)), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("priv", C.c_void_p)]
 
 _lib = None
 
@@ -84,6 +98,14 @@ def lib():
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
     L.gx_profile_enable.argtypes = [vp, C.c_int]
     L.gx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64)]
+    L.gx_server_create.argtypes = [vp, C.POINTER(ServerCfg), C.POINTER(vp)]
+    L.gx_server_submit.argtypes = [vp, C.c_int32, C.c_int, vp, u64, u32, u64]
+    L.gx_server_poll.argtypes = [vp, C.POINTER(Completion), u32, C.c_int]
+    L.gx_server_release.argtypes = [vp, C.POINTER(Completion)]
+    L.gx_server_release.restype = None
+    L.gx_server_drain.argtypes = [vp]
+    L.gx_server_destroy.argtypes = [vp]
+    L.gx_server_destroy.restype = None
     _lib = L
     return L
 
@@ -262,3 +284,46 @@ def parse_ring(buf: bytes):
         out.append(bytes(buf[pos + 8:pos + 8 + ln]))
         pos += 8 + ((ln + 7) & ~7)
     return out
+
+
+class Server:
+    """Continuous-batching request loop on a Runtime (see gx_server_* in the header)."""
+
+    def __init__(self, rt: "Runtime", budget_bytes: int, streams: int = 4, mode: int = SERVE_CONTINUOUS,
+                 max_group: int = 0):
+        self.rt = rt
+        cfg = ServerCfg(budget_bytes, streams, mode, max_group, 0)
+        self._h = C.c_void_p()
+        _check(lib().gx_server_create(rt._h, C.byref(cfg), C.byref(self._h)), "gx_server_create")
+
+    def submit(self, tenant, prog_fd, events: np.ndarray, req_id: int):
+        ev = np.ascontiguousarray(events)
+        _check(lib().gx_server_submit(self._h, tenant, prog_fd, ev.ctypes.data_as(C.c_void_p), len(ev),
+                                      ev.dtype.itemsize, req_id), "gx_server_submit")
+
+    def poll(self, max_n=256, wait_ms=0, keep_rc=True):
+        """List of dicts (req_id, tenant, status, rc copy or None, t_submit, t_admit, t_done)."""
+        arr = (Completion * max_n)()
+        n = lib().gx_server_poll(self._h, arr, max_n, wait_ms)
+        out = []
+        for i in range(max(n, 0)):
+            c = arr[i]
+            rc = np.ctypeslib.as_array(c.rc, shape=(c.n_events,)).copy() if keep_rc and c.rc else None
+            out.append({"req_id": c.req_id, "tenant": c.tenant, "status": c.status, "n_events": c.n_events,
+                        "rc": rc, "t_submit": c.t_submit, "t_admit": c.t_admit, "t_done": c.t_done})
+            lib().gx_server_release(self._h, C.byref(c))
+        return out
+
+    def drain(self):
+        _check(lib().gx_server_drain(self._h), "gx_server_drain")
+
+    def close(self):
+        if self._h:
+            lib().gx_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
