@@ -60,6 +60,200 @@ def cpu_baseline(pol, ev, streams_in_sample):
     }
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None):
+    """Back-to-back plain launches of an event-parallel policy over rotated
+    resident batches; events/s from the wall clock, HBM fraction from the VM
+    kernel's own time (record + rc + ring bytes per event)."""
+    import torch
+    fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+    prog = rt.load_program(pol.code, pol.hook, fds)
+    n = batches[0].numel() // pol.record_size
+    rc = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ring = [0]
+
+    def step(k):
+        b = k % len(batches)
+        if init_per_batch is not None:
+            for mi, key, val in init_per_batch[b]:
+                rt.map_update(fds[mi], key, val)
+        rt.run_batch(prog, batches[b], n_events=n, record_size=pol.record_size, rc=rc, stream=stream)
+        if ring_fd is not None:
+            buf, _ = rt.drain_ringbuf(fds[ring_fd])
+            ring[0] += len(buf)
+
+    for k in range(2):
+        step(k)
+    torch.cuda.synchronize()
+    rt.profile_read()
+    rt.profile_enable(True)
+    ring[0] = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    vm_ms, launches = rt.profile_read()
+    rt.profile_enable(False)
+    vm_s = vm_ms / 1000 / max(launches, 1)
+    alg = n * (pol.record_size + 4) + ring[0] / steps
+    return {
+        "workload": name,
+        "events_per_batch": n,
+        "events_per_s": n * steps / wall,
+        "vm_kernel_us": vm_s * 1e6,
+        "vm_events_per_s": n / vm_s,
+        "alg_bytes_per_launch": alg,
+        "hbm_frac": alg / vm_s / 1e9 / HBM_PEAK_GBS,
+    }
+
+
+def bench_memory_bound(G, W, rt, steps):
+    """The two event-parallel policies: access counter (2^20 records, 48
+    rotated batches = 1.1 GiB) and latency histogram (2^26 records, 2 rotated
+    batches = 2 GiB, ring drained every launch)."""
+    import numpy as np
+    import torch
+    out = {}
+    acc = [torch.from_numpy(W.gen_mem_uniform(1 << 20, 1000 + k).view(np.uint8)).cuda() for k in range(48)]
+    out["access_counter"] = bench_event_parallel(
+        G, W, rt, "access counter, 2^20 x 24 B records, ARRAY 4096 x u64 shared", W.access_counter_policy(), acc,
+        steps * 20)
+    del acc
+    hosts = [W.gen_timing(1 << 26, 1002 + k) for k in range(2)]
+    init = [[(1, b"\0\0\0\0", np.uint64(W.p99_threshold(h["lat"])).tobytes())] for h in hosts]
+    lat = [torch.from_numpy(h.view(np.uint8)).cuda() for h in hosts]
+    del hosts
+    out["latency_hist"] = bench_event_parallel(
+        G, W, rt, "latency histogram + p99 tail records, 2^26 x 16 B records, ARRAY 4096 x 64 x u64 shared, "
+        "64 MiB ring", W.latency_hist_policy(), lat, steps, init_per_batch=init, ring_fd=2)
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(G, W, rt, reps):
+    """256 generated programs over their own batches (2^10..2^20 events):
+    one batched launch against 256 plain launches in order, same outputs."""
+    import numpy as np
+    import torch
+    progs, sizes = W.batched_workload(256)
+    stream = torch.cuda.current_stream()
+    runs = []
+    for i, (pol, n) in enumerate(zip(progs, sizes)):
+        fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+        prog = rt.load_program(pol.code, pol.hook, fds)
+        ev = torch.from_numpy(W.gen_mem_uniform(int(n), W.subseed(1003, 1000 + i)).view(np.uint8)).cuda()
+        runs.append((prog, fds, ev, int(n), torch.zeros(int(n), dtype=torch.int32, device="cuda")))
+    total = int(sizes.sum())
+
+    def reset():
+        for _, fds, _, _, _ in runs:
+            for fd in fds:
+                rt.map_clear(fd)
+        torch.cuda.synchronize()
+
+    def plain():
+        for prog, _, ev, n, rc in runs:
+            rt.run_batch(prog, ev, n_events=n, record_size=24, rc=rc, stream=stream)
+
+    def batched():
+        rt.run_batches([(prog, ev, n, 24, rc) for prog, _, ev, n, rc in runs], stream=stream)
+
+    res = {}
+    rcs = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        ts = []
+        for r in range(reps + 1):
+            reset()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(time.perf_counter() - t0)
+        res[name] = total / float(np.median(ts))
+        rcs[name] = torch.cat([rc for *_, rc in runs]).clone()
+    same = bool(torch.equal(rcs["plain"], rcs["batched"]))
+    del runs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"256 generated programs (16-512 slots), own batches of 2^10..2^20 records, {total} events",
+        "plain_events_per_s": res["plain"],
+        "batched_events_per_s": res["batched"],
+        "speedup": res["batched"] / res["plain"],
+        "same_rc": same,
+    }
+
+
+def bench_serving(G, W, rt, seconds, warm_s=0.2):
+    """Open-loop Poisson trace (20k requests/s, 64 tenants, 32 programs,
+    2^8..2^18 events per request, 256 MiB of hash map per tenant = 16 GiB
+    resident) through the continuous server and the per-request baseline.
+    Latency = completion time - the request's scheduled arrival."""
+    import threading
+
+    import numpy as np
+    import torch
+    progs = [W.gen_program(W.subseed(1004, 100 + p)) for p in range(32)]
+    tenants = []
+    for t in range(64):
+        pol = progs[t % 32]
+        fds = []
+        for m in pol.maps:
+            ents = (1 << 22) if m.type == W.MAP_HASH else m.max_entries
+            fds.append(rt.create_map(m.type, m.key_size, m.value_size, ents, m.flags))
+        tenants.append((fds, rt.load_program(pol.code, pol.hook, fds)))
+    n_req = int(20000 * (seconds + warm_s))
+    arrival, tenant, _, n_ev = W.serving_trace(n_req)
+    slices = 64
+    pool = torch.from_numpy(W.gen_mem_uniform(slices << 18, 1004).view(np.uint8)).pin_memory()
+    base = pool.data_ptr()
+    out = {}
+    for mode, name in ((G.SERVE_CONTINUOUS, "continuous"), (G.SERVE_PER_REQUEST, "per_request")):
+        for fds, _ in tenants:
+            for fd in fds:
+                rt.map_clear(fd)
+        srv = G.Server(rt, budget_bytes=4 << 30, streams=4, mode=mode)
+        done = {}
+
+        def poller():
+            while len(done) < n_req:
+                for c in srv.poll(1024, wait_ms=50, keep_rc=False):
+                    done[c["req_id"]] = (c["t_done"], c["status"])
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.monotonic() + 0.01
+        for i in range(n_req):
+            target = t0 + arrival[i]
+            while time.monotonic() < target:
+                pass
+            t = int(tenant[i])
+            srv.submit_borrowed(t, tenants[t][1], base + (i % slices) * (24 << 18), int(n_ev[i]), 24, i)
+        th.join()
+        srv.close()
+        keep = arrival >= warm_s
+        lat = np.array([done[i][0] - (t0 + arrival[i]) for i in range(n_req)])[keep]
+        end = max(done[i][0] for i in range(n_req))
+        ev = float(n_ev[keep].sum())
+        span = end - (t0 + warm_s)
+        out[name] = {
+            "p50_ms": _pct(lat, 50) * 1e3,
+            "p99_ms": _pct(lat, 99) * 1e3,
+            "events_per_s": ev / span,
+            "requests": int(keep.sum()),
+            "errors": int(sum(1 for i in range(n_req) if done[i][1] != 0)),
+        }
+    out["workload"] = (f"{n_req} requests, Poisson 20k/s, 64 tenants x 256 MiB resident hash map, 32 generated "
+                       f"programs, 2^8..2^18 events per request, 4 GiB admission budget, first {warm_s}s excluded")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +263,9 @@ def main():
     ap.add_argument("--batches", type=int, default=2)
     ap.add_argument("--cpu-streams", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the memory-bound policies, the batched and the served forms")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this runtime runs on one GPU; multi-GPU sharding is a design note "
@@ -122,6 +319,19 @@ def main():
     ms_per_step = 1000 * wall / args.steps
     events_per_s = n * args.steps / wall
 
+    forms = None
+    if not args.no_forms:
+        forms = {}
+        for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10)),
+                        ("batched", lambda: bench_batched(G, W, rt, 2)),
+                        ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds))):
+            log(f"form: {key}")
+            try:
+                forms[key] = fn()
+            except Exception as e:  # reported in the line, the main figure stands
+                forms[key] = {"error": repr(e)}
+            log(f"form {key}: {json.dumps(forms[key])}")
+
     cpu = None
     insns_per_event = None
     if not args.no_cpu:
@@ -172,6 +382,7 @@ def main():
         "cpu_baseline": {k: v for k, v in cpu.items() if k in ("value", "unit", "cores", "kind", "sample")}
         if cpu else None,
         "stats": st,
+        "forms": forms,
     }
     print(json.dumps(out))
     rt.close()

@@ -218,6 +218,13 @@ int gx_server_create(gx_rt* rt, const gx_server_cfg* cfg, gx_server** out);
  * exceeds the budget, -EINVAL for a bad program or record size. */
 int gx_server_submit(gx_server* srv, int32_t tenant, int prog_fd, const void* host_events, uint64_t n_events,
                      uint32_t record_size, uint64_t req_id);
+/* As gx_server_submit, without the copy: the server reads ``host_events``
+ * when it admits the request, so the caller keeps that memory valid and
+ * unchanged until the request's completion has been returned by
+ * gx_server_poll.  Pinned memory (hipHostMalloc) makes the transfer
+ * asynchronous; pageable memory works but is staged by the HIP runtime. */
+int gx_server_submit_borrowed(gx_server* srv, int32_t tenant, int prog_fd, const void* host_events,
+                              uint64_t n_events, uint32_t record_size, uint64_t req_id);
 /* Take up to ``max`` completions, waiting up to wait_ms for the first one.
  * Returns the number written. */
 int gx_server_poll(gx_server* srv, gx_completion* out, uint32_t max, int wait_ms);

@@ -83,6 +83,7 @@ struct Req {
   uint32_t rs = 0;
   size_t ev_bytes = 0, dev_len = 0, dev_off = 0, pin_off = 0, pin_len = 0;
   bool pinned = false;
+  const void* borrowed = nullptr;  // caller-owned events (submit_borrowed)
   std::vector<uint8_t> heap;   // events when the pinned pool was full
   std::vector<uint32_t> rc;    // return codes when not pinned
   uint32_t* rc_host = nullptr;
@@ -165,7 +166,8 @@ void launch(gx_server* s, std::vector<Req*>& grp) {
   int status = 0;
   for (Req* r : grp) {
     uint8_t* d_ev = s->d_pool + r->dev_off;
-    const void* src = r->pinned ? (const void*)(s->h_pool + r->pin_off) : (const void*)r->heap.data();
+    const void* src = r->borrowed ? r->borrowed
+                      : r->pinned ? (const void*)(s->h_pool + r->pin_off) : (const void*)r->heap.data();
     if (hipMemcpyAsync(d_ev, src, r->ev_bytes, hipMemcpyHostToDevice, st) != hipSuccess) status = -EIO;
     uint32_t* d_rc = (uint32_t*)(s->d_pool + r->dev_off + ((r->ev_bytes + 255) & ~(size_t)255));
     descs.push_back(gx_batch{r->prog, r->rs, d_ev, r->n, d_rc});
@@ -181,7 +183,9 @@ void launch(gx_server* s, std::vector<Req*>& grp) {
   for (size_t i = 0; i < grp.size(); i++) {
     Req* r = grp[i];
     if (r->pinned) {
-      r->rc_host = (uint32_t*)(s->h_pool + r->pin_off);  // events already consumed: reuse
+      // the pinned range holds the copied events (consumed by now) or, for a
+      // borrowed request, was sized for the return codes alone
+      r->rc_host = (uint32_t*)(s->h_pool + r->pin_off);
       (void)hipMemcpyAsync(r->rc_host, descs[i].d_rc, 4 * r->n, hipMemcpyDeviceToHost, st);
     }
   }
@@ -295,9 +299,11 @@ int gx_server_create(gx_rt* rt, const gx_server_cfg* cfg, gx_server** out) {
   return 0;
 }
 
-int gx_server_submit(gx_server* s, int32_t tenant, int prog_fd, const void* host_events, uint64_t n_events,
-                     uint32_t record_size, uint64_t req_id) {
-  if (!s || (!host_events && n_events) || n_events == 0) return -EINVAL;
+namespace {
+
+int submit(gx_server* s, int32_t tenant, int prog_fd, const void* host_events, uint64_t n_events,
+           uint32_t record_size, uint64_t req_id, bool borrow) {
+  if (!s || !host_events || n_events == 0) return -EINVAL;
   gx_prog_info info;
   if (gx_prog_info_get(s->rt, prog_fd, &info)) return -EINVAL;
   uint32_t want_rs = info.hook == GX_HOOK_MEM_ACCESS ? 24 : 16;
@@ -317,10 +323,12 @@ int gx_server_submit(gx_server* s, int32_t tenant, int prog_fd, const void* host
   }
   {
     std::lock_guard<std::mutex> g(s->pin_mu);
-    r->pin_len = r->ev_bytes;
+    r->pin_len = borrow ? 4 * n_events : r->ev_bytes;
     r->pinned = s->pin_alloc->alloc(r->pin_len, &r->pin_off);
   }
-  if (r->pinned)
+  if (borrow)
+    r->borrowed = host_events;
+  else if (r->pinned)
     std::memcpy(s->h_pool + r->pin_off, host_events, r->ev_bytes);
   else
     r->heap.assign((const uint8_t*)host_events, (const uint8_t*)host_events + r->ev_bytes);
@@ -330,6 +338,18 @@ int gx_server_submit(gx_server* s, int32_t tenant, int prog_fd, const void* host
   s->outstanding++;
   s->cv.notify_one();
   return 0;
+}
+
+}  // namespace
+
+int gx_server_submit(gx_server* s, int32_t tenant, int prog_fd, const void* host_events, uint64_t n_events,
+                     uint32_t record_size, uint64_t req_id) {
+  return submit(s, tenant, prog_fd, host_events, n_events, record_size, req_id, false);
+}
+
+int gx_server_submit_borrowed(gx_server* s, int32_t tenant, int prog_fd, const void* host_events,
+                              uint64_t n_events, uint32_t record_size, uint64_t req_id) {
+  return submit(s, tenant, prog_fd, host_events, n_events, record_size, req_id, true);
 }
 
 int gx_server_poll(gx_server* s, gx_completion* out, uint32_t max, int wait_ms) {

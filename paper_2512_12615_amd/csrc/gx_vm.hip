@@ -713,11 +713,18 @@ __device__ __forceinline__ void stream_wave(const RunArgs& A, uint32_t q0, uint3
   }
   uint32_t cnt = end - beg;
   uint32_t rounds = __builtin_amdgcn_wave_reduce_max_u32(cnt, 0);
+  // the next event's index and record are loaded while this one runs
+  uint64_t ni = cnt > 0 ? A.order[beg] : 0;
+  Ctx nc{0, 0, 0};
+  if (cnt > 0) nc = load_record(A, ni);
   for (uint32_t k = 0; k < rounds; k++) {
-    bool live = k < cnt;
-    uint64_t i = live ? A.order[beg + k] : 0;
-    Ctx c{0, 0, 0};
-    if (live) c = load_record(A, i);
+    const bool live = k < cnt;
+    const uint64_t i = ni;
+    const Ctx c = nc;
+    if (k + 1 < cnt) {
+      ni = A.order[beg + k + 1];
+      nc = load_record(A, ni);
+    }
     uint32_t rc = vm_run(A, live, c.c0, c.c1, c.c2, stk, steps);
     if (live && A.rc) A.rc[i] = rc;
     if (steps > A.step_limit) break;

@@ -44,8 +44,8 @@ class Batch(C.Structure):
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
            "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
-           "gx_server_create", "gx_server_submit", "gx_server_poll", "gx_server_release", "gx_server_drain",
-           "gx_server_destroy"]
+           "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
+           "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
 
 
@@ -100,6 +100,7 @@ def lib():
     L.gx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64)]
     L.gx_server_create.argtypes = [vp, C.POINTER(ServerCfg), C.POINTER(vp)]
     L.gx_server_submit.argtypes = [vp, C.c_int32, C.c_int, vp, u64, u32, u64]
+    L.gx_server_submit_borrowed.argtypes = [vp, C.c_int32, C.c_int, vp, u64, u32, u64]
     L.gx_server_poll.argtypes = [vp, C.POINTER(Completion), u32, C.c_int]
     L.gx_server_release.argtypes = [vp, C.POINTER(Completion)]
     L.gx_server_release.restype = None
@@ -300,6 +301,12 @@ class Server:
         ev = np.ascontiguousarray(events)
         _check(lib().gx_server_submit(self._h, tenant, prog_fd, ev.ctypes.data_as(C.c_void_p), len(ev),
                                       ev.dtype.itemsize, req_id), "gx_server_submit")
+
+    def submit_borrowed(self, tenant, prog_fd, host_ptr: int, n_events: int, record_size: int, req_id: int):
+        """Queue a request whose events stay at ``host_ptr`` (caller-owned,
+        ideally pinned) until its completion has been polled."""
+        _check(lib().gx_server_submit_borrowed(self._h, tenant, prog_fd, C.c_void_p(host_ptr), n_events,
+                                               record_size, req_id), "gx_server_submit_borrowed")
 
     def poll(self, max_n=256, wait_ms=0, keep_rc=True):
         """List of dicts (req_id, tenant, status, rc copy or None, t_submit, t_admit, t_done)."""

@@ -32,17 +32,24 @@ def _tenants(rt, k_tenants, k_programs):
     return ten
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_serve_same_alone_and_in_mix(rt, mode):
+@pytest.mark.parametrize("mode,borrow", [(0, False), (1, False), (0, True)])
+def test_serve_same_alone_and_in_mix(rt, mode, borrow):
+    import torch
     from paper_2512_12615_amd import gxbpf as G
     from oracle import oracle as O
-    print(f"serve mode={mode}", flush=True)
+    print(f"serve mode={mode} borrow={borrow}", flush=True)
     ten = _tenants(rt, 8, 4)
     arrival, tenant, _, n_ev = W.serving_trace(80, seed=77, tenants=8, min_log2=6, max_log2=12)
     reqs = [(i, int(t), W.gen_mem_uniform(int(n), 5000 + i)) for i, (t, n) in enumerate(zip(tenant, n_ev))]
     srv = G.Server(rt, budget_bytes=1 << 22, streams=3, mode=mode)
+    pinned = []
     for i, t, ev in reqs:
-        srv.submit(t, ten[t][2], ev, i)
+        if borrow:
+            h = torch.from_numpy(ev.view(np.uint8)).pin_memory()
+            pinned.append(h)
+            srv.submit_borrowed(t, ten[t][2], h.data_ptr(), len(ev), ev.dtype.itemsize, i)
+        else:
+            srv.submit(t, ten[t][2], ev, i)
     srv.drain()
     done = {}
     while len(done) < len(reqs):
