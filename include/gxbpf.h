@@ -136,6 +136,26 @@ int gx_prog_info_get(gx_rt* rt, int prog_fd, gx_prog_info* out);
 int gx_verify(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
               uint32_t n_maps, char* log, uint32_t log_size, gx_prog_info* info);
 
+/* Compile a loaded program to native gfx950 code (the paper lowers verified
+ * bytecode through LLVM and inlines helpers and map accesses: section 5.1,
+ * section 4.4 "Warp-level Execution Optimizations").  The micro-ops become
+ * HIP source compiled with hipRTC; later gx_run_batch calls of this program
+ * launch the compiled kernels (gx_run_batches keeps interpreting).  Results
+ * are identical to the interpreter's.  Returns 0 (also if already
+ * compiled), -EINVAL for a bad fd, -EIO if compilation or module loading
+ * fails (compiler log in ``log``).  Takes seconds: call it at load time. */
+int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size);
+
+/* The HIP source gx_jit_program would compile for a program (no device
+ * needed; map descriptors get stand-in addresses).  Same program and shape
+ * arguments as gx_verify.  With compile != 0 the source is also compiled
+ * for gfx950.  Writes up to cap - 1 bytes of source (NUL-terminated) to
+ * ``out`` (may be NULL) and returns the full length; -EACCES if the
+ * verifier rejects (reason in out), -EIO if compilation fails (compiler log
+ * in out). */
+int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
+                      uint32_t n_maps, int compile, char* out, uint64_t cap);
+
 /* Run a program over n_events records at d_events (device memory, record
  * size given by the hook) asynchronously on ``stream``; writes the u32 return
  * code of event i to d_rc[i] if d_rc is not NULL.  Maps change in place.

@@ -1,0 +1,269 @@
+// Compilation of verified programs to native gfx950 code.
+//
+// The paper lowers verified bytecode through LLVM to the GPU's own ISA and
+// inlines the helpers and map accesses (section 5.1, section 4.4
+// "Warp-level Execution Optimizations").  Here the pre-decoded micro-ops of
+// a verified program are written out as HIP source, one statement per
+// instruction with a label at every jump target, and compiled at load time
+// with hipRTC for gfx950.  eBPF registers become 64-bit locals, so the
+// compiler keeps them in VGPRs, folds constant stack offsets into LDS
+// addresses and lets the hardware's EXEC mask handle divergent branches;
+// helper calls go straight to the same device helpers the interpreter uses,
+// with each map's descriptor address as a constant.  Verification has
+// already bounded every loop, so the generated code carries no step counter.
+#include "gx_jit.h"
+
+#include <hip/hiprtc.h>
+
+#include <cerrno>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace gx {
+
+namespace {
+
+std::string lit(uint64_t v) {
+  char b[40];
+  std::snprintf(b, sizeof b, "0x%llxull", (unsigned long long)v);
+  return b;
+}
+
+std::string reg(uint32_t i) { return "r" + std::to_string(i); }
+
+const char* kTy[4] = {"uint8_t", "uint16_t", "uint32_t", "uint64_t"};
+const char* kSTy[3] = {"int8_t", "int16_t", "int32_t"};
+
+// value of size code sc, sign-extended when sx
+std::string extend(const std::string& v, int sc, bool sx) {
+  if (!sx || sc == 3) return "(uint64_t)(" + v + ")";
+  return std::string("(uint64_t)(int64_t)(") + kSTy[sc] + ")(" + v + ")";
+}
+
+void emit_uop(std::string& o, const Uop& u, uint32_t pc) {
+  const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, s = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
+  const bool K = (u.w0 >> 24) & 1;
+  const std::string D = reg(d), S = reg(s);
+  const std::string B = K ? lit(u.imm) : S;
+  const std::string xa = "(uint32_t)" + D, xb = "(uint32_t)" + B;
+  const int sc = a8 & 3;
+  const bool sxf = (a8 & 4) != 0;
+  const std::string off = std::to_string(u.aux);
+  const std::string tgt = "goto L" + std::to_string((uint32_t)u.aux) + ";";
+  const std::string M = "(const MapDev*)" + lit(u.imm);
+  auto set = [&](const std::string& e) { o += "  " + D + " = " + e + ";\n"; };
+  auto set32 = [&](const std::string& e) { o += "  " + D + " = (uint64_t)(uint32_t)(" + e + ");\n"; };
+  auto jmp = [&](const std::string& c) { o += "  if (" + c + ") " + tgt + "\n"; };
+  auto guarded = [&](const std::string& addr, uint32_t size, const std::string& body) {
+    o += "  { const uint64_t ad = " + addr + ";\n    if (!A.checked || guard_ok(A, " + std::to_string(pc) + "u, ad, " +
+         std::to_string(size) + "u)) { " + body + " } }\n";
+  };
+  const std::string sgn_a = "(int64_t)" + D, sgn_b = "(int64_t)" + B;
+  const std::string sa32 = "(int32_t)" + xa, sb32 = "(int32_t)" + xb;
+  switch (h) {
+    case H_ADD64: set(D + " + " + B); break;
+    case H_SUB64: set(D + " - " + B); break;
+    case H_MUL64: set(D + " * " + B); break;
+    case H_DIV64: set(B + " ? " + D + " / " + B + " : 0ull"); break;
+    case H_SDIV64:
+      set("!" + B + " ? 0ull : (" + sgn_a + " == INT64_MIN && " + sgn_b + " == -1) ? " + D + " : (uint64_t)(" + sgn_a +
+          " / " + sgn_b + ")");
+      break;
+    case H_OR64: set(D + " | " + B); break;
+    case H_AND64: set(D + " & " + B); break;
+    case H_LSH64: set(D + " << (" + B + " & 63)"); break;
+    case H_RSH64: set(D + " >> (" + B + " & 63)"); break;
+    case H_NEG64: set("0ull - " + D); break;
+    case H_MOD64: set(B + " ? " + D + " % " + B + " : " + D); break;
+    case H_SMOD64:
+      set("!" + B + " ? " + D + " : (" + sgn_b + " == -1) ? 0ull : (uint64_t)(" + sgn_a + " % " + sgn_b + ")");
+      break;
+    case H_XOR64: set(D + " ^ " + B); break;
+    case H_MOV64: set(B); break;
+    case H_ARSH64: set("(uint64_t)(" + sgn_a + " >> (" + B + " & 63))"); break;
+    case H_MOVSX64: set(extend(B, a8 == 8 ? 0 : a8 == 16 ? 1 : 2, true)); break;
+    case H_BSWAP:
+      if (a8 == 16) set("(uint64_t)__builtin_bswap16((uint16_t)" + D + ")");
+      else if (a8 == 32) set("(uint64_t)__builtin_bswap32((uint32_t)" + D + ")");
+      else set("__builtin_bswap64(" + D + ")");
+      break;
+    case H_TRUNC:
+      if (a8 == 16) set(D + " & 0xffffull");
+      else if (a8 == 32) set(D + " & 0xffffffffull");
+      break;
+    case H_ADD32: set32(xa + " + " + xb); break;
+    case H_SUB32: set32(xa + " - " + xb); break;
+    case H_MUL32: set32(xa + " * " + xb); break;
+    case H_DIV32: set32(xb + " ? " + xa + " / " + xb + " : 0u"); break;
+    case H_SDIV32:
+      set32("!" + xb + " ? 0u : (" + sa32 + " == INT32_MIN && " + sb32 + " == -1) ? " + xa + " : (uint32_t)(" +
+            sa32 + " / " + sb32 + ")");
+      break;
+    case H_OR32: set32(xa + " | " + xb); break;
+    case H_AND32: set32(xa + " & " + xb); break;
+    case H_LSH32: set32(xa + " << (" + xb + " & 31)"); break;
+    case H_RSH32: set32(xa + " >> (" + xb + " & 31)"); break;
+    case H_NEG32: set32("0u - " + xa); break;
+    case H_MOD32: set32(xb + " ? " + xa + " % " + xb + " : " + xa); break;
+    case H_SMOD32:
+      set32("!" + xb + " ? " + xa + " : (" + sb32 + " == -1) ? 0u : (uint32_t)(" + sa32 + " % " + sb32 + ")");
+      break;
+    case H_XOR32: set32(xa + " ^ " + xb); break;
+    case H_MOV32: set32(xb); break;
+    case H_ARSH32: set32("(uint32_t)(" + sa32 + " >> (" + xb + " & 31))"); break;
+    case H_MOVSX32: set32(extend(B, a8 == 8 ? 0 : 1, true)); break;
+    case H_JA: o += "  " + tgt + "\n"; break;
+    case H_JEQ: jmp(D + " == " + B); break;
+    case H_JGT: jmp(D + " > " + B); break;
+    case H_JGE: jmp(D + " >= " + B); break;
+    case H_JSET: jmp("(" + D + " & " + B + ") != 0"); break;
+    case H_JNE: jmp(D + " != " + B); break;
+    case H_JSGT: jmp(sgn_a + " > " + sgn_b); break;
+    case H_JSGE: jmp(sgn_a + " >= " + sgn_b); break;
+    case H_JLT: jmp(D + " < " + B); break;
+    case H_JLE: jmp(D + " <= " + B); break;
+    case H_JSLT: jmp(sgn_a + " < " + sgn_b); break;
+    case H_JSLE: jmp(sgn_a + " <= " + sgn_b); break;
+    case H_JEQ32: jmp(xa + " == " + xb); break;
+    case H_JGT32: jmp(xa + " > " + xb); break;
+    case H_JGE32: jmp(xa + " >= " + xb); break;
+    case H_JSET32: jmp("(" + xa + " & " + xb + ") != 0u"); break;
+    case H_JNE32: jmp(xa + " != " + xb); break;
+    case H_JSGT32: jmp(sa32 + " > " + sb32); break;
+    case H_JSGE32: jmp(sa32 + " >= " + sb32); break;
+    case H_JLT32: jmp(xa + " < " + xb); break;
+    case H_JLE32: jmp(xa + " <= " + xb); break;
+    case H_JSLT32: jmp(sa32 + " < " + sb32); break;
+    case H_JSLE32: jmp(sa32 + " <= " + sb32); break;
+    case H_LDX_CTX: {
+      const uint32_t wi = (uint32_t)u.aux >> 3, sh = 8 * ((uint32_t)u.aux & 7);
+      std::string w = "(c" + std::to_string(wi) + " >> " + std::to_string(sh) + ")";
+      set(extend(std::string("(") + kTy[sc] + ")" + w, sc, sxf));
+      break;
+    }
+    case H_LDX_STACK:
+      set(extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf));
+      break;
+    case H_LDX_MAP:
+      guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
+              D + " = " + extend(std::string("*(const ") + kTy[sc] + "*)ad", sc, sxf) + ";");
+      break;
+    case H_ST_STACK:
+    case H_STX_STACK:
+      o += std::string("  *(") + kTy[sc] + "*)saddr(stk, (uint32_t)" + D + " + " + off + ") = (" + kTy[sc] + ")" +
+           (h == H_ST_STACK ? lit(u.imm) : S) + ";\n";
+      break;
+    case H_ST_MAP:
+    case H_STX_MAP:
+      guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
+              std::string("*(") + kTy[sc] + "*)ad = (" + kTy[sc] + ")" + (h == H_ST_MAP ? lit(u.imm) : S) + ";");
+      break;
+    case H_ATOMIC_STACK:
+    case H_ATOMIC_MAP: {
+      const uint32_t op = (uint32_t)u.imm;
+      std::string call = h == H_ATOMIC_STACK
+                             ? "atomic_stack(saddr(stk, (uint32_t)" + D + " + " + off + "), " + S + ", " +
+                                   std::to_string(op) + "u, " + std::to_string(sc) + ", r0)"
+                             : "atomic_global(ad, " + S + ", " + std::to_string(op) + "u, " + std::to_string(sc) +
+                                   ", r0)";
+      std::string wb = op == 0xf1 ? "r0 = t;" : (op & 1) ? S + " = t;" : "(void)t;";
+      if (h == H_ATOMIC_STACK)
+        o += "  { const uint64_t t = " + call + "; " + wb + " }\n";
+      else
+        guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = " + call + "; " + wb);
+      break;
+    }
+    case H_LDIMM: set(lit(u.imm)); break;
+    case H_LOOKUP_ARRAY:
+      o += "  r0 = array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk);\n";
+      break;
+    case H_LOOKUP_HASH:
+      o += "  r0 = hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch);\n";
+      break;
+    case H_UPDATE_ARRAY:
+      o += "  r0 = (uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
+           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk);\n";
+      break;
+    case H_UPDATE_HASH:
+      o += "  r0 = (uint64_t)hash_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
+           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk, A.epoch);\n";
+      break;
+    case H_DELETE_HASH:
+      o += "  r0 = (uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch);\n";
+      break;
+    case H_RET_EINVAL: o += "  r0 = (uint64_t)-22ll;\n"; break;
+    case H_RINGBUF_OUTPUT:
+      o += "  r0 = ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " + std::to_string((uint32_t)u.aux) +
+           "u, r4, true, stk);\n";
+      break;
+    case H_EXIT:
+    default: o += "  return (uint32_t)r0;\n"; break;
+  }
+}
+
+bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
+
+}  // namespace
+
+std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes) {
+  std::vector<char> target(U.size() + 1, 0);
+  for (const Uop& u : U)
+    if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
+  const uint32_t lds = stack_bytes ? 64u * stack_bytes : 16u;
+  std::string o;
+  o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n#include \"gx_dev.h\"\n\nnamespace gx {\n\n";
+  o += "struct Prog {\n  static __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, "
+       "uint64_t c1, uint64_t c2, const Stk stk, uint64_t& steps) {\n";
+  o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
+  o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
+  o += "  uint64_t r10 = " + std::to_string(stack_bytes) + "ull;\n";
+  o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
+  for (uint32_t pc = 0; pc < U.size(); pc++) {
+    if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
+    emit_uop(o, U[pc], pc);
+    if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
+  }
+  o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
+  o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_event_parallel(gx::RunArgs A) {\n"
+       "  gx::Stk stk{0, gx::lane_id() * 8u};\n  uint64_t steps = 0;\n"
+       "  gx::event_tile<gx::Prog>(A, (uint64_t)blockIdx.x * 64u, stk, steps);\n}\n\n";
+  o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
+       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u};\n  uint64_t steps = 0;\n"
+       "  gx::stream_wave<gx::Prog>(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);\n}\n";
+  return o;
+}
+
+int jit_compile(const std::string& src, std::vector<char>* code, std::string* log) {
+  hiprtcProgram prog;
+  const char* hdrs[2] = {kJitHdrDev, kJitHdrInternal};
+  const char* names[2] = {"gx_dev.h", "gx_internal.h"};
+  if (hiprtcCreateProgram(&prog, src.c_str(), "gx_prog.hip", 2, hdrs, names) != HIPRTC_SUCCESS) {
+    if (log) *log = "hiprtcCreateProgram failed";
+    return -EIO;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops", "-Wno-unused-label"};
+  hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  size_t n = 0;
+  if (log && hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 1) {
+    log->assign(n, '\0');
+    (void)hiprtcGetProgramLog(prog, &(*log)[0]);
+    log->resize(n - 1);
+  }
+  if (r != HIPRTC_SUCCESS) {
+    (void)hiprtcDestroyProgram(&prog);
+    return -EIO;
+  }
+  size_t cs = 0;
+  if (hiprtcGetCodeSize(prog, &cs) != HIPRTC_SUCCESS || cs == 0) {
+    (void)hiprtcDestroyProgram(&prog);
+    return -EIO;
+  }
+  code->assign(cs, 0);
+  r = hiprtcGetCode(prog, code->data());
+  (void)hiprtcDestroyProgram(&prog);
+  return r == HIPRTC_SUCCESS ? 0 : -EIO;
+}
+
+}  // namespace gx

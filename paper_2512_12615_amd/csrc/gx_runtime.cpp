@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gx_internal.h"
+#include "gx_jit.h"
 #include "gx_verifier.h"
 #include "gxbpf.h"
 
@@ -52,6 +53,10 @@ struct ProgObj {
   Uop* d_uops = nullptr;
   uint64_t* d_guards = nullptr;
   std::vector<int> fds;
+  std::vector<Uop> uops;  // host copy (source of the compiled form)
+  // compiled form (gx_jit_program): module and its two kernels
+  hipModule_t jmod = nullptr;
+  hipFunction_t jf_ep = nullptr, jf_seq = nullptr;
 };
 
 uint64_t next_pow2(uint64_t x) {
@@ -197,7 +202,12 @@ int jmp_handler(int o, bool w32) {
   return (w32 ? t32 : t64)[o >> 4];
 }
 
-std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const std::vector<MapObj*>& tab) {
+struct MapRef {
+  uint32_t type;
+  uint64_t desc;  // device address of the map descriptor
+};
+
+std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const std::vector<MapRef>& tab) {
   std::vector<Uop> U(P.size());
   for (auto& u : U) u = Uop{uop_w0(H_EXIT, 0, 0, 0, true), 0, 0};
   for (size_t pc = 0; pc < P.size(); pc++) {
@@ -223,18 +233,18 @@ std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const s
       } else if (o == 0x80) {
         int mi = V.call_map[pc];
         if (mi < 0) continue;  // unreachable
-        MapObj* m = tab[mi];
+        const MapRef& m = tab[mi];
         int a2 = V.arg2_kind[pc] < 0 ? 0 : V.arg2_kind[pc];
         int a3 = V.arg3_kind[pc] < 0 ? 0 : V.arg3_kind[pc];
         int h = H_EXIT, aux = 0;
-        bool arr = m->h.type == MAP_ARRAY;
+        bool arr = m.type == MAP_ARRAY;
         switch (in.imm) {
           case 1: h = arr ? H_LOOKUP_ARRAY : H_LOOKUP_HASH; break;
           case 2: h = arr ? H_UPDATE_ARRAY : H_UPDATE_HASH; break;
           case 3: h = arr ? H_RET_EINVAL : H_DELETE_HASH; break;
           case 130: h = H_RINGBUF_OUTPUT; aux = (int)V.ring_size[pc]; break;
         }
-        u = Uop{uop_w0(h, 0, 0, a2 | (a3 << 1), true), aux, (uint64_t)(uintptr_t)m->d_desc};
+        u = Uop{uop_w0(h, 0, 0, a2 | (a3 << 1), true), aux, m.desc};
       } else {
         int t = (int)pc + 1 + ((w32 && o == 0) ? in.imm : in.off);
         int h = jmp_handler(o, w32);
@@ -265,7 +275,7 @@ std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const s
         val = (uint64_t)(uint32_t)in.imm | ((uint64_t)(uint32_t)P[pc + 1].imm << 32);
       } else {
         int mi = V.ld_map[pc];
-        val = mi >= 0 ? (uint64_t)(uintptr_t)tab[mi]->d_desc : 0;
+        val = mi >= 0 ? tab[mi].desc : 0;
       }
       u = Uop{uop_w0(H_LDIMM, in.dst, 0, 0, true), 0, val};
       U[pc] = u;
@@ -336,6 +346,7 @@ void gx_close(gx_rt* rt) {
   for (auto& p : rt->progs) {
     if (p.d_uops) (void)hipFree(p.d_uops);
     if (p.d_guards) (void)hipFree(p.d_guards);
+    if (p.jmod) (void)hipModuleUnload(p.jmod);
   }
   for (auto& se : rt->stream_events) (void)hipEventDestroy(se.second);
   for (auto* v : {&rt->prof_pending, &rt->prof_free})
@@ -551,7 +562,9 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
   Verdict v = verify(P, (int)hook_type, shapes, fds);
   write_log(log, log_size, v.log);
   if (!v.ok) return -EACCES;
-  std::vector<Uop> U = predecode(P, v, tab);
+  std::vector<MapRef> refs;
+  for (MapObj* m : tab) refs.push_back(MapRef{m->h.type, (uint64_t)(uintptr_t)m->d_desc});
+  std::vector<Uop> U = predecode(P, v, refs);
   std::vector<uint64_t> guards(2 * P.size(), 0);
   for (size_t pc = 0; pc < P.size(); pc++)
     if (v.mem_map[pc] >= 0) {
@@ -579,9 +592,69 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
     return -EIO;
   }
   p.v = std::move(v);
+  p.uops = std::move(U);
   p.live = true;
   rt->progs.push_back(std::move(p));
   return (int)rt->progs.size() - 1;
+}
+
+int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p) return -EINVAL;
+  if (p->jmod) return 0;
+  std::vector<char> code;
+  std::string lg;
+  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes), &code, &lg);
+  write_log(log, log_size, lg);
+  if (r) return r;
+  DevGuard g(rt->dev);
+  hipModule_t mod = nullptr;
+  hipFunction_t fe = nullptr, fs = nullptr;
+  if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return -EIO;
+  if (hipModuleGetFunction(&fe, mod, "gx_j_event_parallel") != hipSuccess ||
+      hipModuleGetFunction(&fs, mod, "gx_j_stream_seq") != hipSuccess) {
+    (void)hipModuleUnload(mod);
+    return -EIO;
+  }
+  p->jmod = mod;
+  p->jf_ep = fe;
+  p->jf_seq = fs;
+  return 0;
+}
+
+int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
+                      uint32_t n_maps, int compile, char* out, uint64_t cap) {
+  if (!insns && n_insns) return -EINVAL;
+  if (n_insns > (uint32_t)kMaxInsns) return -E2BIG;
+  uint32_t rs, so, ss;
+  if (!hook_layout((int)hook_type, &rs, &so, &ss)) return -EINVAL;
+  std::vector<MapShape> shapes(n_maps);
+  std::vector<int> fds(n_maps);
+  std::vector<MapRef> refs(n_maps);
+  for (uint32_t i = 0; i < n_maps; i++) {
+    shapes[i] = MapShape{map_shapes[5 * i], map_shapes[5 * i + 1], map_shapes[5 * i + 2], map_shapes[5 * i + 3],
+                         map_shapes[5 * i + 4]};
+    fds[i] = (int)i;
+    refs[i] = MapRef{map_shapes[5 * i], 0x100000000ull + 64ull * i};  // stand-in descriptor addresses
+  }
+  std::vector<Insn> P = decode_insns(insns, n_insns);
+  Verdict v = verify(P, (int)hook_type, shapes, fds);
+  if (!v.ok) {
+    write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
+    return -EACCES;
+  }
+  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes);
+  if (compile) {
+    std::vector<char> code;
+    std::string lg;
+    int r = jit_compile(src, &code, &lg);
+    if (r) {
+      write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), lg);
+      return r;
+    }
+  }
+  if (out && cap) write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), src);
+  return (int64_t)src.size();
 }
 
 int gx_prog_info_get(gx_rt* rt, int prog_fd, gx_prog_info* out) {
@@ -621,7 +694,12 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   if (p->v.event_parallel) {
     A.step_limit = per_event;
     if (pe.first) (void)hipEventRecord(pe.first, s);
-    e = launch_event_parallel(A, s);
+    if (p->jf_ep) {
+      void* args[] = {&A};
+      e = hipModuleLaunchKernel(p->jf_ep, (uint32_t)((n_events + 63) / 64), 1, 1, 64, 1, 1, 0, s, args, nullptr);
+    } else {
+      e = launch_event_parallel(A, s);
+    }
     if (pe.second) (void)hipEventRecord(pe.second, s);
     rt->stats.launches += 1;
   } else {
@@ -641,7 +719,13 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
       A.n_queues = L;
       uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
       if (pe.first) (void)hipEventRecord(pe.first, s);
-      e = launch_stream_seq(A, lanes, nt, s);
+      if (p->jf_seq) {
+        uint32_t qstride = nt;
+        void* args[] = {&A, &lanes, &qstride};
+        e = hipModuleLaunchKernel(p->jf_seq, (L + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+      } else {
+        e = launch_stream_seq(A, lanes, nt, s);
+      }
       if (pe.second) (void)hipEventRecord(pe.second, s);
     }
     (void)hipEventRecord(rt->ws_event, s);

@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_run_batches", "gx_jit_program", "gx_jit_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
@@ -93,6 +93,9 @@ def lib():
     L.gx_verify.argtypes = [vp, u32, u32, vp, u32, C.c_char_p, u32, C.POINTER(ProgInfo)]
     L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
+    L.gx_jit_program.argtypes = [vp, C.c_int, C.c_char_p, u32]
+    L.gx_jit_source.argtypes = [vp, u32, u32, vp, u32, C.c_int, C.c_char_p, u64]
+    L.gx_jit_source.restype = i64
     L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.gx_drain_ringbuf.restype = i64
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
@@ -134,6 +137,21 @@ def verify(code: bytes, hook: int, shapes):
     r = lib().gx_verify(w.ctypes.data_as(C.c_void_p), len(code) // 8, hook, sh.ctypes.data_as(C.c_void_p),
                         len(sh), log, 512, C.byref(info))
     return r == 0, log.value.decode(), info
+
+
+def jit_source(code: bytes, hook: int, shapes, compile: bool = False) -> str:
+    """HIP source the JIT generates for a program (no device needed); with
+    ``compile`` it is also compiled for gfx950.  Raises GxError on rejection
+    or compile failure (message holds the log)."""
+    sh = np.array(shapes, dtype=np.uint32).reshape(-1, 5) if shapes else np.zeros((0, 5), np.uint32)
+    w = _words(code)
+    cap = 1 << 22
+    out = C.create_string_buffer(cap)
+    r = lib().gx_jit_source(w.ctypes.data_as(C.c_void_p), len(code) // 8, hook, sh.ctypes.data_as(C.c_void_p),
+                            len(sh), int(compile), out, cap)
+    if r < 0:
+        raise GxError(-r, f"gx_jit_source: {os.strerror(-r)}: {out.value.decode(errors='replace')}")
+    return out.value.decode()
 
 
 def _dptr(t):
@@ -225,6 +243,14 @@ class Runtime:
         if r < 0:
             raise GxError(-r, f"gx_load_program: {os.strerror(-r)}: {log.value.decode()}")
         return r
+
+    def jit_program(self, fd):
+        """Compile a loaded program to native gfx950 code (later run_batch
+        calls of it launch the compiled kernels)."""
+        log = C.create_string_buffer(1 << 16)
+        r = lib().gx_jit_program(self._h, fd, log, 1 << 16)
+        if r < 0:
+            raise GxError(-r, f"gx_jit_program: {os.strerror(-r)}: {log.value.decode(errors='replace')}")
 
     def prog_info(self, fd) -> ProgInfo:
         info = ProgInfo()

@@ -13,11 +13,13 @@ def to_device(events):
     return torch.from_numpy(np.ascontiguousarray(events).view(np.uint8).reshape(-1)).cuda()
 
 
-def setup(rt, policy, init=None):
+def setup(rt, policy, init=None, jit=False):
     fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in policy.maps]
     for mi, k, v in init or []:
         assert rt.map_update(fds[mi], k, v) == 0
     prog = rt.load_program(policy.code, policy.hook, fds)
+    if jit:
+        rt.jit_program(prog)
     return fds, prog
 
 
@@ -37,9 +39,9 @@ def collect(rt, policy, fds, rc):
     return res
 
 
-def gpu_run(rt, policy, events, init=None, d_events=None):
+def gpu_run(rt, policy, events, init=None, d_events=None, jit=False):
     import torch
-    fds, prog = setup(rt, policy, init)
+    fds, prog = setup(rt, policy, init, jit)
     n = len(events)
     ev = to_device(events) if d_events is None else d_events
     rc = torch.zeros(max(n, 1), dtype=torch.int32, device="cuda")
