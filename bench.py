@@ -65,13 +65,15 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None):
+def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None, jit=True):
     """Back-to-back plain launches of an event-parallel policy over rotated
     resident batches; events/s from the wall clock, HBM fraction from the VM
     kernel's own time (record + rc + ring bytes per event)."""
     import torch
     fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
     prog = rt.load_program(pol.code, pol.hook, fds)
+    if jit:
+        rt.jit_program(prog)
     n = batches[0].numel() // pol.record_size
     rc = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -104,6 +106,7 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     alg = n * (pol.record_size + 4) + ring[0] / steps
     return {
         "workload": name,
+        "engine": "jit" if jit else "interp",
         "events_per_batch": n,
         "events_per_s": n * steps / wall,
         "vm_kernel_us": vm_s * 1e6,
@@ -113,7 +116,7 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     }
 
 
-def bench_memory_bound(G, W, rt, steps):
+def bench_memory_bound(G, W, rt, steps, jit=True):
     """The two event-parallel policies: access counter (2^20 records, 48
     rotated batches = 1.1 GiB) and latency histogram (2^26 records, 2 rotated
     batches = 2 GiB, ring drained every launch)."""
@@ -123,7 +126,7 @@ def bench_memory_bound(G, W, rt, steps):
     acc = [torch.from_numpy(W.gen_mem_uniform(1 << 20, 1000 + k).view(np.uint8)).cuda() for k in range(48)]
     out["access_counter"] = bench_event_parallel(
         G, W, rt, "access counter, 2^20 x 24 B records, ARRAY 4096 x u64 shared", W.access_counter_policy(), acc,
-        steps * 20)
+        steps * 20, jit=jit)
     del acc
     hosts = [W.gen_timing(1 << 26, 1002 + k) for k in range(2)]
     init = [[(1, b"\0\0\0\0", np.uint64(W.p99_threshold(h["lat"])).tobytes())] for h in hosts]
@@ -131,7 +134,7 @@ def bench_memory_bound(G, W, rt, steps):
     del hosts
     out["latency_hist"] = bench_event_parallel(
         G, W, rt, "latency histogram + p99 tail records, 2^26 x 16 B records, ARRAY 4096 x 64 x u64 shared, "
-        "64 MiB ring", W.latency_hist_policy(), lat, steps, init_per_batch=init, ring_fd=2)
+        "64 MiB ring", W.latency_hist_policy(), lat, steps, init_per_batch=init, ring_fd=2, jit=jit)
     del lat
     torch.cuda.empty_cache()
     return out
@@ -263,9 +266,14 @@ def main():
     ap.add_argument("--batches", type=int, default=2)
     ap.add_argument("--cpu-streams", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--engine", choices=["jit", "interp"], default="jit",
+                    help="run the program compiled to native code (jit) or interpreted")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the memory-bound policies, the batched and the served forms")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size kernel that "
+                         "scales the HBM byte counters of a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this runtime runs on one GPU; multi-GPU sharding is a design note "
@@ -278,6 +286,14 @@ def main():
     from paper_2512_12615_amd import gxbpf as G
     from paper_2512_12615_amd import workloads as W
 
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calib_mib} MiB device to device")
+        del src, dst
+
     n = 1 << args.events_log2
     pol = W.stride_prefetch_policy()
     log(f"generating {args.batches} batches of {n} events")
@@ -289,6 +305,10 @@ def main():
     fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
     prog = rt.load_program(pol.code, pol.hook, fds)
     info = rt.prog_info(prog)
+    if args.engine == "jit":
+        t = time.perf_counter()
+        rt.jit_program(prog)
+        log(f"compiled to native code in {time.perf_counter() - t:.2f} s")
     ring_fd = fds[1]
     stream = torch.cuda.current_stream()
 
@@ -322,7 +342,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = {}
-        for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10)),
+        for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit")),
                         ("batched", lambda: bench_batched(G, W, rt, 2)),
                         ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds))):
             log(f"form: {key}")
@@ -363,6 +383,7 @@ def main():
             "events_per_batch": n,
             "batches_rotated": args.batches,
             "mode": "stream-sequential",
+            "engine": args.engine,
         },
         "insns_per_s": events_per_s * insns_per_event if insns_per_event else None,
         "insns_per_event": insns_per_event,
@@ -376,7 +397,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "gx_k_stream_seq",
+            "kernel": "gx_j_stream_seq" if args.engine == "jit" else "gx_k_stream_seq",
             "bytes_per_event": "24 B record + 4 B rc + ring bytes",
         },
         "cpu_baseline": {k: v for k, v in cpu.items() if k in ("value", "unit", "cores", "kind", "sample")}

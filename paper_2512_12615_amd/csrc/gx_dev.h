@@ -18,6 +18,15 @@
 
 namespace gx {
 
+// Map helpers: a compiled program inlines them (its map descriptors are
+// constants, so sizes, masks and addresses fold into the code); the
+// interpreter calls them.
+#ifdef GX_LDS_BYTES
+#define GX_HELPER __device__ __forceinline__
+#else
+#define GX_HELPER __device__
+#endif
+
 // Stack frames live in this LDS array.  A compiled program sizes it
 // statically (GX_LDS_BYTES); the interpreter's kernels size it at launch.
 #ifdef GX_LDS_BYTES
@@ -79,6 +88,7 @@ __device__ __forceinline__ T ld_relaxed(T* p) {
 struct Stk {
   uint32_t base;   // byte offset of this wave's frames in g_lds
   uint32_t lane8;  // lane * 8
+  uint32_t owner;  // global thread index: identifies the hardware lane for the launch
 };
 
 __device__ __forceinline__ uint8_t* saddr(const Stk& k, uint32_t o) {
@@ -157,11 +167,21 @@ __device__ __forceinline__ uint64_t key_hash(const MapDev* m, int kind, uint64_t
 // written with device-coherent relaxed atomics (no fences: on a multi-XCD
 // device a release/acquire fence writes back / invalidates the whole L2).
 // Values are written by the one lane that owns the key, with plain accesses.
-// A slot freed in this launch (tombstone with the current epoch) is not
-// reclaimed until a later launch, so no two lanes of one launch ever write
-// the same slot's bytes.
+// A tombstone records the launch (epoch) and the hardware lane (owner) that
+// freed it; within that launch only the same lane may reclaim it, so no two
+// lanes - possibly on different XCDs, whose L2s write back in no fixed
+// order - ever write the same slot's bytes in one launch.  Later launches
+// may reclaim any tombstone (a launch boundary writes every L2 back).
 __device__ __forceinline__ uint64_t hdr_word(uint32_t state, uint32_t epoch, uint32_t tag) {
   return (uint64_t)state | ((uint64_t)(epoch & 0xffffffu) << 8) | ((uint64_t)tag << 32);
+}
+
+// May this launch's lane ``owner`` claim the slot whose header is st?
+__device__ __forceinline__ bool claimable(uint64_t st, uint32_t epoch, uint32_t owner) {
+  const uint32_t state = (uint32_t)st & 0xff;
+  if (state == SLOT_EMPTY) return true;
+  if (state != SLOT_TOMB) return false;
+  return ((uint32_t)(st >> 8) & 0xffffffu) != (epoch & 0xffffffu) || (uint32_t)(st >> 32) == owner;
 }
 
 __device__ __forceinline__ bool key_eq(const MapDev* m, uint8_t* hdr, int kind, uint64_t kp, const Stk& stk) {
@@ -173,7 +193,7 @@ __device__ __forceinline__ bool key_eq(const MapDev* m, uint8_t* hdr, int kind, 
 
 // Probe for a key.  Returns the slot index or -1; *free_slot receives the
 // first slot this launch may claim (or -1).
-__device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, const Stk& stk,
+GX_HELPER int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, const Stk& stk,
                              uint32_t epoch, int64_t* free_slot) {
   uint32_t mask = m->slot_mask;
   uint32_t i = (uint32_t)h & mask;
@@ -188,7 +208,7 @@ __device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp,
       break;
     }
     if (state == SLOT_TOMB) {
-      if (fr < 0 && ((uint32_t)(st >> 8) & 0xffffffu) != (epoch & 0xffffffu)) fr = i;
+      if (fr < 0 && claimable(st, epoch, stk.owner)) fr = i;
     } else if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && key_eq(m, hdr, kind, kp, stk)) {
       if (free_slot) *free_slot = fr;
       return i;
@@ -199,13 +219,13 @@ __device__ int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp,
   return -1;
 }
 
-__device__ uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
+GX_HELPER uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
   uint64_t h = key_hash(m, kind, kp, stk);
   int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
   return s < 0 ? 0 : (uint64_t)(m->data + (uint64_t)s * m->vstride);
 }
 
-__device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp,
+GX_HELPER int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp,
                                uint64_t flags, const Stk& stk, uint32_t epoch) {
   if (flags > 2) return -E_INVAL;
   uint64_t h = key_hash(m, kkind, kp, stk);
@@ -229,10 +249,7 @@ __device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkin
   for (uint32_t probe = 0; probe <= mask; probe++) {
     uint64_t* hw = (uint64_t*)(m->slots + (uint64_t)i * m->sstride);
     uint64_t cur = ld_relaxed(hw);
-    uint32_t state = (uint32_t)cur & 0xff;
-    bool claimable = state == SLOT_EMPTY ||
-                     (state == SLOT_TOMB && ((uint32_t)(cur >> 8) & 0xffffffu) != (epoch & 0xffffffu));
-    if (claimable &&
+    if (claimable(cur, epoch, stk.owner) &&
         __hip_atomic_compare_exchange_strong(hw, &cur, hdr_word(SLOT_BUSY, epoch, tag), __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       uint32_t nw = (m->key_size + 7) / 8;
@@ -253,12 +270,12 @@ __device__ int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkin
   return -E_2BIG;
 }
 
-__device__ int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
+GX_HELPER int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
   uint64_t h = key_hash(m, kind, kp, stk);
   int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
   if (s < 0) return -E_NOENT;
   __hip_atomic_store((uint64_t*)(m->slots + (uint64_t)s * m->sstride),
-                     hdr_word(SLOT_TOMB, epoch, (uint32_t)(h >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                     hdr_word(SLOT_TOMB, epoch, stk.owner), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
@@ -268,7 +285,7 @@ __device__ __forceinline__ uint64_t array_lookup(const MapDev* m, int kind, uint
   return idx < m->max_entries ? (uint64_t)(m->data + (uint64_t)idx * m->vstride) : 0;
 }
 
-__device__ int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp, uint64_t flags,
+GX_HELPER int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkind, uint64_t vp, uint64_t flags,
                                 const Stk& stk) {
   if (flags > 2) return -E_INVAL;
   uint32_t idx = (uint32_t)chunk(kkind, kp, 0, 4, stk);
@@ -280,7 +297,7 @@ __device__ int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vki
 
 // ringbuf_output for the whole wave; ``act`` lanes take part.  Space for all
 // outputs of the wave is reserved with one compare-and-swap on the head.
-__device__ uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t size, uint64_t flags,
+GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t size, uint64_t flags,
                                 bool act, const Stk& stk) {
   uint64_t res = 0;
   bool want = act && flags == 0;

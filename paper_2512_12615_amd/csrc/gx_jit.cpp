@@ -41,7 +41,25 @@ std::string extend(const std::string& v, int sc, bool sx) {
   return std::string("(uint64_t)(int64_t)(") + kSTy[sc] + ")(" + v + ")";
 }
 
-void emit_uop(std::string& o, const Uop& u, uint32_t pc) {
+// name of the constant descriptor of the map at device address ``desc``
+std::string map_name(const std::vector<std::pair<uint64_t, MapDev>>& maps, uint64_t desc) {
+  for (size_t k = 0; k < maps.size(); k++)
+    if (maps[k].first == desc) return "&M" + std::to_string(k);
+  return "(const MapDev*)" + lit(desc);
+}
+
+std::string map_const(size_t k, const MapDev& m) {
+  char b[512];
+  std::snprintf(b, sizeof b,
+                "  const MapDev M%zu = {%uu, %uu, %uu, %uu, %uu, %uu, %uu, %uu, (uint8_t*)%s, (uint8_t*)%s, "
+                "(uint64_t*)%s, 0ull};\n",
+                k, m.type, m.key_size, m.value_size, m.max_entries, m.flags, m.vstride, m.slot_mask, m.sstride,
+                lit((uint64_t)(uintptr_t)m.data).c_str(), lit((uint64_t)(uintptr_t)m.slots).c_str(),
+                lit((uint64_t)(uintptr_t)m.ctrl).c_str());
+  return b;
+}
+
+void emit_uop(std::string& o, const Uop& u, uint32_t pc, const std::vector<std::pair<uint64_t, MapDev>>& maps) {
   const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, s = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
   const bool K = (u.w0 >> 24) & 1;
   const std::string D = reg(d), S = reg(s);
@@ -51,7 +69,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc) {
   const bool sxf = (a8 & 4) != 0;
   const std::string off = std::to_string(u.aux);
   const std::string tgt = "goto L" + std::to_string((uint32_t)u.aux) + ";";
-  const std::string M = "(const MapDev*)" + lit(u.imm);
+  const std::string M = map_name(maps, u.imm);
   auto set = [&](const std::string& e) { o += "  " + D + " = " + e + ";\n"; };
   auto set32 = [&](const std::string& e) { o += "  " + D + " = (uint64_t)(uint32_t)(" + e + ");\n"; };
   auto jmp = [&](const std::string& c) { o += "  if (" + c + ") " + tgt + "\n"; };
@@ -206,7 +224,8 @@ bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
 
 }  // namespace
 
-std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes) {
+std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
+                       const std::vector<std::pair<uint64_t, MapDev>>& maps) {
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
@@ -218,18 +237,19 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes) {
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
   o += "  uint64_t r10 = " + std::to_string(stack_bytes) + "ull;\n";
+  for (size_t k = 0; k < maps.size(); k++) o += map_const(k, maps[k].second);
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
   for (uint32_t pc = 0; pc < U.size(); pc++) {
     if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
-    emit_uop(o, U[pc], pc);
+    emit_uop(o, U[pc], pc, maps);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
   o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_event_parallel(gx::RunArgs A) {\n"
-       "  gx::Stk stk{0, gx::lane_id() * 8u};\n  uint64_t steps = 0;\n"
+       "  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n  uint64_t steps = 0;\n"
        "  gx::event_tile<gx::Prog>(A, (uint64_t)blockIdx.x * 64u, stk, steps);\n}\n\n";
   o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
-       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u};\n  uint64_t steps = 0;\n"
+       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n  uint64_t steps = 0;\n"
        "  gx::stream_wave<gx::Prog>(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);\n}\n";
   return o;
 }

@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gx_internal.h"
@@ -14,7 +15,11 @@ namespace gx {
 // descriptors as constants, and the two event-loop kernels
 // (gx_j_event_parallel, gx_j_stream_seq; 64 threads per block, stack frames
 // in a static LDS array).
-std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes);
+// ``maps`` holds (descriptor device address, descriptor contents) of every
+// map the program uses; the generated code gets each descriptor as a
+// constant, so key sizes, slot masks and addresses fold into the code.
+std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
+                       const std::vector<std::pair<uint64_t, MapDev>>& maps);
 
 // Compile a generated source for gfx950.  Returns 0 and the code object, or
 // -EIO with the compiler log.

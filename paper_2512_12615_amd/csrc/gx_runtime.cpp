@@ -604,7 +604,13 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   if (p->jmod) return 0;
   std::vector<char> code;
   std::string lg;
-  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes), &code, &lg);
+  std::vector<std::pair<uint64_t, MapDev>> maps;
+  for (int fd : p->fds) {
+    MapObj* m = get_map(rt, fd);
+    if (!m) return -EINVAL;
+    maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
+  }
+  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps), &code, &lg);
   write_log(log, log_size, lg);
   if (r) return r;
   DevGuard g(rt->dev);
@@ -637,13 +643,29 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     fds[i] = (int)i;
     refs[i] = MapRef{map_shapes[5 * i], 0x100000000ull + 64ull * i};  // stand-in descriptor addresses
   }
+  std::vector<std::pair<uint64_t, MapDev>> maps;
+  for (uint32_t i = 0; i < n_maps; i++) {
+    MapDev d{};
+    d.type = shapes[i].type;
+    d.key_size = shapes[i].key_size;
+    d.value_size = shapes[i].value_size;
+    d.max_entries = shapes[i].max_entries;
+    d.flags = shapes[i].flags;
+    d.vstride = (d.value_size + 7) & ~7u;
+    d.slot_mask = 15;
+    d.sstride = 8 + ((d.key_size + 7) & ~7u);
+    d.data = (uint8_t*)(uintptr_t)(0x200000000ull + (1ull << 28) * i);  // stand-in addresses
+    d.slots = d.data + (1ull << 27);
+    d.ctrl = (uint64_t*)(d.data + (1ull << 27) + (1ull << 26));
+    maps.push_back({refs[i].desc, d});
+  }
   std::vector<Insn> P = decode_insns(insns, n_insns);
   Verdict v = verify(P, (int)hook_type, shapes, fds);
   if (!v.ok) {
     write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
     return -EACCES;
   }
-  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes);
+  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps);
   if (compile) {
     std::vector<char> code;
     std::string lg;

@@ -298,14 +298,14 @@ struct Interp {
 // Event-parallel mode: lane = event.
 extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A) {
   const uint32_t wave = threadIdx.x >> 6;
-  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u};
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   uint64_t steps = 0;
   event_tile<Interp>(A, (uint64_t)blockIdx.x * blockDim.x + wave * 64u, stk, steps);
 }
 
 // Stream-sequential mode: ``lanes`` lanes of each one-wave block own queues.
 extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
-  Stk stk{0, lane_id() * 8u};
+  Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   uint64_t steps = 0;
   stream_wave<Interp>(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);
 }
@@ -320,7 +320,7 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_batched(const BatchDev* B,
                                                               uint32_t* next) {
   typedef const __attribute__((address_space(4))) uint64_t cu64;
   static_assert(sizeof(BatchDev) % 8 == 0, "BatchDev is loaded as 8-byte words");
-  Stk stk{0, lane_id() * 8u};
+  Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   uint64_t steps = 0;
   for (;;) {
     uint32_t it = 0;
@@ -487,7 +487,7 @@ extern "C" __global__ void __launch_bounds__(256) gx_k_scan_add(uint32_t* data, 
 extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val,
                                        uint64_t flags, int64_t* ret, uint8_t* val_out, uint32_t epoch) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Stk stk{0, 0};
+  Stk stk{0, 0, 0xffffffffu};
   uint64_t kp = (uint64_t)key, vp = (uint64_t)val;
   int64_t r = -E_INVAL;
   if (m->type == MAP_ARRAY) {
