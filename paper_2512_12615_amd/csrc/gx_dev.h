@@ -295,8 +295,42 @@ GX_HELPER int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkin
   return 0;
 }
 
+// Ring space.  ctrl[0] head (bytes reserved so far), ctrl[1] tail (bytes
+// the host consumed), ctrl[2] drops, ctrl[3] = ~(start of the first
+// reservation that overflowed), 0 if none.  A reservation is one fetch-add
+// on the head (no compare-and-swap retries under contention); the head
+// and tail are read first, so a request that cannot fit moves nothing.
+// When two requests race past the end, the late one finds its range beyond
+// the space, gives it up and records where it started: every later
+// reservation lies further out and fails too, so the committed data ends
+// exactly at the smallest such start, and the host's drain cuts the head
+// back to it.
+__device__ __forceinline__ bool ring_reserve(const MapDev* m, uint64_t total, uint64_t* base) {
+  const uint64_t cap = (uint64_t)m->slot_mask + 1;
+  const uint64_t t = ld_relaxed(&m->ctrl[1]);
+  const uint64_t h = ld_relaxed(&m->ctrl[0]);
+  if (h + total - t > cap) return false;
+  const uint64_t old = __hip_atomic_fetch_add(&m->ctrl[0], total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (old + total - t > cap) {
+    __hip_atomic_fetch_max(&m->ctrl[3], ~old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+  *base = old;
+  return true;
+}
+
+
+__device__ __forceinline__ void ring_put(const MapDev* m, uint64_t pos, int kind, uint64_t dp, uint32_t size,
+                                         const Stk& stk) {
+  const uint64_t mask = m->slot_mask;
+  const uint32_t nw = (size + 7) / 8;
+  for (uint32_t w = 0; w < nw; w++) *(uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask)) = chunk(kind, dp, w, size, stk);
+  // records are read by the host once the producing launch has completed
+  *(uint64_t*)(m->data + (pos & mask)) = (uint64_t)size;
+}
+
 // ringbuf_output for the whole wave; ``act`` lanes take part.  Space for all
-// outputs of the wave is reserved with one compare-and-swap on the head.
+// outputs of the wave is reserved at once by the first active lane.
 GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t size, uint64_t flags,
                                 bool act, const Stk& stk) {
   uint64_t res = 0;
@@ -308,22 +342,12 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
   uint32_t cnt = popc64(wm);
   uint32_t leader = (uint32_t)__builtin_ctzll(wm);
   uint64_t total = (uint64_t)need * cnt;
-  uint64_t cap = (uint64_t)m->slot_mask + 1;
   uint32_t ok = 0, base_lo = 0, base_hi = 0;
   if (lane_id() == leader) {
-    uint64_t* head = &m->ctrl[0];
-    uint64_t h = ld_relaxed(head);
-    for (int tries = 0; tries < 1 << 20; tries++) {
-      uint64_t t = ld_relaxed(&m->ctrl[1]);
-      if (h + total - t > cap) break;
-      if (__hip_atomic_compare_exchange_strong(head, &h, h + total, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT)) {
-        ok = 1;
-        break;
-      }
-    }
-    base_lo = (uint32_t)h;
-    base_hi = (uint32_t)(h >> 32);
+    uint64_t b = 0;
+    ok = ring_reserve(m, total, &b) ? 1u : 0u;
+    base_lo = (uint32_t)b;
+    base_hi = (uint32_t)(b >> 32);
     if (!ok) __hip_atomic_fetch_add(&m->ctrl[2], (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   ok = rdlane(ok, leader);
@@ -333,17 +357,92 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
     return res;
   }
   if (want) {
-    uint64_t pos = base + (uint64_t)need * rank_in(wm);
-    uint64_t mask = cap - 1;
-    uint32_t nw = (size + 7) / 8;
-    for (uint32_t w = 0; w < nw; w++)
-      *(uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask)) = chunk(kind, dp, w, size, stk);
-    // records are read by the host once the producing launch has completed
-    *(uint64_t*)(m->data + (pos & mask)) = (uint64_t)size;
+    ring_put(m, base + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
     res = 0;
   }
   return res;
 }
+
+// A wave's chunk of reserved ring space (compiled programs): ring outputs
+// carve their records from it, so most outputs reserve nothing globally.
+// The chunk lives in LDS, one slot per (wave, ring): its lanes may reach a
+// ring output under different EXEC masks, and LDS keeps one copy that every
+// lane sees.
+struct RingChunk {
+  uint64_t pos;
+  uint64_t left;
+};
+
+#ifdef GX_RING_SLOTS
+__shared__ RingChunk g_rchunk[GX_RING_SLOTS];
+
+__device__ __forceinline__ uint64_t ring_chunk_bytes(uint64_t cap, uint64_t waves) {
+  uint64_t c = cap / (4 * (waves ? waves : 1));
+  c = c < 64 ? 64 : c > 8192 ? 8192 : c;
+  return c & ~7ull;
+}
+
+__device__ __forceinline__ void ring_chunk_init(uint32_t slot) {
+  if (lane_id() == 0) g_rchunk[slot] = RingChunk{0, 0};
+}
+
+// Close the chunk: the unused rest becomes one discarded record.
+__device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
+  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos;
+  if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
+    if (left >= 8)
+      *(uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask)) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+    g_rchunk[slot].left = 0;
+  }
+}
+
+// ringbuf_output carving from the wave's chunk; a new chunk of ``chunk_bytes``
+// (or the wave's whole request, if larger) is reserved when this one is
+// short.  Same results as ring_output while space lasts; near a full ring a
+// request may fail a little earlier (the unused parts of chunks count as
+// used until the drain).
+__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint64_t chunk_bytes,
+                                                         int kind, uint64_t dp, uint32_t size, uint64_t flags,
+                                                         const Stk& stk) {
+  uint64_t res = 0;
+  const bool want = flags == 0;
+  if (!want) res = (uint64_t)-E_INVAL;
+  const uint64_t wm = ballot(want);
+  if (wm == 0) return res;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(ballot(true));
+  const uint32_t need = 8 + ((size + 7) & ~7u);
+  const uint32_t cnt = popc64(wm);
+  const uint64_t total = (uint64_t)need * cnt;
+  uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left;
+  if (total > left) {
+    if (lane_id() == leader && left >= 8)
+      *(uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask)) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+    const uint64_t ask = total > chunk_bytes ? total : chunk_bytes;
+    uint32_t ok = 0, lo = 0, hi = 0;
+    if (lane_id() == leader) {
+      uint64_t b = 0;
+      ok = ring_reserve(m, ask, &b) ? 1u : 0u;
+      if (!ok && ask > total) ok = ring_reserve(m, total, &b) ? 2u : 0u;
+      lo = (uint32_t)b;
+      hi = (uint32_t)(b >> 32);
+      if (!ok) __hip_atomic_fetch_add(&m->ctrl[2], (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ok = rdlane(ok, leader);
+    if (!ok) {
+      if (lane_id() == leader) g_rchunk[slot].left = 0;
+      return want ? (uint64_t)-E_AGAIN : res;
+    }
+    pos = ((uint64_t)rdlane(hi, leader) << 32) | rdlane(lo, leader);
+    left = ok == 1 ? ask : total;
+  }
+  if (want) {
+    ring_put(m, pos + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
+    res = 0;
+  }
+  if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos + total, left - total};
+  return res;
+}
+#endif
 
 // Atomic read-modify-write on global memory; commutative non-fetching forms
 // are reduced across the active lanes when they all hit one address.
@@ -399,6 +498,90 @@ __device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS accumulation of a shared map's commutative atomics (compiled programs,
+// event-parallel kernels; section 4.4's aggregation of duplicate map
+// updates taken from the wave to the workgroup).  A shared map takes one
+// commutative operation at one width and is never read during a run, so a
+// block may sum its updates in LDS and apply them to the map once, when it
+// finishes: the map's final contents are the same.  Small maps are mirrored
+// whole (word i of the LDS copy is word i of the value area); larger ones
+// get a tagged cache keyed by address, whose misses go to the map directly.
+
+template <typename T>
+__device__ __forceinline__ T op_identity(uint32_t op) {
+  return op == 0x50 ? (T)~(T)0 : (T)0;
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_rmw(T* p, T v, uint32_t op) {
+  switch (op) {
+    case 0x00: __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); break;
+    case 0x40: __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); break;
+    case 0x50: __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); break;
+    default: __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); break;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void global_rmw(T* p, T v, uint32_t op) {
+  switch (op) {
+    case 0x00: __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    case 0x40: __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    case 0x50: __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    default: __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+  }
+}
+
+// whole-map mirror: acc[0..words) starts at the identity
+template <typename T>
+__device__ __forceinline__ void mirror_init(T* acc, uint32_t words, uint32_t op) {
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) acc[i] = op_identity<T>(op);
+}
+// consecutive threads flush consecutive words: coalesced device atomics
+template <typename T>
+__device__ __forceinline__ void mirror_flush(const T* acc, uint32_t words, uint32_t op, uint8_t* data) {
+  const T id = op_identity<T>(op);
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) {
+    const T v = acc[i];
+    if (v != id) global_rmw((T*)data + i, v, op);
+  }
+}
+
+// tagged cache: slot s holds the sum for device address tag[s] (0: free)
+template <typename T>
+__device__ __forceinline__ void cache_init(uint64_t* tag, T* val, uint32_t slots, uint32_t op) {
+  for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+    tag[i] = 0;
+    val[i] = op_identity<T>(op);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void cache_rmw(uint64_t* tag, T* val, uint32_t slots, uint64_t addr, T v, uint32_t op) {
+  const uint32_t s = (uint32_t)(((addr / sizeof(T)) * 0x9E3779B97F4A7C15ull) >> 40) & (slots - 1);
+  uint64_t t = __hip_atomic_load(&tag[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (t == 0) {
+    uint64_t e = 0;
+    t = __hip_atomic_compare_exchange_strong(&tag[s], &e, addr, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP)
+            ? addr
+            : e;
+  }
+  if (t == addr)
+    lds_rmw(&val[s], v, op);
+  else
+    global_rmw((T*)addr, v, op);
+}
+template <typename T>
+__device__ __forceinline__ void cache_flush(const uint64_t* tag, const T* val, uint32_t slots, uint32_t op) {
+  const T id = op_identity<T>(op);
+  for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+    const uint64_t t = tag[i];
+    const T v = val[i];
+    if (t && v != id) global_rmw((T*)t, v, op);
+  }
+}
+
 // Read-modify-write on the lane's own stack (private: no atomicity needed).
 __device__ __forceinline__ uint64_t atomic_stack(uint8_t* p, uint64_t v, uint32_t op, int sc, uint64_t r0) {
   uint64_t old = load_sized(p, sc), nv;
@@ -450,7 +633,7 @@ __device__ __forceinline__ bool guard_ok(const RunArgs& A, uint32_t pc, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// event loops.  ``Run::run(A, live, c0, c1, c2, stk, steps)`` executes one
+// event loops.  ``R.run(A, live, c0, c1, c2, stk, steps)`` executes one
 // invocation per live lane and returns its rc.
 
 struct Ctx {
@@ -468,20 +651,63 @@ __device__ __forceinline__ Ctx load_record(const RunArgs& A, uint64_t i) {
 
 // One wave-tile of an event-parallel run: lane l runs event first + l.
 template <class Run>
-__device__ __forceinline__ void event_tile(const RunArgs& A, uint64_t first, const Stk& stk, uint64_t& steps) {
+__device__ __forceinline__ void event_tile(Run& R, const RunArgs& A, uint64_t first, const Stk& stk, uint64_t& steps) {
   const uint64_t i = first + lane_id();
   const bool live = i < A.n_events;
   Ctx c{0, 0, 0};
   if (live) c = load_record(A, i);
-  uint32_t rc = Run::run(A, live, c.c0, c.c1, c.c2, stk, steps);
+  uint32_t rc = R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
   if (live && A.rc) A.rc[i] = rc;
 }
 
-// One wave of a stream-sequential run: lane l < lanes owns queue q0 + l and
-// runs that queue's events (order[qstart[q] ..]) in index order.
+// A wave's share of an event-parallel run: tiles t0, t0 + tstep, ... with
+// the next tile's records loaded while the current one runs.
 template <class Run>
-__device__ __forceinline__ void stream_wave(const RunArgs& A, uint32_t q0, uint32_t lanes, uint32_t qstride,
+__device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0, uint64_t tstep, const Stk& stk) {
+  uint64_t steps = 0;
+  const uint64_t tiles = (A.n_events + 63) / 64;
+  const uint32_t l = lane_id();
+  uint64_t t = t0, i = t0 * 64 + l;
+  bool live = t < tiles && i < A.n_events;
+  Ctx c{0, 0, 0};
+  if (live) c = load_record(A, i);
+  while (t < tiles) {
+    const uint64_t tn = t + tstep, in = tn * 64 + l;
+    const bool ln = tn < tiles && in < A.n_events;
+    Ctx cn{0, 0, 0};
+    if (ln) cn = load_record(A, in);
+    const uint32_t rc = R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
+    if (live && A.rc) A.rc[i] = rc;
+    t = tn;
+    i = in;
+    live = ln;
+    c = cn;
+  }
+}
+
+// Record k of the queue-ordered copy.
+__device__ __forceinline__ Ctx load_sorted(const RunArgs& A, uint64_t k) {
+  const uint64_t* p = (const uint64_t*)(A.sorted + k * kSortedStride);
+  Ctx c;
+  c.c0 = p[0];
+  c.c1 = p[1];
+  c.c2 = A.record_size > 16 ? p[2] : 0;
+  return c;
+}
+
+// One wave of a stream-sequential run: lane l < lanes owns queue q0 + l and
+// runs that queue's events in index order.  The partition left each queue's
+// records together (sorted[qstart[q] ..]) and their event indices in
+// order[].  A lane's next kStreamBlock records and indices are loaded in
+// one go while the current block runs: loads complete in issue order on
+// this hardware, so one wait per block replaces one per event.  Return
+// codes are kept in registers and stored once per block.
+constexpr uint32_t kStreamBlock = 8;
+
+template <class Run>
+__device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q0, uint32_t lanes, uint32_t qstride,
                                             uint32_t qend_last, const Stk& stk, uint64_t& steps) {
+  constexpr uint32_t B = kStreamBlock;
   const uint32_t l = lane_id();
   const uint32_t q = q0 + l;
   const bool own = l < lanes && q < A.n_queues;
@@ -490,22 +716,51 @@ __device__ __forceinline__ void stream_wave(const RunArgs& A, uint32_t q0, uint3
     beg = A.qstart[(uint64_t)q * qstride];
     end = q + 1 < A.n_queues ? A.qstart[(uint64_t)(q + 1) * qstride] : qend_last;
   }
-  uint32_t cnt = end - beg;
+  const uint32_t cnt = end - beg;
   const uint32_t rounds = wave_max_active(cnt);
-  // the next event's index and record are loaded while this one runs
-  uint64_t ni = cnt > 0 ? A.order[beg] : 0;
-  Ctx nc{0, 0, 0};
-  if (cnt > 0) nc = load_record(A, ni);
-  for (uint32_t k = 0; k < rounds; k++) {
-    const bool live = k < cnt;
-    const uint64_t i = ni;
-    const Ctx c = nc;
-    if (k + 1 < cnt) {
-      ni = A.order[beg + k + 1];
-      nc = load_record(A, ni);
+  Ctx nx[B];
+  uint32_t ni[B];
+#pragma unroll
+  for (uint32_t j = 0; j < B; j++) {
+    nx[j] = Ctx{0, 0, 0};
+    ni[j] = 0;
+    if (j < cnt) {
+      nx[j] = load_sorted(A, (uint64_t)beg + j);
+      ni[j] = A.order[beg + j];
     }
-    uint32_t rc = Run::run(A, live, c.c0, c.c1, c.c2, stk, steps);
-    if (live && A.rc) A.rc[i] = rc;
+  }
+  for (uint32_t k0 = 0; k0 < rounds; k0 += B) {
+    Ctx cu[B];
+    uint32_t si[B], crc[B];
+#pragma unroll
+    for (uint32_t j = 0; j < B; j++) {
+      cu[j] = nx[j];
+      si[j] = ni[j];
+      crc[j] = 0;
+    }
+    if (k0 + B < rounds) {
+#pragma unroll
+      for (uint32_t j = 0; j < B; j++)
+        if (k0 + B + j < cnt) {
+          nx[j] = load_sorted(A, (uint64_t)beg + k0 + B + j);
+          ni[j] = A.order[beg + k0 + B + j];
+        }
+    }
+    for (uint32_t j = 0; j < B; j++) {
+      const Ctx c = cu[0];
+#pragma unroll
+      for (uint32_t x = 0; x + 1 < B; x++) cu[x] = cu[x + 1];
+      uint32_t rc = 0;
+      if (k0 + j < rounds) rc = R.run(A, k0 + j < cnt, c.c0, c.c1, c.c2, stk, steps);
+#pragma unroll
+      for (uint32_t x = 0; x + 1 < B; x++) crc[x] = crc[x + 1];
+      crc[B - 1] = rc;
+    }
+    if (A.rc) {
+#pragma unroll
+      for (uint32_t j = 0; j < B; j++)
+        if (k0 + j < cnt) A.rc[si[j]] = crc[j];
+    }
     if (steps > A.step_limit) break;
   }
 }

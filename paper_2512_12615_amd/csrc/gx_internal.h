@@ -70,9 +70,15 @@ struct __attribute__((aligned(64))) MapDev {
   uint32_t sstride;     // hash: slot header stride (8 + key bytes rounded to 8)
   uint8_t* data;        // array / hash: values; ring: data area
   uint8_t* slots;       // hash: slot headers {u32 state; u32 pad; key bytes}
-  uint64_t* ctrl;       // hash: [0] live, [1] e2big; ring: [0] head, [1] tail, [2] drops
+  uint64_t* ctrl;       // hash: [0] live, [1] e2big; ring: [0] head, [1] tail, [2] drops,
+                        // [3] ~(start of the first overflowing reservation) or 0
   uint64_t pad;
 };
+
+// Ring record header word: {u32 len, u32 flags}; a header of 0 marks space
+// that is reserved but not yet written.  Padding that closes a chunk of
+// reserved space is a record with the discard flag, which the drain skips.
+constexpr uint32_t RING_DISCARD = 1;
 
 // Hash slot states.
 enum : uint32_t { SLOT_EMPTY = 0, SLOT_BUSY = 1, SLOT_LIVE = 2, SLOT_TOMB = 3 };
@@ -96,7 +102,11 @@ struct RunArgs {
   uint32_t pad2;
   uint64_t* err;           // device error counter
   const uint64_t* guards;  // per slot {lo, hi} of the map data a map-value access may touch
+  const uint8_t* sorted;   // stream-sequential: the records in queue order, kSortedStride apart
 };
+
+// Stride of the queue-ordered record copy (the largest record).
+constexpr uint32_t kSortedStride = 24;
 
 // Batched form: one entry per run in a persistent launch.
 struct BatchDev {

@@ -15,6 +15,7 @@
 
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cerrno>
 #include <cstdio>
 #include <string>
@@ -41,25 +42,88 @@ std::string extend(const std::string& v, int sc, bool sx) {
   return std::string("(uint64_t)(int64_t)(") + kSTy[sc] + ")(" + v + ")";
 }
 
-// name of the constant descriptor of the map at device address ``desc``
-std::string map_name(const std::vector<std::pair<uint64_t, MapDev>>& maps, uint64_t desc) {
-  for (size_t k = 0; k < maps.size(); k++)
-    if (maps[k].first == desc) return "&M" + std::to_string(k);
-  return "(const MapDev*)" + lit(desc);
+// How the event-parallel kernel accumulates one shared map's atomics.
+struct Acc {
+  int kind = 0;        // 0 none, 1 whole-map mirror in LDS, 2 tagged LDS cache
+  uint32_t op = 0;     // ADD 0x00, OR 0x40, AND 0x50, XOR 0xa0
+  int sc = -1;         // operand width: 2 (u32) or 3 (u64); -1 if the map takes no atomics
+  uint32_t words = 0;  // mirror: words of the value area; cache: slots
+};
+
+// LDS the accumulators of one program may take, beyond stacks and ring slots
+constexpr uint64_t kAccBudget = 48 << 10;
+constexpr uint64_t kLdsMax = 150 << 10;
+
+// Maps of a program as the generated code sees them.
+struct JMaps {
+  const std::vector<std::pair<uint64_t, MapDev>>& m;
+  const std::vector<int>& mem_map;  // map of each map-value access (by slot)
+  std::vector<int> ring;  // ring index per map (-1 if not a ring)
+  int n_rings = 0;
+  std::vector<Acc> acc;   // per map
+  JMaps(const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mm) : m(maps), mem_map(mm) {
+    for (auto& e : maps) ring.push_back(e.second.type == MAP_RINGBUF ? n_rings++ : -1);
+    acc.resize(maps.size());
+  }
+  // plan the LDS accumulators of the shared maps the program updates
+  void plan(const std::vector<Uop>& U, uint64_t lds_used) {
+    for (uint32_t pc = 0; pc < U.size() && pc < mem_map.size(); pc++) {
+      if ((U[pc].w0 & 0xff) != H_ATOMIC_MAP || mem_map[pc] < 0 || mem_map[pc] >= (int)m.size()) continue;
+      const MapDev& d = m[mem_map[pc]].second;
+      if (!(d.flags & F_SHARED) || d.type != MAP_ARRAY) continue;
+      Acc& a = acc[mem_map[pc]];
+      a.op = (uint32_t)U[pc].imm & 0xf0;
+      a.sc = (int)((U[pc].w0 >> 16) & 3);
+    }
+    uint64_t left = std::min<uint64_t>(kAccBudget, kLdsMax > lds_used ? kLdsMax - lds_used : 0);
+    for (size_t k = 0; k < m.size(); k++) {
+      Acc& a = acc[k];
+      if (a.sc < 2) continue;
+      const uint64_t w = a.sc == 3 ? 8 : 4;
+      const uint64_t area = (uint64_t)m[k].second.max_entries * m[k].second.vstride;
+      if (a.sc == 2 || a.sc == 3) {
+        if (area <= left && area <= (32u << 10)) {
+          a.kind = 1;
+          a.words = (uint32_t)(area / w);
+          left -= area;
+        } else {
+          uint64_t slots = 1;
+          while (slots * 2 * (8 + w) <= std::min<uint64_t>(left, 32u << 10)) slots *= 2;
+          if (slots >= 256) {
+            a.kind = 2;
+            a.words = (uint32_t)slots;
+            left -= slots * (8 + w);
+          }
+        }
+      }
+    }
+  }
+  int index(uint64_t desc) const {
+    for (size_t k = 0; k < m.size(); k++)
+      if (m[k].first == desc) return (int)k;
+    return -1;
+  }
+  uint64_t ring_cap(int k) const { return (uint64_t)m[k].second.slot_mask + 1; }
+};
+
+std::string map_name(const JMaps& J, uint64_t desc) {
+  int k = J.index(desc);
+  return k >= 0 ? "&M" + std::to_string(k) : "(const MapDev*)" + lit(desc);
 }
 
-std::string map_const(size_t k, const MapDev& m) {
-  char b[512];
+// the descriptor as a function returning a constant (folds into the code)
+std::string map_fn(size_t k, const MapDev& m) {
+  char b[600];
   std::snprintf(b, sizeof b,
-                "  const MapDev M%zu = {%uu, %uu, %uu, %uu, %uu, %uu, %uu, %uu, (uint8_t*)%s, (uint8_t*)%s, "
-                "(uint64_t*)%s, 0ull};\n",
+                "__device__ __forceinline__ MapDev gx_map%zu() {\n  return MapDev{%uu, %uu, %uu, %uu, %uu, %uu, %uu, "
+                "%uu, (uint8_t*)%s, (uint8_t*)%s, (uint64_t*)%s, 0ull};\n}\n",
                 k, m.type, m.key_size, m.value_size, m.max_entries, m.flags, m.vstride, m.slot_mask, m.sstride,
                 lit((uint64_t)(uintptr_t)m.data).c_str(), lit((uint64_t)(uintptr_t)m.slots).c_str(),
                 lit((uint64_t)(uintptr_t)m.ctrl).c_str());
   return b;
 }
 
-void emit_uop(std::string& o, const Uop& u, uint32_t pc, const std::vector<std::pair<uint64_t, MapDev>>& maps) {
+void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
   const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, s = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
   const bool K = (u.w0 >> 24) & 1;
   const std::string D = reg(d), S = reg(s);
@@ -69,7 +133,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const std::vector<std::
   const bool sxf = (a8 & 4) != 0;
   const std::string off = std::to_string(u.aux);
   const std::string tgt = "goto L" + std::to_string((uint32_t)u.aux) + ";";
-  const std::string M = map_name(maps, u.imm);
+  const std::string M = map_name(J, u.imm);
   auto set = [&](const std::string& e) { o += "  " + D + " = " + e + ";\n"; };
   auto set32 = [&](const std::string& e) { o += "  " + D + " = (uint64_t)(uint32_t)(" + e + ");\n"; };
   auto jmp = [&](const std::string& c) { o += "  if (" + c + ") " + tgt + "\n"; };
@@ -186,10 +250,24 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const std::vector<std::
                              : "atomic_global(ad, " + S + ", " + std::to_string(op) + "u, " + std::to_string(sc) +
                                    ", r0)";
       std::string wb = op == 0xf1 ? "r0 = t;" : (op & 1) ? S + " = t;" : "(void)t;";
-      if (h == H_ATOMIC_STACK)
+      const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+      const Acc* ac = (h == H_ATOMIC_MAP && mk >= 0 && mk < (int)J.acc.size() && J.acc[mk].kind) ? &J.acc[mk] : nullptr;
+      if (h == H_ATOMIC_STACK) {
         o += "  { const uint64_t t = " + call + "; " + wb + " }\n";
-      else
+      } else if (ac) {
+        // shared map: summed in LDS by the event-parallel kernel
+        const std::string T = ac->sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(mk);
+        const std::string ops = std::to_string(ac->op) + "u";
+        const std::string lds =
+            ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(ad - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
+                                std::to_string(ac->sc) + "], (" + T + ")" + S + ", " + ops + ");"
+                          : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(ac->words) +
+                                "u, ad, (" + T + ")" + S + ", " + ops + ");";
+        guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
+                "if (PRIV) { " + lds + " } else { const uint64_t t = " + call + "; " + wb + " }");
+      } else {
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = " + call + "; " + wb);
+      }
       break;
     }
     case H_LDIMM: set(lit(u.imm)); break;
@@ -211,10 +289,17 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const std::vector<std::
       o += "  r0 = (uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch);\n";
       break;
     case H_RET_EINVAL: o += "  r0 = (uint64_t)-22ll;\n"; break;
-    case H_RINGBUF_OUTPUT:
-      o += "  r0 = ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " + std::to_string((uint32_t)u.aux) +
-           "u, r4, true, stk);\n";
+    case H_RINGBUF_OUTPUT: {
+      const int k = J.index(u.imm);
+      if (k >= 0 && J.ring[k] >= 0)
+        o += "  r0 = ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, chunk[" +
+             std::to_string(J.ring[k]) + "], " + std::to_string(a8 & 1) + ", r2, " +
+             std::to_string((uint32_t)u.aux) + "u, r4, stk);\n";
+      else
+        o += "  r0 = ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " + std::to_string((uint32_t)u.aux) +
+             "u, r4, true, stk);\n";
       break;
+    }
     case H_EXIT:
     default: o += "  return (uint32_t)r0;\n"; break;
   }
@@ -225,32 +310,111 @@ bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
 }  // namespace
 
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
-                       const std::vector<std::pair<uint64_t, MapDev>>& maps) {
+                       const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
+                       uint64_t* acc_words) {
+  JMaps J(maps, mem_map);
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
-  const uint32_t lds = stack_bytes ? 64u * stack_bytes : 16u;
+  const uint32_t lds = stack_bytes ? kJitWaves * 64u * stack_bytes : 16u;
+  const int nr = J.n_rings ? J.n_rings : 1;
+  J.plan(U, lds + 16ull * kJitWaves * nr);
+  if (acc_words) {
+    *acc_words = 0;
+    for (const Acc& a : J.acc)
+      if (a.kind) *acc_words += a.words;
+  }
   std::string o;
-  o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n#include \"gx_dev.h\"\n\nnamespace gx {\n\n";
-  o += "struct Prog {\n  static __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, "
-       "uint64_t c1, uint64_t c2, const Stk stk, uint64_t& steps) {\n";
+  o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
+  o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
+  o += "#define GX_RING_SLOTS " + std::to_string(kJitWaves * nr) + "\n";
+  o += "#include \"gx_dev.h\"\n\nnamespace gx {\n\n";
+  for (size_t k = 0; k < maps.size(); k++) o += map_fn(k, maps[k].second);
+  bool any_acc = false;
+  for (size_t k = 0; k < maps.size(); k++) {
+    const Acc& a = J.acc[k];
+    if (!a.kind) continue;
+    any_acc = true;
+    const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k), N = std::to_string(a.words);
+    if (a.kind == 1)
+      o += "__shared__ " + T + " g_acc" + K + "[" + N + "];\n";
+    else
+      o += "__shared__ uint64_t g_tag" + K + "[" + N + "];\n__shared__ " + T + " g_val" + K + "[" + N + "];\n";
+  }
+  // PRIV: the event-parallel kernel sums shared-map atomics in LDS
+  o += "\ntemplate <bool PRIV>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
+       "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave reserves at once, per ring\n\n";
+  // begin / end: open and close the wave's ring chunks and the block's accumulators
+  // a chunk is the ring's capacity over four times the waves of the
+  // launch (64 B to 8 KiB): chunks in flight then hold at most a quarter
+  o += "  __device__ __forceinline__ void begin() {\n";
+  o += "    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64u);\n    (void)waves;\n";
+  for (size_t k = 0; k < maps.size(); k++)
+    if (J.ring[k] >= 0)
+      o += "    chunk[" + std::to_string(J.ring[k]) + "] = ring_chunk_bytes(" + std::to_string(J.ring_cap((int)k)) +
+           "ull, waves);\n";
+  for (int r = 0; r < J.n_rings; r++) o += "    ring_chunk_init(wave * GX_NRINGS + " + std::to_string(r) + "u);\n";
+  if (any_acc) {
+    o += "    if (PRIV) {\n";
+    for (size_t k = 0; k < maps.size(); k++) {
+      const Acc& a = J.acc[k];
+      const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k);
+      if (a.kind == 1)
+        o += "      mirror_init<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
+             "u);\n";
+      else if (a.kind == 2)
+        o += "      cache_init<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
+             std::to_string(a.op) + "u);\n";
+    }
+    o += "      __syncthreads();\n    }\n";
+  }
+  o += "  }\n  __device__ __forceinline__ void end() {\n";
+  for (size_t k = 0; k < maps.size(); k++)
+    if (J.ring[k] >= 0)
+      o += "    { const MapDev M = gx_map" + std::to_string(k) + "(); ring_chunk_close(&M, wave * GX_NRINGS + " +
+           std::to_string(J.ring[k]) + "u); }\n";
+  if (any_acc) {
+    o += "    if (PRIV) {\n      __syncthreads();\n";
+    for (size_t k = 0; k < maps.size(); k++) {
+      const Acc& a = J.acc[k];
+      const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k);
+      if (a.kind == 1)
+        o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
+             "u, gx_map" + K + "().data);\n";
+      else if (a.kind == 2)
+        o += "      cache_flush<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
+             std::to_string(a.op) + "u);\n";
+    }
+    o += "    }\n";
+  }
+  o += "  }\n\n";
+  o += "  __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2, "
+       "const Stk stk, uint64_t& steps) {\n";
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
   o += "  uint64_t r10 = " + std::to_string(stack_bytes) + "ull;\n";
-  for (size_t k = 0; k < maps.size(); k++) o += map_const(k, maps[k].second);
+  for (size_t k = 0; k < maps.size(); k++)
+    o += "  const MapDev M" + std::to_string(k) + " = gx_map" + std::to_string(k) + "();\n";
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
   for (uint32_t pc = 0; pc < U.size(); pc++) {
     if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
-    emit_uop(o, U[pc], pc, maps);
+    emit_uop(o, U[pc], pc, J);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
-  o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_event_parallel(gx::RunArgs A) {\n"
-       "  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n  uint64_t steps = 0;\n"
-       "  gx::event_tile<gx::Prog>(A, (uint64_t)blockIdx.x * 64u, stk, steps);\n}\n\n";
+  const std::string W = std::to_string(kJitWaves), T = std::to_string(64 * kJitWaves);
+  o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
+       "  const uint32_t wave = threadIdx.x >> 6;\n"
+       "  gx::Stk stk{wave * 64u * " + std::to_string(stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
+       "u + threadIdx.x};\n"
+       "  gx::Prog<true> P{wave};\n  P.begin();\n"
+       "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
+       "  P.end();\n}\n\n";
   o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
-       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n  uint64_t steps = 0;\n"
-       "  gx::stream_wave<gx::Prog>(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);\n}\n";
+       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
+       "  gx::Prog<false> P{0u};\n  P.begin();\n  uint64_t steps = 0;\n"
+       "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);\n"
+       "  P.end();\n}\n";
   return o;
 }
 

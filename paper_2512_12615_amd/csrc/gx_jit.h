@@ -10,16 +10,27 @@
 
 namespace gx {
 
+// Waves per block of a compiled program's event-parallel kernel (each block
+// loops over 64-event tiles, grid-stride).
+constexpr uint32_t kJitWaves = 4;
+
 // HIP source of one program: its micro-ops written out as straight-line
 // code with labels at jump targets, helpers called directly with the map
-// descriptors as constants, and the two event-loop kernels
-// (gx_j_event_parallel, gx_j_stream_seq; 64 threads per block, stack frames
-// in a static LDS array).
+// descriptors as constants, and the two event-loop kernels:
+// gx_j_event_parallel (kJitWaves waves per block, grid-stride over 64-event
+// tiles) and gx_j_stream_seq (one wave per block).  Stack frames live in a
+// static LDS array; each wave carves ring records from its own chunk of
+// reserved ring space.
 // ``maps`` holds (descriptor device address, descriptor contents) of every
 // map the program uses; the generated code gets each descriptor as a
 // constant, so key sizes, slot masks and addresses fold into the code.
+// ``mem_map`` is the verifier's map of each map-value access (by slot):
+// the event-parallel kernel sums the atomics of shared maps in LDS.
+// *acc_words receives the LDS accumulator words a block flushes at its end
+// (0: no accumulators), which the launch uses to size its grid.
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
-                       const std::vector<std::pair<uint64_t, MapDev>>& maps);
+                       const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
+                       uint64_t* acc_words = nullptr);
 
 // Compile a generated source for gfx950.  Returns 0 and the code object, or
 // -EIO with the compiler log.

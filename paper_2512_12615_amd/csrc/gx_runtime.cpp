@@ -23,12 +23,12 @@ hipError_t vm_init();
 hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s);
 hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride, hipStream_t s);
 hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
-                            uint32_t* sums, uint32_t* order, hipStream_t s);
+                            uint32_t* sums, uint32_t* order, uint8_t* sorted, hipStream_t s);
 hipError_t launch_map_op(const MapDev* m, int op, const uint8_t* key, const uint8_t* val, uint64_t flags,
                          int64_t* ret, uint8_t* val_out, uint32_t epoch, hipStream_t s);
 hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, uint32_t n_tiles, uint32_t max_lbits,
                                  uint64_t total_counts, uint32_t* counts, uint32_t* sums, uint32_t* order,
-                                 hipStream_t s);
+                                 uint8_t* sorted, hipStream_t s);
 hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
                           uint32_t waves, uint32_t stack_max, hipStream_t s);
 }  // namespace gx
@@ -36,6 +36,10 @@ hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint3
 using namespace gx;
 
 namespace {
+
+// Blocks of a compiled event-parallel launch: enough for every CU to hold
+// several (256 CUs), each looping over tiles beyond that.
+constexpr uint64_t kJitMaxBlocks = 2048;
 
 struct MapObj {
   bool live = false;
@@ -57,6 +61,7 @@ struct ProgObj {
   // compiled form (gx_jit_program): module and its two kernels
   hipModule_t jmod = nullptr;
   hipFunction_t jf_ep = nullptr, jf_seq = nullptr;
+  uint64_t jacc_words = 0;  // LDS accumulator words each block flushes
 };
 
 uint64_t next_pow2(uint64_t x) {
@@ -83,7 +88,8 @@ struct gx_rt {
   uint32_t* d_counts = nullptr;
   uint32_t* d_sums = nullptr;
   uint32_t* d_order = nullptr;
-  size_t counts_cap = 0, sums_cap = 0, order_cap = 0;
+  uint8_t* d_sorted = nullptr;  // records in queue order (kSortedStride apart)
+  size_t counts_cap = 0, sums_cap = 0, order_cap = 0, sorted_cap = 0;
   hipEvent_t ws_event = nullptr;
   bool ws_used = false;
   // batched form: device tables, their pinned staging copy, the work counter
@@ -304,6 +310,8 @@ int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
   if ((r = grow(&rt->d_counts, &rt->counts_cap, counts))) return r;
   if ((r = grow(&rt->d_sums, &rt->sums_cap, sums))) return r;
   if ((r = grow(&rt->d_order, &rt->order_cap, order))) return r;
+  // the queue-ordered records: kSortedStride bytes per event (u32 units)
+  if ((r = grow((uint32_t**)&rt->d_sorted, &rt->sorted_cap, order * (kSortedStride / 4)))) return r;
   return 0;
 }
 
@@ -359,7 +367,8 @@ void gx_close(gx_rt* rt) {
   if (rt->h_stage) (void)hipHostFree(rt->h_stage);
   if (rt->d_tables) (void)hipFree(rt->d_tables);
   if (rt->d_next) (void)hipFree(rt->d_next);
-  for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_err, (void*)rt->d_stage})
+  for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_sorted, (void*)rt->d_err,
+                  (void*)rt->d_stage})
     if (p) (void)hipFree(p);
   if (rt->internal) (void)hipStreamDestroy(rt->internal);
   delete rt;
@@ -610,7 +619,8 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
     if (!m) return -EINVAL;
     maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
   }
-  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps), &code, &lg);
+  uint64_t acc_words = 0;
+  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, &acc_words), &code, &lg);
   write_log(log, log_size, lg);
   if (r) return r;
   DevGuard g(rt->dev);
@@ -625,6 +635,7 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   p->jmod = mod;
   p->jf_ep = fe;
   p->jf_seq = fs;
+  p->jacc_words = acc_words;
   return 0;
 }
 
@@ -652,7 +663,9 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     d.max_entries = shapes[i].max_entries;
     d.flags = shapes[i].flags;
     d.vstride = (d.value_size + 7) & ~7u;
-    d.slot_mask = 15;
+    d.slot_mask = d.type == MAP_RINGBUF ? d.max_entries - 1
+                  : d.type == MAP_HASH  ? (uint32_t)next_pow2(std::max<uint64_t>(2ull * d.max_entries, 16)) - 1
+                                        : 0;
     d.sstride = 8 + ((d.key_size + 7) & ~7u);
     d.data = (uint8_t*)(uintptr_t)(0x200000000ull + (1ull << 28) * i);  // stand-in addresses
     d.slots = d.data + (1ull << 27);
@@ -665,7 +678,7 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
     return -EACCES;
   }
-  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps);
+  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map);
   if (compile) {
     std::vector<char> code;
     std::string lg;
@@ -718,7 +731,15 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
     if (pe.first) (void)hipEventRecord(pe.first, s);
     if (p->jf_ep) {
       void* args[] = {&A};
-      e = hipModuleLaunchKernel(p->jf_ep, (uint32_t)((n_events + 63) / 64), 1, 1, 64, 1, 1, 0, s, args, nullptr);
+      const uint64_t tiles = (n_events + 63) / 64;
+      uint64_t nb = std::min<uint64_t>((tiles + kJitWaves - 1) / kJitWaves, kJitMaxBlocks);
+      // each block flushes its accumulators once: give every block at
+      // least as many events as it flushes words (but keep one block per CU)
+      if (p->jacc_words) nb = std::min(nb, std::max<uint64_t>(256, n_events / p->jacc_words));
+      const int ov = env_int("GX_JIT_BLOCKS", 0);  // tuning override
+      if (ov > 0) nb = std::min<uint64_t>((uint64_t)ov, 65536);
+      const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
+      e = hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * kJitWaves, 1, 1, 0, s, args, nullptr);
     } else {
       e = launch_event_parallel(A, s);
     }
@@ -734,9 +755,10 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
     if (r) return r;
     if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
     A.step_limit = per_event * n_events;
-    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, s);
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
     if (e == hipSuccess) {
       A.order = rt->d_order;
+      A.sorted = rt->d_sorted;
       A.qstart = rt->d_counts;
       A.n_queues = L;
       uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
@@ -862,6 +884,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
       const PartJob& pj = J[bd.A.pad2 - 1];
       bd.A.qstart = rt->d_counts + pj.cbase;
       bd.A.order = rt->d_order;
+      bd.A.sorted = rt->d_sorted;
       bd.A.pad2 = 0;
     }
   // items, largest runs first
@@ -899,7 +922,8 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (!J.empty())
     e = launch_partition_jobs((const PartJob*)(rt->d_tables + oj), (const uint2*)(rt->d_tables + ot),
-                              (uint32_t)tiles.size(), max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order, s);
+                              (uint32_t)tiles.size(), max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order,
+                              rt->d_sorted, s);
   std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
   if (rt->profile) pe = prof_pair(rt);
   if (e == hipSuccess) {
@@ -957,43 +981,54 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   if (!m || m->h.type != MAP_RINGBUF || (!host_buf && buf_bytes)) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  uint64_t ctrl[2];
-  if (hipMemcpy(ctrl, m->h.ctrl, 16, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  uint64_t ctrl[4];
+  if (hipMemcpy(ctrl, m->h.ctrl, 32, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
   uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
+  // a reservation that overflowed ended the committed data at its start
+  const bool cut = ctrl[3] != 0;
+  if (cut && ~ctrl[3] < head) head = ~ctrl[3];
   uint64_t avail = head - tail;
   if (n_records) *n_records = 0;
-  if (avail == 0) return 0;
-  std::vector<uint8_t> buf(avail);
-  uint64_t t0 = tail & (cap - 1);
-  uint64_t first = std::min(avail, cap - t0);
-  if (hipMemcpy(buf.data(), m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
-  if (first < avail && hipMemcpy(buf.data() + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
-    return -EIO;
-  uint64_t pos = 0, nrec = 0;
-  while (pos + 8 <= avail) {
-    uint32_t len;
-    std::memcpy(&len, buf.data() + pos, 4);
-    if (len == 0) break;  // reserved, not yet committed
-    uint64_t need = 8 + ((len + 7ull) & ~7ull);
-    if (pos + need > avail || pos + need > buf_bytes) break;
-    std::memcpy((uint8_t*)host_buf + pos, buf.data() + pos, need);
-    pos += need;
-    nrec++;
+  uint64_t pos = 0, out = 0, nrec = 0;
+  if (avail) {
+    std::vector<uint8_t> buf(avail);
+    uint64_t t0 = tail & (cap - 1);
+    uint64_t first = std::min(avail, cap - t0);
+    if (hipMemcpy(buf.data(), m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+    if (first < avail && hipMemcpy(buf.data() + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
+      return -EIO;
+    while (pos + 8 <= avail) {
+      uint32_t len, flags;
+      std::memcpy(&len, buf.data() + pos, 4);
+      std::memcpy(&flags, buf.data() + pos + 4, 4);
+      if (len == 0 && flags == 0) break;  // reserved, not yet committed
+      uint64_t need = 8 + ((len + 7ull) & ~7ull);
+      if (pos + need > avail) break;
+      if (!(flags & RING_DISCARD)) {
+        if (out + need > buf_bytes) break;
+        std::memcpy((uint8_t*)host_buf + out, buf.data() + pos, need);
+        out += need;
+        nrec++;
+      }
+      pos += need;
+    }
   }
-  if (pos) {
+  if (pos || cut) {
     // clear the consumed bytes so that headers read as uncommitted, then
-    // publish the new tail
+    // publish the new tail (and, after an overflow, the cut-back head)
+    uint64_t t0 = tail & (cap - 1);
     uint64_t c0 = std::min(pos, cap - t0);
-    bool ok = hipMemset(m->h.data + t0, 0, c0) == hipSuccess &&
+    bool ok = (pos == 0 || hipMemset(m->h.data + t0, 0, c0) == hipSuccess) &&
               (c0 == pos || hipMemset(m->h.data, 0, pos - c0) == hipSuccess);
-    uint64_t nt = tail + pos;
-    ok = ok && hipMemcpy(m->h.ctrl + 1, &nt, 8, hipMemcpyHostToDevice) == hipSuccess &&
+    uint64_t nc[4] = {head, tail + pos, ctrl[2], 0};
+    ok = ok && (cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
+                    : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess) &&
          hipDeviceSynchronize() == hipSuccess;
     if (!ok) return -EIO;
   }
-  rt->stats.bytes_drained += pos;
+  rt->stats.bytes_drained += out;
   if (n_records) *n_records = nrec;
-  return (int64_t)pos;
+  return (int64_t)out;
 }
 
 int gx_profile_enable(gx_rt* rt, int on) {

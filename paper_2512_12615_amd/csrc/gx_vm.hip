@@ -289,8 +289,8 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
 }
 
 struct Interp {
-  static __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2,
-                                                 const Stk stk, uint64_t& steps) {
+  __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2,
+                                          const Stk stk, uint64_t& steps) {
     return vm_run(A, live, c0, c1, c2, stk, steps);
   }
 };
@@ -300,14 +300,16 @@ extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A)
   const uint32_t wave = threadIdx.x >> 6;
   Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   uint64_t steps = 0;
-  event_tile<Interp>(A, (uint64_t)blockIdx.x * blockDim.x + wave * 64u, stk, steps);
+  Interp I;
+  event_tile(I, A, (uint64_t)blockIdx.x * blockDim.x + wave * 64u, stk, steps);
 }
 
 // Stream-sequential mode: ``lanes`` lanes of each one-wave block own queues.
 extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
   Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   uint64_t steps = 0;
-  stream_wave<Interp>(A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);
+  Interp I;
+  stream_wave(I, A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +323,7 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_batched(const BatchDev* B,
   typedef const __attribute__((address_space(4))) uint64_t cu64;
   static_assert(sizeof(BatchDev) % 8 == 0, "BatchDev is loaded as 8-byte words");
   Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
+  Interp I;
   uint64_t steps = 0;
   for (;;) {
     uint32_t it = 0;
@@ -340,9 +343,9 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_batched(const BatchDev* B,
     const RunArgs& A = bdv.A;
     steps = 0;
     if (bd->mode == 0)
-      event_tile<Interp>(A, (uint64_t)chunk * 64u, stk, steps);
+      event_tile(I, A, (uint64_t)chunk * 64u, stk, steps);
     else
-      stream_wave<Interp>(A, chunk * bd->lanes, bd->lanes, bd->qstride, bd->qend_last, stk, steps);
+      stream_wave(I, A, chunk * bd->lanes, bd->lanes, bd->qstride, bd->qend_last, stk, steps);
   }
 }
 
@@ -369,7 +372,8 @@ __device__ __forceinline__ void part_count(const PartJob& J, uint32_t t, uint32_
   for (uint32_t q = l; q < L; q += 64) counts[J.cbase + (uint64_t)q * J.nt + t] = cnt[q];
 }
 
-__device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const uint32_t* offs, uint32_t* order) {
+__device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const uint32_t* offs, uint32_t* order,
+                                             uint8_t* sorted) {
   uint32_t* base = (uint32_t*)g_lds;
   const uint32_t L = 1u << J.lbits, l = lane_id();
   for (uint32_t q = l; q < L; q += 64) base[q] = offs[J.cbase + (uint64_t)q * J.nt + t];
@@ -392,6 +396,12 @@ __device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const
     if (v) {
       order[pos] = (uint32_t)i;
       if (rank == 0) base[key] = pos + popc64(peers);
+      // the record itself, so that each queue's records lie together
+      const uint64_t* src = (const uint64_t*)(J.events + i * J.record_size);
+      uint64_t* dst = (uint64_t*)(sorted + (uint64_t)pos * kSortedStride);
+      dst[0] = src[0];
+      dst[1] = src[1];
+      if (J.record_size > 16) dst[2] = src[2];
     }
   }
 }
@@ -405,10 +415,11 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_part_count(const PartJob* 
 }
 
 extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter(const PartJob* jobs, const uint2* tiles,
-                                                                   const uint32_t* offs, uint32_t* order) {
+                                                                   const uint32_t* offs, uint32_t* order,
+                                                                   uint8_t* sorted) {
   const uint2 jt = tiles[blockIdx.x];
   const PartJob J = jobs[jt.x];
-  part_scatter(J, jt.y, offs, order);
+  part_scatter(J, jt.y, offs, order, sorted);
 }
 
 // Single-run forms take the job by value.
@@ -416,8 +427,9 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_part_count1(PartJob J, uin
   part_count(J, blockIdx.x, counts);
 }
 
-extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter1(PartJob J, const uint32_t* offs, uint32_t* order) {
-  part_scatter(J, blockIdx.x, offs, order);
+extern "C" __global__ void __launch_bounds__(64) gx_k_part_scatter1(PartJob J, const uint32_t* offs, uint32_t* order,
+                                                                    uint8_t* sorted) {
+  part_scatter(J, blockIdx.x, offs, order, sorted);
 }
 
 // exclusive scan of u32 data[0..n): block sums, then the sums, then add back
@@ -561,13 +573,13 @@ hipError_t launch_scan(uint32_t* data, uint64_t m, uint32_t* sums, hipStream_t s
 // Stable partition of one run's event indices into 2^lbits queues.  counts
 // must hold 2^lbits * nt entries, sums ceil(2^lbits * nt / 4096), order n.
 hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
-                            uint32_t* sums, uint32_t* order, hipStream_t s) {
+                            uint32_t* sums, uint32_t* order, uint8_t* sorted, hipStream_t s) {
   uint32_t L = 1u << lbits;
   PartJob J{A.events, A.n_events, A.record_size, A.stream_off, lbits, tile, nt, 0, 0};
   hipLaunchKernelGGL(gx_k_part_count1, dim3(nt), dim3(64), L * 4, s, J, counts);
   hipError_t e = launch_scan(counts, (uint64_t)L * nt, sums, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gx_k_part_scatter1, dim3(nt), dim3(64), L * 4, s, J, (const uint32_t*)counts, order);
+  hipLaunchKernelGGL(gx_k_part_scatter1, dim3(nt), dim3(64), L * 4, s, J, (const uint32_t*)counts, order, sorted);
   return hipGetLastError();
 }
 
@@ -576,14 +588,14 @@ hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uin
 // order array in which run j's events occupy a contiguous range.
 hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, uint32_t n_tiles, uint32_t max_lbits,
                                  uint64_t total_counts, uint32_t* counts, uint32_t* sums, uint32_t* order,
-                                 hipStream_t s) {
+                                 uint8_t* sorted, hipStream_t s) {
   if (n_tiles == 0) return hipSuccess;
   uint32_t L = 1u << max_lbits;
   hipLaunchKernelGGL(gx_k_part_count, dim3(n_tiles), dim3(64), L * 4, s, d_jobs, d_tiles, counts);
   hipError_t e = launch_scan(counts, total_counts, sums, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gx_k_part_scatter, dim3(n_tiles), dim3(64), L * 4, s, d_jobs, d_tiles,
-                     (const uint32_t*)counts, order);
+                     (const uint32_t*)counts, order, sorted);
   return hipGetLastError();
 }
 

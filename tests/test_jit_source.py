@@ -36,7 +36,7 @@ def test_source_structure(G):
     pol = W.stride_prefetch_policy()
     src = G.jit_source(pol.code, pol.hook, _shapes(pol))
     assert src.count("hash_lookup(") == 1 and src.count("hash_update(") == 1
-    assert src.count("ring_output(") == 1
+    assert src.count("ring_output_chunked(") == 1
     labels = set(re.findall(r"^L(\d+):;", src, re.M))
     gotos = set(re.findall(r"goto L(\d+);", src))
     assert labels == gotos
@@ -47,3 +47,32 @@ def test_rejected_program_reports_reason(G):
     with pytest.raises(G.GxError) as e:
         G.jit_source(code, W.HOOK_MEM_ACCESS, [])
     assert e.value.errno == 13
+
+
+BIG_STACK_SHARED = """
+    ldxdw r6, [r1+0]
+    stdw [r10-512], 0
+    stxdw [r10-8], r6
+    mov64 r1, r6
+    and64 r1, 4095
+    stxw [r10-16], r1
+    lddw r1, map:sh
+    mov64 r2, r10
+    add64 r2, -16
+    call map_lookup_elem
+    jeq r0, 0, out
+    mov64 r1, 1
+    aadd64 [r0+0], r1
+out:
+    ldxdw r0, [r10-512]
+    exit
+"""
+
+
+@pytest.mark.parametrize("entries", [4096, 1 << 16])
+def test_largest_frame_with_accumulators_compiles(G, entries):
+    """A 512-byte frame (the largest) plus a shared map's LDS accumulator
+    (whole-map mirror or tagged cache) stays within the LDS of a block."""
+    pol = W.Policy("big", W.HOOK_MEM_ACCESS, BIG_STACK_SHARED, [W.MapSpec("sh", W.MAP_ARRAY, 4, 8, entries, W.F_SHARED)])
+    src = G.jit_source(pol.code, pol.hook, _shapes(pol), compile=True)
+    assert "g_acc0" in src or "g_tag0" in src or "if (PRIV)" not in src
