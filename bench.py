@@ -33,6 +33,42 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_fingerprint(G, pol, engine):
+    """sha256 of what decides the timed kernel's code: the generated source
+    of the compiled program (or the interpreter source) and the device
+    headers.  A traffic figure measured for another fingerprint is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2512_12615_amd", "csrc")
+    if engine == "jit":
+        shapes = [(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+        h.update(G.jit_source(pol.code, pol.hook, shapes).encode())
+    else:
+        with open(os.path.join(csrc, "gx_vm.hip"), "rb") as f:
+            h.update(f.read())
+    for name in ("gx_dev.h", "gx_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(fingerprint):
+    """HBM bytes per launch from a committed counter summary
+    (profiles/*traffic*.md: lines 'kernel_sha256: ...' and
+    'traffic_bytes_per_launch: ...'), if it was taken for this kernel."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip().strip("`* ")] = v.strip().strip("`* ")
+        if kv.get("kernel_sha256") == fingerprint and "traffic_bytes_per_launch" in kv:
+            return float(kv["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
+
+
 def cpu_baseline(pol, ev, streams_in_sample):
     """The oracle, single-threaded, on the events of a subset of streams (a
     valid sub-run: streams are independent)."""
@@ -359,6 +395,8 @@ def main():
         cpu = cpu_baseline(pol, host_batches[0], args.cpu_streams)
         insns_per_event = cpu["insns_per_event"]
 
+    fp = kernel_fingerprint(G, pol, args.engine)
+    traffic, traffic_src = measured_traffic(fp)
     vm_avg_s = vm_ms / 1000 / max(vm_launches, 1)
     ring_per_launch = ring_bytes[0] / args.steps
     alg_bytes = n * (24 + 4) + ring_per_launch
@@ -396,7 +434,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
+            "kernel_sha256": fp,
             "kernel": "gx_j_stream_seq" if args.engine == "jit" else "gx_k_stream_seq",
             "bytes_per_event": "24 B record + 4 B rc + ring bytes",
         },
