@@ -122,7 +122,7 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
                 rt.map_update(fds[mi], key, val)
         rt.run_batch(prog, batches[b], n_events=n, record_size=pol.record_size, rc=rc, stream=stream)
         if ring_fd is not None:
-            buf, _ = rt.drain_ringbuf(fds[ring_fd])
+            buf, _ = rt.drain_ringbuf(fds[ring_fd], copy=False)
             ring[0] += len(buf)
 
     for k in range(2):
@@ -352,7 +352,7 @@ def main():
 
     def step(k):
         rt.run_batch(prog, dev_batches[k % len(dev_batches)], n_events=n, record_size=24, rc=rc, stream=stream)
-        buf, nrec = rt.drain_ringbuf(ring_fd)
+        buf, nrec = rt.drain_ringbuf(ring_fd, copy=False)
         ring_bytes[0] += len(buf)
 
     log("warmup")

@@ -411,9 +411,9 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
        "  P.end();\n}\n\n";
   o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
-       "uint32_t qstride) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
+       "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
        "  gx::Prog<false> P{0u};\n  P.begin();\n  uint64_t steps = 0;\n"
-       "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, (uint32_t)A.n_events, stk, steps);\n"
+       "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, qend_last, stk, steps);\n"
        "  P.end();\n}\n";
   return o;
 }

@@ -46,6 +46,8 @@ struct MapObj {
   MapDev h{};              // host copy of the descriptor
   MapDev* d_desc = nullptr;
   size_t data_bytes = 0, slot_bytes = 0;
+  uint8_t* h_pin = nullptr;  // ring: pinned staging for drains
+  size_t pin_cap = 0;
 };
 
 struct ProgObj {
@@ -80,6 +82,19 @@ int env_int(const char* name, int dflt) {
 struct gx_rt {
   int dev = 0;
   hipStream_t internal = nullptr;
+  // batched form: compiled runs of a phase run side by side on these
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
+  // staging of batched tables: a ring of slots, so a phase never waits for
+  // the previous phase's table copy
+  static constexpr int kStage = 4;
+  uint8_t* h_stage_ring[kStage] = {};
+  uint8_t* d_tables_ring[kStage] = {};
+  size_t stage_ring_cap[kStage] = {};
+  hipEvent_t stage_ring_ev[kStage] = {};
+  bool stage_ring_used[kStage] = {};
+  uint32_t stage_next = 0;
   std::vector<MapObj> maps;
   std::vector<ProgObj> progs;
   uint64_t* d_err = nullptr;
@@ -93,12 +108,6 @@ struct gx_rt {
   hipEvent_t ws_event = nullptr;
   bool ws_used = false;
   // batched form: device tables, their pinned staging copy, the work counter
-  uint8_t* d_tables = nullptr;
-  size_t tables_cap = 0;
-  uint8_t* h_stage = nullptr;
-  size_t stage_cap = 0;
-  hipEvent_t stage_event = nullptr;
-  bool stage_used = false;
   uint32_t* d_next = nullptr;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
@@ -152,6 +161,7 @@ void free_map(MapObj& m) {
   if (m.h.slots) (void)hipFree(m.h.slots);
   if (m.h.ctrl) (void)hipFree(m.h.ctrl);
   if (m.d_desc) (void)hipFree(m.d_desc);
+  if (m.h_pin) (void)hipHostFree(m.h_pin);
   m = MapObj{};
 }
 
@@ -315,6 +325,28 @@ int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
   return 0;
 }
 
+// Launch a program's compiled kernel over one run.  mode 0: event-parallel;
+// mode 1: stream-sequential over queues [0, A.n_queues) of ``lanes`` per
+// wave, counts with row stride ``qstride``, the run's last queue ending at
+// ``qend_last`` in order[].
+hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes, uint32_t qstride,
+                      uint32_t qend_last, hipStream_t s) {
+  if (mode == 0) {
+    void* args[] = {&A};
+    const uint64_t tiles = (A.n_events + 63) / 64;
+    uint64_t nb = std::min<uint64_t>((tiles + kJitWaves - 1) / kJitWaves, kJitMaxBlocks);
+    // each block flushes its accumulators once: give every block at least
+    // as many events as it flushes words (but keep one block per CU)
+    if (p->jacc_words) nb = std::min(nb, std::max<uint64_t>(256, A.n_events / p->jacc_words));
+    const int ov = env_int("GX_JIT_BLOCKS", 0);  // tuning override
+    if (ov > 0) nb = std::min<uint64_t>((uint64_t)ov, 65536);
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
+    return hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * kJitWaves, 1, 1, 0, s, args, nullptr);
+  }
+  void* args[] = {&A, &lanes, &qstride, &qend_last};
+  return hipModuleLaunchKernel(p->jf_seq, (A.n_queues + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -334,11 +366,22 @@ int gx_open(int hip_device, gx_rt** out) {
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
       hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&rt->stage_event, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc((void**)&rt->d_next, 64) != hipSuccess || vm_init() != hipSuccess) {
+      hipMalloc((void**)&rt->d_next, 64) != hipSuccess || vm_init() != hipSuccess ||
+      hipEventCreateWithFlags(&rt->fork_ev, hipEventDisableTiming) != hipSuccess) {
     gx_close(rt);
     return -ENOMEM;
   }
+  for (int i = 0; i < gx_rt::kSide; i++)
+    if (hipStreamCreateWithFlags(&rt->side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&rt->join_ev[i], hipEventDisableTiming) != hipSuccess) {
+      gx_close(rt);
+      return -ENOMEM;
+    }
+  for (int i = 0; i < gx_rt::kStage; i++)
+    if (hipEventCreateWithFlags(&rt->stage_ring_ev[i], hipEventDisableTiming) != hipSuccess) {
+      gx_close(rt);
+      return -ENOMEM;
+    }
   (void)hipMemset(rt->d_err, 0, 64);
   (void)hipDeviceSynchronize();
   *out = rt;
@@ -362,10 +405,17 @@ void gx_close(gx_rt* rt) {
       (void)hipEventDestroy(pe.first);
       (void)hipEventDestroy(pe.second);
     }
+  for (int i = 0; i < gx_rt::kSide; i++) {
+    if (rt->side[i]) (void)hipStreamDestroy(rt->side[i]);
+    if (rt->join_ev[i]) (void)hipEventDestroy(rt->join_ev[i]);
+  }
+  if (rt->fork_ev) (void)hipEventDestroy(rt->fork_ev);
+  for (int i = 0; i < gx_rt::kStage; i++) {
+    if (rt->h_stage_ring[i]) (void)hipHostFree(rt->h_stage_ring[i]);
+    if (rt->d_tables_ring[i]) (void)hipFree(rt->d_tables_ring[i]);
+    if (rt->stage_ring_ev[i]) (void)hipEventDestroy(rt->stage_ring_ev[i]);
+  }
   if (rt->ws_event) (void)hipEventDestroy(rt->ws_event);
-  if (rt->stage_event) (void)hipEventDestroy(rt->stage_event);
-  if (rt->h_stage) (void)hipHostFree(rt->h_stage);
-  if (rt->d_tables) (void)hipFree(rt->d_tables);
   if (rt->d_next) (void)hipFree(rt->d_next);
   for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_sorted, (void*)rt->d_err,
                   (void*)rt->d_stage})
@@ -730,16 +780,7 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
     A.step_limit = per_event;
     if (pe.first) (void)hipEventRecord(pe.first, s);
     if (p->jf_ep) {
-      void* args[] = {&A};
-      const uint64_t tiles = (n_events + 63) / 64;
-      uint64_t nb = std::min<uint64_t>((tiles + kJitWaves - 1) / kJitWaves, kJitMaxBlocks);
-      // each block flushes its accumulators once: give every block at
-      // least as many events as it flushes words (but keep one block per CU)
-      if (p->jacc_words) nb = std::min(nb, std::max<uint64_t>(256, n_events / p->jacc_words));
-      const int ov = env_int("GX_JIT_BLOCKS", 0);  // tuning override
-      if (ov > 0) nb = std::min<uint64_t>((uint64_t)ov, 65536);
-      const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
-      e = hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * kJitWaves, 1, 1, 0, s, args, nullptr);
+      e = launch_jit(p, A, 0, 0, 0, 0, s);
     } else {
       e = launch_event_parallel(A, s);
     }
@@ -764,9 +805,7 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
       uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
       if (pe.first) (void)hipEventRecord(pe.first, s);
       if (p->jf_seq) {
-        uint32_t qstride = nt;
-        void* args[] = {&A, &lanes, &qstride};
-        e = hipModuleLaunchKernel(p->jf_seq, (L + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+        e = launch_jit(p, A, 1, lanes, nt, (uint32_t)n_events, s);
       } else {
         e = launch_stream_seq(A, lanes, nt, s);
       }
@@ -813,25 +852,17 @@ bool shares_map(ProgObj* a, ProgObj* b, const std::vector<MapObj>& maps) {
   return false;
 }
 
-int ensure_dev(uint8_t** p, size_t* cap, size_t need) {
-  if (*cap >= need) return 0;
-  if (*p) (void)hipFree(*p);
-  *p = nullptr;
-  *cap = 0;
-  size_t n = std::max<size_t>(need, 1 << 16);
-  if (hipMalloc((void**)p, n) != hipSuccess) return -ENOMEM;
-  *cap = n;
-  return 0;
-}
-
-// One persistent launch (after one combined partition) for runs that share
-// no map, so running them concurrently gives the result of running them in
-// order.
+// One phase: runs that share no map, so running them concurrently gives the
+// result of running them in order.  One combined partition of the
+// stream-sequential runs, then one persistent interpreter launch over the
+// runs of interpreted programs and, side by side with it, one launch per
+// run of a compiled program.
 int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   std::vector<BatchDev> B;
   std::vector<PartJob> J;
   std::vector<uint2> tiles, items;
   std::vector<std::pair<uint64_t, uint32_t>> order_by_cost;  // (cost, batch)
+  std::vector<const ProgObj*> bprog;  // program of each run
   uint64_t counts_total = 0, order_total = 0;
   uint32_t stack_max = 0, max_lbits = 0;
   uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
@@ -873,6 +904,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     uint64_t cost = (uint64_t)(p->v.max_insns + 1) * (p->v.event_parallel ? 64 : (d[i].n_events / 64 + 1));
     order_by_cost.push_back({cost, (uint32_t)B.size()});
     B.push_back(bd);
+    bprog.push_back(p);
     (void)nchunks;
   }
   if (B.empty()) return 0;
@@ -892,8 +924,15 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
                    [](const std::pair<uint64_t, uint32_t>& a, const std::pair<uint64_t, uint32_t>& b) {
                      return a.first > b.first;
                    });
+  // runs of compiled programs get their own kernels (below); the rest are
+  // work items of the persistent interpreter
+  std::vector<uint32_t> jit_runs;
   for (auto& oc : order_by_cost) {
     const BatchDev& bd = B[oc.second];
+    if (bprog[oc.second]->jmod) {
+      jit_runs.push_back(oc.second);
+      continue;
+    }
     uint32_t nchunks = bd.mode == 0 ? (uint32_t)((bd.A.n_events + 63) / 64) : (bd.A.n_queues + bd.lanes - 1) / bd.lanes;
     for (uint32_t c = 0; c < nchunks; c++) items.push_back(make_uint2(oc.second, c));
   }
@@ -901,44 +940,68 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   auto al = [](size_t x) { return (x + 63) & ~(size_t)63; };
   size_t ob = 0, oi = al(ob + B.size() * sizeof(BatchDev)), oj = al(oi + items.size() * sizeof(uint2)),
          ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
-  if (rt->stage_used && hipEventSynchronize(rt->stage_event) != hipSuccess) return -EIO;
-  if (rt->stage_cap < total) {
-    if (rt->h_stage) (void)hipHostFree(rt->h_stage);
-    rt->h_stage = nullptr;
-    rt->stage_cap = 0;
+  // a staging slot whose previous copy has long completed
+  const uint32_t k = rt->stage_next++ % gx_rt::kStage;
+  if (rt->stage_ring_used[k] && hipEventSynchronize(rt->stage_ring_ev[k]) != hipSuccess) return -EIO;
+  if (rt->stage_ring_cap[k] < total) {
+    if (rt->h_stage_ring[k]) (void)hipHostFree(rt->h_stage_ring[k]);
+    if (rt->d_tables_ring[k]) (void)hipFree(rt->d_tables_ring[k]);
+    rt->h_stage_ring[k] = nullptr;
+    rt->d_tables_ring[k] = nullptr;
+    rt->stage_ring_cap[k] = 0;
     size_t cap = std::max<size_t>(total, 1 << 16);
-    if (hipHostMalloc((void**)&rt->h_stage, cap, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
-    rt->stage_cap = cap;
+    if (hipHostMalloc((void**)&rt->h_stage_ring[k], cap, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+    if (hipMalloc((void**)&rt->d_tables_ring[k], cap) != hipSuccess) return -ENOMEM;
+    rt->stage_ring_cap[k] = cap;
   }
+  uint8_t* h_stage = rt->h_stage_ring[k];
+  uint8_t* d_tables = rt->d_tables_ring[k];
   if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
-  if ((r = ensure_dev(&rt->d_tables, &rt->tables_cap, total))) return r;
-  std::memcpy(rt->h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
-  std::memcpy(rt->h_stage + oi, items.data(), items.size() * sizeof(uint2));
-  if (!J.empty()) std::memcpy(rt->h_stage + oj, J.data(), J.size() * sizeof(PartJob));
-  if (!tiles.empty()) std::memcpy(rt->h_stage + ot, tiles.data(), tiles.size() * sizeof(uint2));
-  if (hipMemcpyAsync(rt->d_tables, rt->h_stage, total, hipMemcpyHostToDevice, s) != hipSuccess) return -EIO;
-  (void)hipEventRecord(rt->stage_event, s);
-  rt->stage_used = true;
+  std::memcpy(h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
+  std::memcpy(h_stage + oi, items.data(), items.size() * sizeof(uint2));
+  if (!J.empty()) std::memcpy(h_stage + oj, J.data(), J.size() * sizeof(PartJob));
+  if (!tiles.empty()) std::memcpy(h_stage + ot, tiles.data(), tiles.size() * sizeof(uint2));
+  if (hipMemcpyAsync(d_tables, h_stage, total, hipMemcpyHostToDevice, s) != hipSuccess) return -EIO;
+  (void)hipEventRecord(rt->stage_ring_ev[k], s);
+  rt->stage_ring_used[k] = true;
   hipError_t e = hipSuccess;
   if (!J.empty())
-    e = launch_partition_jobs((const PartJob*)(rt->d_tables + oj), (const uint2*)(rt->d_tables + ot),
-                              (uint32_t)tiles.size(), max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order,
-                              rt->d_sorted, s);
+    e = launch_partition_jobs((const PartJob*)(d_tables + oj), (const uint2*)(d_tables + ot), (uint32_t)tiles.size(),
+                              max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
   std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
   if (rt->profile) pe = prof_pair(rt);
-  if (e == hipSuccess) {
+  if (pe.first) (void)hipEventRecord(pe.first, s);
+  // compiled runs: their own kernels, side by side on the side streams,
+  // after the partition; joined back into s
+  int used_side = 0;
+  if (e == hipSuccess && !jit_runs.empty()) {
+    (void)hipEventRecord(rt->fork_ev, s);
+    for (size_t x = 0; x < jit_runs.size() && e == hipSuccess; x++) {
+      const uint32_t b = jit_runs[x];
+      hipStream_t ss = rt->side[x % gx_rt::kSide];
+      if ((int)x < gx_rt::kSide) {
+        (void)hipStreamWaitEvent(ss, rt->fork_ev, 0);
+        used_side++;
+      }
+      e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, ss);
+    }
+  }
+  if (e == hipSuccess && !items.empty()) {
     uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
     uint32_t waves = (uint32_t)std::min<size_t>(items.size(), 256 * per_cu);
-    if (pe.first) (void)hipEventRecord(pe.first, s);
-    e = launch_batched((const BatchDev*)(rt->d_tables + ob), (const uint2*)(rt->d_tables + oi), (uint32_t)items.size(),
+    e = launch_batched((const BatchDev*)(d_tables + ob), (const uint2*)(d_tables + oi), (uint32_t)items.size(),
                        rt->d_next, waves, stack_max, s);
-    if (pe.second) (void)hipEventRecord(pe.second, s);
   }
+  for (int x = 0; x < used_side; x++) {
+    (void)hipEventRecord(rt->join_ev[x], rt->side[x]);
+    (void)hipStreamWaitEvent(s, rt->join_ev[x], 0);
+  }
+  if (pe.second) (void)hipEventRecord(pe.second, s);
   if (pe.first) rt->prof_pending.push_back(pe);
   (void)hipEventRecord(rt->ws_event, s);
   rt->ws_used = true;
   if (e != hipSuccess) return to_errno(e);
-  rt->stats.launches += J.empty() ? 2 : 7;
+  rt->stats.launches += (J.empty() ? 0 : 5) + (items.empty() ? 0 : 2) + jit_runs.size();
   for (auto& bd : B) rt->stats.events += bd.A.n_events;
   note_stream(rt, s);
   return 0;
@@ -987,26 +1050,36 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   // a reservation that overflowed ended the committed data at its start
   const bool cut = ctrl[3] != 0;
   if (cut && ~ctrl[3] < head) head = ~ctrl[3];
-  uint64_t avail = head - tail;
   if (n_records) *n_records = 0;
+  // Every byte of [tail, head) has been written: reservations are
+  // contiguous and every one is filled (records, or a discard record over a
+  // chunk's unused rest) before its launch ends, and no launch is running.
+  const uint64_t avail = head - tail;
   uint64_t pos = 0, out = 0, nrec = 0;
   if (avail) {
-    std::vector<uint8_t> buf(avail);
-    uint64_t t0 = tail & (cap - 1);
-    uint64_t first = std::min(avail, cap - t0);
-    if (hipMemcpy(buf.data(), m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
-    if (first < avail && hipMemcpy(buf.data() + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
+    if (m->pin_cap < avail) {
+      if (m->h_pin) (void)hipHostFree(m->h_pin);
+      m->h_pin = nullptr;
+      m->pin_cap = 0;
+      if (hipHostMalloc((void**)&m->h_pin, avail, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+      m->pin_cap = avail;
+    }
+    uint8_t* buf = m->h_pin;
+    const uint64_t t0 = tail & (cap - 1);
+    const uint64_t first = std::min(avail, cap - t0);
+    if (hipMemcpy(buf, m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+    if (first < avail && hipMemcpy(buf + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
       return -EIO;
     while (pos + 8 <= avail) {
       uint32_t len, flags;
-      std::memcpy(&len, buf.data() + pos, 4);
-      std::memcpy(&flags, buf.data() + pos + 4, 4);
-      if (len == 0 && flags == 0) break;  // reserved, not yet committed
-      uint64_t need = 8 + ((len + 7ull) & ~7ull);
+      std::memcpy(&len, buf + pos, 4);
+      std::memcpy(&flags, buf + pos + 4, 4);
+      if (len == 0 && flags == 0) break;  // not written (cannot happen after a completed launch)
+      const uint64_t need = 8 + ((len + 7ull) & ~7ull);
       if (pos + need > avail) break;
       if (!(flags & RING_DISCARD)) {
         if (out + need > buf_bytes) break;
-        std::memcpy((uint8_t*)host_buf + out, buf.data() + pos, need);
+        std::memcpy((uint8_t*)host_buf + out, buf + pos, need);
         out += need;
         nrec++;
       }
@@ -1014,16 +1087,10 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
     }
   }
   if (pos || cut) {
-    // clear the consumed bytes so that headers read as uncommitted, then
     // publish the new tail (and, after an overflow, the cut-back head)
-    uint64_t t0 = tail & (cap - 1);
-    uint64_t c0 = std::min(pos, cap - t0);
-    bool ok = (pos == 0 || hipMemset(m->h.data + t0, 0, c0) == hipSuccess) &&
-              (c0 == pos || hipMemset(m->h.data, 0, pos - c0) == hipSuccess);
     uint64_t nc[4] = {head, tail + pos, ctrl[2], 0};
-    ok = ok && (cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
-                    : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess) &&
-         hipDeviceSynchronize() == hipSuccess;
+    const bool ok = cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
+                        : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return -EIO;
   }
   rt->stats.bytes_drained += out;

@@ -184,6 +184,7 @@ class Runtime:
         self._h = C.c_void_p()
         _check(lib().gx_open(device, C.byref(self._h)), "gx_open")
         self.maps: dict[int, MapInfo] = {}
+        self._drain_bufs: dict[int, np.ndarray] = {}
         self.device = device
 
     def close(self):
@@ -279,15 +280,20 @@ class Runtime:
         _check(lib().gx_run_batches(self._h, arr, len(descs), _stream_handle(stream)), "gx_run_batches")
 
     # ring buffers -----------------------------------------------------------
-    def drain_ringbuf(self, fd, cap=None):
-        """Returns (bytes, n_records) of committed records."""
+    def drain_ringbuf(self, fd, cap=None, copy=True):
+        """Returns (records, n_records): the committed records as bytes, or
+        (copy=False) as a view of a buffer the next drain of this ring
+        reuses."""
         if cap is None:
             cap = self.maps[fd].max_entries
-        buf = np.zeros(max(cap, 8), np.uint8)
+        buf = self._drain_bufs.get(fd)
+        if buf is None or len(buf) < max(cap, 8):
+            buf = np.empty(max(cap, 8), np.uint8)
+            self._drain_bufs[fd] = buf
         n = C.c_uint64(0)
         nb = _check(lib().gx_drain_ringbuf(self._h, fd, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
                     "gx_drain_ringbuf")
-        return buf[:nb].tobytes(), n.value
+        return (buf[:nb].tobytes() if copy else buf[:nb]), n.value
 
     def profile_enable(self, on=True):
         _check(lib().gx_profile_enable(self._h, int(on)), "gx_profile_enable")

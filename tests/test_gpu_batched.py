@@ -68,3 +68,33 @@ def test_batched_same_program_twice_runs_in_order(rt):
     o = oracle_run(pol, both)
     g = collect(rt, pol, fds, np.concatenate([rc1.cpu().numpy(), rc2.cpu().numpy()]).view(np.uint32))
     assert_same(g, o, "two phases")
+
+
+def test_batched_mixed_compiled_and_interpreted(rt):
+    """Compiled programs in a batch run as their own kernels beside the
+    persistent interpreter (after the shared partition); every run still
+    matches the oracle."""
+    import torch
+    print("batched mixed compiled/interpreted", flush=True)
+    runs = _mixed_runs(6, 2024)
+    descs, keep = [], []
+    for j, (pol, ev, init) in enumerate(runs):
+        fds, prog = setup(rt, pol, init, jit=(j % 2 == 1) or j >= 6)
+        dev = to_device(ev)
+        rc = torch.zeros(max(len(ev), 1), dtype=torch.int32, device="cuda")
+        descs.append((prog, dev, len(ev), pol.record_size, rc))
+        keep.append((pol, ev, init, fds, rc))
+    want = [oracle_run(pol, ev, init) for pol, ev, init, _, _ in keep]
+    for rep in range(2):  # the second batch reuses the staging ring and side streams
+        rt.run_batches(descs)
+        torch.cuda.synchronize()
+        for i, (pol, ev, init, fds, rc) in enumerate(keep):
+            g = collect(rt, pol, fds, rc[:len(ev)].cpu().numpy().view(np.uint32))
+            assert_same(g, want[i], f"rep {rep} run {i} ({pol.name})")
+        if rep == 0:
+            for pol, ev, init, fds, rc in keep:
+                for fd, m in zip(fds, pol.maps):
+                    rt.map_clear(fd)
+                for mi, k, v in init or []:
+                    assert rt.map_update(fds[mi], k, v) == 0
+    assert rt.stats()["vm_errors"] == 0
