@@ -101,7 +101,8 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None, jit=True):
+def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None, jit=True,
+                         tuned=True):
     """Back-to-back plain launches of an event-parallel policy over rotated
     resident batches; events/s from the wall clock, HBM fraction from the VM
     kernel's own time (record + rc + ring bytes per event)."""
@@ -113,6 +114,11 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     n = batches[0].numel() // pol.record_size
     rc = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    if init_per_batch is not None:
+        for mi, key, val in init_per_batch[0]:
+            rt.map_update(fds[mi], key, val)
+    tune = rt.autotune(prog, batches[0], n_events=n, record_size=pol.record_size, rc=rc, stream=stream) if tuned \
+        else None
     ring = [0]
 
     def step(k):
@@ -143,6 +149,7 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     return {
         "workload": name,
         "engine": "jit" if jit else "interp",
+        "blocks": (tune["blocks"] or "sized per run") if tune else "default",
         "events_per_batch": n,
         "events_per_s": n * steps / wall,
         "vm_kernel_us": vm_s * 1e6,
@@ -304,6 +311,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--engine", choices=["jit", "interp"], default="jit",
                     help="run the program compiled to native code (jit) or interpreted")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shape)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the memory-bound policies, the batched and the served forms")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
@@ -347,12 +355,22 @@ def main():
         log(f"compiled to native code in {time.perf_counter() - t:.2f} s")
     ring_fd = fds[1]
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_tune:
+        t = time.perf_counter()
+        tune = rt.autotune(prog, dev_batches[0], n_events=n, record_size=24, rc=rc, stream=stream)
+        log(f"autotune: {tune} in {time.perf_counter() - t:.2f} s")
 
     ring_bytes = [0]
 
+    drain_s = [0.0]
+
     def step(k):
         rt.run_batch(prog, dev_batches[k % len(dev_batches)], n_events=n, record_size=24, rc=rc, stream=stream)
+        stream.synchronize()  # the drain waits for the launch anyway; time the drain alone
+        t = time.perf_counter()
         buf, nrec = rt.drain_ringbuf(ring_fd, copy=False)
+        drain_s[0] += time.perf_counter() - t
         ring_bytes[0] += len(buf)
 
     log("warmup")
@@ -362,6 +380,7 @@ def main():
     rt.profile_read()
     rt.profile_enable(True)
     ring_bytes[0] = 0
+    drain_s[0] = 0.0
     log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -422,10 +441,12 @@ def main():
             "batches_rotated": args.batches,
             "mode": "stream-sequential",
             "engine": args.engine,
+            "launch_shape": ({"lanes_per_wave": tune["lanes"], "queues_log2": tune["qbits"]} if tune else "default"),
         },
         "insns_per_s": events_per_s * insns_per_event if insns_per_event else None,
         "insns_per_event": insns_per_event,
         "vm_kernel_ms": vm_avg_s * 1000,
+        "drain_ms": 1000 * drain_s[0] / args.steps,
         "vm_events_per_s": n / vm_avg_s,
         "ring_bytes_per_step": ring_per_launch,
         "roofline": {

@@ -146,6 +146,26 @@ int gx_verify(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const
  * fails (compiler log in ``log``).  Takes seconds: call it at load time. */
 int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size);
 
+/* Autotuner: the launch shape of a program's runs (stream-sequential:
+ * queues per wave and queue count; compiled event-parallel: block count) is
+ * chosen by timing each candidate on a sample batch (d_events, n_events
+ * records of record_size bytes in device memory; d_rc receives return codes
+ * and may be NULL) on ``stream``.  Map and ring contents are saved first
+ * and restored before every trial and at the end, so the only lasting
+ * effect is the choice, which later gx_run_batch / gx_run_batches calls of
+ * the program use.  Synchronous.  Fills *out (may be NULL).  Returns 0,
+ * -EINVAL for bad arguments, -ENOMEM. */
+typedef struct gx_tune {
+  uint32_t lanes;     /* stream-sequential: queues per wave */
+  uint32_t qbits;     /* stream-sequential: log2 queue count */
+  uint32_t blocks;    /* compiled event-parallel: blocks (0: sized per run) */
+  uint32_t trials;    /* candidates timed */
+  double best_ms;     /* time of the chosen shape on the sample */
+  double default_ms;  /* time of the default shape on the sample */
+} gx_tune;
+int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size, uint32_t* d_rc,
+                void* stream, gx_tune* out);
+
 /* The HIP source gx_jit_program would compile for a program (no device
  * needed; map descriptors get stand-in addresses).  Same program and shape
  * arguments as gx_verify.  With compile != 0 the source is also compiled

@@ -311,7 +311,7 @@ bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
 
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
                        const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       uint64_t* acc_words) {
+                       bool event_parallel, uint64_t* acc_words) {
   JMaps J(maps, mem_map);
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
@@ -403,14 +403,16 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
   const std::string W = std::to_string(kJitWaves), T = std::to_string(64 * kJitWaves);
-  o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
+  if (event_parallel)
+    o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
        "  const uint32_t wave = threadIdx.x >> 6;\n"
        "  gx::Stk stk{wave * 64u * " + std::to_string(stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
        "u + threadIdx.x};\n"
        "  gx::Prog<true> P{wave};\n  P.begin();\n"
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
        "  P.end();\n}\n\n";
-  o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
+  else
+    o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
        "  gx::Prog<false> P{0u};\n  P.begin();\n  uint64_t steps = 0;\n"
        "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, qend_last, stk, steps);\n"

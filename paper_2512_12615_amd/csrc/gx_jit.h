@@ -16,9 +16,9 @@ constexpr uint32_t kJitWaves = 4;
 
 // HIP source of one program: its micro-ops written out as straight-line
 // code with labels at jump targets, helpers called directly with the map
-// descriptors as constants, and the two event-loop kernels:
+// descriptors as constants, and the event-loop kernel of its mode:
 // gx_j_event_parallel (kJitWaves waves per block, grid-stride over 64-event
-// tiles) and gx_j_stream_seq (one wave per block).  Stack frames live in a
+// tiles) or gx_j_stream_seq (one wave per block).  Stack frames live in a
 // static LDS array; each wave carves ring records from its own chunk of
 // reserved ring space.
 // ``maps`` holds (descriptor device address, descriptor contents) of every
@@ -28,9 +28,10 @@ constexpr uint32_t kJitWaves = 4;
 // the event-parallel kernel sums the atomics of shared maps in LDS.
 // *acc_words receives the LDS accumulator words a block flushes at its end
 // (0: no accumulators), which the launch uses to size its grid.
+// Only the kernel of the program's execution mode is emitted.
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
                        const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       uint64_t* acc_words = nullptr);
+                       bool event_parallel, uint64_t* acc_words = nullptr);
 
 // Compile a generated source for gfx950.  Returns 0 and the code object, or
 // -EIO with the compiler log.

@@ -64,7 +64,17 @@ struct ProgObj {
   hipModule_t jmod = nullptr;
   hipFunction_t jf_ep = nullptr, jf_seq = nullptr;
   uint64_t jacc_words = 0;  // LDS accumulator words each block flushes
+  // launch shape chosen by gx_autotune (0: default)
+  uint32_t tuned_lanes = 0, tuned_qbits = 0, tuned_blocks = 0;
 };
+
+// Launch shape of one run.
+struct Knobs {
+  uint32_t lanes;   // stream-sequential: queues (lanes) per wave
+  uint32_t qbits;   // stream-sequential: log2 of the queue count
+  uint32_t blocks;  // compiled event-parallel: blocks (0: sized from the run)
+};
+
 
 uint64_t next_pow2(uint64_t x) {
   uint64_t p = 1;
@@ -75,6 +85,22 @@ uint64_t next_pow2(uint64_t x) {
 int env_int(const char* name, int dflt) {
   const char* s = std::getenv(name);
   return s && *s ? std::atoi(s) : dflt;
+}
+
+// Default queues per wave: a compiled program runs one queue per wave (its
+// lanes' paths would otherwise serialize under divergence: measured 1.9x
+// faster than 64 on the stride-prefetch workload); the interpreter fills the
+// wave (its dispatch costs the same for one lane or 64).
+uint32_t default_lanes(const ProgObj* p) {
+  return (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", p->jmod ? 1 : 64)));
+}
+
+Knobs knobs_of(const ProgObj* p) {
+  Knobs k;
+  k.lanes = p->tuned_lanes ? p->tuned_lanes : default_lanes(p);
+  k.qbits = p->tuned_qbits ? p->tuned_qbits : (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
+  k.blocks = p->tuned_blocks ? p->tuned_blocks : (uint32_t)std::min(65536, std::max(0, env_int("GX_JIT_BLOCKS", 0)));
+  return k;
 }
 
 }  // namespace
@@ -330,7 +356,7 @@ int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
 // wave, counts with row stride ``qstride``, the run's last queue ending at
 // ``qend_last`` in order[].
 hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes, uint32_t qstride,
-                      uint32_t qend_last, hipStream_t s) {
+                      uint32_t qend_last, uint32_t blocks_override, hipStream_t s) {
   if (mode == 0) {
     void* args[] = {&A};
     const uint64_t tiles = (A.n_events + 63) / 64;
@@ -338,13 +364,77 @@ hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes
     // each block flushes its accumulators once: give every block at least
     // as many events as it flushes words (but keep one block per CU)
     if (p->jacc_words) nb = std::min(nb, std::max<uint64_t>(256, A.n_events / p->jacc_words));
-    const int ov = env_int("GX_JIT_BLOCKS", 0);  // tuning override
-    if (ov > 0) nb = std::min<uint64_t>((uint64_t)ov, 65536);
+    if (blocks_override) nb = blocks_override;
     const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
     return hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * kJitWaves, 1, 1, 0, s, args, nullptr);
   }
   void* args[] = {&A, &lanes, &qstride, &qend_last};
   return hipModuleLaunchKernel(p->jf_seq, (A.n_queues + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
+}
+
+// One plain run of a program with launch shape k (validated arguments).
+int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint32_t* d_rc, hipStream_t s,
+            const Knobs& k) {
+  RunArgs A{};
+  A.uops = p->d_uops;
+  A.events = (const uint8_t*)d_events;
+  A.rc = d_rc;
+  A.n_events = n_events;
+  A.record_size = p->record_size;
+  A.stack_bytes = p->v.stack_bytes;
+  A.stream_off = p->stream_off;
+  A.stream_size = p->stream_size;
+  A.err = rt->d_err;
+  A.guards = p->d_guards;
+  A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
+  A.epoch = ++rt->epoch;
+  uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
+  hipError_t e;
+  std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
+  if (rt->profile) pe = prof_pair(rt);
+  if (p->v.event_parallel) {
+    A.step_limit = per_event;
+    if (pe.first) (void)hipEventRecord(pe.first, s);
+    if (p->jf_ep) {
+      e = launch_jit(p, A, 0, 0, 0, 0, k.blocks, s);
+    } else {
+      e = launch_event_parallel(A, s);
+    }
+    if (pe.second) (void)hipEventRecord(pe.second, s);
+    rt->stats.launches += 1;
+  } else {
+    const uint32_t lbits = k.qbits;
+    const uint32_t L = 1u << lbits;
+    uint64_t tile = std::max<uint64_t>(4096, next_pow2((n_events + 255) / 256));
+    uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
+    uint64_t m = (uint64_t)L * nt;
+    int r = ensure_ws(rt, m, (m + 4095) / 4096 + 1, n_events);
+    if (r) return r;
+    if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
+    A.step_limit = per_event * n_events;
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
+    if (e == hipSuccess) {
+      A.order = rt->d_order;
+      A.sorted = rt->d_sorted;
+      A.qstart = rt->d_counts;
+      A.n_queues = L;
+      if (pe.first) (void)hipEventRecord(pe.first, s);
+      if (p->jf_seq) {
+        e = launch_jit(p, A, 1, k.lanes, nt, (uint32_t)n_events, 0, s);
+      } else {
+        e = launch_stream_seq(A, k.lanes, nt, s);
+      }
+      if (pe.second) (void)hipEventRecord(pe.second, s);
+    }
+    (void)hipEventRecord(rt->ws_event, s);
+    rt->ws_used = true;
+    rt->stats.launches += 6;
+  }
+  if (pe.first) rt->prof_pending.push_back(pe);
+  if (e != hipSuccess) return to_errno(e);
+  rt->stats.events += n_events;
+  note_stream(rt, s);
+  return 0;
 }
 
 }  // namespace
@@ -657,6 +747,110 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
   return (int)rt->progs.size() - 1;
 }
 
+int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size, uint32_t* d_rc,
+                void* stream, gx_tune* out) {
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p || record_size != p->record_size || !d_events || n_events == 0) return -EINVAL;
+  if (n_events >= (1ull << 32)) return -E2BIG;
+  DevGuard g(rt->dev);
+  hipStream_t s = (hipStream_t)stream;
+  // candidate shapes
+  std::vector<Knobs> cand;
+  const Knobs def = Knobs{default_lanes(p), (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12))), 0};
+  cand.push_back(def);
+  if (p->v.event_parallel) {
+    if (p->jf_ep)
+      for (uint32_t b : {256u, 512u, 1024u, 2048u, 4096u, 8192u}) cand.push_back(Knobs{def.lanes, def.qbits, b});
+  } else {
+    for (uint32_t q : {10u, 12u, 14u})
+      for (uint32_t l : {1u, 2u, 4u, 8u, 16u, 32u, 64u}) cand.push_back(Knobs{l, q, 0});
+  }
+  // the trials run the program for real: save every map's state and put it
+  // back before each trial and at the end
+  struct Save {
+    void* src;
+    void* tmp;
+    size_t bytes;
+  };
+  std::vector<Save> saves;
+  auto cleanup = [&]() {
+    for (auto& sv : saves)
+      if (sv.tmp) (void)hipFree(sv.tmp);
+  };
+  for (int fd : p->fds) {
+    MapObj* m = get_map(rt, fd);
+    if (!m) continue;
+    for (auto pr : {std::make_pair((void*)m->h.data, m->data_bytes), std::make_pair((void*)m->h.slots, m->slot_bytes),
+                    std::make_pair((void*)m->h.ctrl, (size_t)64)}) {
+      if (!pr.first || !pr.second) continue;
+      Save sv{pr.first, nullptr, pr.second};
+      if (hipMalloc(&sv.tmp, sv.bytes) != hipSuccess) {
+        cleanup();
+        return -ENOMEM;
+      }
+      saves.push_back(sv);
+    }
+  }
+  if (wait_all(rt)) {
+    cleanup();
+    return -EIO;
+  }
+  for (auto& sv : saves) (void)hipMemcpyAsync(sv.tmp, sv.src, sv.bytes, hipMemcpyDeviceToDevice, s);
+  auto restore = [&]() {
+    for (auto& sv : saves) (void)hipMemcpyAsync(sv.src, sv.tmp, sv.bytes, hipMemcpyDeviceToDevice, s);
+  };
+  const bool prof = rt->profile;
+  const gx_stats st = rt->stats;
+  rt->profile = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int r = 0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = -ENOMEM;
+  double best = 1e300, def_ms = 0;
+  Knobs bestk = def;
+  // one untimed run first (first-touch of workspaces and code)
+  if (!r) {
+    restore();
+    r = run_one(rt, p, d_events, n_events, d_rc, s, def);
+  }
+  for (size_t c = 0; c < cand.size() && !r; c++) {
+    restore();
+    (void)hipEventRecord(e0, s);
+    r = run_one(rt, p, d_events, n_events, d_rc, s, cand[c]);
+    (void)hipEventRecord(e1, s);
+    if (r) break;
+    float ms = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      r = -EIO;
+      break;
+    }
+    if (c == 0) def_ms = ms;
+    if (ms < best) {
+      best = ms;
+      bestk = cand[c];
+    }
+  }
+  restore();
+  (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  cleanup();
+  rt->profile = prof;
+  rt->stats = st;
+  if (r) return r;
+  p->tuned_lanes = bestk.lanes;
+  p->tuned_qbits = bestk.qbits;
+  p->tuned_blocks = bestk.blocks;
+  if (out) {
+    out->lanes = bestk.lanes;
+    out->qbits = bestk.qbits;
+    out->blocks = bestk.blocks;
+    out->trials = (uint32_t)cand.size();
+    out->best_ms = best;
+    out->default_ms = def_ms;
+  }
+  return 0;
+}
+
 int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   ProgObj* p = get_prog(rt, prog_fd);
   if (!p) return -EINVAL;
@@ -670,15 +864,16 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
     maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
   }
   uint64_t acc_words = 0;
-  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, &acc_words), &code, &lg);
+  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, p->v.event_parallel, &acc_words),
+                      &code, &lg);
   write_log(log, log_size, lg);
   if (r) return r;
   DevGuard g(rt->dev);
   hipModule_t mod = nullptr;
   hipFunction_t fe = nullptr, fs = nullptr;
   if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return -EIO;
-  if (hipModuleGetFunction(&fe, mod, "gx_j_event_parallel") != hipSuccess ||
-      hipModuleGetFunction(&fs, mod, "gx_j_stream_seq") != hipSuccess) {
+  if (p->v.event_parallel ? hipModuleGetFunction(&fe, mod, "gx_j_event_parallel") != hipSuccess
+                          : hipModuleGetFunction(&fs, mod, "gx_j_stream_seq") != hipSuccess) {
     (void)hipModuleUnload(mod);
     return -EIO;
   }
@@ -728,7 +923,7 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
     return -EACCES;
   }
-  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map);
+  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map, v.event_parallel);
   if (compile) {
     std::vector<char> code;
     std::string lg;
@@ -757,69 +952,8 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   if (n_events == 0) return 0;
   if (!d_events) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
-  hipStream_t s = (hipStream_t)stream;
   DevGuard g(rt->dev);
-  RunArgs A{};
-  A.uops = p->d_uops;
-  A.events = (const uint8_t*)d_events;
-  A.rc = d_rc;
-  A.n_events = n_events;
-  A.record_size = p->record_size;
-  A.stack_bytes = p->v.stack_bytes;
-  A.stream_off = p->stream_off;
-  A.stream_size = p->stream_size;
-  A.err = rt->d_err;
-  A.guards = p->d_guards;
-  A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
-  A.epoch = ++rt->epoch;
-  uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
-  hipError_t e;
-  std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
-  if (rt->profile) pe = prof_pair(rt);
-  if (p->v.event_parallel) {
-    A.step_limit = per_event;
-    if (pe.first) (void)hipEventRecord(pe.first, s);
-    if (p->jf_ep) {
-      e = launch_jit(p, A, 0, 0, 0, 0, s);
-    } else {
-      e = launch_event_parallel(A, s);
-    }
-    if (pe.second) (void)hipEventRecord(pe.second, s);
-    rt->stats.launches += 1;
-  } else {
-    uint32_t lbits = (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
-    uint32_t L = 1u << lbits;
-    uint64_t tile = std::max<uint64_t>(4096, next_pow2((n_events + 255) / 256));
-    uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
-    uint64_t m = (uint64_t)L * nt;
-    int r = ensure_ws(rt, m, (m + 4095) / 4096 + 1, n_events);
-    if (r) return r;
-    if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
-    A.step_limit = per_event * n_events;
-    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
-    if (e == hipSuccess) {
-      A.order = rt->d_order;
-      A.sorted = rt->d_sorted;
-      A.qstart = rt->d_counts;
-      A.n_queues = L;
-      uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
-      if (pe.first) (void)hipEventRecord(pe.first, s);
-      if (p->jf_seq) {
-        e = launch_jit(p, A, 1, lanes, nt, (uint32_t)n_events, s);
-      } else {
-        e = launch_stream_seq(A, lanes, nt, s);
-      }
-      if (pe.second) (void)hipEventRecord(pe.second, s);
-    }
-    (void)hipEventRecord(rt->ws_event, s);
-    rt->ws_used = true;
-    rt->stats.launches += 6;
-  }
-  if (pe.first) rt->prof_pending.push_back(pe);
-  if (e != hipSuccess) return to_errno(e);
-  rt->stats.events += n_events;
-  note_stream(rt, s);
-  return 0;
+  return run_one(rt, p, d_events, n_events, d_rc, (hipStream_t)stream, knobs_of(p));
 }
 
 }  // extern "C"
@@ -865,11 +999,11 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   std::vector<const ProgObj*> bprog;  // program of each run
   uint64_t counts_total = 0, order_total = 0;
   uint32_t stack_max = 0, max_lbits = 0;
-  uint32_t lanes = (uint32_t)std::min(64, std::max(1, env_int("GX_SEQ_LANES", 64)));
-  uint32_t qbits = (uint32_t)std::min(16, std::max(6, env_int("GX_QUEUE_BITS", 12)));
   for (uint32_t i = 0; i < n; i++) {
     if (d[i].n_events == 0) continue;
     ProgObj* p = get_prog(rt, d[i].prog_fd);
+    const Knobs kn = knobs_of(p);
+    const uint32_t lanes = kn.lanes, qbits = kn.qbits;
     RunArgs A = make_args(rt, p, d[i].d_events, d[i].n_events, d[i].d_rc);
     BatchDev bd{};
     stack_max = std::max(stack_max, p->v.stack_bytes);
@@ -983,7 +1117,8 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
         (void)hipStreamWaitEvent(ss, rt->fork_ev, 0);
         used_side++;
       }
-      e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, ss);
+      e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, knobs_of(bprog[b]).blocks,
+                     ss);
     }
   }
   if (e == hipSuccess && !items.empty()) {
@@ -1070,6 +1205,12 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
     if (hipMemcpy(buf, m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
     if (first < avail && hipMemcpy(buf + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
       return -EIO;
+    // records between discards are copied as one run
+    uint64_t run = 0;  // start of the current run of kept records
+    auto flush = [&](uint64_t end) {
+      if (end > run) std::memcpy((uint8_t*)host_buf + out, buf + run, end - run);
+      out += end - run;
+    };
     while (pos + 8 <= avail) {
       uint32_t len, flags;
       std::memcpy(&len, buf + pos, 4);
@@ -1077,14 +1218,16 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
       if (len == 0 && flags == 0) break;  // not written (cannot happen after a completed launch)
       const uint64_t need = 8 + ((len + 7ull) & ~7ull);
       if (pos + need > avail) break;
-      if (!(flags & RING_DISCARD)) {
-        if (out + need > buf_bytes) break;
-        std::memcpy((uint8_t*)host_buf + out, buf + pos, need);
-        out += need;
+      if (flags & RING_DISCARD) {
+        flush(pos);
+        run = pos + need;
+      } else {
+        if (out + (pos - run) + need > buf_bytes) break;
         nrec++;
       }
       pos += need;
     }
+    flush(pos);
   }
   if (pos || cut) {
     // publish the new tail (and, after an overflow, the cut-back head)

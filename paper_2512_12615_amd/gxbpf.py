@@ -43,10 +43,15 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_jit_program", "gx_jit_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_run_batches", "gx_autotune", "gx_jit_program", "gx_jit_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
+
+
+class Tune(C.Structure):
+    _fields_ = [("lanes", C.c_uint32), ("qbits", C.c_uint32), ("blocks", C.c_uint32), ("trials", C.c_uint32),
+                ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -93,6 +98,7 @@ def lib():
     L.gx_verify.argtypes = [vp, u32, u32, vp, u32, C.c_char_p, u32, C.POINTER(ProgInfo)]
     L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
+    L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_jit_program.argtypes = [vp, C.c_int, C.c_char_p, u32]
     L.gx_jit_source.argtypes = [vp, u32, u32, vp, u32, C.c_int, C.c_char_p, u64]
     L.gx_jit_source.restype = i64
@@ -244,6 +250,18 @@ class Runtime:
         if r < 0:
             raise GxError(-r, f"gx_load_program: {os.strerror(-r)}: {log.value.decode()}")
         return r
+
+    def autotune(self, prog_fd, events, n_events=None, record_size=None, rc=None, stream=None) -> dict:
+        """Time the candidate launch shapes of a program on a sample batch
+        (map contents restored afterwards) and keep the fastest."""
+        if record_size is None:
+            record_size = RECORD_SIZE[self.prog_info(prog_fd).hook]
+        if n_events is None:
+            n_events = events.numel() * events.element_size() // record_size
+        t = Tune()
+        _check(lib().gx_autotune(self._h, prog_fd, _dptr(events), n_events, record_size, _dptr(rc),
+                                 _stream_handle(stream), C.byref(t)), "gx_autotune")
+        return {k: getattr(t, k) for k, _ in Tune._fields_}
 
     def jit_program(self, fd):
         """Compile a loaded program to native gfx950 code (later run_batch

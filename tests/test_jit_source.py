@@ -23,7 +23,11 @@ def G():
 def test_policies_compile(G, name):
     pol = getattr(W, f"{name}_policy")()
     src = G.jit_source(pol.code, pol.hook, _shapes(pol), compile=True)
-    assert "gx_j_event_parallel" in src and "gx_j_stream_seq" in src
+    # only the kernel of the program's mode
+    if name == "stride_prefetch":
+        assert "gx_j_stream_seq" in src and "gx_j_event_parallel" not in src
+    else:
+        assert "gx_j_event_parallel" in src and "gx_j_stream_seq" not in src
 
 
 @pytest.mark.parametrize("i", range(6))
