@@ -9,7 +9,7 @@
 // compiler keeps them in VGPRs, folds constant stack offsets into LDS
 // addresses and lets the hardware's EXEC mask handle divergent branches;
 // helper calls go straight to the same device helpers the interpreter uses,
-// with each map's descriptor address as a constant.  Verification has
+// with each map's shape as constants.  Verification has
 // already bounded every loop, so the generated code carries no step counter.
 #include "gx_jit.h"
 
@@ -58,10 +58,12 @@ constexpr uint64_t kLdsMax = 150 << 10;
 struct JMaps {
   const std::vector<std::pair<uint64_t, MapDev>>& m;
   const std::vector<int>& mem_map;  // map of each map-value access (by slot)
+  const std::vector<int>& ld_map;   // map of each lddw map reference (by slot)
   std::vector<int> ring;  // ring index per map (-1 if not a ring)
   int n_rings = 0;
   std::vector<Acc> acc;   // per map
-  JMaps(const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mm) : m(maps), mem_map(mm) {
+  JMaps(const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mm, const std::vector<int>& lm)
+      : m(maps), mem_map(mm), ld_map(lm) {
     for (auto& e : maps) ring.push_back(e.second.type == MAP_RINGBUF ? n_rings++ : -1);
     acc.resize(maps.size());
   }
@@ -111,15 +113,19 @@ std::string map_name(const JMaps& J, uint64_t desc) {
   return k >= 0 ? "&M" + std::to_string(k) : "(const MapDev*)" + lit(desc);
 }
 
-// the descriptor as a function returning a constant (folds into the code)
+// The descriptor of map k: its shape as constants (sizes, masks and strides
+// fold into the code), its addresses from the run's map table (the program
+// instance's maps), so instances of one program with maps of one shape share
+// a compiled module.  The loads are from constant memory and become scalar.
 std::string map_fn(size_t k, const MapDev& m) {
-  char b[600];
+  char b[800];
   std::snprintf(b, sizeof b,
-                "__device__ __forceinline__ MapDev gx_map%zu() {\n  return MapDev{%uu, %uu, %uu, %uu, %uu, %uu, %uu, "
-                "%uu, (uint8_t*)%s, (uint8_t*)%s, (uint64_t*)%s, 0ull};\n}\n",
-                k, m.type, m.key_size, m.value_size, m.max_entries, m.flags, m.vstride, m.slot_mask, m.sstride,
-                lit((uint64_t)(uintptr_t)m.data).c_str(), lit((uint64_t)(uintptr_t)m.slots).c_str(),
-                lit((uint64_t)(uintptr_t)m.ctrl).c_str());
+                "__device__ __forceinline__ MapDev gx_map%zu(const RunArgs& A) {\n"
+                "  typedef const __attribute__((address_space(4))) uint64_t cu64;\n"
+                "  const cu64* d = (const cu64*)(((const cu64*)A.maptab)[%zu]);\n"
+                "  return MapDev{%uu, %uu, %uu, %uu, %uu, %uu, %uu, %uu, (uint8_t*)d[4], (uint8_t*)d[5], "
+                "(uint64_t*)d[6], 0ull};\n}\n",
+                k, k, m.type, m.key_size, m.value_size, m.max_entries, m.flags, m.vstride, m.slot_mask, m.sstride);
   return b;
 }
 
@@ -270,7 +276,15 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
       }
       break;
     }
-    case H_LDIMM: set(lit(u.imm)); break;
+    case H_LDIMM:
+      // a map reference only reaches helper calls, which name the map by
+      // index; the handle's value is left out so that the source holds no
+      // address of this instance's maps
+      if (pc < J.ld_map.size() && J.ld_map[pc] >= 0)
+        set(std::to_string(J.ld_map[pc]) + "ull /* map */");
+      else
+        set(lit(u.imm));
+      break;
     case H_LOOKUP_ARRAY:
       o += "  r0 = array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk);\n";
       break;
@@ -311,8 +325,8 @@ bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
 
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
                        const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       bool event_parallel, uint64_t* acc_words) {
-  JMaps J(maps, mem_map);
+                       const std::vector<int>& ld_map, bool event_parallel, uint64_t* acc_words) {
+  JMaps J(maps, mem_map, ld_map);
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
@@ -347,7 +361,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   // begin / end: open and close the wave's ring chunks and the block's accumulators
   // a chunk is the ring's capacity over four times the waves of the
   // launch (64 B to 8 KiB): chunks in flight then hold at most a quarter
-  o += "  __device__ __forceinline__ void begin() {\n";
+  o += "  __device__ __forceinline__ void begin(const RunArgs& A) {\n    (void)A;\n";
   o += "    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64u);\n    (void)waves;\n";
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
@@ -368,10 +382,10 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
     }
     o += "      __syncthreads();\n    }\n";
   }
-  o += "  }\n  __device__ __forceinline__ void end() {\n";
+  o += "  }\n  __device__ __forceinline__ void end(const RunArgs& A) {\n    (void)A;\n";
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
-      o += "    { const MapDev M = gx_map" + std::to_string(k) + "(); ring_chunk_close(&M, wave * GX_NRINGS + " +
+      o += "    { const MapDev M = gx_map" + std::to_string(k) + "(A); ring_chunk_close(&M, wave * GX_NRINGS + " +
            std::to_string(J.ring[k]) + "u); }\n";
   if (any_acc) {
     o += "    if (PRIV) {\n      __syncthreads();\n";
@@ -380,7 +394,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
       const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k);
       if (a.kind == 1)
         o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
-             "u, gx_map" + K + "().data);\n";
+             "u, gx_map" + K + "(A).data);\n";
       else if (a.kind == 2)
         o += "      cache_flush<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
              std::to_string(a.op) + "u);\n";
@@ -394,7 +408,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
   o += "  uint64_t r10 = " + std::to_string(stack_bytes) + "ull;\n";
   for (size_t k = 0; k < maps.size(); k++)
-    o += "  const MapDev M" + std::to_string(k) + " = gx_map" + std::to_string(k) + "();\n";
+    o += "  const MapDev M" + std::to_string(k) + " = gx_map" + std::to_string(k) + "(A);\n";
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
   for (uint32_t pc = 0; pc < U.size(); pc++) {
     if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
@@ -408,15 +422,15 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
        "  const uint32_t wave = threadIdx.x >> 6;\n"
        "  gx::Stk stk{wave * 64u * " + std::to_string(stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
        "u + threadIdx.x};\n"
-       "  gx::Prog<true> P{wave};\n  P.begin();\n"
+       "  gx::Prog<true> P{wave};\n  P.begin(A);\n"
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
-       "  P.end();\n}\n\n";
+       "  P.end(A);\n}\n\n";
   else
     o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
-       "  gx::Prog<false> P{0u};\n  P.begin();\n  uint64_t steps = 0;\n"
+       "  gx::Prog<false> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
        "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, qend_last, stk, steps);\n"
-       "  P.end();\n}\n";
+       "  P.end(A);\n}\n";
   return o;
 }
 

@@ -22,16 +22,20 @@ constexpr uint32_t kJitWaves = 4;
 // static LDS array; each wave carves ring records from its own chunk of
 // reserved ring space.
 // ``maps`` holds (descriptor device address, descriptor contents) of every
-// map the program uses; the generated code gets each descriptor as a
-// constant, so key sizes, slot masks and addresses fold into the code.
+// map the program uses, in its map-table order; the generated code gets each
+// map's shape as constants, so key sizes, slot masks and strides fold into
+// the code.
 // ``mem_map`` is the verifier's map of each map-value access (by slot):
 // the event-parallel kernel sums the atomics of shared maps in LDS.
 // *acc_words receives the LDS accumulator words a block flushes at its end
 // (0: no accumulators), which the launch uses to size its grid.
-// Only the kernel of the program's execution mode is emitted.
+// ``ld_map`` is the verifier's map of each lddw map reference.  Only the
+// kernel of the program's execution mode is emitted.  The source holds the
+// maps' shapes but none of their addresses (those come from RunArgs::maptab),
+// so program instances with same-shaped maps compile to the same source.
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
                        const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       bool event_parallel, uint64_t* acc_words = nullptr);
+                       const std::vector<int>& ld_map, bool event_parallel, uint64_t* acc_words = nullptr);
 
 // Compile a generated source for gfx950.  Returns 0 and the code object, or
 // -EIO with the compiler log.

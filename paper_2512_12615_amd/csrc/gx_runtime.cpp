@@ -7,6 +7,7 @@
 #include <cerrno>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -60,6 +61,7 @@ struct ProgObj {
   uint64_t* d_guards = nullptr;
   std::vector<int> fds;
   std::vector<Uop> uops;  // host copy (source of the compiled form)
+  uint64_t* d_maptab = nullptr;  // device addresses of its map descriptors (map-table order)
   // compiled form (gx_jit_program): module and its two kernels
   hipModule_t jmod = nullptr;
   hipFunction_t jf_ep = nullptr, jf_seq = nullptr;
@@ -108,6 +110,15 @@ Knobs knobs_of(const ProgObj* p) {
 struct gx_rt {
   int dev = 0;
   hipStream_t internal = nullptr;
+  // compiled modules by generated source (instances of one program with
+  // same-shaped maps share one); guarded for concurrent gx_jit_program calls
+  struct JitMod {
+    hipModule_t mod = nullptr;
+    hipFunction_t fe = nullptr, fs = nullptr;
+    uint64_t acc_words = 0;
+  };
+  std::map<std::string, JitMod> jit_cache;
+  std::mutex jit_mu;
   // batched form: compiled runs of a phase run side by side on these
   static constexpr int kSide = 4;
   hipStream_t side[kSide] = {};
@@ -386,6 +397,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   A.stream_size = p->stream_size;
   A.err = rt->d_err;
   A.guards = p->d_guards;
+  A.maptab = p->d_maptab;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
@@ -487,8 +499,10 @@ void gx_close(gx_rt* rt) {
   for (auto& p : rt->progs) {
     if (p.d_uops) (void)hipFree(p.d_uops);
     if (p.d_guards) (void)hipFree(p.d_guards);
-    if (p.jmod) (void)hipModuleUnload(p.jmod);
+    if (p.d_maptab) (void)hipFree(p.d_maptab);
   }
+  for (auto& jm : rt->jit_cache)
+    if (jm.second.mod) (void)hipModuleUnload(jm.second.mod);
   for (auto& se : rt->stream_events) (void)hipEventDestroy(se.second);
   for (auto* v : {&rt->prof_pending, &rt->prof_free})
     for (auto& pe : *v) {
@@ -740,6 +754,15 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
     (void)hipFree(p.d_guards);
     return -EIO;
   }
+  std::vector<uint64_t> mt(std::max<size_t>(tab.size(), 1), 0);
+  for (size_t i = 0; i < tab.size(); i++) mt[i] = (uint64_t)(uintptr_t)tab[i]->d_desc;
+  if (hipMalloc((void**)&p.d_maptab, mt.size() * 8) != hipSuccess ||
+      hipMemcpy(p.d_maptab, mt.data(), mt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p.d_uops);
+    (void)hipFree(p.d_guards);
+    if (p.d_maptab) (void)hipFree(p.d_maptab);
+    return -ENOMEM;
+  }
   p.v = std::move(v);
   p.uops = std::move(U);
   p.live = true;
@@ -855,8 +878,6 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   ProgObj* p = get_prog(rt, prog_fd);
   if (!p) return -EINVAL;
   if (p->jmod) return 0;
-  std::vector<char> code;
-  std::string lg;
   std::vector<std::pair<uint64_t, MapDev>> maps;
   for (int fd : p->fds) {
     MapObj* m = get_map(rt, fd);
@@ -864,23 +885,41 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
     maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
   }
   uint64_t acc_words = 0;
-  int r = jit_compile(jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, p->v.event_parallel, &acc_words),
-                      &code, &lg);
+  const std::string src =
+      jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, p->v.ld_map, p->v.event_parallel, &acc_words);
+  auto adopt = [&](const gx_rt::JitMod& jm) {
+    p->jf_ep = jm.fe;
+    p->jf_seq = jm.fs;
+    p->jacc_words = jm.acc_words;
+    p->jmod = jm.mod;
+  };
+  {
+    std::lock_guard<std::mutex> lk(rt->jit_mu);
+    auto it = rt->jit_cache.find(src);
+    if (it != rt->jit_cache.end()) {
+      adopt(it->second);
+      write_log(log, log_size, "");
+      return 0;
+    }
+  }
+  std::vector<char> code;
+  std::string lg;
+  int r = jit_compile(src, &code, &lg);
   write_log(log, log_size, lg);
   if (r) return r;
   DevGuard g(rt->dev);
-  hipModule_t mod = nullptr;
-  hipFunction_t fe = nullptr, fs = nullptr;
-  if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return -EIO;
-  if (p->v.event_parallel ? hipModuleGetFunction(&fe, mod, "gx_j_event_parallel") != hipSuccess
-                          : hipModuleGetFunction(&fs, mod, "gx_j_stream_seq") != hipSuccess) {
-    (void)hipModuleUnload(mod);
+  gx_rt::JitMod jm;
+  jm.acc_words = acc_words;
+  if (hipModuleLoadData(&jm.mod, code.data()) != hipSuccess) return -EIO;
+  if (p->v.event_parallel ? hipModuleGetFunction(&jm.fe, jm.mod, "gx_j_event_parallel") != hipSuccess
+                          : hipModuleGetFunction(&jm.fs, jm.mod, "gx_j_stream_seq") != hipSuccess) {
+    (void)hipModuleUnload(jm.mod);
     return -EIO;
   }
-  p->jmod = mod;
-  p->jf_ep = fe;
-  p->jf_seq = fs;
-  p->jacc_words = acc_words;
+  std::lock_guard<std::mutex> lk(rt->jit_mu);
+  auto ins = rt->jit_cache.emplace(src, jm);
+  if (!ins.second) (void)hipModuleUnload(jm.mod);  // compiled concurrently by another call
+  adopt(ins.first->second);
   return 0;
 }
 
@@ -923,7 +962,7 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
     return -EACCES;
   }
-  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map, v.event_parallel);
+  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map, v.ld_map, v.event_parallel);
   if (compile) {
     std::vector<char> code;
     std::string lg;
@@ -972,6 +1011,7 @@ RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events
   A.stream_size = p->stream_size;
   A.err = rt->d_err;
   A.guards = p->d_guards;
+  A.maptab = p->d_maptab;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;

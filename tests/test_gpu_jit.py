@@ -258,3 +258,22 @@ def test_jit_ring_partial_drains(rt):
         total += nrec
     assert sorted(got) == list(range(0, n, 8))
     assert rt.stats()["ring_drops"] == 0
+
+
+def test_jit_instances_share_code_keep_their_maps(rt):
+    """Two instances of one program on separate maps (one compiled module)
+    run in one batch; each matches the oracle on its own events."""
+    import torch
+    _log("jit two instances")
+    pol = W.stride_prefetch_policy()
+    runs = []
+    for j in range(2):
+        fds, prog = setup(rt, pol, jit=True)
+        ev = W.gen_mem_stride(30000 + 7 * j, 400 + j, streams=64)
+        rc = torch.zeros(len(ev), dtype=torch.int32, device="cuda")
+        runs.append((fds, prog, ev, to_device(ev), rc))
+    rt.run_batches([(prog, d, len(ev), 24, rc) for fds, prog, ev, d, rc in runs])
+    torch.cuda.synchronize()
+    for j, (fds, prog, ev, d, rc) in enumerate(runs):
+        g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
+        assert_same(g, oracle_run(pol, ev), f"instance {j}")

@@ -80,3 +80,12 @@ def test_largest_frame_with_accumulators_compiles(G, entries):
     pol = W.Policy("big", W.HOOK_MEM_ACCESS, BIG_STACK_SHARED, [W.MapSpec("sh", W.MAP_ARRAY, 4, 8, entries, W.F_SHARED)])
     src = G.jit_source(pol.code, pol.hook, _shapes(pol), compile=True)
     assert "g_acc0" in src or "g_tag0" in src or "if (PRIV)" not in src
+
+
+def test_source_holds_no_map_addresses(G):
+    """Map addresses come from the run's map table, so the text carries only
+    shapes: program instances with same-shaped maps share one module."""
+    for pol in (W.stride_prefetch_policy(), W.latency_hist_policy(), W.gen_program(W.subseed(1003, 101))):
+        src = G.jit_source(pol.code, pol.hook, _shapes(pol))
+        assert "0x1000000" not in src and "0x2000000" not in src  # the stand-in descriptor/data addresses
+        assert "A.maptab" in src
