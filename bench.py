@@ -236,7 +236,7 @@ def bench_batched(G, W, rt, reps):
     }
 
 
-def bench_serving(G, W, rt, seconds, warm_s=0.2):
+def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
     """Open-loop Poisson trace (20k requests/s, 64 tenants, 32 programs,
     2^8..2^18 events per request, 256 MiB of hash map per tenant = 16 GiB
     resident) through the continuous server and the per-request baseline.
@@ -245,6 +245,7 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2):
 
     import numpy as np
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     progs = [W.gen_program(W.subseed(1004, 100 + p)) for p in range(32)]
     tenants = []
     for t in range(64):
@@ -254,6 +255,15 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2):
             ents = (1 << 22) if m.type == W.MAP_HASH else m.max_entries
             fds.append(rt.create_map(m.type, m.key_size, m.value_size, ents, m.flags))
         tenants.append((fds, rt.load_program(pol.code, pol.hook, fds)))
+    if jit:
+        # 32 distinct programs: the first 32 tenants compile them, the other
+        # 32 instances (same shapes) reuse the modules
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(8) as ex:
+            list(ex.map(lambda t: rt.jit_program(tenants[t][1]), range(32)))
+        for t in range(32, 64):
+            rt.jit_program(tenants[t][1])
+        log(f"serving: compiled 32 programs in {time.perf_counter() - t0:.1f} s")
     n_req = int(20000 * (seconds + warm_s))
     arrival, tenant, _, n_ev = W.serving_trace(n_req)
     slices = 64
@@ -297,6 +307,7 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2):
         }
     out["workload"] = (f"{n_req} requests, Poisson 20k/s, 64 tenants x 256 MiB resident hash map, 32 generated "
                        f"programs, 2^8..2^18 events per request, 4 GiB admission budget, first {warm_s}s excluded")
+    out["engine"] = "jit" if jit else "interp"
     return out
 
 
@@ -399,7 +410,7 @@ def main():
         forms = {}
         for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit")),
                         ("batched", lambda: bench_batched(G, W, rt, 2)),
-                        ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds))):
+                        ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit"))):
             log(f"form: {key}")
             try:
                 forms[key] = fn()

@@ -323,6 +323,13 @@ bool is_jump(uint32_t h) { return h >= H_JA && h <= H_JSLE32; }
 
 }  // namespace
 
+uint32_t jit_waves(uint32_t stack_bytes, bool event_parallel) {
+  if (!event_parallel) return 1;
+  uint32_t w = kJitMaxWaves;
+  while (w > 1 && (uint64_t)w * 64 * stack_bytes > (64u << 10)) w /= 2;
+  return w;
+}
+
 std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
                        const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
                        const std::vector<int>& ld_map, bool event_parallel, uint64_t* acc_words) {
@@ -330,9 +337,10 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
-  const uint32_t lds = stack_bytes ? kJitWaves * 64u * stack_bytes : 16u;
+  const uint32_t nw = jit_waves(stack_bytes, event_parallel);
+  const uint32_t lds = stack_bytes ? nw * 64u * stack_bytes : 16u;
   const int nr = J.n_rings ? J.n_rings : 1;
-  J.plan(U, lds + 16ull * kJitWaves * nr);
+  J.plan(U, lds + 16ull * nw * nr);
   if (acc_words) {
     *acc_words = 0;
     for (const Acc& a : J.acc)
@@ -341,7 +349,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   std::string o;
   o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
   o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
-  o += "#define GX_RING_SLOTS " + std::to_string(kJitWaves * nr) + "\n";
+  o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\nnamespace gx {\n\n";
   for (size_t k = 0; k < maps.size(); k++) o += map_fn(k, maps[k].second);
   bool any_acc = false;
@@ -416,7 +424,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
-  const std::string W = std::to_string(kJitWaves), T = std::to_string(64 * kJitWaves);
+  const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
   if (event_parallel)
     o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
        "  const uint32_t wave = threadIdx.x >> 6;\n"

@@ -11,14 +11,17 @@
 namespace gx {
 
 // Waves per block of a compiled program's event-parallel kernel (each block
-// loops over 64-event tiles, grid-stride).
-constexpr uint32_t kJitWaves = 4;
+// loops over 64-event tiles, grid-stride): as many as 64 KiB of LDS stack
+// frames allow, at most kJitMaxWaves.  More waves per block share one LDS
+// accumulator, so each block flushes it over more events.
+constexpr uint32_t kJitMaxWaves = 16;
+uint32_t jit_waves(uint32_t stack_bytes, bool event_parallel);
 
 // HIP source of one program: its micro-ops written out as straight-line
 // code with labels at jump targets, helpers called directly with the map
 // descriptors as constants, and the event-loop kernel of its mode:
-// gx_j_event_parallel (kJitWaves waves per block, grid-stride over 64-event
-// tiles) or gx_j_stream_seq (one wave per block).  Stack frames live in a
+// gx_j_event_parallel (jit_waves() waves per block, grid-stride over
+// 64-event tiles) or gx_j_stream_seq (one wave per block).  Stack frames live in a
 // static LDS array; each wave carves ring records from its own chunk of
 // reserved ring space.
 // ``maps`` holds (descriptor device address, descriptor contents) of every

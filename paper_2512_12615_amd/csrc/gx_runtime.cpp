@@ -371,13 +371,14 @@ hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes
   if (mode == 0) {
     void* args[] = {&A};
     const uint64_t tiles = (A.n_events + 63) / 64;
-    uint64_t nb = std::min<uint64_t>((tiles + kJitWaves - 1) / kJitWaves, kJitMaxBlocks);
+    const uint32_t nw = jit_waves(p->v.stack_bytes, true);
+    uint64_t nb = std::min<uint64_t>((tiles + nw - 1) / nw, kJitMaxBlocks);
     // each block flushes its accumulators once: give every block at least
     // as many events as it flushes words (but keep one block per CU)
     if (p->jacc_words) nb = std::min(nb, std::max<uint64_t>(256, A.n_events / p->jacc_words));
     if (blocks_override) nb = blocks_override;
     const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
-    return hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * kJitWaves, 1, 1, 0, s, args, nullptr);
+    return hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * nw, 1, 1, 0, s, args, nullptr);
   }
   void* args[] = {&A, &lanes, &qstride, &qend_last};
   return hipModuleLaunchKernel(p->jf_seq, (A.n_queues + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);

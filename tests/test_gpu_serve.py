@@ -22,23 +22,27 @@ def rt():
     r.close()
 
 
-def _tenants(rt, k_tenants, k_programs):
+def _tenants(rt, k_tenants, k_programs, jit=False):
     progs = [W.gen_program(W.subseed(1004, 100 + p)) for p in range(k_programs)]
     ten = []
     for t in range(k_tenants):
         pol = progs[t % k_programs]
         fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
-        ten.append((pol, fds, rt.load_program(pol.code, pol.hook, fds)))
+        prog = rt.load_program(pol.code, pol.hook, fds)
+        if jit:
+            rt.jit_program(prog)
+        ten.append((pol, fds, prog))
     return ten
 
 
-@pytest.mark.parametrize("mode,borrow", [(0, False), (1, False), (0, True)])
-def test_serve_same_alone_and_in_mix(rt, mode, borrow):
+@pytest.mark.parametrize("mode,borrow,jit", [(0, False, False), (1, False, False), (0, True, False), (0, True, True),
+                                             (1, False, True)])
+def test_serve_same_alone_and_in_mix(rt, mode, borrow, jit):
     import torch
     from paper_2512_12615_amd import gxbpf as G
     from oracle import oracle as O
-    print(f"serve mode={mode} borrow={borrow}", flush=True)
-    ten = _tenants(rt, 8, 4)
+    print(f"serve mode={mode} borrow={borrow} jit={jit}", flush=True)
+    ten = _tenants(rt, 8, 4, jit)
     arrival, tenant, _, n_ev = W.serving_trace(80, seed=77, tenants=8, min_log2=6, max_log2=12)
     reqs = [(i, int(t), W.gen_mem_uniform(int(n), 5000 + i)) for i, (t, n) in enumerate(zip(tenant, n_ev))]
     srv = G.Server(rt, budget_bytes=1 << 22, streams=3, mode=mode)
