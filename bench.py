@@ -263,7 +263,12 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
             list(ex.map(lambda t: rt.jit_program(tenants[t][1]), range(32)))
         for t in range(32, 64):
             rt.jit_program(tenants[t][1])
-        log(f"serving: compiled 32 programs in {time.perf_counter() - t0:.1f} s")
+        # the batched (continuous) path: four program sets of 8 programs
+        # (16 tenants) each, whose runs share one persistent launch per set
+        with ThreadPoolExecutor(4) as ex:
+            list(ex.map(lambda k: rt.jit_program_set([tenants[t][1] for t in range(64) if (t % 32) % 4 == k]),
+                        range(4)))
+        log(f"serving: compiled 32 programs and 4 program sets in {time.perf_counter() - t0:.1f} s")
     n_req = int(20000 * (seconds + warm_s))
     arrival, tenant, _, n_ev = W.serving_trace(n_req)
     slices = 64

@@ -166,6 +166,20 @@ typedef struct gx_tune {
 int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size, uint32_t* d_rc,
                 void* stream, gx_tune* out);
 
+/* Compile several loaded programs (at most 64, each once) into one module
+ * whose persistent kernel serves the batched form: in later gx_run_batches
+ * calls (and in the served form), the runs of all programs of a set in one
+ * phase share one persistent launch, as the interpreter's runs do, instead
+ * of one launch per run.  Instances of one program with same-shaped maps
+ * share one copy of the code.  A program belongs to the set of its latest
+ * call.
+ * Plain gx_run_batch runs keep using gx_jit_program's form or the
+ * interpreter.  Results are identical to the interpreter's.  Returns the set
+ * id (>= 0), -EINVAL for a bad or repeated fd, -EIO if compilation fails (log
+ * in ``log``).  Thread-safe against concurrent gx_jit_program /
+ * gx_jit_program_set calls on other programs, not against gx_load_program. */
+int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, uint32_t log_size);
+
 /* The HIP source gx_jit_program would compile for a program (no device
  * needed; map descriptors get stand-in addresses).  Same program and shape
  * arguments as gx_verify.  With compile != 0 the source is also compiled
@@ -175,6 +189,12 @@ int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
  * in out). */
 int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
                       uint32_t n_maps, int compile, char* out, uint64_t cap);
+/* The same for a program set (gx_jit_program_set): n_progs programs whose
+ * slots are concatenated in ``insns`` (n_insns[i] each), hooks[i], and map
+ * shapes concatenated in ``map_shapes`` (5 u32 per map, n_maps[i] maps). */
+int64_t gx_jit_set_source(const uint64_t* insns, const uint32_t* n_insns, const uint32_t* hooks,
+                          const uint32_t* map_shapes, const uint32_t* n_maps, uint32_t n_progs, int compile, char* out,
+                          uint64_t cap);
 
 /* Run a program over n_events records at d_events (device memory, record
  * size given by the hook) asynchronously on ``stream``; writes the u32 return

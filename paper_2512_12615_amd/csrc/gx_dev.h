@@ -765,4 +765,29 @@ __device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q
   }
 }
 
+// Persistent loop of the batched form: each wave claims work items (run,
+// chunk) from a counter until none is left and calls f(batch, chunk).  The
+// tables are read-only for the launch, so they are read with scalar loads.
+template <class F>
+__device__ __forceinline__ void batched_items(const BatchDev* B, const uint2* items, uint32_t n_items,
+                                              uint32_t* next, F&& f) {
+  typedef const __attribute__((address_space(4))) uint64_t cu64;
+  static_assert(sizeof(BatchDev) % 8 == 0, "BatchDev is loaded as 8-byte words");
+  for (;;) {
+    uint32_t it = 0;
+    if (lane_id() == 0) it = atomicAdd(next, 1u);
+    it = __builtin_amdgcn_readlane(it, 0);
+    if (it >= n_items) break;
+    const uint64_t wv = ((const cu64*)items)[it];
+    const uint32_t run = (uint32_t)wv, chunk = (uint32_t)(wv >> 32);
+    uint64_t words[sizeof(BatchDev) / 8];
+    const cu64* src = (const cu64*)(B + run);
+#pragma unroll
+    for (uint32_t k = 0; k < sizeof(BatchDev) / 8; k++) words[k] = src[k];
+    BatchDev bd;
+    __builtin_memcpy(&bd, words, sizeof(BatchDev));
+    f(bd, chunk);
+  }
+}
+
 }  // namespace gx

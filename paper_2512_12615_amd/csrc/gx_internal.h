@@ -116,6 +116,8 @@ struct BatchDev {
   uint32_t lanes;
   uint32_t qstride;
   uint32_t qend_last;  // position after the run's last queue in order[]
+  uint32_t slot;       // compiled program sets: the program's index in its set
+  uint32_t pad;
 };
 
 // Stable-partition job of one stream-sequential run.

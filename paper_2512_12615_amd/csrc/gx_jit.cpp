@@ -330,27 +330,26 @@ uint32_t jit_waves(uint32_t stack_bytes, bool event_parallel) {
   return w;
 }
 
-std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
-                       const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       const std::vector<int>& ld_map, bool event_parallel, uint64_t* acc_words) {
-  JMaps J(maps, mem_map, ld_map);
+namespace {
+
+// One program's part of a source, in namespace gx::<ns>: map descriptor
+// functions, LDS accumulators (when ``allow_acc``) and struct Prog<PRIV>
+// with begin / end / run.  ``lds_used``: LDS the kernel already takes.
+std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, uint64_t lds_used,
+                      uint64_t* acc_words) {
+  const std::vector<Uop>& U = *P.U;
+  const auto& maps = *P.maps;
+  JMaps J(maps, *P.mem_map, *P.ld_map);
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
-  const uint32_t nw = jit_waves(stack_bytes, event_parallel);
-  const uint32_t lds = stack_bytes ? nw * 64u * stack_bytes : 16u;
-  const int nr = J.n_rings ? J.n_rings : 1;
-  J.plan(U, lds + 16ull * nw * nr);
+  if (allow_acc) J.plan(U, lds_used);
   if (acc_words) {
     *acc_words = 0;
     for (const Acc& a : J.acc)
       if (a.kind) *acc_words += a.words;
   }
-  std::string o;
-  o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
-  o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
-  o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
-  o += "#include \"gx_dev.h\"\n\nnamespace gx {\n\n";
+  std::string o = "namespace gx {\nnamespace " + ns + " {\n\n";
   for (size_t k = 0; k < maps.size(); k++) o += map_fn(k, maps[k].second);
   bool any_acc = false;
   for (size_t k = 0; k < maps.size(); k++) {
@@ -366,9 +365,10 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
   o += "\ntemplate <bool PRIV>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
        "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave reserves at once, per ring\n\n";
-  // begin / end: open and close the wave's ring chunks and the block's accumulators
-  // a chunk is the ring's capacity over four times the waves of the
-  // launch (64 B to 8 KiB): chunks in flight then hold at most a quarter
+  // begin / end: open and close the wave's ring chunks and the block's
+  // accumulators.  A chunk is the ring's capacity over four times the waves
+  // of the launch (64 B to 8 KiB): chunks in flight then hold at most a
+  // quarter of the ring.
   o += "  __device__ __forceinline__ void begin(const RunArgs& A) {\n    (void)A;\n";
   o += "    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64u);\n    (void)waves;\n";
   for (size_t k = 0; k < maps.size(); k++)
@@ -414,7 +414,7 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
        "const Stk stk, uint64_t& steps) {\n";
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
-  o += "  uint64_t r10 = " + std::to_string(stack_bytes) + "ull;\n";
+  o += "  uint64_t r10 = " + std::to_string(P.stack_bytes) + "ull;\n";
   for (size_t k = 0; k < maps.size(); k++)
     o += "  const MapDev M" + std::to_string(k) + " = gx_map" + std::to_string(k) + "(A);\n";
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
@@ -423,22 +423,74 @@ std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
     emit_uop(o, U[pc], pc, J);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
-  o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace gx\n\n";
+  o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace " + ns + "\n}  // namespace gx\n\n";
+  return o;
+}
+
+int ring_count(const JitProg& P) {
+  int n = 0;
+  for (auto& m : *P.maps) n += m.second.type == MAP_RINGBUF;
+  return n;
+}
+
+}  // namespace
+
+std::string jit_source(const JitProg& P, uint64_t* acc_words) {
+  const uint32_t nw = jit_waves(P.stack_bytes, P.event_parallel);
+  const uint32_t lds = P.stack_bytes ? nw * 64u * P.stack_bytes : 16u;
+  const int nr = std::max(ring_count(P), 1);
+  std::string o;
+  o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
+  o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
+  o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
+  o += "#include \"gx_dev.h\"\n\n";
+  o += emit_prog(P, "p0", true, lds + 16ull * nw * nr, acc_words);
   const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
-  if (event_parallel)
+  if (P.event_parallel)
     o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
        "  const uint32_t wave = threadIdx.x >> 6;\n"
-       "  gx::Stk stk{wave * 64u * " + std::to_string(stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
+       "  gx::Stk stk{wave * 64u * " + std::to_string(P.stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
        "u + threadIdx.x};\n"
-       "  gx::Prog<true> P{wave};\n  P.begin(A);\n"
+       "  gx::p0::Prog<true> P{wave};\n  P.begin(A);\n"
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
        "  P.end(A);\n}\n\n";
   else
     o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
-       "  gx::Prog<false> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
+       "  gx::p0::Prog<false> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
        "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, qend_last, stk, steps);\n"
        "  P.end(A);\n}\n";
+  return o;
+}
+
+std::string jit_set_source(const std::vector<JitProg>& progs) {
+  uint32_t stack = 8;
+  int nr = 1;
+  for (auto& P : progs) {
+    stack = std::max(stack, P.stack_bytes);
+    nr = std::max(nr, ring_count(P));
+  }
+  std::string o;
+  o += "#define GX_LDS_BYTES " + std::to_string(64u * stack) + "\n";
+  o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
+  o += "#define GX_RING_SLOTS " + std::to_string(nr) + "\n";
+  o += "#include \"gx_dev.h\"\n\n";
+  for (size_t k = 0; k < progs.size(); k++) o += emit_prog(progs[k], "p" + std::to_string(k), false, 0, nullptr);
+  o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_set(const gx::BatchDev* B, const uint2* items, "
+       "uint32_t n_items, uint32_t* next) {\n"
+       "  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
+       "  gx::batched_items(B, items, n_items, next, [&](const gx::BatchDev& bd, uint32_t chunk) {\n"
+       "    uint64_t steps = 0;\n    switch (bd.slot) {\n";
+  for (size_t k = 0; k < progs.size(); k++) {
+    const std::string K = std::to_string(k);
+    o += "      case " + K + "u: {\n        gx::p" + K + "::Prog<false> P{0u};\n        P.begin(bd.A);\n";
+    if (progs[k].event_parallel)
+      o += "        gx::event_tile(P, bd.A, (uint64_t)chunk * 64u, stk, steps);\n";
+    else
+      o += "        gx::stream_wave(P, bd.A, chunk * bd.lanes, bd.lanes, bd.qstride, bd.qend_last, stk, steps);\n";
+    o += "        P.end(bd.A);\n        break;\n      }\n";
+  }
+  o += "      default: break;\n    }\n  });\n}\n";
   return o;
 }
 

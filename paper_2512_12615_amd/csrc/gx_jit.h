@@ -17,28 +17,36 @@ namespace gx {
 constexpr uint32_t kJitMaxWaves = 16;
 uint32_t jit_waves(uint32_t stack_bytes, bool event_parallel);
 
+// A verified program as the code generator sees it: its micro-ops, frame
+// size, maps as (descriptor device address, descriptor contents) in its
+// map-table order, the verifier's map of each map-value access and of each
+// lddw map reference (by slot), and its execution mode.
+struct JitProg {
+  const std::vector<Uop>* U;
+  uint32_t stack_bytes;
+  const std::vector<std::pair<uint64_t, MapDev>>* maps;
+  const std::vector<int>* mem_map;
+  const std::vector<int>* ld_map;
+  bool event_parallel;
+};
+
 // HIP source of one program: its micro-ops written out as straight-line
-// code with labels at jump targets, helpers called directly with the map
-// descriptors as constants, and the event-loop kernel of its mode:
-// gx_j_event_parallel (jit_waves() waves per block, grid-stride over
-// 64-event tiles) or gx_j_stream_seq (one wave per block).  Stack frames live in a
-// static LDS array; each wave carves ring records from its own chunk of
-// reserved ring space.
-// ``maps`` holds (descriptor device address, descriptor contents) of every
-// map the program uses, in its map-table order; the generated code gets each
-// map's shape as constants, so key sizes, slot masks and strides fold into
-// the code.
-// ``mem_map`` is the verifier's map of each map-value access (by slot):
-// the event-parallel kernel sums the atomics of shared maps in LDS.
+// code with labels at jump targets, helpers called directly with each map's
+// shape as constants (sizes, masks and strides fold into the code), and the
+// event-loop kernel of its mode: gx_j_event_parallel (jit_waves() waves per
+// block, grid-stride over 64-event tiles; shared-map atomics summed in LDS)
+// or gx_j_stream_seq (one wave per block).  Stack frames live in a static
+// LDS array; each wave carves ring records from its own chunk of reserved
+// ring space.  The source holds no map address (those come from
+// RunArgs::maptab), so instances with same-shaped maps share it.
 // *acc_words receives the LDS accumulator words a block flushes at its end
-// (0: no accumulators), which the launch uses to size its grid.
-// ``ld_map`` is the verifier's map of each lddw map reference.  Only the
-// kernel of the program's execution mode is emitted.  The source holds the
-// maps' shapes but none of their addresses (those come from RunArgs::maptab),
-// so program instances with same-shaped maps compile to the same source.
-std::string jit_source(const std::vector<Uop>& U, uint32_t stack_bytes,
-                       const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mem_map,
-                       const std::vector<int>& ld_map, bool event_parallel, uint64_t* acc_words = nullptr);
+// (0: none), which the launch uses to size its grid.
+std::string jit_source(const JitProg& p, uint64_t* acc_words = nullptr);
+
+// HIP source of a program set: every program in its own namespace and one
+// persistent kernel gx_j_set over the batched form's work items, which picks
+// the program by BatchDev::slot (one wave per block; no LDS accumulators).
+std::string jit_set_source(const std::vector<JitProg>& progs);
 
 // Compile a generated source for gfx950.  Returns 0 and the code object, or
 // -EIO with the compiler log.

@@ -32,6 +32,7 @@ hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, ui
                                  uint8_t* sorted, hipStream_t s);
 hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
                           uint32_t waves, uint32_t stack_max, hipStream_t s);
+hipError_t launch_zero(uint32_t* p, uint32_t n, hipStream_t s);
 }  // namespace gx
 
 using namespace gx;
@@ -41,6 +42,11 @@ namespace {
 // Blocks of a compiled event-parallel launch: enough for every CU to hold
 // several (256 CUs), each looping over tiles beyond that.
 constexpr uint64_t kJitMaxBlocks = 2048;
+// Program sets one phase launches at most (each takes one of the runtime's
+// item counters; the interpreter takes counter 0 of 16)
+constexpr size_t kMaxSetsPerPhase = 15;
+// Programs one compiled set holds at most
+constexpr uint32_t kMaxSetPrograms = 64;
 
 struct MapObj {
   bool live = false;
@@ -68,6 +74,9 @@ struct ProgObj {
   uint64_t jacc_words = 0;  // LDS accumulator words each block flushes
   // launch shape chosen by gx_autotune (0: default)
   uint32_t tuned_lanes = 0, tuned_qbits = 0, tuned_blocks = 0;
+  // member of a compiled program set: its set and its slot there (-1: none)
+  int set_id = -1;
+  uint32_t set_slot = 0;
 };
 
 // Launch shape of one run.
@@ -119,6 +128,11 @@ struct gx_rt {
   };
   std::map<std::string, JitMod> jit_cache;
   std::mutex jit_mu;
+  // compiled program sets (gx_jit_program_set): persistent kernel per set
+  struct JitSet {
+    hipFunction_t f = nullptr;
+  };
+  std::vector<JitSet> sets;
   // batched form: compiled runs of a phase run side by side on these
   static constexpr int kSide = 4;
   hipStream_t side[kSide] = {};
@@ -447,6 +461,55 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   if (e != hipSuccess) return to_errno(e);
   rt->stats.events += n_events;
   note_stream(rt, s);
+  return 0;
+}
+
+// A program verified and pre-decoded against stand-in map descriptors, for
+// showing or compiling generated source without a device.
+struct StandIn {
+  Verdict v;
+  std::vector<Uop> U;
+  std::vector<std::pair<uint64_t, MapDev>> maps;
+  std::string log;
+  JitProg prog() const { return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel}; }
+};
+
+int stand_in(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes, uint32_t n_maps,
+             StandIn* out) {
+  if (!insns && n_insns) return -EINVAL;
+  if (n_insns > (uint32_t)kMaxInsns) return -E2BIG;
+  uint32_t rs, so, ss;
+  if (!hook_layout((int)hook_type, &rs, &so, &ss)) return -EINVAL;
+  std::vector<MapShape> shapes(n_maps);
+  std::vector<int> fds(n_maps);
+  std::vector<MapRef> refs(n_maps);
+  for (uint32_t i = 0; i < n_maps; i++) {
+    shapes[i] = MapShape{map_shapes[5 * i], map_shapes[5 * i + 1], map_shapes[5 * i + 2], map_shapes[5 * i + 3],
+                         map_shapes[5 * i + 4]};
+    fds[i] = (int)i;
+    refs[i] = MapRef{map_shapes[5 * i], 0x100000000ull + 64ull * i};  // stand-in descriptor addresses
+  }
+  for (uint32_t i = 0; i < n_maps; i++) {
+    MapDev d{};
+    d.type = shapes[i].type;
+    d.key_size = shapes[i].key_size;
+    d.value_size = shapes[i].value_size;
+    d.max_entries = shapes[i].max_entries;
+    d.flags = shapes[i].flags;
+    d.vstride = (d.value_size + 7) & ~7u;
+    d.slot_mask = d.type == MAP_RINGBUF ? d.max_entries - 1
+                  : d.type == MAP_HASH  ? (uint32_t)next_pow2(std::max<uint64_t>(2ull * d.max_entries, 16)) - 1
+                                        : 0;
+    d.sstride = 8 + ((d.key_size + 7) & ~7u);
+    out->maps.push_back({refs[i].desc, d});
+  }
+  std::vector<Insn> P = decode_insns(insns, n_insns);
+  out->v = verify(P, (int)hook_type, shapes, fds);
+  if (!out->v.ok) {
+    out->log = out->v.log;
+    return -EACCES;
+  }
+  out->U = predecode(P, out->v, refs);
   return 0;
 }
 
@@ -887,7 +950,8 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   }
   uint64_t acc_words = 0;
   const std::string src =
-      jit_source(p->uops, p->v.stack_bytes, maps, p->v.mem_map, p->v.ld_map, p->v.event_parallel, &acc_words);
+      jit_source(JitProg{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel},
+                 &acc_words);
   auto adopt = [&](const gx_rt::JitMod& jm) {
     p->jf_ep = jm.fe;
     p->jf_seq = jm.fs;
@@ -924,50 +988,116 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   return 0;
 }
 
-int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
-                      uint32_t n_maps, int compile, char* out, uint64_t cap) {
-  if (!insns && n_insns) return -EINVAL;
-  if (n_insns > (uint32_t)kMaxInsns) return -E2BIG;
-  uint32_t rs, so, ss;
-  if (!hook_layout((int)hook_type, &rs, &so, &ss)) return -EINVAL;
-  std::vector<MapShape> shapes(n_maps);
-  std::vector<int> fds(n_maps);
-  std::vector<MapRef> refs(n_maps);
-  for (uint32_t i = 0; i < n_maps; i++) {
-    shapes[i] = MapShape{map_shapes[5 * i], map_shapes[5 * i + 1], map_shapes[5 * i + 2], map_shapes[5 * i + 3],
-                         map_shapes[5 * i + 4]};
-    fds[i] = (int)i;
-    refs[i] = MapRef{map_shapes[5 * i], 0x100000000ull + 64ull * i};  // stand-in descriptor addresses
+int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, uint32_t log_size) {
+  if (!rt || !prog_fds || n == 0 || n > kMaxSetPrograms) return -EINVAL;
+  std::vector<ProgObj*> ps;
+  std::vector<std::vector<std::pair<uint64_t, MapDev>>> maps(n);
+  std::vector<JitProg> jp;
+  for (uint32_t i = 0; i < n; i++) {
+    ProgObj* p = get_prog(rt, prog_fds[i]);
+    if (!p) return -EINVAL;
+    for (ProgObj* q : ps)
+      if (q == p) return -EINVAL;  // each program once
+    ps.push_back(p);
+    for (int fd : p->fds) {
+      MapObj* m = get_map(rt, fd);
+      if (!m) return -EINVAL;
+      maps[i].push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
+    }
   }
-  std::vector<std::pair<uint64_t, MapDev>> maps;
-  for (uint32_t i = 0; i < n_maps; i++) {
-    MapDev d{};
-    d.type = shapes[i].type;
-    d.key_size = shapes[i].key_size;
-    d.value_size = shapes[i].value_size;
-    d.max_entries = shapes[i].max_entries;
-    d.flags = shapes[i].flags;
-    d.vstride = (d.value_size + 7) & ~7u;
-    d.slot_mask = d.type == MAP_RINGBUF ? d.max_entries - 1
-                  : d.type == MAP_HASH  ? (uint32_t)next_pow2(std::max<uint64_t>(2ull * d.max_entries, 16)) - 1
-                                        : 0;
-    d.sstride = 8 + ((d.key_size + 7) & ~7u);
-    d.data = (uint8_t*)(uintptr_t)(0x200000000ull + (1ull << 28) * i);  // stand-in addresses
-    d.slots = d.data + (1ull << 27);
-    d.ctrl = (uint64_t*)(d.data + (1ull << 27) + (1ull << 26));
-    maps.push_back({refs[i].desc, d});
+  // instances of one program with same-shaped maps share a slot (their
+  // generated text is the same)
+  std::vector<uint32_t> slot(n);
+  std::map<std::string, uint32_t> uniq;
+  for (uint32_t i = 0; i < n; i++) {
+    const JitProg q{&ps[i]->uops, ps[i]->v.stack_bytes, &maps[i], &ps[i]->v.mem_map, &ps[i]->v.ld_map,
+                    ps[i]->v.event_parallel};
+    auto ins = uniq.emplace(jit_source(q), (uint32_t)jp.size());
+    if (ins.second) jp.push_back(q);
+    slot[i] = ins.first->second;
   }
-  std::vector<Insn> P = decode_insns(insns, n_insns);
-  Verdict v = verify(P, (int)hook_type, shapes, fds);
-  if (!v.ok) {
-    write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), v.log);
-    return -EACCES;
+  const std::string src = jit_set_source(jp);
+  hipFunction_t f = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(rt->jit_mu);
+    auto it = rt->jit_cache.find(src);
+    if (it != rt->jit_cache.end()) f = it->second.fs;
   }
-  std::string src = jit_source(predecode(P, v, refs), v.stack_bytes, maps, v.mem_map, v.ld_map, v.event_parallel);
+  if (!f) {
+    std::vector<char> code;
+    std::string lg;
+    int r = jit_compile(src, &code, &lg);
+    write_log(log, log_size, lg);
+    if (r) return r;
+    DevGuard g(rt->dev);
+    gx_rt::JitMod jm;
+    if (hipModuleLoadData(&jm.mod, code.data()) != hipSuccess) return -EIO;
+    if (hipModuleGetFunction(&jm.fs, jm.mod, "gx_j_set") != hipSuccess) {
+      (void)hipModuleUnload(jm.mod);
+      return -EIO;
+    }
+    std::lock_guard<std::mutex> lk(rt->jit_mu);
+    auto ins = rt->jit_cache.emplace(src, jm);
+    if (!ins.second) (void)hipModuleUnload(jm.mod);
+    f = ins.first->second.fs;
+  } else {
+    write_log(log, log_size, "");
+  }
+  std::lock_guard<std::mutex> lk(rt->jit_mu);
+  const int id = (int)rt->sets.size();
+  rt->sets.push_back(gx_rt::JitSet{f});
+  for (uint32_t i = 0; i < n; i++) {
+    ps[i]->set_id = id;
+    ps[i]->set_slot = slot[i];
+  }
+  return id;
+}
+
+int64_t gx_jit_set_source(const uint64_t* insns, const uint32_t* n_insns, const uint32_t* hooks,
+                          const uint32_t* map_shapes, const uint32_t* n_maps, uint32_t n_progs, int compile, char* out,
+                          uint64_t cap) {
+  if (!insns || !n_insns || !hooks || !n_maps || n_progs == 0 || n_progs > kMaxSetPrograms) return -EINVAL;
+  std::vector<StandIn> sp(n_progs);
+  std::vector<JitProg> jp;
+  const uint64_t* ip = insns;
+  const uint32_t* sh = map_shapes;
+  for (uint32_t i = 0; i < n_progs; i++) {
+    int r = stand_in(ip, n_insns[i], hooks[i], sh, n_maps[i], &sp[i]);
+    if (r) {
+      write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), sp[i].log);
+      return r;
+    }
+    ip += n_insns[i];
+    sh += 5 * n_maps[i];
+  }
+  for (auto& x : sp) jp.push_back(x.prog());
+  std::string src = jit_set_source(jp);
   if (compile) {
     std::vector<char> code;
     std::string lg;
     int r = jit_compile(src, &code, &lg);
+    if (r) {
+      write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), lg);
+      return r;
+    }
+  }
+  if (out && cap) write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), src);
+  return (int64_t)src.size();
+}
+
+int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes,
+                      uint32_t n_maps, int compile, char* out, uint64_t cap) {
+  StandIn si;
+  int r = stand_in(insns, n_insns, hook_type, map_shapes, n_maps, &si);
+  if (r) {
+    if (r == -EACCES) write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), si.log);
+    return r;
+  }
+  std::string src = jit_source(si.prog());
+  if (compile) {
+    std::vector<char> code;
+    std::string lg;
+    r = jit_compile(src, &code, &lg);
     if (r) {
       write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), lg);
       return r;
@@ -1102,9 +1232,18 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   // runs of compiled programs get their own kernels (below); the rest are
   // work items of the persistent interpreter
   std::vector<uint32_t> jit_runs;
+  std::map<int, std::vector<uint2>> set_items;  // set id -> its work items
   for (auto& oc : order_by_cost) {
-    const BatchDev& bd = B[oc.second];
-    if (bprog[oc.second]->jmod) {
+    BatchDev& bd = B[oc.second];
+    const ProgObj* bp = bprog[oc.second];
+    if (bp->set_id >= 0 && (set_items.count(bp->set_id) || set_items.size() < kMaxSetsPerPhase)) {
+      bd.slot = bp->set_slot;
+      uint32_t nchunks = bd.mode == 0 ? (uint32_t)((bd.A.n_events + 63) / 64) : (bd.A.n_queues + bd.lanes - 1) / bd.lanes;
+      auto& v = set_items[bp->set_id];
+      for (uint32_t c = 0; c < nchunks; c++) v.push_back(make_uint2(oc.second, c));
+      continue;
+    }
+    if (bp->jmod) {
       jit_runs.push_back(oc.second);
       continue;
     }
@@ -1113,8 +1252,13 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   }
   // pack the tables: batches | items | jobs | tiles (each 64-byte aligned)
   auto al = [](size_t x) { return (x + 63) & ~(size_t)63; };
-  size_t ob = 0, oi = al(ob + B.size() * sizeof(BatchDev)), oj = al(oi + items.size() * sizeof(uint2)),
-         ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
+  size_t ob = 0, oi = al(ob + B.size() * sizeof(BatchDev)), os_ = al(oi + items.size() * sizeof(uint2));
+  std::vector<std::pair<int, size_t>> set_off;  // (set id, offset of its items)
+  for (auto& si : set_items) {
+    set_off.push_back({si.first, os_});
+    os_ = al(os_ + si.second.size() * sizeof(uint2));
+  }
+  size_t oj = os_, ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
   // a staging slot whose previous copy has long completed
   const uint32_t k = rt->stage_next++ % gx_rt::kStage;
   if (rt->stage_ring_used[k] && hipEventSynchronize(rt->stage_ring_ev[k]) != hipSuccess) return -EIO;
@@ -1134,6 +1278,10 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
   std::memcpy(h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
   std::memcpy(h_stage + oi, items.data(), items.size() * sizeof(uint2));
+  for (auto& so : set_off) {
+    const auto& v = set_items[so.first];
+    std::memcpy(h_stage + so.second, v.data(), v.size() * sizeof(uint2));
+  }
   if (!J.empty()) std::memcpy(h_stage + oj, J.data(), J.size() * sizeof(PartJob));
   if (!tiles.empty()) std::memcpy(h_stage + ot, tiles.data(), tiles.size() * sizeof(uint2));
   if (hipMemcpyAsync(d_tables, h_stage, total, hipMemcpyHostToDevice, s) != hipSuccess) return -EIO;
@@ -1149,18 +1297,36 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   // compiled runs: their own kernels, side by side on the side streams,
   // after the partition; joined back into s
   int used_side = 0;
-  if (e == hipSuccess && !jit_runs.empty()) {
-    (void)hipEventRecord(rt->fork_ev, s);
-    for (size_t x = 0; x < jit_runs.size() && e == hipSuccess; x++) {
-      const uint32_t b = jit_runs[x];
-      hipStream_t ss = rt->side[x % gx_rt::kSide];
-      if ((int)x < gx_rt::kSide) {
-        (void)hipStreamWaitEvent(ss, rt->fork_ev, 0);
-        used_side++;
-      }
-      e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, knobs_of(bprog[b]).blocks,
-                     ss);
+  size_t x = 0;  // launches handed to side streams so far
+  auto side = [&]() {
+    hipStream_t ss = rt->side[x % gx_rt::kSide];
+    if ((int)x < gx_rt::kSide) {
+      (void)hipStreamWaitEvent(ss, rt->fork_ev, 0);
+      used_side++;
     }
+    x++;
+    return ss;
+  };
+  if (e == hipSuccess && (!jit_runs.empty() || !set_off.empty())) (void)hipEventRecord(rt->fork_ev, s);
+  // program sets: one persistent launch each, with a counter of its own
+  for (size_t k = 0; k < set_off.size() && e == hipSuccess; k++) {
+    hipStream_t ss = side();
+    const auto& v = set_items[set_off[k].first];
+    const BatchDev* db = (const BatchDev*)(d_tables + ob);
+    const uint2* di = (const uint2*)(d_tables + set_off[k].second);
+    uint32_t ni = (uint32_t)v.size();
+    uint32_t* next = rt->d_next + 1 + k;
+    uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
+    uint32_t waves = (uint32_t)std::min<size_t>(v.size(), 256 * per_cu);
+    e = launch_zero(next, 1, ss);
+    void* args[] = {&db, &di, &ni, &next};
+    if (e == hipSuccess)
+      e = hipModuleLaunchKernel(rt->sets[set_off[k].first].f, waves, 1, 1, 64, 1, 1, 0, ss, args, nullptr);
+  }
+  for (size_t y = 0; y < jit_runs.size() && e == hipSuccess; y++) {
+    const uint32_t b = jit_runs[y];
+    e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, knobs_of(bprog[b]).blocks,
+                   side());
   }
   if (e == hipSuccess && !items.empty()) {
     uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
@@ -1177,7 +1343,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   (void)hipEventRecord(rt->ws_event, s);
   rt->ws_used = true;
   if (e != hipSuccess) return to_errno(e);
-  rt->stats.launches += (J.empty() ? 0 : 5) + (items.empty() ? 0 : 2) + jit_runs.size();
+  rt->stats.launches += (J.empty() ? 0 : 5) + (items.empty() ? 0 : 2) + jit_runs.size() + 2 * set_off.size();
   for (auto& bd : B) rt->stats.events += bd.A.n_events;
   note_stream(rt, s);
   return 0;

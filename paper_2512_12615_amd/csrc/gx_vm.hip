@@ -320,33 +320,15 @@ extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint
 
 extern "C" __global__ void __launch_bounds__(64) gx_k_batched(const BatchDev* B, const uint2* items, uint32_t n_items,
                                                               uint32_t* next) {
-  typedef const __attribute__((address_space(4))) uint64_t cu64;
-  static_assert(sizeof(BatchDev) % 8 == 0, "BatchDev is loaded as 8-byte words");
   Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
   Interp I;
-  uint64_t steps = 0;
-  for (;;) {
-    uint32_t it = 0;
-    if (lane_id() == 0) it = atomicAdd(next, 1u);
-    it = rdlane(it, 0);
-    if (it >= n_items) break;
-    // tables are read-only for the launch: scalar loads
-    const uint64_t wv = ((const cu64*)items)[it];
-    const uint32_t run = (uint32_t)wv, chunk = (uint32_t)(wv >> 32);
-    uint64_t words[sizeof(BatchDev) / 8];
-    const cu64* src = (const cu64*)(B + run);
-#pragma unroll
-    for (uint32_t k = 0; k < sizeof(BatchDev) / 8; k++) words[k] = src[k];
-    BatchDev bdv;
-    __builtin_memcpy(&bdv, words, sizeof(BatchDev));
-    const BatchDev* bd = &bdv;
-    const RunArgs& A = bdv.A;
-    steps = 0;
-    if (bd->mode == 0)
-      event_tile(I, A, (uint64_t)chunk * 64u, stk, steps);
+  batched_items(B, items, n_items, next, [&](const BatchDev& bd, uint32_t chunk) {
+    uint64_t steps = 0;
+    if (bd.mode == 0)
+      event_tile(I, bd.A, (uint64_t)chunk * 64u, stk, steps);
     else
-      stream_wave(I, A, chunk * bd->lanes, bd->lanes, bd->qstride, bd->qend_last, stk, steps);
-  }
+      stream_wave(I, bd.A, chunk * bd.lanes, bd.lanes, bd.qstride, bd.qend_last, stk, steps);
+  });
 }
 
 extern "C" __global__ void gx_k_zero(uint32_t* p, uint32_t n) {
@@ -596,6 +578,11 @@ hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, ui
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gx_k_part_scatter, dim3(n_tiles), dim3(64), L * 4, s, d_jobs, d_tiles,
                      (const uint32_t*)counts, order, sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(uint32_t* p, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_zero, dim3(1), dim3(64), 0, s, p, n);
   return hipGetLastError();
 }
 

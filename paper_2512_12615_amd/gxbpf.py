@@ -43,7 +43,8 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_autotune", "gx_jit_program", "gx_jit_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_run_batches", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
+           "gx_jit_set_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
@@ -100,8 +101,11 @@ def lib():
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_jit_program.argtypes = [vp, C.c_int, C.c_char_p, u32]
+    L.gx_jit_program_set.argtypes = [vp, vp, u32, C.c_char_p, u32]
     L.gx_jit_source.argtypes = [vp, u32, u32, vp, u32, C.c_int, C.c_char_p, u64]
     L.gx_jit_source.restype = i64
+    L.gx_jit_set_source.argtypes = [vp, vp, vp, vp, vp, u32, C.c_int, C.c_char_p, u64]
+    L.gx_jit_set_source.restype = i64
     L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.gx_drain_ringbuf.restype = i64
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
@@ -157,6 +161,25 @@ def jit_source(code: bytes, hook: int, shapes, compile: bool = False) -> str:
                             len(sh), int(compile), out, cap)
     if r < 0:
         raise GxError(-r, f"gx_jit_source: {os.strerror(-r)}: {out.value.decode(errors='replace')}")
+    return out.value.decode()
+
+
+def jit_set_source(programs, compile: bool = False) -> str:
+    """Source of a program set; ``programs``: list of (code, hook, shapes)."""
+    words = [_words(c) for c, _, _ in programs]
+    insns = np.concatenate(words) if words else np.zeros(1, "<u8")
+    n_insns = np.array([len(c) // 8 for c, _, _ in programs], np.uint32)
+    hooks = np.array([h for _, h, _ in programs], np.uint32)
+    shapes = [np.array(sh, np.uint32).reshape(-1, 5) if sh else np.zeros((0, 5), np.uint32) for _, _, sh in programs]
+    n_maps = np.array([len(x) for x in shapes], np.uint32)
+    flat = np.concatenate([x.reshape(-1) for x in shapes] + [np.zeros(1, np.uint32)])
+    cap = 1 << 24
+    out = C.create_string_buffer(cap)
+    r = lib().gx_jit_set_source(insns.ctypes.data_as(C.c_void_p), n_insns.ctypes.data_as(C.c_void_p),
+                                hooks.ctypes.data_as(C.c_void_p), flat.ctypes.data_as(C.c_void_p),
+                                n_maps.ctypes.data_as(C.c_void_p), len(programs), int(compile), out, cap)
+    if r < 0:
+        raise GxError(-r, f"gx_jit_set_source: {os.strerror(-r)}: {out.value.decode(errors='replace')[:4000]}")
     return out.value.decode()
 
 
@@ -270,6 +293,16 @@ class Runtime:
         r = lib().gx_jit_program(self._h, fd, log, 1 << 16)
         if r < 0:
             raise GxError(-r, f"gx_jit_program: {os.strerror(-r)}: {log.value.decode(errors='replace')}")
+
+    def jit_program_set(self, fds) -> int:
+        """Compile several programs into one module whose persistent kernel
+        runs all their runs of a batched phase in one launch."""
+        arr = np.array(list(fds), dtype=np.int32)
+        log = C.create_string_buffer(1 << 16)
+        r = lib().gx_jit_program_set(self._h, arr.ctypes.data_as(C.c_void_p), len(arr), log, 1 << 16)
+        if r < 0:
+            raise GxError(-r, f"gx_jit_program_set: {os.strerror(-r)}: {log.value.decode(errors='replace')}")
+        return r
 
     def prog_info(self, fd) -> ProgInfo:
         info = ProgInfo()

@@ -98,3 +98,31 @@ def test_batched_mixed_compiled_and_interpreted(rt):
                 for mi, k, v in init or []:
                     assert rt.map_update(fds[mi], k, v) == 0
     assert rt.stats()["vm_errors"] == 0
+
+
+def test_batched_program_set(rt):
+    """Runs of programs compiled as one set share one persistent launch
+    (beside a compiled single program and an interpreted one); two instances
+    of one program share a slot and keep their own maps."""
+    import torch
+    print("batched program set", flush=True)
+    runs = _mixed_runs(5, 3031)
+    # a second instance of the first generated program, on its own maps and events
+    runs.append((runs[0][0], W.gen_mem_uniform(3333, 919), None))
+    descs, keep, set_fds = [], [], []
+    for j, (pol, ev, init) in enumerate(runs):
+        fds, prog = setup(rt, pol, init, jit=(j == 1))
+        if j != 2:
+            set_fds.append(prog)
+        dev = to_device(ev)
+        rc = torch.zeros(max(len(ev), 1), dtype=torch.int32, device="cuda")
+        descs.append((prog, dev, len(ev), pol.record_size, rc))
+        keep.append((pol, ev, init, fds, rc))
+    sid = rt.jit_program_set(set_fds)
+    assert sid >= 0
+    rt.run_batches(descs)
+    torch.cuda.synchronize()
+    for i, (pol, ev, init, fds, rc) in enumerate(keep):
+        g = collect(rt, pol, fds, rc[:len(ev)].cpu().numpy().view(np.uint32))
+        assert_same(g, oracle_run(pol, ev, init), f"run {i} ({pol.name})")
+    assert rt.stats()["vm_errors"] == 0

@@ -89,3 +89,14 @@ def test_source_holds_no_map_addresses(G):
         src = G.jit_source(pol.code, pol.hook, _shapes(pol))
         assert "0x1000000" not in src and "0x2000000" not in src  # the stand-in descriptor/data addresses
         assert "A.maptab" in src
+
+
+def test_program_set_compiles(G):
+    """A set of programs of both modes compiles into one module with one
+    persistent kernel that switches on the program's slot."""
+    pols = [W.access_counter_policy(), W.stride_prefetch_policy(), W.latency_hist_policy()] + \
+        [W.gen_program(W.subseed(1003, 100 + i)) for i in range(3)]
+    src = G.jit_set_source([(p.code, p.hook, _shapes(p)) for p in pols], compile=True)
+    assert src.count("gx_j_set(") == 1
+    for k in range(len(pols)):
+        assert f"namespace p{k} " in src and f"case {k}u:" in src
