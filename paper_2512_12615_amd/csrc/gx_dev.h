@@ -498,6 +498,16 @@ __device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uin
   }
 }
 
+// Load from memory that is constant for the launch: a scalar load when
+// every active lane reads the same address, else a vector load.
+template <typename T>
+__device__ __forceinline__ T load_uniform(uint64_t addr) {
+  typedef const __attribute__((address_space(4))) T cT;
+  const uint64_t u = rfl64(addr);
+  if (ballot(addr != u) == 0) return *(const cT*)u;
+  return *(const T*)addr;
+}
+
 // ---------------------------------------------------------------------------
 // LDS accumulation of a shared map's commutative atomics (compiled programs,
 // event-parallel kernels; section 4.4's aggregation of duplicate map
@@ -548,37 +558,49 @@ __device__ __forceinline__ void mirror_flush(const T* acc, uint32_t words, uint3
   }
 }
 
-// tagged cache: slot s holds the sum for device address tag[s] (0: free)
+// tagged cache, 4-way set associative: slot s holds the sum for word
+// tag[s] - 1 of the map's value area (0: free); a word claims the first free
+// way of its set and keeps it for the block's lifetime, so a word whose set
+// is full goes to the map directly
+constexpr uint32_t kCacheWays = 4;
+
 template <typename T>
-__device__ __forceinline__ void cache_init(uint64_t* tag, T* val, uint32_t slots, uint32_t op) {
+__device__ __forceinline__ void cache_init(uint32_t* tag, T* val, uint32_t slots, uint32_t op) {
   for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
     tag[i] = 0;
     val[i] = op_identity<T>(op);
   }
 }
 template <typename T>
-__device__ __forceinline__ void cache_rmw(uint64_t* tag, T* val, uint32_t slots, uint64_t addr, T v, uint32_t op) {
-  const uint32_t s = (uint32_t)(((addr / sizeof(T)) * 0x9E3779B97F4A7C15ull) >> 40) & (slots - 1);
-  uint64_t t = __hip_atomic_load(&tag[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (t == 0) {
-    uint64_t e = 0;
-    t = __hip_atomic_compare_exchange_strong(&tag[s], &e, addr, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_WORKGROUP)
-            ? addr
-            : e;
+__device__ __forceinline__ void cache_rmw(uint32_t* tag, T* val, uint32_t slots, uint8_t* data, uint64_t addr, T v,
+                                          uint32_t op) {
+  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)) + 1;
+  const uint32_t base = (((key * 0x9E3779B9u) >> 8) & (slots / kCacheWays - 1)) * kCacheWays;
+  for (uint32_t w = 0; w < kCacheWays; w++) {
+    uint32_t* tp = &tag[base + w];
+    uint32_t t = __hip_atomic_load(tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (t == 0) {
+      uint32_t e = 0;
+      t = __hip_atomic_compare_exchange_strong(tp, &e, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP)
+              ? key
+              : e;
+    }
+    if (t == key) {
+      lds_rmw(&val[base + w], v, op);
+      return;
+    }
   }
-  if (t == addr)
-    lds_rmw(&val[s], v, op);
-  else
-    global_rmw((T*)addr, v, op);
+  global_rmw((T*)addr, v, op);
 }
 template <typename T>
-__device__ __forceinline__ void cache_flush(const uint64_t* tag, const T* val, uint32_t slots, uint32_t op) {
+__device__ __forceinline__ void cache_flush(const uint32_t* tag, const T* val, uint32_t slots, uint32_t op,
+                                            uint8_t* data) {
   const T id = op_identity<T>(op);
   for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
-    const uint64_t t = tag[i];
+    const uint32_t t = tag[i];
     const T v = val[i];
-    if (t && v != id) global_rmw((T*)t, v, op);
+    if (t && v != id) global_rmw((T*)data + (t - 1), v, op);
   }
 }
 

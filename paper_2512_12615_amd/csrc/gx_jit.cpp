@@ -90,11 +90,11 @@ struct JMaps {
           left -= area;
         } else {
           uint64_t slots = 1;
-          while (slots * 2 * (8 + w) <= std::min<uint64_t>(left, 32u << 10)) slots *= 2;
+          while (slots * 2 * (4 + w) <= std::min<uint64_t>(left, 48u << 10)) slots *= 2;
           if (slots >= 256) {
             a.kind = 2;
             a.words = (uint32_t)slots;
-            left -= slots * (8 + w);
+            left -= slots * (4 + w);
           }
         }
       }
@@ -233,10 +233,21 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
     case H_LDX_STACK:
       set(extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf));
       break;
-    case H_LDX_MAP:
-      guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
-              D + " = " + extend(std::string("*(const ") + kTy[sc] + "*)ad", sc, sxf) + ";");
+    case H_LDX_MAP: {
+      const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+      const bool ro = mk >= 0 && mk < (int)J.m.size() && (J.m[mk].second.flags & F_READ_ONLY);
+      if (ro) {
+        // read-only map: constant for the launch, so when the wave reads one
+        // address it is read with a scalar load, which does not wait behind
+        // the wave's outstanding vector loads (they complete in order)
+        guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
+                D + " = " + extend(std::string("load_uniform<") + kTy[sc] + ">(ad)", sc, sxf) + ";");
+      } else {
+        guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
+                D + " = " + extend(std::string("*(const ") + kTy[sc] + "*)ad", sc, sxf) + ";");
+      }
       break;
+    }
     case H_ST_STACK:
     case H_STX_STACK:
       o += std::string("  *(") + kTy[sc] + "*)saddr(stk, (uint32_t)" + D + " + " + off + ") = (" + kTy[sc] + ")" +
@@ -268,7 +279,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
             ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(ad - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
                                 std::to_string(ac->sc) + "], (" + T + ")" + S + ", " + ops + ");"
                           : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(ac->words) +
-                                "u, ad, (" + T + ")" + S + ", " + ops + ");";
+                                "u, M" + K + ".data, ad, (" + T + ")" + S + ", " + ops + ");";
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
                 "if (PRIV) { " + lds + " } else { const uint64_t t = " + call + "; " + wb + " }");
       } else {
@@ -360,7 +371,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     if (a.kind == 1)
       o += "__shared__ " + T + " g_acc" + K + "[" + N + "];\n";
     else
-      o += "__shared__ uint64_t g_tag" + K + "[" + N + "];\n__shared__ " + T + " g_val" + K + "[" + N + "];\n";
+      o += "__shared__ uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + T + " g_val" + K + "[" + N + "];\n";
   }
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
   o += "\ntemplate <bool PRIV>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
@@ -405,7 +416,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
              "u, gx_map" + K + "(A).data);\n";
       else if (a.kind == 2)
         o += "      cache_flush<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
-             std::to_string(a.op) + "u);\n";
+             std::to_string(a.op) + "u, gx_map" + K + "(A).data);\n";
     }
     o += "    }\n";
   }

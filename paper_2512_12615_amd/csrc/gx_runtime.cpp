@@ -131,7 +131,9 @@ struct gx_rt {
   // compiled program sets (gx_jit_program_set): persistent kernel per set
   struct JitSet {
     hipFunction_t f = nullptr;
+    uint32_t blocks_per_cu = 0;  // resident one-wave blocks per CU (occupancy)
   };
+  uint32_t n_cu = 256;  // compute units of the device
   std::vector<JitSet> sets;
   // batched form: compiled runs of a phase run side by side on these
   static constexpr int kSide = 4;
@@ -529,6 +531,9 @@ int gx_open(int hip_device, gx_rt** out) {
   if (!rt) return -ENOMEM;
   rt->dev = hip_device;
   DevGuard g(hip_device);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && ncu > 0)
+    rt->n_cu = (uint32_t)ncu;
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
       hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess ||
@@ -1045,7 +1050,9 @@ int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, ui
   }
   std::lock_guard<std::mutex> lk(rt->jit_mu);
   const int id = (int)rt->sets.size();
-  rt->sets.push_back(gx_rt::JitSet{f});
+  int bpc = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, f, 64, 0) != hipSuccess) bpc = 0;
+  rt->sets.push_back(gx_rt::JitSet{f, (uint32_t)std::max(bpc, 0)});
   for (uint32_t i = 0; i < n; i++) {
     ps[i]->set_id = id;
     ps[i]->set_slot = slot[i];
@@ -1316,8 +1323,12 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     const uint2* di = (const uint2*)(d_tables + set_off[k].second);
     uint32_t ni = (uint32_t)v.size();
     uint32_t* next = rt->d_next + 1 + k;
-    uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
-    uint32_t waves = (uint32_t)std::min<size_t>(v.size(), 256 * per_cu);
+    // as many waves as the device holds at once: the items are chains of
+    // dependent memory accesses, so throughput comes from concurrency
+    const gx_rt::JitSet& js = rt->sets[set_off[k].first];
+    uint32_t per_cu = js.blocks_per_cu ? js.blocks_per_cu : 8;
+    per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", (int)per_cu)));
+    uint32_t waves = (uint32_t)std::min<size_t>(v.size(), (size_t)rt->n_cu * per_cu);
     e = launch_zero(next, 1, ss);
     void* args[] = {&db, &di, &ni, &next};
     if (e == hipSuccess)
