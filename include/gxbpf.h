@@ -215,6 +215,22 @@ typedef struct gx_batch {
 } gx_batch;
 int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream);
 
+/* A batch captured into a HIP graph (the batched form's launches, replayed
+ * without host work).  gx_graph_create runs the batch once to size a
+ * workspace of the graph's own (the maps it touches are saved first and put
+ * back, so that run leaves no trace), then captures the same launches.
+ * gx_graph_launch replays them on ``stream``: the same programs over the
+ * same device buffers (events, return codes) as given to create, whose
+ * contents the caller may change between launches; each replay has the
+ * effect of one gx_run_batches call with those descriptors.  Launches of
+ * one graph must be ordered (one stream, or synchronized), like batches
+ * over the same maps.  Errors: -EINVAL, -E2BIG as gx_run_batches, -ENOMEM,
+ * -EIO if capture or instantiation fails. */
+typedef struct gx_graph gx_graph;
+int gx_graph_create(gx_rt* rt, const gx_batch* descs, uint32_t n, gx_graph** out);
+int gx_graph_launch(gx_graph* g, void* stream);
+void gx_graph_destroy(gx_graph* g);
+
 /* Copy committed ring records to host memory as {u32 len; u32 flags;
  * payload padded to 8} and release their space.  Returns the bytes written
  * (whole records only) and the record count in *n_records.  Waits for work

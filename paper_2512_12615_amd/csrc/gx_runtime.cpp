@@ -114,6 +114,70 @@ Knobs knobs_of(const ProgObj* p) {
   return k;
 }
 
+// Execution resources of runs: the stream-sequential workspace, the batched
+// form's side streams, table staging and work counters.  The runtime has one
+// set; a captured graph owns another, swapped in while it is captured.
+constexpr int kExecSide = 4;
+struct Stage {
+  uint8_t* h = nullptr;  // pinned host copy of a phase's tables
+  uint8_t* d = nullptr;  // device tables
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;  // after the tables' copy
+  bool used = false;
+};
+struct Exec {
+  // batched form: compiled runs of a phase run side by side on these
+  hipStream_t side[kExecSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kExecSide] = {};
+  // staging of batched tables: a ring of slots, so a phase never waits for
+  // the previous phase's table copy (a capture takes a fresh slot per phase)
+  std::vector<Stage> stage;
+  uint32_t stage_next = 0;
+  // stream-sequential workspace
+  uint32_t* d_counts = nullptr;
+  uint32_t* d_sums = nullptr;
+  uint32_t* d_order = nullptr;
+  uint8_t* d_sorted = nullptr;  // records in queue order (kSortedStride apart)
+  size_t counts_cap = 0, sums_cap = 0, order_cap = 0, sorted_cap = 0;
+  hipEvent_t ws_event = nullptr;
+  bool ws_used = false;
+  uint32_t* d_next = nullptr;  // work counters of persistent launches (16)
+  bool capturing = false;      // launches are being captured into a graph
+  bool per_phase = false;      // staging: slot i for the i-th phase (graphs)
+  size_t stage_cursor = 0;
+};
+
+constexpr int kStageRing = 4;
+
+int exec_init(Exec& x) {
+  if (hipEventCreateWithFlags(&x.ws_event, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&x.fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc((void**)&x.d_next, 64) != hipSuccess)
+    return -ENOMEM;
+  for (int i = 0; i < kExecSide; i++)
+    if (hipStreamCreateWithFlags(&x.side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&x.join_ev[i], hipEventDisableTiming) != hipSuccess)
+      return -ENOMEM;
+  return 0;
+}
+
+void exec_free(Exec& x) {
+  for (int i = 0; i < kExecSide; i++) {
+    if (x.side[i]) (void)hipStreamDestroy(x.side[i]);
+    if (x.join_ev[i]) (void)hipEventDestroy(x.join_ev[i]);
+  }
+  if (x.fork_ev) (void)hipEventDestroy(x.fork_ev);
+  for (auto& st : x.stage) {
+    if (st.h) (void)hipHostFree(st.h);
+    if (st.d) (void)hipFree(st.d);
+    if (st.ev) (void)hipEventDestroy(st.ev);
+  }
+  if (x.ws_event) (void)hipEventDestroy(x.ws_event);
+  for (void* p : {(void*)x.d_counts, (void*)x.d_sums, (void*)x.d_order, (void*)x.d_sorted, (void*)x.d_next})
+    if (p) (void)hipFree(p);
+  x = Exec{};
+}
+
 }  // namespace
 
 struct gx_rt {
@@ -135,33 +199,12 @@ struct gx_rt {
   };
   uint32_t n_cu = 256;  // compute units of the device
   std::vector<JitSet> sets;
-  // batched form: compiled runs of a phase run side by side on these
-  static constexpr int kSide = 4;
-  hipStream_t side[kSide] = {};
-  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
-  // staging of batched tables: a ring of slots, so a phase never waits for
-  // the previous phase's table copy
-  static constexpr int kStage = 4;
-  uint8_t* h_stage_ring[kStage] = {};
-  uint8_t* d_tables_ring[kStage] = {};
-  size_t stage_ring_cap[kStage] = {};
-  hipEvent_t stage_ring_ev[kStage] = {};
-  bool stage_ring_used[kStage] = {};
-  uint32_t stage_next = 0;
+  static constexpr int kSide = kExecSide;
+  Exec ex;  // execution resources of runs (a captured graph swaps in its own)
   std::vector<MapObj> maps;
   std::vector<ProgObj> progs;
   uint64_t* d_err = nullptr;
   uint8_t* d_stage = nullptr;  // control-plane staging (keys, values, results)
-  // stream-sequential workspace
-  uint32_t* d_counts = nullptr;
-  uint32_t* d_sums = nullptr;
-  uint32_t* d_order = nullptr;
-  uint8_t* d_sorted = nullptr;  // records in queue order (kSortedStride apart)
-  size_t counts_cap = 0, sums_cap = 0, order_cap = 0, sorted_cap = 0;
-  hipEvent_t ws_event = nullptr;
-  bool ws_used = false;
-  // batched form: device tables, their pinned staging copy, the work counter
-  uint32_t* d_next = nullptr;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
   uint32_t epoch = 0;  // launch counter for hash tombstone reuse
@@ -370,11 +413,11 @@ int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
     return 0;
   };
   int r;
-  if ((r = grow(&rt->d_counts, &rt->counts_cap, counts))) return r;
-  if ((r = grow(&rt->d_sums, &rt->sums_cap, sums))) return r;
-  if ((r = grow(&rt->d_order, &rt->order_cap, order))) return r;
+  if ((r = grow(&rt->ex.d_counts, &rt->ex.counts_cap, counts))) return r;
+  if ((r = grow(&rt->ex.d_sums, &rt->ex.sums_cap, sums))) return r;
+  if ((r = grow(&rt->ex.d_order, &rt->ex.order_cap, order))) return r;
   // the queue-ordered records: kSortedStride bytes per event (u32 units)
-  if ((r = grow((uint32_t**)&rt->d_sorted, &rt->sorted_cap, order * (kSortedStride / 4)))) return r;
+  if ((r = grow((uint32_t**)&rt->ex.d_sorted, &rt->ex.sorted_cap, order * (kSortedStride / 4)))) return r;
   return 0;
 }
 
@@ -439,13 +482,13 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
     uint64_t m = (uint64_t)L * nt;
     int r = ensure_ws(rt, m, (m + 4095) / 4096 + 1, n_events);
     if (r) return r;
-    if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
+    if (rt->ex.ws_used) (void)hipStreamWaitEvent(s, rt->ex.ws_event, 0);
     A.step_limit = per_event * n_events;
-    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->ex.d_counts, rt->ex.d_sums, rt->ex.d_order, rt->ex.d_sorted, s);
     if (e == hipSuccess) {
-      A.order = rt->d_order;
-      A.sorted = rt->d_sorted;
-      A.qstart = rt->d_counts;
+      A.order = rt->ex.d_order;
+      A.sorted = rt->ex.d_sorted;
+      A.qstart = rt->ex.d_counts;
       A.n_queues = L;
       if (pe.first) (void)hipEventRecord(pe.first, s);
       if (p->jf_seq) {
@@ -455,8 +498,8 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
       }
       if (pe.second) (void)hipEventRecord(pe.second, s);
     }
-    (void)hipEventRecord(rt->ws_event, s);
-    rt->ws_used = true;
+    (void)hipEventRecord(rt->ex.ws_event, s);
+    rt->ex.ws_used = true;
     rt->stats.launches += 6;
   }
   if (pe.first) rt->prof_pending.push_back(pe);
@@ -515,6 +558,43 @@ int stand_in(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const 
   return 0;
 }
 
+// Device copies of maps' state (values, hash slots, control words, ring
+// data), taken and put back on a stream: runs made only to measure or to
+// size something leave no trace.
+struct MapSnapshot {
+  struct Part {
+    void* src;
+    void* tmp;
+    size_t bytes;
+  };
+  std::vector<Part> parts;
+  int take(gx_rt* rt, const std::vector<int>& fds, hipStream_t s) {
+    std::vector<int> seen;
+    for (int fd : fds) {
+      if (std::find(seen.begin(), seen.end(), fd) != seen.end()) continue;
+      seen.push_back(fd);
+      MapObj* m = get_map(rt, fd);
+      if (!m) continue;
+      for (auto pr : {std::make_pair((void*)m->h.data, m->data_bytes), std::make_pair((void*)m->h.slots, m->slot_bytes),
+                      std::make_pair((void*)m->h.ctrl, (size_t)64)}) {
+        if (!pr.first || !pr.second) continue;
+        Part pt{pr.first, nullptr, pr.second};
+        if (hipMalloc(&pt.tmp, pt.bytes) != hipSuccess) return -ENOMEM;
+        parts.push_back(pt);
+        (void)hipMemcpyAsync(pt.tmp, pt.src, pt.bytes, hipMemcpyDeviceToDevice, s);
+      }
+    }
+    return 0;
+  }
+  void restore(hipStream_t s) {
+    for (auto& pt : parts) (void)hipMemcpyAsync(pt.src, pt.tmp, pt.bytes, hipMemcpyDeviceToDevice, s);
+  }
+  ~MapSnapshot() {
+    for (auto& pt : parts)
+      if (pt.tmp) (void)hipFree(pt.tmp);
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -536,23 +616,10 @@ int gx_open(int hip_device, gx_rt** out) {
     rt->n_cu = (uint32_t)ncu;
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
-      hipEventCreateWithFlags(&rt->ws_event, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc((void**)&rt->d_next, 64) != hipSuccess || vm_init() != hipSuccess ||
-      hipEventCreateWithFlags(&rt->fork_ev, hipEventDisableTiming) != hipSuccess) {
+      vm_init() != hipSuccess || exec_init(rt->ex) != 0) {
     gx_close(rt);
     return -ENOMEM;
   }
-  for (int i = 0; i < gx_rt::kSide; i++)
-    if (hipStreamCreateWithFlags(&rt->side[i], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&rt->join_ev[i], hipEventDisableTiming) != hipSuccess) {
-      gx_close(rt);
-      return -ENOMEM;
-    }
-  for (int i = 0; i < gx_rt::kStage; i++)
-    if (hipEventCreateWithFlags(&rt->stage_ring_ev[i], hipEventDisableTiming) != hipSuccess) {
-      gx_close(rt);
-      return -ENOMEM;
-    }
   (void)hipMemset(rt->d_err, 0, 64);
   (void)hipDeviceSynchronize();
   *out = rt;
@@ -578,20 +645,8 @@ void gx_close(gx_rt* rt) {
       (void)hipEventDestroy(pe.first);
       (void)hipEventDestroy(pe.second);
     }
-  for (int i = 0; i < gx_rt::kSide; i++) {
-    if (rt->side[i]) (void)hipStreamDestroy(rt->side[i]);
-    if (rt->join_ev[i]) (void)hipEventDestroy(rt->join_ev[i]);
-  }
-  if (rt->fork_ev) (void)hipEventDestroy(rt->fork_ev);
-  for (int i = 0; i < gx_rt::kStage; i++) {
-    if (rt->h_stage_ring[i]) (void)hipHostFree(rt->h_stage_ring[i]);
-    if (rt->d_tables_ring[i]) (void)hipFree(rt->d_tables_ring[i]);
-    if (rt->stage_ring_ev[i]) (void)hipEventDestroy(rt->stage_ring_ev[i]);
-  }
-  if (rt->ws_event) (void)hipEventDestroy(rt->ws_event);
-  if (rt->d_next) (void)hipFree(rt->d_next);
-  for (void* p : {(void*)rt->d_counts, (void*)rt->d_sums, (void*)rt->d_order, (void*)rt->d_sorted, (void*)rt->d_err,
-                  (void*)rt->d_stage})
+  exec_free(rt->ex);
+  for (void* p : {(void*)rt->d_err, (void*)rt->d_stage})
     if (p) (void)hipFree(p);
   if (rt->internal) (void)hipStreamDestroy(rt->internal);
   delete rt;
@@ -859,38 +914,10 @@ int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
   }
   // the trials run the program for real: save every map's state and put it
   // back before each trial and at the end
-  struct Save {
-    void* src;
-    void* tmp;
-    size_t bytes;
-  };
-  std::vector<Save> saves;
-  auto cleanup = [&]() {
-    for (auto& sv : saves)
-      if (sv.tmp) (void)hipFree(sv.tmp);
-  };
-  for (int fd : p->fds) {
-    MapObj* m = get_map(rt, fd);
-    if (!m) continue;
-    for (auto pr : {std::make_pair((void*)m->h.data, m->data_bytes), std::make_pair((void*)m->h.slots, m->slot_bytes),
-                    std::make_pair((void*)m->h.ctrl, (size_t)64)}) {
-      if (!pr.first || !pr.second) continue;
-      Save sv{pr.first, nullptr, pr.second};
-      if (hipMalloc(&sv.tmp, sv.bytes) != hipSuccess) {
-        cleanup();
-        return -ENOMEM;
-      }
-      saves.push_back(sv);
-    }
-  }
-  if (wait_all(rt)) {
-    cleanup();
-    return -EIO;
-  }
-  for (auto& sv : saves) (void)hipMemcpyAsync(sv.tmp, sv.src, sv.bytes, hipMemcpyDeviceToDevice, s);
-  auto restore = [&]() {
-    for (auto& sv : saves) (void)hipMemcpyAsync(sv.src, sv.tmp, sv.bytes, hipMemcpyDeviceToDevice, s);
-  };
+  if (wait_all(rt)) return -EIO;
+  MapSnapshot snap;
+  if (snap.take(rt, p->fds, s)) return -ENOMEM;
+  auto restore = [&]() { snap.restore(s); };
   const bool prof = rt->profile;
   const gx_stats st = rt->stats;
   rt->profile = false;
@@ -925,7 +952,6 @@ int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
   (void)hipStreamSynchronize(s);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  cleanup();
   rt->profile = prof;
   rt->stats = st;
   if (r) return r;
@@ -1226,9 +1252,9 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   for (auto& bd : B)
     if (bd.mode == 1) {
       const PartJob& pj = J[bd.A.pad2 - 1];
-      bd.A.qstart = rt->d_counts + pj.cbase;
-      bd.A.order = rt->d_order;
-      bd.A.sorted = rt->d_sorted;
+      bd.A.qstart = rt->ex.d_counts + pj.cbase;
+      bd.A.order = rt->ex.d_order;
+      bd.A.sorted = rt->ex.d_sorted;
       bd.A.pad2 = 0;
     }
   // items, largest runs first
@@ -1266,23 +1292,34 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     os_ = al(os_ + si.second.size() * sizeof(uint2));
   }
   size_t oj = os_, ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
-  // a staging slot whose previous copy has long completed
-  const uint32_t k = rt->stage_next++ % gx_rt::kStage;
-  if (rt->stage_ring_used[k] && hipEventSynchronize(rt->stage_ring_ev[k]) != hipSuccess) return -EIO;
-  if (rt->stage_ring_cap[k] < total) {
-    if (rt->h_stage_ring[k]) (void)hipHostFree(rt->h_stage_ring[k]);
-    if (rt->d_tables_ring[k]) (void)hipFree(rt->d_tables_ring[k]);
-    rt->h_stage_ring[k] = nullptr;
-    rt->d_tables_ring[k] = nullptr;
-    rt->stage_ring_cap[k] = 0;
-    size_t cap = std::max<size_t>(total, 1 << 16);
-    if (hipHostMalloc((void**)&rt->h_stage_ring[k], cap, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
-    if (hipMalloc((void**)&rt->d_tables_ring[k], cap) != hipSuccess) return -ENOMEM;
-    rt->stage_ring_cap[k] = cap;
+  // a staging slot whose previous copy has long completed; a capture takes
+  // a fresh slot per phase, which the graph then owns
+  Exec& X = rt->ex;
+  size_t k;
+  if (X.per_phase) {
+    k = X.stage_cursor++;
+    if (k >= X.stage.size()) X.stage.emplace_back();
+  } else {
+    if (X.stage.size() < (size_t)kStageRing) X.stage.resize(kStageRing);
+    k = X.stage_next++ % kStageRing;
   }
-  uint8_t* h_stage = rt->h_stage_ring[k];
-  uint8_t* d_tables = rt->d_tables_ring[k];
-  if (rt->ws_used) (void)hipStreamWaitEvent(s, rt->ws_event, 0);
+  Stage& st = X.stage[k];
+  if (!st.ev && hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) != hipSuccess) return -ENOMEM;
+  if (st.used && hipEventSynchronize(st.ev) != hipSuccess) return -EIO;
+  if (st.cap < total) {
+    if (st.h) (void)hipHostFree(st.h);
+    if (st.d) (void)hipFree(st.d);
+    st.h = nullptr;
+    st.d = nullptr;
+    st.cap = 0;
+    size_t cap = std::max<size_t>(total, 1 << 16);
+    if (hipHostMalloc((void**)&st.h, cap, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+    if (hipMalloc((void**)&st.d, cap) != hipSuccess) return -ENOMEM;
+    st.cap = cap;
+  }
+  uint8_t* h_stage = st.h;
+  uint8_t* d_tables = st.d;
+  if (rt->ex.ws_used) (void)hipStreamWaitEvent(s, rt->ex.ws_event, 0);
   std::memcpy(h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
   std::memcpy(h_stage + oi, items.data(), items.size() * sizeof(uint2));
   for (auto& so : set_off) {
@@ -1292,12 +1329,12 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   if (!J.empty()) std::memcpy(h_stage + oj, J.data(), J.size() * sizeof(PartJob));
   if (!tiles.empty()) std::memcpy(h_stage + ot, tiles.data(), tiles.size() * sizeof(uint2));
   if (hipMemcpyAsync(d_tables, h_stage, total, hipMemcpyHostToDevice, s) != hipSuccess) return -EIO;
-  (void)hipEventRecord(rt->stage_ring_ev[k], s);
-  rt->stage_ring_used[k] = true;
+  (void)hipEventRecord(st.ev, s);
+  st.used = !X.per_phase;
   hipError_t e = hipSuccess;
   if (!J.empty())
     e = launch_partition_jobs((const PartJob*)(d_tables + oj), (const uint2*)(d_tables + ot), (uint32_t)tiles.size(),
-                              max_lbits, counts_total, rt->d_counts, rt->d_sums, rt->d_order, rt->d_sorted, s);
+                              max_lbits, counts_total, rt->ex.d_counts, rt->ex.d_sums, rt->ex.d_order, rt->ex.d_sorted, s);
   std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
   if (rt->profile) pe = prof_pair(rt);
   if (pe.first) (void)hipEventRecord(pe.first, s);
@@ -1306,15 +1343,15 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   int used_side = 0;
   size_t x = 0;  // launches handed to side streams so far
   auto side = [&]() {
-    hipStream_t ss = rt->side[x % gx_rt::kSide];
-    if ((int)x < gx_rt::kSide) {
-      (void)hipStreamWaitEvent(ss, rt->fork_ev, 0);
+    hipStream_t ss = rt->ex.side[x % kExecSide];
+    if ((int)x < kExecSide) {
+      (void)hipStreamWaitEvent(ss, rt->ex.fork_ev, 0);
       used_side++;
     }
     x++;
     return ss;
   };
-  if (e == hipSuccess && (!jit_runs.empty() || !set_off.empty())) (void)hipEventRecord(rt->fork_ev, s);
+  if (e == hipSuccess && (!jit_runs.empty() || !set_off.empty())) (void)hipEventRecord(rt->ex.fork_ev, s);
   // program sets: one persistent launch each, with a counter of its own
   for (size_t k = 0; k < set_off.size() && e == hipSuccess; k++) {
     hipStream_t ss = side();
@@ -1322,7 +1359,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     const BatchDev* db = (const BatchDev*)(d_tables + ob);
     const uint2* di = (const uint2*)(d_tables + set_off[k].second);
     uint32_t ni = (uint32_t)v.size();
-    uint32_t* next = rt->d_next + 1 + k;
+    uint32_t* next = rt->ex.d_next + 1 + k;
     // as many waves as the device holds at once: the items are chains of
     // dependent memory accesses, so throughput comes from concurrency
     const gx_rt::JitSet& js = rt->sets[set_off[k].first];
@@ -1343,36 +1380,26 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
     uint32_t waves = (uint32_t)std::min<size_t>(items.size(), 256 * per_cu);
     e = launch_batched((const BatchDev*)(d_tables + ob), (const uint2*)(d_tables + oi), (uint32_t)items.size(),
-                       rt->d_next, waves, stack_max, s);
+                       rt->ex.d_next, waves, stack_max, s);
   }
   for (int x = 0; x < used_side; x++) {
-    (void)hipEventRecord(rt->join_ev[x], rt->side[x]);
-    (void)hipStreamWaitEvent(s, rt->join_ev[x], 0);
+    (void)hipEventRecord(rt->ex.join_ev[x], rt->ex.side[x]);
+    (void)hipStreamWaitEvent(s, rt->ex.join_ev[x], 0);
   }
   if (pe.second) (void)hipEventRecord(pe.second, s);
   if (pe.first) rt->prof_pending.push_back(pe);
-  (void)hipEventRecord(rt->ws_event, s);
-  rt->ws_used = true;
+  (void)hipEventRecord(rt->ex.ws_event, s);
+  rt->ex.ws_used = true;
   if (e != hipSuccess) return to_errno(e);
+  if (X.capturing) return 0;  // a graph's launches are counted when it is launched
   rt->stats.launches += (J.empty() ? 0 : 5) + (items.empty() ? 0 : 2) + jit_runs.size() + 2 * set_off.size();
   for (auto& bd : B) rt->stats.events += bd.A.n_events;
   note_stream(rt, s);
   return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
-  if (!rt || (!descs && n)) return -EINVAL;
-  for (uint32_t i = 0; i < n; i++) {
-    ProgObj* p = get_prog(rt, descs[i].prog_fd);
-    if (!p || descs[i].record_size != p->record_size || (descs[i].n_events && !descs[i].d_events)) return -EINVAL;
-    if (descs[i].n_events >= (1ull << 32)) return -E2BIG;
-  }
-  DevGuard g(rt->dev);
-  hipStream_t s = (hipStream_t)stream;
+// The phases of a batch, one after another on s (validated descriptors).
+int run_batches_impl(gx_rt* rt, const gx_batch* descs, uint32_t n, hipStream_t s) {
   // split into phases of runs that share no map (their order then cannot
   // matter); phases run one after another on the stream
   uint32_t a = 0;
@@ -1390,6 +1417,121 @@ int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
     a = b;
   }
   return 0;
+}
+
+int check_batches(gx_rt* rt, const gx_batch* descs, uint32_t n) {
+  if (!rt || (!descs && n)) return -EINVAL;
+  for (uint32_t i = 0; i < n; i++) {
+    ProgObj* p = get_prog(rt, descs[i].prog_fd);
+    if (!p || descs[i].record_size != p->record_size || (descs[i].n_events && !descs[i].d_events)) return -EINVAL;
+    if (descs[i].n_events >= (1ull << 32)) return -E2BIG;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
+  int r = check_batches(rt, descs, n);
+  if (r) return r;
+  DevGuard g(rt->dev);
+  return run_batches_impl(rt, descs, n, (hipStream_t)stream);
+}
+
+struct gx_graph {
+  gx_rt* rt = nullptr;
+  Exec ex;  // the graph's own workspace, staging and side streams
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t events = 0;
+  uint32_t phases = 0;
+};
+
+int gx_graph_create(gx_rt* rt, const gx_batch* descs, uint32_t n, gx_graph** out) {
+  if (!out) return -EINVAL;
+  *out = nullptr;
+  int r = check_batches(rt, descs, n);
+  if (r) return r;
+  DevGuard g(rt->dev);
+  gx_graph* G = new (std::nothrow) gx_graph();
+  if (!G) return -ENOMEM;
+  G->rt = rt;
+  auto fail = [&](int code) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    if (G->cs) (void)hipStreamDestroy(G->cs);
+    exec_free(G->ex);
+    delete G;
+    return code;
+  };
+  if (exec_init(G->ex) || hipStreamCreateWithFlags(&G->cs, hipStreamNonBlocking) != hipSuccess) return fail(-ENOMEM);
+  for (uint32_t i = 0; i < n; i++) G->events += descs[i].n_events;
+  // the batch runs once for real to size the graph's workspace and tables
+  // (nothing may be allocated while capturing); the maps it touches are
+  // saved first and put back after
+  std::vector<int> fds;
+  for (uint32_t i = 0; i < n; i++)
+    for (int fd : get_prog(rt, descs[i].prog_fd)->fds) fds.push_back(fd);
+  if (wait_all(rt)) return fail(-EIO);
+  MapSnapshot snap;
+  if (snap.take(rt, fds, G->cs)) return fail(-ENOMEM);
+  const bool prof = rt->profile;
+  const gx_stats st = rt->stats;
+  rt->profile = false;
+  std::swap(rt->ex, G->ex);
+  rt->ex.per_phase = true;
+  rt->ex.stage_cursor = 0;
+  r = run_batches_impl(rt, descs, n, G->cs);
+  if (!r) {
+    snap.restore(G->cs);
+    if (hipStreamSynchronize(G->cs) != hipSuccess) r = -EIO;
+  }
+  if (!r) {
+    rt->ex.capturing = true;
+    rt->ex.ws_used = false;
+    rt->ex.stage_cursor = 0;
+    if (hipStreamBeginCapture(G->cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      r = -EIO;
+    } else {
+      r = run_batches_impl(rt, descs, n, G->cs);
+      if (hipStreamEndCapture(G->cs, &G->graph) != hipSuccess && !r) r = -EIO;
+    }
+    rt->ex.capturing = false;
+    G->phases = (uint32_t)rt->ex.stage_cursor;
+  }
+  std::swap(rt->ex, G->ex);
+  rt->profile = prof;
+  rt->stats = st;
+  if (r) return fail(r);
+  if (hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0) != hipSuccess) return fail(-EIO);
+  *out = G;
+  return 0;
+}
+
+int gx_graph_launch(gx_graph* G, void* stream) {
+  if (!G) return -EINVAL;
+  gx_rt* rt = G->rt;
+  DevGuard g(rt->dev);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipGraphLaunch(G->exec, s) != hipSuccess) return -EIO;
+  rt->stats.launches += 1;
+  rt->stats.events += G->events;
+  note_stream(rt, s);
+  return 0;
+}
+
+void gx_graph_destroy(gx_graph* G) {
+  if (!G) return;
+  DevGuard g(G->rt->dev);
+  (void)hipDeviceSynchronize();
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  if (G->cs) (void)hipStreamDestroy(G->cs);
+  exec_free(G->ex);
+  delete G;
 }
 
 int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_bytes, uint64_t* n_records) {

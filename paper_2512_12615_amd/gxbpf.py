@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
+           "gx_run_batches", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
@@ -100,6 +100,10 @@ def lib():
     L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
+    L.gx_graph_create.argtypes = [vp, C.POINTER(Batch), u32, C.POINTER(vp)]
+    L.gx_graph_launch.argtypes = [vp, vp]
+    L.gx_graph_destroy.argtypes = [vp]
+    L.gx_graph_destroy.restype = None
     L.gx_jit_program.argtypes = [vp, C.c_int, C.c_char_p, u32]
     L.gx_jit_program_set.argtypes = [vp, vp, u32, C.c_char_p, u32]
     L.gx_jit_source.argtypes = [vp, u32, u32, vp, u32, C.c_int, C.c_char_p, u64]
@@ -321,14 +325,11 @@ class Runtime:
 
     def run_batches(self, descs, stream=None):
         """descs: list of (prog_fd, events tensor, n_events, record_size, rc tensor or None)."""
-        arr = (Batch * len(descs))()
-        for i, (p, ev, n, rs, rc) in enumerate(descs):
-            arr[i].prog_fd = p
-            arr[i].record_size = rs
-            arr[i].d_events = ev.data_ptr()
-            arr[i].n_events = n
-            arr[i].d_rc = rc.data_ptr() if rc is not None else None
-        _check(lib().gx_run_batches(self._h, arr, len(descs), _stream_handle(stream)), "gx_run_batches")
+        _check(lib().gx_run_batches(self._h, _batch_array(descs), len(descs), _stream_handle(stream)), "gx_run_batches")
+
+    def graph_create(self, descs) -> "Graph":
+        """Capture a batch (descs as for run_batches) into a replayable graph."""
+        return Graph(self, descs)
 
     # ring buffers -----------------------------------------------------------
     def drain_ringbuf(self, fd, cap=None, copy=True):
@@ -359,6 +360,41 @@ class Runtime:
         s = Stats()
         _check(lib().gx_stats_get(self._h, C.byref(s)), "gx_stats_get")
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def _batch_array(descs):
+    arr = (Batch * max(len(descs), 1))()
+    for i, (p, ev, n, rs, rc) in enumerate(descs):
+        arr[i].prog_fd = p
+        arr[i].record_size = rs
+        arr[i].d_events = ev.data_ptr()
+        arr[i].n_events = n
+        arr[i].d_rc = rc.data_ptr() if rc is not None else None
+    return arr
+
+
+class Graph:
+    """A batch captured into a HIP graph (gx_graph_*): launch() replays it."""
+
+    def __init__(self, rt: "Runtime", descs):
+        self.rt = rt
+        self._keep = list(descs)  # the device buffers must outlive the graph
+        self._h = C.c_void_p()
+        _check(lib().gx_graph_create(rt._h, _batch_array(descs), len(descs), C.byref(self._h)), "gx_graph_create")
+
+    def launch(self, stream=None):
+        _check(lib().gx_graph_launch(self._h, _stream_handle(stream)), "gx_graph_launch")
+
+    def close(self):
+        if self._h:
+            lib().gx_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def parse_ring(buf: bytes):
