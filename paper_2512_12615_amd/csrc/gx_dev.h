@@ -49,6 +49,16 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t l) { return __builtin_amdgcn_readlane(x, l); }
+
+// Wave-uniform execution (a compiled program run by one lane of a wave, one
+// queue per wave): values the compiler cannot prove uniform are read from
+// the first active lane, so the program's arithmetic, compares and branches
+// run on the scalar unit (one instruction a cycle, no EXEC-mask updates)
+// instead of as 64-lane vector operations of which one lane is used.
+template <bool UNI>
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+  return UNI ? rfl64(x) : x;
+}
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__builtin_popcountll(m); }
 __device__ __forceinline__ uint32_t rank_in(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -76,9 +86,20 @@ __device__ __forceinline__ uint32_t wave_max_active(uint32_t x) {
 #endif
 }
 
+// Map memory is device memory.  Its pointers come from descriptors, not
+// kernel arguments, so the compiler cannot tell their address space; the
+// casts make every access a global_* instruction instead of a flat_* one
+// (a flat access also counts against the LDS counter, so a stack access
+// after it would wait for the global one to finish).
+#define GX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GX_GLOBAL T* gl(T* p) {
+  return (GX_GLOBAL T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -120,6 +141,23 @@ __device__ __forceinline__ void store_sized(uint8_t* p, uint64_t v, int sc) {
     default: *(uint64_t*)p = v; break;
   }
 }
+// the same on map memory
+__device__ __forceinline__ uint64_t load_sized_g(uint64_t a, int sc) {
+  switch (sc) {
+    case 0: return *(const GX_GLOBAL uint8_t*)a;
+    case 1: return *(const GX_GLOBAL uint16_t*)a;
+    case 2: return *(const GX_GLOBAL uint32_t*)a;
+  }
+  return *(const GX_GLOBAL uint64_t*)a;
+}
+__device__ __forceinline__ void store_sized_g(uint64_t a, uint64_t v, int sc) {
+  switch (sc) {
+    case 0: *(GX_GLOBAL uint8_t*)a = (uint8_t)v; break;
+    case 1: *(GX_GLOBAL uint16_t*)a = (uint16_t)v; break;
+    case 2: *(GX_GLOBAL uint32_t*)a = (uint32_t)v; break;
+    default: *(GX_GLOBAL uint64_t*)a = v; break;
+  }
+}
 
 // Bytes [8w, 8w + 8) of an object of ``n`` bytes at ``p`` (stack offset or
 // global address), zero beyond n.
@@ -134,9 +172,9 @@ __device__ __forceinline__ uint64_t chunk(int kind, uint64_t p, uint32_t w, uint
     for (uint32_t i = 0; i < m; i++) v |= (uint64_t)*saddr(stk, o + i) << (8 * i);
     return v;
   }
-  const uint8_t* q = (const uint8_t*)p + 8 * w;
-  if (m == 8 && ((uintptr_t)q & 7) == 0) return *(const uint64_t*)q;
-  if (m == 4 && ((uintptr_t)q & 3) == 0) return *(const uint32_t*)q;
+  const GX_GLOBAL uint8_t* q = (const GX_GLOBAL uint8_t*)(p + 8 * w);
+  if (m == 8 && ((uintptr_t)q & 7) == 0) return *(const GX_GLOBAL uint64_t*)q;
+  if (m == 4 && ((uintptr_t)q & 3) == 0) return *(const GX_GLOBAL uint32_t*)q;
   uint64_t v = 0;
   for (uint32_t i = 0; i < m; i++) v |= (uint64_t)q[i] << (8 * i);
   return v;
@@ -145,10 +183,10 @@ __device__ __forceinline__ uint64_t chunk(int kind, uint64_t p, uint32_t w, uint
 // Copy n bytes from (kind, p) to global memory dst (8-byte aligned).
 __device__ __forceinline__ void copy_in(uint8_t* dst, int kind, uint64_t p, uint32_t n, const Stk& stk) {
   uint32_t full = n / 8;
-  for (uint32_t w = 0; w < full; w++) ((uint64_t*)dst)[w] = chunk(kind, p, w, n, stk);
+  for (uint32_t w = 0; w < full; w++) gl((uint64_t*)dst)[w] = chunk(kind, p, w, n, stk);
   for (uint32_t i = full * 8; i < n; i++) {
     uint64_t c = chunk(kind, p, i / 8, n, stk);
-    dst[i] = (uint8_t)(c >> (8 * (i & 7)));
+    gl(dst)[i] = (uint8_t)(c >> (8 * (i & 7)));
   }
 }
 
@@ -191,6 +229,21 @@ __device__ __forceinline__ bool key_eq(const MapDev* m, uint8_t* hdr, int kind, 
   return true;
 }
 
+// A slot's header word and its one key word (keys of up to 8 bytes: a
+// 16-byte slot) read in one device-coherent 16-byte access.  One access
+// returns one state of the slot: an inserter's key words are complete at
+// the coherence point before its header turns live, so a live header never
+// comes with a stale key.  It replaces two dependent device-coherent reads,
+// each of which goes past the XCD's L2.  The wait is part of the access
+// (the header is needed at once).
+typedef uint32_t gx_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load_slot16(const uint8_t* hdr, uint64_t* st, uint64_t* key) {
+  gx_u32x4 v;
+  __asm__ volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(hdr) : "memory");
+  *st = (uint64_t)v.x | ((uint64_t)v.y << 32);
+  *key = (uint64_t)v.z | ((uint64_t)v.w << 32);
+}
+
 // Probe for a key.  Returns the slot index or -1; *free_slot receives the
 // first slot this launch may claim (or -1).
 GX_HELPER int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, const Stk& stk,
@@ -199,9 +252,15 @@ GX_HELPER int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, 
   uint32_t i = (uint32_t)h & mask;
   uint32_t tag = (uint32_t)(h >> 32);
   int64_t fr = -1;
+  const bool pair = m->sstride == 16;  // key of at most 8 bytes
+  const uint64_t k0 = pair ? chunk(kind, kp, 0, m->key_size, stk) : 0;
   for (uint32_t probe = 0; probe <= mask; probe++) {
     uint8_t* hdr = m->slots + (uint64_t)i * m->sstride;
-    uint64_t st = ld_relaxed((uint64_t*)hdr);
+    uint64_t st, sk = 0;
+    if (pair)
+      load_slot16(hdr, &st, &sk);
+    else
+      st = ld_relaxed((uint64_t*)hdr);
     uint32_t state = (uint32_t)st & 0xff;
     if (state == SLOT_EMPTY) {
       if (fr < 0) fr = i;
@@ -209,7 +268,7 @@ GX_HELPER int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, 
     }
     if (state == SLOT_TOMB) {
       if (fr < 0 && claimable(st, epoch, stk.owner)) fr = i;
-    } else if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && key_eq(m, hdr, kind, kp, stk)) {
+    } else if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && (pair ? sk == k0 : key_eq(m, hdr, kind, kp, stk))) {
       if (free_slot) *free_slot = fr;
       return i;
     }
@@ -237,10 +296,10 @@ GX_HELPER int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind
     return 0;
   }
   if (flags == 2) return -E_NOENT;
-  uint64_t live = __hip_atomic_fetch_add(&m->ctrl[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t live = __hip_atomic_fetch_add(gl(&m->ctrl[0]), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (live >= m->max_entries) {
-    __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&m->ctrl[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gl(&m->ctrl[0]), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gl(&m->ctrl[1]), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return -E_2BIG;
   }
   uint32_t mask = m->slot_mask;
@@ -250,23 +309,23 @@ GX_HELPER int64_t hash_update(const MapDev* m, int kkind, uint64_t kp, int vkind
     uint64_t* hw = (uint64_t*)(m->slots + (uint64_t)i * m->sstride);
     uint64_t cur = ld_relaxed(hw);
     if (claimable(cur, epoch, stk.owner) &&
-        __hip_atomic_compare_exchange_strong(hw, &cur, hdr_word(SLOT_BUSY, epoch, tag), __ATOMIC_RELAXED,
+        __hip_atomic_compare_exchange_strong(gl(hw), &cur, hdr_word(SLOT_BUSY, epoch, tag), __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       uint32_t nw = (m->key_size + 7) / 8;
       for (uint32_t w = 0; w < nw; w++)
-        __hip_atomic_store(hw + 1 + w, chunk(kkind, kp, w, m->key_size, stk), __ATOMIC_RELAXED,
+        __hip_atomic_store(gl(hw + 1 + w), chunk(kkind, kp, w, m->key_size, stk), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       copy_in(m->data + (uint64_t)i * m->vstride, vkind, vp, m->value_size, stk);
       // the key words reach the coherence point before the slot turns live
       __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __hip_atomic_store(hw, hdr_word(SLOT_LIVE, epoch, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gl(hw), hdr_word(SLOT_LIVE, epoch, tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return 0;
     }
     i = (i + 1) & mask;
   }
   // no claimable slot in this launch; undo the reservation
-  __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(&m->ctrl[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(gl(&m->ctrl[0]), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(gl(&m->ctrl[1]), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return -E_2BIG;
 }
 
@@ -274,9 +333,9 @@ GX_HELPER int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk&
   uint64_t h = key_hash(m, kind, kp, stk);
   int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
   if (s < 0) return -E_NOENT;
-  __hip_atomic_store((uint64_t*)(m->slots + (uint64_t)s * m->sstride),
+  __hip_atomic_store(gl((uint64_t*)(m->slots + (uint64_t)s * m->sstride)),
                      hdr_word(SLOT_TOMB, epoch, stk.owner), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(&m->ctrl[0], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(gl(&m->ctrl[0]), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
 
@@ -310,9 +369,9 @@ __device__ __forceinline__ bool ring_reserve(const MapDev* m, uint64_t total, ui
   const uint64_t t = ld_relaxed(&m->ctrl[1]);
   const uint64_t h = ld_relaxed(&m->ctrl[0]);
   if (h + total - t > cap) return false;
-  const uint64_t old = __hip_atomic_fetch_add(&m->ctrl[0], total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t old = __hip_atomic_fetch_add(gl(&m->ctrl[0]), total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (old + total - t > cap) {
-    __hip_atomic_fetch_max(&m->ctrl[3], ~old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(gl(&m->ctrl[3]), ~old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return false;
   }
   *base = old;
@@ -324,9 +383,9 @@ __device__ __forceinline__ void ring_put(const MapDev* m, uint64_t pos, int kind
                                          const Stk& stk) {
   const uint64_t mask = m->slot_mask;
   const uint32_t nw = (size + 7) / 8;
-  for (uint32_t w = 0; w < nw; w++) *(uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask)) = chunk(kind, dp, w, size, stk);
+  for (uint32_t w = 0; w < nw; w++) *gl((uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask))) = chunk(kind, dp, w, size, stk);
   // records are read by the host once the producing launch has completed
-  *(uint64_t*)(m->data + (pos & mask)) = (uint64_t)size;
+  *gl((uint64_t*)(m->data + (pos & mask))) = (uint64_t)size;
 }
 
 // ringbuf_output for the whole wave; ``act`` lanes take part.  Space for all
@@ -348,7 +407,7 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
     ok = ring_reserve(m, total, &b) ? 1u : 0u;
     base_lo = (uint32_t)b;
     base_hi = (uint32_t)(b >> 32);
-    if (!ok) __hip_atomic_fetch_add(&m->ctrl[2], (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ok) __hip_atomic_fetch_add(gl(&m->ctrl[2]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   ok = rdlane(ok, leader);
   uint64_t base = ((uint64_t)rdlane(base_hi, leader) << 32) | rdlane(base_lo, leader);
@@ -391,7 +450,7 @@ __device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot)
   const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos;
   if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
     if (left >= 8)
-      *(uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask)) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+      *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
     g_rchunk[slot].left = 0;
   }
 }
@@ -416,7 +475,7 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
   uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left;
   if (total > left) {
     if (lane_id() == leader && left >= 8)
-      *(uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask)) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+      *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
     const uint64_t ask = total > chunk_bytes ? total : chunk_bytes;
     uint32_t ok = 0, lo = 0, hi = 0;
     if (lane_id() == leader) {
@@ -425,7 +484,7 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
       if (!ok && ask > total) ok = ring_reserve(m, total, &b) ? 2u : 0u;
       lo = (uint32_t)b;
       hi = (uint32_t)(b >> 32);
-      if (!ok) __hip_atomic_fetch_add(&m->ctrl[2], (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!ok) __hip_atomic_fetch_add(gl(&m->ctrl[2]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     ok = rdlane(ok, leader);
     if (!ok) {
@@ -468,7 +527,7 @@ __device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uin
   }
 #endif
   if (w64) {
-    uint64_t* p = (uint64_t*)addr;
+    GX_GLOBAL uint64_t* p = (GX_GLOBAL uint64_t*)addr;
     switch (op) {
       case 0x00: case 0x01: return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       case 0x40: case 0x41: return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -482,7 +541,7 @@ __device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uin
       }
     }
   }
-  uint32_t* p = (uint32_t*)addr;
+  GX_GLOBAL uint32_t* p = (GX_GLOBAL uint32_t*)addr;
   uint32_t x = (uint32_t)v;
   switch (op) {
     case 0x00: case 0x01: return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -534,7 +593,8 @@ __device__ __forceinline__ void lds_rmw(T* p, T v, uint32_t op) {
 }
 
 template <typename T>
-__device__ __forceinline__ void global_rmw(T* p, T v, uint32_t op) {
+__device__ __forceinline__ void global_rmw(T* q, T v, uint32_t op) {
+  GX_GLOBAL T* p = gl(q);
   switch (op) {
     case 0x00: __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
     case 0x40: __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
@@ -650,7 +710,7 @@ __device__ __forceinline__ bool guard_ok(const RunArgs& A, uint32_t pc, uint64_t
   typedef const __attribute__((address_space(4))) uint64_t cu64;
   const cu64* g = (const cu64*)(A.guards + 2 * pc);
   bool ok = addr >= g[0] && addr + size <= g[1];
-  if (!ok) __hip_atomic_fetch_add(A.err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!ok) __hip_atomic_fetch_add(gl(A.err), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return ok;
 }
 
@@ -782,6 +842,71 @@ __device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q
 #pragma unroll
       for (uint32_t j = 0; j < B; j++)
         if (k0 + j < cnt) A.rc[si[j]] = crc[j];
+    }
+    if (steps > A.step_limit) break;
+  }
+}
+
+// One queue of a stream-sequential run, by lane 0 of the wave with
+// wave-uniform values (compiled programs, one queue per wave).  The queue
+// bounds, queue-ordered records and event indices are constant for the
+// launch (the partition wrote them before it), so they are read with scalar
+// loads, which do not wait behind the wave's outstanding vector accesses;
+// the next block of records is fetched while this one runs.
+constexpr uint32_t kUniBlock = 4;  // records held in scalar registers
+
+template <class Run>
+__device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q, uint32_t qstride,
+                                           uint32_t qend_last, const Stk& stk, uint64_t& steps) {
+  typedef const __attribute__((address_space(4))) uint32_t cu32;
+  typedef const __attribute__((address_space(4))) uint64_t cu64;
+  constexpr uint32_t B = kUniBlock;
+  if (lane_id() != 0 || q >= A.n_queues) return;
+  const uint32_t beg = ((const cu32*)A.qstart)[(uint64_t)q * qstride];
+  const uint32_t end = q + 1 < A.n_queues ? ((const cu32*)A.qstart)[(uint64_t)(q + 1) * qstride] : qend_last;
+  const bool wide = A.record_size > 16;
+  auto fetch = [&](uint32_t k, Ctx& c, uint32_t& idx) {
+    const cu64* p = (const cu64*)(A.sorted + (uint64_t)k * kSortedStride);
+    c.c0 = p[0];
+    c.c1 = p[1];
+    c.c2 = wide ? p[2] : 0;
+    idx = ((const cu32*)A.order)[k];
+  };
+  Ctx nx[B];
+  uint32_t ni[B];
+#pragma unroll
+  for (uint32_t j = 0; j < B; j++) {
+    nx[j] = Ctx{0, 0, 0};
+    ni[j] = 0;
+    if (beg + j < end) fetch(beg + j, nx[j], ni[j]);
+  }
+  for (uint32_t k0 = beg; k0 < end; k0 += B) {
+    Ctx cu[B];
+    uint32_t si[B], crc[B];
+#pragma unroll
+    for (uint32_t j = 0; j < B; j++) {
+      cu[j] = nx[j];
+      si[j] = ni[j];
+      crc[j] = 0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < B; j++)
+      if (k0 + B + j < end) fetch(k0 + B + j, nx[j], ni[j]);
+    const uint32_t n = end - k0 < B ? end - k0 : B;
+    for (uint32_t j = 0; j < B; j++) {
+      const Ctx c = cu[0];
+#pragma unroll
+      for (uint32_t x = 0; x + 1 < B; x++) cu[x] = cu[x + 1];
+      uint32_t rc = 0;
+      if (j < n) rc = (uint32_t)uni<true>(R.run(A, true, c.c0, c.c1, c.c2, stk, steps));
+#pragma unroll
+      for (uint32_t x = 0; x + 1 < B; x++) crc[x] = crc[x + 1];
+      crc[B - 1] = rc;
+    }
+    if (A.rc) {
+#pragma unroll
+      for (uint32_t j = 0; j < B; j++)
+        if (j < n) A.rc[si[j]] = crc[j];
     }
     if (steps > A.step_limit) break;
   }

@@ -108,6 +108,217 @@ struct JMaps {
   uint64_t ring_cap(int k) const { return (uint64_t)m[k].second.slot_mask + 1; }
 };
 
+// Map-value windows: a lookup of a map whose values this program's lane
+// alone writes (not shared, not read-only; at most 64 bytes) loads the whole
+// value into locals right after the call, one parallel burst of loads, and
+// later reads through that pointer take the locals instead of waiting for
+// one memory round trip each.  Stores through the pointer still go to
+// memory and also update the locals.  A forward data-flow pass over the
+// micro-ops finds, for every access, whether its base register holds the
+// pointer of the lookup site's latest run (copies and constant offsets
+// followed) with no store through another pointer, atomic, update or delete
+// on that map in between; only those accesses use a window.  Anything else
+// reads memory as before, which the stores keep current.
+struct Windows {
+  struct W {
+    uint32_t pc;
+    int map;
+    uint32_t words;
+    bool used;
+  };
+  std::vector<W> win;
+  std::vector<int> site;     // window of each lookup site, by slot (-1 none)
+  std::vector<int> acc;      // window of each map access, by slot (-1 none)
+  std::vector<int32_t> off;  // its byte offset in the value
+};
+
+Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
+  Windows R;
+  const uint32_t n = (uint32_t)U.size();
+  R.site.assign(n, -1);
+  R.acc.assign(n, -1);
+  R.off.assign(n, 0);
+  for (uint32_t pc = 0; pc < n; pc++) {
+    const uint32_t h = U[pc].w0 & 0xff;
+    if (h == H_LDIMM) {
+      pc++;
+      continue;
+    }
+    if (h != H_LOOKUP_HASH && h != H_LOOKUP_ARRAY) continue;
+    const int k = J.index(U[pc].imm);
+    if (k < 0 || R.win.size() >= 64) continue;
+    const MapDev& md = J.m[k].second;
+    if ((md.flags & (F_SHARED | F_READ_ONLY)) || md.value_size == 0 || md.value_size > 64) continue;
+    R.site[pc] = (int)R.win.size();
+    R.win.push_back({pc, k, (md.value_size + 7) / 8, false});
+  }
+  if (R.win.empty()) return R;
+  struct St {
+    bool reached = false;
+    int w[11];
+    int64_t d[11];
+    uint64_t valid = 0;
+  };
+  std::vector<St> in(n);
+  // the access [o, o + size) of window w fits in one of its words
+  auto fits = [&](int w, int64_t o, uint32_t size) {
+    return o >= 0 && o + size <= 8ull * R.win[w].words && (uint64_t)(o & 7) + size <= 8;
+  };
+  auto kill_map = [&](St& s, int k) {
+    for (size_t i = 0; i < R.win.size(); i++)
+      if (k < 0 || R.win[i].map == k) s.valid &= ~(1ull << i);
+  };
+  auto holds = [&](const St& s, uint32_t r) { return r < 11 && s.w[r] >= 0 && ((s.valid >> s.w[r]) & 1); };
+  // transfer: state after slot pc; successors into succ
+  auto step = [&](uint32_t pc, St s, std::vector<uint32_t>& succ, bool mark) {
+    const Uop& u = U[pc];
+    const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, src = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
+    const bool K = (u.w0 >> 24) & 1;
+    const uint32_t size = 1u << (a8 & 3);
+    uint32_t next = pc + 1;
+    auto set_reg = [&](uint32_t r, int w, int64_t dd) {
+      if (r < 11) {
+        s.w[r] = w;
+        s.d[r] = dd;
+      }
+    };
+    if (h <= H_TRUNC) {
+      if (h == H_MOV64 && !K && src < 11)
+        set_reg(d, s.w[src], s.d[src]);
+      else if ((h == H_ADD64 || h == H_SUB64) && K && d < 11 && s.w[d] >= 0)
+        s.d[d] += h == H_ADD64 ? (int64_t)u.imm : -(int64_t)u.imm;
+      else
+        set_reg(d, -1, 0);
+      succ.push_back(next);
+    } else if (h >= H_JA && h <= H_JSLE32) {
+      if (h != H_JA) succ.push_back(next);
+      succ.push_back((uint32_t)u.aux);
+    } else {
+      switch (h) {
+        case H_LDX_MAP:
+          if (mark && holds(s, src) && fits(s.w[src], s.d[src] + u.aux, size)) {
+            R.acc[pc] = s.w[src];
+            R.off[pc] = (int32_t)(s.d[src] + u.aux);
+            R.win[s.w[src]].used = true;
+          }
+          set_reg(d, -1, 0);
+          succ.push_back(next);
+          break;
+        case H_LDX_CTX:
+        case H_LDX_STACK:
+          set_reg(d, -1, 0);
+          succ.push_back(next);
+          break;
+        case H_ST_STACK:
+        case H_STX_STACK:
+          succ.push_back(next);
+          break;
+        case H_ST_MAP:
+        case H_STX_MAP: {
+          const int k = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+          if (holds(s, d) && fits(s.w[d], s.d[d] + u.aux, size)) {
+            // a store through the window: the locals follow it; any other
+            // pointer into the map may alias it
+            const int w = s.w[d];
+            if (mark) {
+              R.acc[pc] = w;
+              R.off[pc] = (int32_t)(s.d[d] + u.aux);
+            }
+            kill_map(s, R.win[w].map);
+            s.valid |= 1ull << w;
+          } else {
+            kill_map(s, k);
+          }
+          succ.push_back(next);
+          break;
+        }
+        case H_ATOMIC_STACK:
+        case H_ATOMIC_MAP:
+          if (h == H_ATOMIC_MAP) kill_map(s, pc < J.mem_map.size() ? J.mem_map[pc] : -1);
+          if ((uint32_t)u.imm == 0xf1)
+            set_reg(0, -1, 0);
+          else if (u.imm & 1)
+            set_reg(src, -1, 0);
+          succ.push_back(next);
+          break;
+        case H_LDIMM:
+          set_reg(d, -1, 0);
+          succ.push_back(pc + 2);
+          break;
+        case H_LOOKUP_ARRAY:
+        case H_LOOKUP_HASH:
+        case H_UPDATE_ARRAY:
+        case H_UPDATE_HASH:
+        case H_DELETE_HASH:
+        case H_RET_EINVAL:
+        case H_RINGBUF_OUTPUT: {
+          for (uint32_t r = 0; r <= 5; r++) set_reg(r, -1, 0);
+          if (h == H_UPDATE_ARRAY || h == H_UPDATE_HASH || h == H_DELETE_HASH) kill_map(s, J.index(u.imm));
+          const int w = R.site[pc];
+          if (w >= 0) {
+            for (uint32_t r = 0; r < 11; r++)
+              if (s.w[r] == w) set_reg(r, -1, 0);
+            set_reg(0, w, 0);
+            s.valid |= 1ull << w;
+          }
+          succ.push_back(next);
+          break;
+        }
+        default:  // exit
+          break;
+      }
+    }
+    return s;
+  };
+  St entry;
+  entry.reached = true;
+  for (int r = 0; r < 11; r++) {
+    entry.w[r] = -1;
+    entry.d[r] = 0;
+  }
+  in[0] = entry;
+  std::vector<uint32_t> work{0};
+  std::vector<char> queued(n, 0);
+  queued[0] = 1;
+  while (!work.empty()) {
+    const uint32_t pc = work.back();
+    work.pop_back();
+    queued[pc] = 0;
+    std::vector<uint32_t> succ;
+    const St out = step(pc, in[pc], succ, false);
+    for (uint32_t t : succ) {
+      if (t >= n) continue;
+      St& dst = in[t];
+      bool changed = false;
+      if (!dst.reached) {
+        dst = out;
+        changed = true;
+      } else {
+        for (int r = 0; r < 11; r++)
+          if (dst.w[r] >= 0 && (dst.w[r] != out.w[r] || dst.d[r] != out.d[r])) {
+            dst.w[r] = -1;
+            changed = true;
+          }
+        const uint64_t v = dst.valid & out.valid;
+        if (v != dst.valid) {
+          dst.valid = v;
+          changed = true;
+        }
+      }
+      if (changed && !queued[t]) {
+        queued[t] = 1;
+        work.push_back(t);
+      }
+    }
+  }
+  for (uint32_t pc = 0; pc < n; pc++) {
+    if (!in[pc].reached) continue;
+    std::vector<uint32_t> succ;
+    (void)step(pc, in[pc], succ, true);
+  }
+  return R;
+}
+
 std::string map_name(const JMaps& J, uint64_t desc) {
   int k = J.index(desc);
   return k >= 0 ? "&M" + std::to_string(k) : "(const MapDev*)" + lit(desc);
@@ -129,7 +340,7 @@ std::string map_fn(size_t k, const MapDev& m) {
   return b;
 }
 
-void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
+void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const Windows& Wn) {
   const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, s = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
   const bool K = (u.w0 >> 24) & 1;
   const std::string D = reg(d), S = reg(s);
@@ -148,6 +359,21 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
          std::to_string(size) + "u)) { " + body + " } }\n";
   };
   const std::string sgn_a = "(int64_t)" + D, sgn_b = "(int64_t)" + B;
+  // window word holding this access, and the access's bit shift in it
+  const int wa = pc < Wn.acc.size() ? Wn.acc[pc] : -1;
+  const std::string wword =
+      wa >= 0 ? "w" + std::to_string(wa) + "_" + std::to_string(Wn.off[pc] / 8) : std::string();
+  const std::string wsh = wa >= 0 ? std::to_string(8 * (Wn.off[pc] % 8)) : std::string();
+  // after a lookup with a window: the value's words, loaded together
+  auto window_load = [&]() {
+    const int w = pc < Wn.site.size() ? Wn.site[pc] : -1;
+    if (w < 0 || !Wn.win[w].used) return;
+    o += "  if (r0) {";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++)
+      o += " w" + std::to_string(w) + "_" + std::to_string(j) + " = uni<UNI>(*(const GX_GLOBAL uint64_t*)(r0 + " +
+           std::to_string(8 * j) + "ull));";
+    o += " }\n";
+  };
   const std::string sa32 = "(int32_t)" + xa, sb32 = "(int32_t)" + xb;
   switch (h) {
     case H_ADD64: set(D + " + " + B); break;
@@ -231,7 +457,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
       break;
     }
     case H_LDX_STACK:
-      set(extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf));
+      set("uni<UNI>(" + extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf) + ")");
       break;
     case H_LDX_MAP: {
       const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
@@ -242,9 +468,11 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
         // the wave's outstanding vector loads (they complete in order)
         guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
                 D + " = " + extend(std::string("load_uniform<") + kTy[sc] + ">(ad)", sc, sxf) + ";");
+      } else if (wa >= 0) {
+        set(extend(std::string("(") + kTy[sc] + ")(" + wword + " >> " + wsh + ")", sc, sxf));
       } else {
         guarded(S + " + (uint64_t)(int64_t)" + off, 1u << sc,
-                D + " = " + extend(std::string("*(const ") + kTy[sc] + "*)ad", sc, sxf) + ";");
+                D + " = uni<UNI>(" + extend(std::string("*(const GX_GLOBAL ") + kTy[sc] + "*)ad", sc, sxf) + ");");
       }
       break;
     }
@@ -254,10 +482,16 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
            (h == H_ST_STACK ? lit(u.imm) : S) + ";\n";
       break;
     case H_ST_MAP:
-    case H_STX_MAP:
-      guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
-              std::string("*(") + kTy[sc] + "*)ad = (" + kTy[sc] + ")" + (h == H_ST_MAP ? lit(u.imm) : S) + ";");
+    case H_STX_MAP: {
+      const std::string val = std::string("(") + kTy[sc] + ")" + (h == H_ST_MAP ? lit(u.imm) : S);
+      std::string body = std::string("*(GX_GLOBAL ") + kTy[sc] + "*)ad = " + val + ";";
+      if (wa >= 0)
+        body += sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
+                        : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + wsh +
+                              ")) | ((uint64_t)" + val + " << " + wsh + ");";
+      guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, body);
       break;
+    }
     case H_ATOMIC_STACK:
     case H_ATOMIC_MAP: {
       const uint32_t op = (uint32_t)u.imm;
@@ -270,7 +504,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
       const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
       const Acc* ac = (h == H_ATOMIC_MAP && mk >= 0 && mk < (int)J.acc.size() && J.acc[mk].kind) ? &J.acc[mk] : nullptr;
       if (h == H_ATOMIC_STACK) {
-        o += "  { const uint64_t t = " + call + "; " + wb + " }\n";
+        o += "  { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }\n";
       } else if (ac) {
         // shared map: summed in LDS by the event-parallel kernel
         const std::string T = ac->sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(mk);
@@ -281,9 +515,9 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
                           : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(ac->words) +
                                 "u, M" + K + ".data, ad, (" + T + ")" + S + ", " + ops + ");";
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
-                "if (PRIV) { " + lds + " } else { const uint64_t t = " + call + "; " + wb + " }");
+                "if (PRIV) { " + lds + " } else { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
       } else {
-        guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = " + call + "; " + wb);
+        guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = uni<UNI>(" + call + "); " + wb);
       }
       break;
     }
@@ -297,32 +531,34 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J) {
         set(lit(u.imm));
       break;
     case H_LOOKUP_ARRAY:
-      o += "  r0 = array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk);\n";
+      o += "  r0 = uni<UNI>(array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk));\n";
+      window_load();
       break;
     case H_LOOKUP_HASH:
-      o += "  r0 = hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch);\n";
+      o += "  r0 = uni<UNI>(hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));\n";
+      window_load();
       break;
     case H_UPDATE_ARRAY:
-      o += "  r0 = (uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
-           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk);\n";
+      o += "  r0 = uni<UNI>((uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
+           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk));\n";
       break;
     case H_UPDATE_HASH:
-      o += "  r0 = (uint64_t)hash_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
-           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk, A.epoch);\n";
+      o += "  r0 = uni<UNI>((uint64_t)hash_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
+           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk, A.epoch));\n";
       break;
     case H_DELETE_HASH:
-      o += "  r0 = (uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch);\n";
+      o += "  r0 = uni<UNI>((uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));\n";
       break;
     case H_RET_EINVAL: o += "  r0 = (uint64_t)-22ll;\n"; break;
     case H_RINGBUF_OUTPUT: {
       const int k = J.index(u.imm);
       if (k >= 0 && J.ring[k] >= 0)
-        o += "  r0 = ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, chunk[" +
-             std::to_string(J.ring[k]) + "], " + std::to_string(a8 & 1) + ", r2, " +
-             std::to_string((uint32_t)u.aux) + "u, r4, stk);\n";
+        o += "  r0 = uni<UNI>(ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) +
+             "u, chunk[" + std::to_string(J.ring[k]) + "], " + std::to_string(a8 & 1) + ", r2, " +
+             std::to_string((uint32_t)u.aux) + "u, r4, stk));\n";
       else
-        o += "  r0 = ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " + std::to_string((uint32_t)u.aux) +
-             "u, r4, true, stk);\n";
+        o += "  r0 = uni<UNI>(ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
+             std::to_string((uint32_t)u.aux) + "u, r4, true, stk));\n";
       break;
     }
     case H_EXIT:
@@ -374,14 +610,20 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       o += "__shared__ uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + T + " g_val" + K + "[" + N + "];\n";
   }
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
-  o += "\ntemplate <bool PRIV>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
-       "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave reserves at once, per ring\n\n";
+  // UNI: run by one lane with wave-uniform values (one queue per wave)
+  o += "\ntemplate <bool PRIV, bool UNI = false>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
+       "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave reserves at once, per ring\n";
+  // the maps' descriptors, read from the map table once per run (they stay
+  // in scalar registers instead of being reloaded for every event)
+  for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
+  o += "\n";
   // begin / end: open and close the wave's ring chunks and the block's
   // accumulators.  A chunk is the ring's capacity over four times the waves
   // of the launch (64 B to 8 KiB): chunks in flight then hold at most a
   // quarter of the ring.
   o += "  __device__ __forceinline__ void begin(const RunArgs& A) {\n    (void)A;\n";
   o += "    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64u);\n    (void)waves;\n";
+  for (size_t k = 0; k < maps.size(); k++) o += "    m" + std::to_string(k) + " = gx_map" + std::to_string(k) + "(A);\n";
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
       o += "    chunk[" + std::to_string(J.ring[k]) + "] = ring_chunk_bytes(" + std::to_string(J.ring_cap((int)k)) +
@@ -404,8 +646,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   o += "  }\n  __device__ __forceinline__ void end(const RunArgs& A) {\n    (void)A;\n";
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
-      o += "    { const MapDev M = gx_map" + std::to_string(k) + "(A); ring_chunk_close(&M, wave * GX_NRINGS + " +
-           std::to_string(J.ring[k]) + "u); }\n";
+      o += "    ring_chunk_close(&m" + std::to_string(k) + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u);\n";
   if (any_acc) {
     o += "    if (PRIV) {\n      __syncthreads();\n";
     for (size_t k = 0; k < maps.size(); k++) {
@@ -413,10 +654,10 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k);
       if (a.kind == 1)
         o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
-             "u, gx_map" + K + "(A).data);\n";
+             "u, m" + K + ".data);\n";
       else if (a.kind == 2)
         o += "      cache_flush<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
-             std::to_string(a.op) + "u, gx_map" + K + "(A).data);\n";
+             std::to_string(a.op) + "u, m" + K + ".data);\n";
     }
     o += "    }\n";
   }
@@ -424,14 +665,21 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   o += "  __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2, "
        "const Stk stk, uint64_t& steps) {\n";
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
+  o += "  if (UNI) { c0 = rfl64(c0); c1 = rfl64(c1); c2 = rfl64(c2); }\n";
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
   o += "  uint64_t r10 = " + std::to_string(P.stack_bytes) + "ull;\n";
   for (size_t k = 0; k < maps.size(); k++)
-    o += "  const MapDev M" + std::to_string(k) + " = gx_map" + std::to_string(k) + "(A);\n";
+    o += "  const MapDev& M" + std::to_string(k) + " = m" + std::to_string(k) + ";\n";
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
+  const Windows Wn = plan_windows(U, J);
+  for (size_t w = 0; w < Wn.win.size(); w++)
+    for (uint32_t j = 0; j < Wn.win[w].words; j++) {
+      const std::string nm = "w" + std::to_string(w) + "_" + std::to_string(j);
+      o += "  uint64_t " + nm + " = 0; (void)" + nm + ";\n";
+    }
   for (uint32_t pc = 0; pc < U.size(); pc++) {
     if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
-    emit_uop(o, U[pc], pc, J);
+    emit_uop(o, U[pc], pc, J, Wn);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace " + ns + "\n}  // namespace gx\n\n";
@@ -470,6 +718,11 @@ std::string jit_source(const JitProg& P, uint64_t* acc_words) {
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
        "  gx::p0::Prog<false> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
        "  gx::stream_wave(P, A, blockIdx.x * lanes, lanes, qstride, qend_last, stk, steps);\n"
+       "  P.end(A);\n}\n\n"
+       "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_uni(gx::RunArgs A, uint32_t qstride, "
+       "uint32_t qend_last) {\n  gx::Stk stk{0, 0u, blockIdx.x * 64u + threadIdx.x};\n"
+       "  gx::p0::Prog<false, true> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
+       "  gx::stream_uni(P, A, blockIdx.x, qstride, qend_last, stk, steps);\n"
        "  P.end(A);\n}\n";
   return o;
 }
@@ -490,15 +743,18 @@ std::string jit_set_source(const std::vector<JitProg>& progs) {
   o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_set(const gx::BatchDev* B, const uint2* items, "
        "uint32_t n_items, uint32_t* next) {\n"
        "  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
+       "  gx::Stk stku{0, 0u, blockIdx.x * 64u + threadIdx.x};\n  (void)stku;\n"
        "  gx::batched_items(B, items, n_items, next, [&](const gx::BatchDev& bd, uint32_t chunk) {\n"
        "    uint64_t steps = 0;\n    switch (bd.slot) {\n";
   for (size_t k = 0; k < progs.size(); k++) {
     const std::string K = std::to_string(k);
-    o += "      case " + K + "u: {\n        gx::p" + K + "::Prog<false> P{0u};\n        P.begin(bd.A);\n";
-    if (progs[k].event_parallel)
+    const bool ep = progs[k].event_parallel;
+    o += "      case " + K + "u: {\n        gx::p" + K + "::Prog<false" + (ep ? "" : ", true") +
+         "> P{0u};\n        P.begin(bd.A);\n";
+    if (ep)
       o += "        gx::event_tile(P, bd.A, (uint64_t)chunk * 64u, stk, steps);\n";
     else
-      o += "        gx::stream_wave(P, bd.A, chunk * bd.lanes, bd.lanes, bd.qstride, bd.qend_last, stk, steps);\n";
+      o += "        gx::stream_uni(P, bd.A, chunk, bd.qstride, bd.qend_last, stku, steps);\n";
     o += "        P.end(bd.A);\n        break;\n      }\n";
   }
   o += "      default: break;\n    }\n  });\n}\n";

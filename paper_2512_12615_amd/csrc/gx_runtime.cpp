@@ -68,9 +68,11 @@ struct ProgObj {
   std::vector<int> fds;
   std::vector<Uop> uops;  // host copy (source of the compiled form)
   uint64_t* d_maptab = nullptr;  // device addresses of its map descriptors (map-table order)
-  // compiled form (gx_jit_program): module and its two kernels
+  // compiled form (gx_jit_program): module and its kernels (event-parallel;
+  // stream-sequential with any lanes per wave, and with one queue per wave
+  // run on wave-uniform values)
   hipModule_t jmod = nullptr;
-  hipFunction_t jf_ep = nullptr, jf_seq = nullptr;
+  hipFunction_t jf_ep = nullptr, jf_seq = nullptr, jf_uni = nullptr;
   uint64_t jacc_words = 0;  // LDS accumulator words each block flushes
   // launch shape chosen by gx_autotune (0: default)
   uint32_t tuned_lanes = 0, tuned_qbits = 0, tuned_blocks = 0;
@@ -187,7 +189,7 @@ struct gx_rt {
   // same-shaped maps share one); guarded for concurrent gx_jit_program calls
   struct JitMod {
     hipModule_t mod = nullptr;
-    hipFunction_t fe = nullptr, fs = nullptr;
+    hipFunction_t fe = nullptr, fs = nullptr, fu = nullptr;
     uint64_t acc_words = 0;
   };
   std::map<std::string, JitMod> jit_cache;
@@ -438,6 +440,10 @@ hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes
     if (blocks_override) nb = blocks_override;
     const uint32_t blocks = (uint32_t)std::max<uint64_t>(nb, 1);
     return hipModuleLaunchKernel(p->jf_ep, blocks, 1, 1, 64 * nw, 1, 1, 0, s, args, nullptr);
+  }
+  if (lanes == 1 && p->jf_uni) {
+    void* args[] = {&A, &qstride, &qend_last};
+    return hipModuleLaunchKernel(p->jf_uni, A.n_queues, 1, 1, 64, 1, 1, 0, s, args, nullptr);
   }
   void* args[] = {&A, &lanes, &qstride, &qend_last};
   return hipModuleLaunchKernel(p->jf_seq, (A.n_queues + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
@@ -986,6 +992,7 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   auto adopt = [&](const gx_rt::JitMod& jm) {
     p->jf_ep = jm.fe;
     p->jf_seq = jm.fs;
+    p->jf_uni = jm.fu;
     p->jacc_words = jm.acc_words;
     p->jmod = jm.mod;
   };
@@ -1008,7 +1015,8 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   jm.acc_words = acc_words;
   if (hipModuleLoadData(&jm.mod, code.data()) != hipSuccess) return -EIO;
   if (p->v.event_parallel ? hipModuleGetFunction(&jm.fe, jm.mod, "gx_j_event_parallel") != hipSuccess
-                          : hipModuleGetFunction(&jm.fs, jm.mod, "gx_j_stream_seq") != hipSuccess) {
+                          : (hipModuleGetFunction(&jm.fs, jm.mod, "gx_j_stream_seq") != hipSuccess ||
+                             hipModuleGetFunction(&jm.fu, jm.mod, "gx_j_stream_uni") != hipSuccess)) {
     (void)hipModuleUnload(jm.mod);
     return -EIO;
   }
@@ -1271,6 +1279,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     const ProgObj* bp = bprog[oc.second];
     if (bp->set_id >= 0 && (set_items.count(bp->set_id) || set_items.size() < kMaxSetsPerPhase)) {
       bd.slot = bp->set_slot;
+      if (bd.mode == 1) bd.lanes = 1;  // a set runs each queue on wave-uniform values
       uint32_t nchunks = bd.mode == 0 ? (uint32_t)((bd.A.n_events + 63) / 64) : (bd.A.n_queues + bd.lanes - 1) / bd.lanes;
       auto& v = set_items[bp->set_id];
       for (uint32_t c = 0; c < nchunks; c++) v.push_back(make_uint2(oc.second, c));

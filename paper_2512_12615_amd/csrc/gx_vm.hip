@@ -151,7 +151,7 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
       case H_LDX_MAP:
         if (A.checked) act = act && guard_ok(A, pc, b + (int64_t)aux, 1u << sc);
         if (act) {
-          uint64_t v = load_sized((const uint8_t*)(b + (int64_t)aux), sc);
+          uint64_t v = load_sized_g(b + (uint64_t)(int64_t)aux, sc);
           res = (a8 & 4) ? sx(v, sc) : v;
         }
         nwd = d;
@@ -163,7 +163,7 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
       case H_ST_MAP:
       case H_STX_MAP:
         if (A.checked) act = act && guard_ok(A, pc, a + (int64_t)aux, 1u << sc);
-        if (act) store_sized((uint8_t*)(a + (int64_t)aux), b, sc);
+        if (act) store_sized_g(a + (uint64_t)(int64_t)aux, b, sc);
         break;
       case H_ATOMIC_STACK:
       case H_ATOMIC_MAP: {

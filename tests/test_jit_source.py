@@ -100,3 +100,30 @@ def test_program_set_compiles(G):
     assert src.count("gx_j_set(") == 1
     for k in range(len(pols)):
         assert f"namespace p{k} " in src and f"case {k}u:" in src
+
+
+def test_map_value_windows(G):
+    """The stride policy's value reads come from the window loaded after its
+    one lookup; in the alias programs every read after a store through
+    another pointer, an atomic or an update goes to memory."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import jit_window_programs as P
+    pol = W.stride_prefetch_policy()
+    src = G.jit_source(pol.code, pol.hook, _shapes(pol))
+    assert src.count("if (r0) { w0_0 = ") == 1
+    # no value load through a pointer is left: every LDX reads the window
+    assert "r1 = uni<UNI>((uint64_t)(*(const GX_GLOBAL" not in src
+    assert src.count("(w0_0 >> 0)") == 1 and src.count("(w0_1 >> 0)") == 1 and src.count("(w0_2 >> 0)") == 1
+    for name in P.PROGRAMS:
+        p = P.policy(name)
+        s = G.jit_source(p.code, p.hook, _shapes(p), compile=True)
+        body = s[s.index("uint64_t r10"):]
+        lines = body.splitlines()
+        if name == "alias":
+            # after the store through the second pointer, reads of the first go to memory
+            i = next(k for k, l in enumerate(lines) if "w1_0 = (uint64_t)" in l)
+            assert all(" >> " not in l for l in lines[i:])
+        if name in ("atomic", "update"):
+            i = next(k for k, l in enumerate(lines) if "atomic_global(" in l or "array_update(" in l)
+            assert all(" >> " not in l for l in lines[i:])
