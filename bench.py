@@ -430,6 +430,7 @@ def main():
         cpu = cpu_baseline(pol, host_batches[0], args.cpu_streams)
         insns_per_event = cpu["insns_per_event"]
 
+    tune_lanes = tune["lanes"] if tune else int(os.environ.get("GX_SEQ_LANES", "1"))
     fp = kernel_fingerprint(G, pol, args.engine)
     traffic, traffic_src = measured_traffic(fp)
     vm_avg_s = vm_ms / 1000 / max(vm_launches, 1)
@@ -474,9 +475,14 @@ def main():
             "traffic": traffic,
             "traffic_source": traffic_src,
             "kernel_sha256": fp,
-            "kernel": "gx_j_stream_seq" if args.engine == "jit" else "gx_k_stream_seq",
+            "kernel": ("gx_j_stream_uni" if tune_lanes == 1 else "gx_j_stream_seq") if args.engine == "jit"
+            else "gx_k_stream_seq",
             "bytes_per_event": "24 B record + 4 B rc + ring bytes",
         },
+        # the bound that holds here: each stream's events form one dependent
+        # chain (map state carried from event to event), run one after another
+        "chain": {"streams": 1024, "events_per_stream": n / 1024,
+                  "ns_per_event": vm_avg_s * 1e9 / (n / 1024)},
         "cpu_baseline": {k: v for k, v in cpu.items() if k in ("value", "unit", "cores", "kind", "sample")}
         if cpu else None,
         "stats": st,

@@ -422,11 +422,15 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
   return res;
 }
 
-// A wave's chunk of reserved ring space (compiled programs): ring outputs
-// carve their records from it, so most outputs reserve nothing globally.
-// The chunk lives in LDS, one slot per (wave, ring): its lanes may reach a
-// ring output under different EXEC masks, and LDS keeps one copy that every
-// lane sees.
+// Ring space for compiled programs is handed out in two levels, so that the
+// ring's head (one device-wide atomic counter, which every reservation
+// serialises on) is touched rarely: a block reserves a large chunk from the
+// ring, and each of its waves carves its own smaller chunk from the block's
+// under a block-local lock in LDS; ring outputs carve their records from
+// the wave's chunk.  The chunks live in LDS, one per (wave, ring) and one
+// per (block, ring): a wave's lanes may reach a ring output under
+// different EXEC masks, and LDS keeps one copy that every lane sees.
+// Unused rest of a chunk becomes one discarded record when it is closed.
 struct RingChunk {
   uint64_t pos;
   uint64_t left;
@@ -434,34 +438,99 @@ struct RingChunk {
 
 #ifdef GX_RING_SLOTS
 __shared__ RingChunk g_rchunk[GX_RING_SLOTS];
+__shared__ RingChunk g_rblock[GX_NRINGS];
+__shared__ uint32_t g_rlock[GX_NRINGS];
 
+// Chunk sizes: blocks' chunks and waves' chunks in flight each hold at most
+// an eighth of the ring, so reserved-but-unused space never exceeds a
+// quarter of it.
 __device__ __forceinline__ uint64_t ring_chunk_bytes(uint64_t cap, uint64_t waves) {
-  uint64_t c = cap / (4 * (waves ? waves : 1));
+  uint64_t c = cap / (8 * (waves ? waves : 1));
   c = c < 64 ? 64 : c > 8192 ? 8192 : c;
+  return c & ~7ull;
+}
+__device__ __forceinline__ uint64_t ring_block_bytes(uint64_t cap, uint64_t blocks) {
+  uint64_t c = cap / (8 * (blocks ? blocks : 1));
+  c = c < 256 ? 256 : c > (1u << 20) ? (1u << 20) : c;
   return c & ~7ull;
 }
 
 __device__ __forceinline__ void ring_chunk_init(uint32_t slot) {
   if (lane_id() == 0) g_rchunk[slot] = RingChunk{0, 0};
 }
-
-// Close the chunk: the unused rest becomes one discarded record.
-__device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
-  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos;
-  if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
-    if (left >= 8)
-      *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
-    g_rchunk[slot].left = 0;
+// by one wave of the block, before any wave uses the ring
+__device__ __forceinline__ void ring_block_init(uint32_t r) {
+  if (lane_id() == 0) {
+    g_rblock[r] = RingChunk{0, 0};
+    g_rlock[r] = 0;
   }
 }
 
-// ringbuf_output carving from the wave's chunk; a new chunk of ``chunk_bytes``
-// (or the wave's whole request, if larger) is reserved when this one is
-// short.  Same results as ring_output while space lasts; near a full ring a
-// request may fail a little earlier (the unused parts of chunks count as
-// used until the drain).
-__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint64_t chunk_bytes,
-                                                         int kind, uint64_t dp, uint32_t size, uint64_t flags,
+__device__ __forceinline__ void ring_discard(const MapDev* m, uint64_t pos, uint64_t left) {
+  if (left >= 8)
+    *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+}
+
+// Close a wave's chunk (every wave) / the block's chunk (one wave, after
+// every wave of the block has closed its own).
+__device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
+  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos;
+  if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
+    ring_discard(m, pos, left);
+    g_rchunk[slot].left = 0;
+  }
+}
+__device__ __forceinline__ void ring_block_close(const MapDev* m, uint32_t r) {
+  if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
+    ring_discard(m, g_rblock[r].pos, g_rblock[r].left);
+    g_rblock[r].left = 0;
+  }
+}
+
+// A wave's new chunk of ``ask`` bytes (by one lane): cut from the block's
+// chunk, which is refilled from the ring when short.  false: the ring has
+// no room (not even for ``need``, the wave's request itself).
+__device__ __forceinline__ bool ring_block_take(const MapDev* m, uint32_t r, uint64_t block_bytes, uint64_t ask,
+                                                uint64_t need, uint64_t* pos, uint64_t* got) {
+  while (__hip_atomic_exchange(&g_rlock[r], 1u, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+    __builtin_amdgcn_s_sleep(1);
+  RingChunk b = g_rblock[r];
+  bool ok = true;
+  if (b.left < ask) {
+    uint64_t base = 0;
+    const uint64_t bask = ask > block_bytes ? ask : block_bytes;
+    if (ring_reserve(m, bask, &base)) {
+      ring_discard(m, b.pos, b.left);
+      b = RingChunk{base, bask};
+    } else if (b.left >= need) {
+      ask = need;  // the ring is nearly full: finish the block's chunk
+    } else if (ring_reserve(m, need, &base)) {
+      ring_discard(m, b.pos, b.left);
+      b = RingChunk{base, need};
+      ask = need;
+    } else {
+      ok = false;
+    }
+  }
+  if (ok) {
+    *pos = b.pos;
+    *got = ask;
+    b.pos += ask;
+    b.left -= ask;
+    g_rblock[r] = b;
+  }
+  __hip_atomic_store(&g_rlock[r], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return ok;
+}
+
+// ringbuf_output carving from the wave's chunk; a new chunk of
+// ``chunk_bytes`` (or the wave's whole request, if larger) is taken from the
+// block's chunk when this one is short.  Same results as ring_output while
+// space lasts; near a full ring a request may fail a little earlier (the
+// unused parts of chunks count as used until the drain).
+__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint32_t r,
+                                                         uint64_t chunk_bytes, uint64_t block_bytes, int kind,
+                                                         uint64_t dp, uint32_t size, uint64_t flags,
                                                          const Stk& stk) {
   uint64_t res = 0;
   const bool want = flags == 0;
@@ -474,16 +543,15 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
   const uint64_t total = (uint64_t)need * cnt;
   uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left;
   if (total > left) {
-    if (lane_id() == leader && left >= 8)
-      *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
-    const uint64_t ask = total > chunk_bytes ? total : chunk_bytes;
-    uint32_t ok = 0, lo = 0, hi = 0;
+    uint32_t ok = 0, lo = 0, hi = 0, glo = 0, ghi = 0;
     if (lane_id() == leader) {
-      uint64_t b = 0;
-      ok = ring_reserve(m, ask, &b) ? 1u : 0u;
-      if (!ok && ask > total) ok = ring_reserve(m, total, &b) ? 2u : 0u;
+      ring_discard(m, pos, left);
+      uint64_t b = 0, got = 0;
+      ok = ring_block_take(m, r, block_bytes, total > chunk_bytes ? total : chunk_bytes, total, &b, &got) ? 1u : 0u;
       lo = (uint32_t)b;
       hi = (uint32_t)(b >> 32);
+      glo = (uint32_t)got;
+      ghi = (uint32_t)(got >> 32);
       if (!ok) __hip_atomic_fetch_add(gl(&m->ctrl[2]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     ok = rdlane(ok, leader);
@@ -492,7 +560,7 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
       return want ? (uint64_t)-E_AGAIN : res;
     }
     pos = ((uint64_t)rdlane(hi, leader) << 32) | rdlane(lo, leader);
-    left = ok == 1 ? ask : total;
+    left = ((uint64_t)rdlane(ghi, leader) << 32) | rdlane(glo, leader);
   }
   if (want) {
     ring_put(m, pos + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
@@ -624,43 +692,85 @@ __device__ __forceinline__ void mirror_flush(const T* acc, uint32_t words, uint3
 // is full goes to the map directly
 constexpr uint32_t kCacheWays = 4;
 
-template <typename T>
-__device__ __forceinline__ void cache_init(uint32_t* tag, T* val, uint32_t slots, uint32_t op) {
-  for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+// Set of a key in a cache of ``sets`` 4-way sets (any count).
+__device__ __forceinline__ uint32_t cache_set(uint32_t key, uint32_t sets) {
+  return __umulhi(key * 0x9E3779B9u, sets);
+}
+
+template <typename TV>
+__device__ __forceinline__ void cache_init(uint32_t* tag, TV* val, uint32_t sets, uint32_t op) {
+  for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
     tag[i] = 0;
-    val[i] = op_identity<T>(op);
+    val[i] = op_identity<TV>(op);
   }
 }
-template <typename T>
-__device__ __forceinline__ void cache_rmw(uint32_t* tag, T* val, uint32_t slots, uint8_t* data, uint64_t addr, T v,
-                                          uint32_t op) {
-  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)) + 1;
-  const uint32_t base = (((key * 0x9E3779B9u) >> 8) & (slots / kCacheWays - 1)) * kCacheWays;
-  for (uint32_t w = 0; w < kCacheWays; w++) {
-    uint32_t* tp = &tag[base + w];
-    uint32_t t = __hip_atomic_load(tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (t == 0) {
+
+// Way of ``key`` in its set, claiming an empty way if the key has none
+// (-1: the set is full).  A tag goes from 0 to a key once, by compare-and-
+// swap; the set's four tags are first read in one LDS access, and a stale
+// 0 there only sends the lane to the compare-and-swap, which sees the truth.
+__device__ __forceinline__ int cache_way(uint32_t* tag, uint32_t base, uint32_t key) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 t4 = *(volatile u32x4*)&tag[base];
+  const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+  for (int w = 0; w < (int)kCacheWays; w++) {
+    uint32_t c = t[w];
+    if (c == 0) {
       uint32_t e = 0;
-      t = __hip_atomic_compare_exchange_strong(tp, &e, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+      c = __hip_atomic_compare_exchange_strong(&tag[base + w], &e, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP)
               ? key
               : e;
     }
-    if (t == key) {
-      lds_rmw(&val[base + w], v, op);
-      return;
-    }
+    if (c == key) return w;
   }
-  global_rmw((T*)addr, v, op);
+  return -1;
 }
+
 template <typename T>
-__device__ __forceinline__ void cache_flush(const uint32_t* tag, const T* val, uint32_t slots, uint32_t op,
+__device__ __forceinline__ void cache_rmw(uint32_t* tag, T* val, uint32_t sets, uint8_t* data, uint64_t addr, T v,
+                                          uint32_t op) {
+  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)) + 1;
+  const uint32_t base = cache_set(key, sets) * kCacheWays;
+  const int w = cache_way(tag, base, key);
+  if (w >= 0)
+    lds_rmw(&val[base + w], v, op);
+  else
+    global_rmw((T*)addr, v, op);
+}
+
+// 64-bit sums kept as 32-bit partial sums (twice the slots in the same LDS):
+// an addend of 2^32 or more goes to the map directly, and a partial sum that
+// wraps adds the lost 2^32 to the map at once, so map word + partial sums is
+// always the exact total.
+__device__ __forceinline__ void cache_add_narrow(uint32_t* tag, uint32_t* val, uint32_t sets, uint8_t* data,
+                                                 uint64_t addr, uint64_t v) {
+  if (v >> 32) {
+    global_rmw((uint64_t*)addr, v, 0u);
+    return;
+  }
+  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / 8) + 1;
+  const uint32_t base = cache_set(key, sets) * kCacheWays;
+  const int w = cache_way(tag, base, key);
+  if (w < 0) {
+    global_rmw((uint64_t*)addr, v, 0u);
+    return;
+  }
+  const uint32_t old = __hip_atomic_fetch_add(&val[base + w], (uint32_t)v, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+  if ((uint32_t)(old + (uint32_t)v) < old) global_rmw((uint64_t*)addr, (uint64_t)1 << 32, 0u);
+}
+
+// consecutive threads flush consecutive slots; T is the map word, TV the slot
+template <typename T, typename TV>
+__device__ __forceinline__ void cache_flush(const uint32_t* tag, const TV* val, uint32_t sets, uint32_t op,
                                             uint8_t* data) {
-  const T id = op_identity<T>(op);
-  for (uint32_t i = threadIdx.x; i < slots; i += blockDim.x) {
+  const TV id = op_identity<TV>(op);
+  for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
     const uint32_t t = tag[i];
-    const T v = val[i];
-    if (t && v != id) global_rmw((T*)data + (t - 1), v, op);
+    const TV v = val[i];
+    if (t && v != id) global_rmw((T*)data + (t - 1), (T)v, op);
   }
 }
 

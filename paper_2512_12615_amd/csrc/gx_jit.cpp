@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cerrno>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -47,12 +48,24 @@ struct Acc {
   int kind = 0;        // 0 none, 1 whole-map mirror in LDS, 2 tagged LDS cache
   uint32_t op = 0;     // ADD 0x00, OR 0x40, AND 0x50, XOR 0xa0
   int sc = -1;         // operand width: 2 (u32) or 3 (u64); -1 if the map takes no atomics
-  uint32_t words = 0;  // mirror: words of the value area; cache: slots
+  uint32_t words = 0;  // mirror: words of the value area; cache: slots (4 per set)
+  bool narrow = false; // cache of 64-bit sums kept as 32-bit partial sums
+  std::string word_type() const { return sc == 3 ? "uint64_t" : "uint32_t"; }
+  std::string slot_type() const { return sc == 3 && !narrow ? "uint64_t" : "uint32_t"; }
 };
 
-// LDS the accumulators of one program may take, beyond stacks and ring slots
-constexpr uint64_t kAccBudget = 48 << 10;
+// LDS a workgroup may take (gfx950: 160 KiB per CU), of which the
+// accumulators get what stacks and ring slots leave; caches are capped at
+// kCacheMax each (every slot in use costs one device atomic at the flush).
 constexpr uint64_t kLdsMax = 150 << 10;
+constexpr uint64_t kCacheMax = 112 << 10;
+constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
+
+// Cap on each cache in KiB from the environment (tuning experiments).
+int env_int_jit(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : dflt;
+}
 
 // Maps of a program as the generated code sees them.
 struct JMaps {
@@ -77,26 +90,32 @@ struct JMaps {
       a.op = (uint32_t)U[pc].imm & 0xf0;
       a.sc = (int)((U[pc].w0 >> 16) & 3);
     }
-    uint64_t left = std::min<uint64_t>(kAccBudget, kLdsMax > lds_used ? kLdsMax - lds_used : 0);
+    uint64_t left = kLdsMax > lds_used ? kLdsMax - lds_used : 0;
+    // small maps are mirrored whole; the others share what is left as caches
+    int n_cache = 0;
     for (size_t k = 0; k < m.size(); k++) {
       Acc& a = acc[k];
       if (a.sc < 2) continue;
-      const uint64_t w = a.sc == 3 ? 8 : 4;
       const uint64_t area = (uint64_t)m[k].second.max_entries * m[k].second.vstride;
-      if (a.sc == 2 || a.sc == 3) {
-        if (area <= left && area <= (32u << 10)) {
-          a.kind = 1;
-          a.words = (uint32_t)(area / w);
-          left -= area;
-        } else {
-          uint64_t slots = 1;
-          while (slots * 2 * (4 + w) <= std::min<uint64_t>(left, 48u << 10)) slots *= 2;
-          if (slots >= 256) {
-            a.kind = 2;
-            a.words = (uint32_t)slots;
-            left -= slots * (4 + w);
-          }
-        }
+      if (area <= left && area <= (32u << 10)) {
+        a.kind = 1;
+        a.words = (uint32_t)(area / (a.sc == 3 ? 8 : 4));
+        left -= area;
+      } else {
+        n_cache++;
+      }
+    }
+    const uint64_t cap = std::min<uint64_t>(kCacheMax, (uint64_t)std::max(16, env_int_jit("GX_ACC_KIB", 1 << 20)) << 10);
+    const uint64_t share = n_cache ? std::min<uint64_t>(left / n_cache, cap) : 0;
+    for (size_t k = 0; k < m.size(); k++) {
+      Acc& a = acc[k];
+      if (a.sc < 2 || a.kind) continue;
+      a.narrow = a.op == 0x00 && a.sc == 3;
+      const uint64_t slot_bytes = 4 + (a.slot_type() == "uint64_t" ? 8 : 4);
+      const uint64_t sets = share / (kCacheSlotsPerSet * slot_bytes);
+      if (sets >= 64) {
+        a.kind = 2;
+        a.words = (uint32_t)(sets * kCacheSlotsPerSet);
       }
     }
   }
@@ -507,13 +526,16 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         o += "  { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }\n";
       } else if (ac) {
         // shared map: summed in LDS by the event-parallel kernel
-        const std::string T = ac->sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(mk);
+        const std::string T = ac->word_type(), K = std::to_string(mk);
         const std::string ops = std::to_string(ac->op) + "u";
+        const std::string sets = std::to_string(ac->words / kCacheSlotsPerSet) + "u";
         const std::string lds =
             ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(ad - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
                                 std::to_string(ac->sc) + "], (" + T + ")" + S + ", " + ops + ");"
-                          : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(ac->words) +
-                                "u, M" + K + ".data, ad, (" + T + ")" + S + ", " + ops + ");";
+            : ac->narrow ? "cache_add_narrow(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, ad, (uint64_t)" +
+                               S + ");"
+                         : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, ad, (" +
+                               T + ")" + S + ", " + ops + ");";
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
                 "if (PRIV) { " + lds + " } else { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
       } else {
@@ -553,9 +575,10 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
     case H_RINGBUF_OUTPUT: {
       const int k = J.index(u.imm);
       if (k >= 0 && J.ring[k] >= 0)
-        o += "  r0 = uni<UNI>(ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) +
-             "u, chunk[" + std::to_string(J.ring[k]) + "], " + std::to_string(a8 & 1) + ", r2, " +
-             std::to_string((uint32_t)u.aux) + "u, r4, stk));\n";
+        o += "  r0 = uni<UNI>(ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, " +
+             std::to_string(J.ring[k]) + "u, chunk[" + std::to_string(J.ring[k]) + "], bchunk[" +
+             std::to_string(J.ring[k]) + "], " + std::to_string(a8 & 1) + ", r2, " + std::to_string((uint32_t)u.aux) +
+             "u, r4, stk));\n";
       else
         o += "  r0 = uni<UNI>(ring_output(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
              std::to_string((uint32_t)u.aux) + "u, r4, true, stk));\n";
@@ -603,32 +626,37 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     const Acc& a = J.acc[k];
     if (!a.kind) continue;
     any_acc = true;
-    const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k), N = std::to_string(a.words);
+    const std::string T = a.word_type(), K = std::to_string(k), N = std::to_string(a.words);
     if (a.kind == 1)
       o += "__shared__ " + T + " g_acc" + K + "[" + N + "];\n";
     else
-      o += "__shared__ uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + T + " g_val" + K + "[" + N + "];\n";
+      o += "__shared__ __attribute__((aligned(16))) uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + a.slot_type() +
+           " g_val" + K + "[" + N + "];\n";
   }
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
   // UNI: run by one lane with wave-uniform values (one queue per wave)
   o += "\ntemplate <bool PRIV, bool UNI = false>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
-       "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave reserves at once, per ring\n";
+       "  uint64_t chunk[GX_NRINGS];  // bytes of ring space a wave takes at once, per ring\n"
+       "  uint64_t bchunk[GX_NRINGS];  // bytes of ring space the block reserves at once, per ring\n";
   // the maps' descriptors, read from the map table once per run (they stay
   // in scalar registers instead of being reloaded for every event)
   for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
   o += "\n";
-  // begin / end: open and close the wave's ring chunks and the block's
-  // accumulators.  A chunk is the ring's capacity over four times the waves
-  // of the launch (64 B to 8 KiB): chunks in flight then hold at most a
-  // quarter of the ring.
+  // begin / end: open and close the wave's and the block's ring chunks and
+  // the block's accumulators (wave 0 sets up the block's part; the barrier
+  // makes it visible to the other waves).
   o += "  __device__ __forceinline__ void begin(const RunArgs& A) {\n    (void)A;\n";
   o += "    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64u);\n    (void)waves;\n";
   for (size_t k = 0; k < maps.size(); k++) o += "    m" + std::to_string(k) + " = gx_map" + std::to_string(k) + "(A);\n";
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
       o += "    chunk[" + std::to_string(J.ring[k]) + "] = ring_chunk_bytes(" + std::to_string(J.ring_cap((int)k)) +
-           "ull, waves);\n";
-  for (int r = 0; r < J.n_rings; r++) o += "    ring_chunk_init(wave * GX_NRINGS + " + std::to_string(r) + "u);\n";
+           "ull, waves);\n    bchunk[" + std::to_string(J.ring[k]) + "] = ring_block_bytes(" +
+           std::to_string(J.ring_cap((int)k)) + "ull, gridDim.x);\n";
+  for (int r = 0; r < J.n_rings; r++)
+    o += "    ring_chunk_init(wave * GX_NRINGS + " + std::to_string(r) + "u);\n    if (wave == 0) ring_block_init(" +
+         std::to_string(r) + "u);\n";
+  if (J.n_rings) o += "    __syncthreads();\n";
   if (any_acc) {
     o += "    if (PRIV) {\n";
     for (size_t k = 0; k < maps.size(); k++) {
@@ -638,8 +666,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
         o += "      mirror_init<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
              "u);\n";
       else if (a.kind == 2)
-        o += "      cache_init<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
-             std::to_string(a.op) + "u);\n";
+        o += "      cache_init<" + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+             std::to_string(a.words / kCacheSlotsPerSet) + "u, " + std::to_string(a.op) + "u);\n";
     }
     o += "      __syncthreads();\n    }\n";
   }
@@ -647,6 +675,12 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
       o += "    ring_chunk_close(&m" + std::to_string(k) + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u);\n";
+  if (J.n_rings) {
+    o += "    __syncthreads();\n";
+    for (size_t k = 0; k < maps.size(); k++)
+      if (J.ring[k] >= 0)
+        o += "    if (wave == 0) ring_block_close(&m" + std::to_string(k) + ", " + std::to_string(J.ring[k]) + "u);\n";
+  }
   if (any_acc) {
     o += "    if (PRIV) {\n      __syncthreads();\n";
     for (size_t k = 0; k < maps.size(); k++) {
@@ -656,8 +690,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
         o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
              "u, m" + K + ".data);\n";
       else if (a.kind == 2)
-        o += "      cache_flush<" + T + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words) + "u, " +
-             std::to_string(a.op) + "u, m" + K + ".data);\n";
+        o += "      cache_flush<" + T + ", " + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+             std::to_string(a.words / kCacheSlotsPerSet) + "u, " + std::to_string(a.op) + "u, m" + K + ".data);\n";
     }
     o += "    }\n";
   }

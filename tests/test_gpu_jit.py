@@ -166,7 +166,7 @@ def test_jit_ring_records_across_drains(rt):
     assert rt.stats()["ring_drops"] == 0
 
 
-def _shared_prog(op, width, entries):
+def _shared_prog(op, width, entries, operand="and64 r1, 0xffff"):
     """Event-parallel program: one commutative atomic per event on a shared
     array of ``entries`` words, index and operand from the record."""
     mn = {"add": "aadd", "or": "aor", "and": "aand", "xor": "axor"}[op] + ("64" if width == 8 else "32")
@@ -184,14 +184,14 @@ def _shared_prog(op, width, entries):
         call map_lookup_elem
         jeq r0, 0, out
         mov64 r1, r7
-        {'xor64 r1, -1' if op == 'and' else 'and64 r1, 0xffff'}
+        {'xor64 r1, -1' if op == 'and' else operand}
         {mn} [r0+0], r1
     out:
         mov64 r0, r6
         and64 r0, 7
         exit
     """
-    return W.Policy(f"shared_{op}{width}", W.HOOK_MEM_ACCESS, text,
+    return W.Policy(f"shared_{op}{width}_{len(operand)}", W.HOOK_MEM_ACCESS, text,
                     [W.MapSpec("sh", W.MAP_ARRAY, 4, width, entries, W.F_SHARED)])
 
 
@@ -215,6 +215,23 @@ def test_jit_shared_map_lds_accumulation(rt, op, width, entries):
         init = [(0, np.uint32(k).tobytes(), ones) for k in range(entries)]
     g = gpu_run(rt, pol, ev, init, jit=True)
     assert_same(g, oracle_run(pol, ev, init), pol.name)
+    assert g.stats["vm_errors"] == 0
+
+
+@pytest.mark.parametrize("operand", ["rsh64 r1, 32", "mov64 r1, r1", "rsh64 r1, 31"])
+def test_jit_shared_add_partial_sums_wrap(rt, operand):
+    """64-bit sums cached as 32-bit partial sums: operands near 2^32 make the
+    partial sums wrap (the carry goes to the map), operands of 2^32 or more
+    go to the map directly, mixed ones take both paths."""
+    _log(f"jit shared add64 operand={operand}")
+    pol = _shared_prog("add", 8, 1 << 16, operand)
+    n = 400009
+    ev = W.gen_mem_uniform(n, 91)
+    hot = W.splitmix(15, n) % np.uint64(2) == 0
+    ev["addr"] = np.where(hot, (W.splitmix(16, n) % np.uint64(16)) << np.uint64(12), ev["addr"])
+    ev["ts"] = W.splitmix(17, n)
+    g = gpu_run(rt, pol, ev, jit=True)
+    assert_same(g, oracle_run(pol, ev), pol.name)
     assert g.stats["vm_errors"] == 0
 
 
