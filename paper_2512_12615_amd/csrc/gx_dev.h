@@ -692,9 +692,12 @@ __device__ __forceinline__ void mirror_flush(const T* acc, uint32_t words, uint3
 // is full goes to the map directly
 constexpr uint32_t kCacheWays = 4;
 
-// Set of a key in a cache of ``sets`` 4-way sets (any count).
+// Set of a key (a word index) in a cache of ``sets`` 4-way sets: the index
+// modulo an odd set count, so neighbouring words sit in neighbouring sets
+// (the flush below then updates them with neighbouring lanes) while
+// power-of-two strides still spread over all sets.
 __device__ __forceinline__ uint32_t cache_set(uint32_t key, uint32_t sets) {
-  return __umulhi(key * 0x9E3779B9u, sets);
+  return key % sets;
 }
 
 template <typename TV>
@@ -762,14 +765,18 @@ __device__ __forceinline__ void cache_add_narrow(uint32_t* tag, uint32_t* val, u
   if ((uint32_t)(old + (uint32_t)v) < old) global_rmw((uint64_t*)addr, (uint64_t)1 << 32, 0u);
 }
 
-// consecutive threads flush consecutive slots; T is the map word, TV the slot
+// Consecutive threads flush one way of consecutive sets, which mostly hold
+// neighbouring words (the first keys of a region to arrive take way 0):
+// their device atomics then share cache lines.  T is the map word, TV the
+// slot.
 template <typename T, typename TV>
 __device__ __forceinline__ void cache_flush(const uint32_t* tag, const TV* val, uint32_t sets, uint32_t op,
                                             uint8_t* data) {
   const TV id = op_identity<TV>(op);
   for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
-    const uint32_t t = tag[i];
-    const TV v = val[i];
+    const uint32_t w = i / sets, s = i - w * sets;
+    const uint32_t t = tag[s * kCacheWays + w];
+    const TV v = val[s * kCacheWays + w];
     if (t && v != id) global_rmw((T*)data + (t - 1), (T)v, op);
   }
 }

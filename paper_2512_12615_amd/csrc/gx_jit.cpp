@@ -58,7 +58,7 @@ struct Acc {
 // accumulators get what stacks and ring slots leave; caches are capped at
 // kCacheMax each (every slot in use costs one device atomic at the flush).
 constexpr uint64_t kLdsMax = 150 << 10;
-constexpr uint64_t kCacheMax = 112 << 10;
+constexpr uint64_t kCacheMax = 80 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 
 // Cap on each cache in KiB from the environment (tuning experiments).
@@ -112,7 +112,8 @@ struct JMaps {
       if (a.sc < 2 || a.kind) continue;
       a.narrow = a.op == 0x00 && a.sc == 3;
       const uint64_t slot_bytes = 4 + (a.slot_type() == "uint64_t" ? 8 : 4);
-      const uint64_t sets = share / (kCacheSlotsPerSet * slot_bytes);
+      uint64_t sets = share / (kCacheSlotsPerSet * slot_bytes);
+      sets -= sets % 2 == 0 && sets > 0;  // an odd count (the device maps keys to sets modulo it)
       if (sets >= 64) {
         a.kind = 2;
         a.words = (uint32_t)(sets * kCacheSlotsPerSet);
