@@ -148,7 +148,8 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size);
 
 /* Autotuner: the launch shape of a program's runs (stream-sequential:
  * queues per wave and queue count; compiled event-parallel: block count) is
- * chosen by timing each candidate on a sample batch (d_events, n_events
+ * chosen by timing each candidate on a sample batch (the default shape
+ * stays unless a candidate is at least 3 % faster; d_events, n_events
  * records of record_size bytes in device memory; d_rc receives return codes
  * and may be NULL) on ``stream``.  Map and ring contents are saved first
  * and restored before every trial and at the end, so the only lasting

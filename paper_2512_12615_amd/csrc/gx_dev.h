@@ -735,7 +735,7 @@ template <typename T>
 __device__ __forceinline__ void cache_rmw(uint32_t* tag, T* val, uint32_t sets, uint8_t* data, uint64_t addr, T v,
                                           uint32_t op) {
   const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)) + 1;
-  const uint32_t base = cache_set(key, sets) * kCacheWays;
+  const uint32_t base = cache_set(key - 1, sets) * kCacheWays;  // by word index
   const int w = cache_way(tag, base, key);
   if (w >= 0)
     lds_rmw(&val[base + w], v, op);
@@ -754,7 +754,7 @@ __device__ __forceinline__ void cache_add_narrow(uint32_t* tag, uint32_t* val, u
     return;
   }
   const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / 8) + 1;
-  const uint32_t base = cache_set(key, sets) * kCacheWays;
+  const uint32_t base = cache_set(key - 1, sets) * kCacheWays;  // by word index
   const int w = cache_way(tag, base, key);
   if (w < 0) {
     global_rmw((uint64_t*)addr, v, 0u);
@@ -778,6 +778,48 @@ __device__ __forceinline__ void cache_flush(const uint32_t* tag, const TV* val, 
     const uint32_t t = tag[s * kCacheWays + w];
     const TV v = val[s * kCacheWays + w];
     if (t && v != id) global_rmw((T*)data + (t - 1), (T)v, op);
+  }
+}
+
+// The block's cache written out for the reduce kernel: tags [sets][nb][4],
+// then slots [sets][nb][4], this block's four ways of each set side by side.
+template <typename TV>
+__device__ __forceinline__ void cache_spill(const uint32_t* tag, const TV* val, uint32_t sets, uint8_t* spill,
+                                            uint32_t b, uint32_t nb) {
+  uint32_t* st = (uint32_t*)spill;
+  TV* sv = (TV*)(spill + (uint64_t)sets * nb * kCacheWays * 4);
+  for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
+    const uint32_t s = i / kCacheWays, w = i - s * kCacheWays;
+    const uint64_t at = ((uint64_t)s * nb + b) * kCacheWays + w;
+    gl(st)[at] = tag[i];
+    gl(sv)[at] = val[i];
+  }
+}
+
+// One cache set over all blocks of a launch (one reduce block per set):
+// every word of the set is summed in LDS - word key of set s is s + q * sets,
+// so q indexes the LDS sums - and applied to the map with one device atomic.
+template <typename T, typename TV, uint32_t QMAX>
+__device__ __forceinline__ void cache_reduce(const uint8_t* spill, uint32_t sets, uint32_t s, uint32_t nb,
+                                             uint32_t op, uint8_t* data, uint32_t words) {
+  __shared__ T sum[QMAX];
+  const uint32_t* st = (const uint32_t*)spill;
+  const TV* sv = (const TV*)(spill + (uint64_t)sets * nb * kCacheWays * 4);
+  const T id = op_identity<T>(op);
+  for (uint32_t q = threadIdx.x; q < QMAX; q += blockDim.x) sum[q] = id;
+  __syncthreads();
+  const uint64_t base = (uint64_t)s * nb * kCacheWays;
+  for (uint32_t j = threadIdx.x; j < nb * kCacheWays; j += blockDim.x) {
+    const uint32_t t = gl(st)[base + j];
+    if (!t) continue;
+    const TV v = gl(sv)[base + j];
+    if (v != op_identity<TV>(op)) lds_rmw<T>(&sum[(t - 1) / sets], (T)v, op);
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < QMAX; q += blockDim.x) {
+    const T v = sum[q];
+    const uint64_t w = (uint64_t)q * sets + s;
+    if (v != id && w < words) global_rmw((T*)data + w, v, op);
   }
 }
 

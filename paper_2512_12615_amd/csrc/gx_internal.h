@@ -104,6 +104,7 @@ struct RunArgs {
   const uint64_t* guards;  // per slot {lo, hi} of the map data a map-value access may touch
   const uint8_t* sorted;   // stream-sequential: the records in queue order, kSortedStride apart
   const uint64_t* maptab;  // device addresses of the program's map descriptors, in its map-table order
+  uint8_t* spill;          // compiled event-parallel runs: LDS cache spill area (null: caches flush directly)
 };
 
 // Stride of the queue-ordered record copy (the largest record).

@@ -60,6 +60,7 @@ struct Acc {
 constexpr uint64_t kLdsMax = 150 << 10;
 constexpr uint64_t kCacheMax = 80 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
+constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
 
 // Cap on each cache in KiB from the environment (tuning experiments).
 int env_int_jit(const char* name, int dflt) {
@@ -607,7 +608,7 @@ namespace {
 // functions, LDS accumulators (when ``allow_acc``) and struct Prog<PRIV>
 // with begin / end / run.  ``lds_used``: LDS the kernel already takes.
 std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, uint64_t lds_used,
-                      uint64_t* acc_words) {
+                      JitInfo* info) {
   const std::vector<Uop>& U = *P.U;
   const auto& maps = *P.maps;
   JMaps J(maps, *P.mem_map, *P.ld_map);
@@ -615,10 +616,31 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
   if (allow_acc) J.plan(U, lds_used);
-  if (acc_words) {
-    *acc_words = 0;
+  // spill layout of the caches, per launch of nb blocks: cache k's tags
+  // [sets][nb][4] (u32), then its slots [sets][nb][4]; cache k starts at
+  // nb * spill_off[k].  Every cache needs a reduce LDS array of
+  // ceil(map words / sets) words, at most kReduceMax.
+  std::vector<uint64_t> spill_off(maps.size(), 0);
+  uint64_t spill_block = 0;
+  uint32_t red_blocks = 0;
+  bool spill = allow_acc;
+  for (size_t k = 0; k < maps.size(); k++) {
+    const Acc& a = J.acc[k];
+    if (a.kind != 2) continue;
+    const uint64_t sets = a.words / kCacheSlotsPerSet;
+    const uint64_t words = (uint64_t)maps[k].second.max_entries * maps[k].second.vstride / (a.sc == 3 ? 8 : 4);
+    if ((words + sets - 1) / sets > kReduceMax) spill = false;
+    spill_off[k] = spill_block;
+    spill_block += (uint64_t)a.words * (4 + (a.slot_type() == "uint64_t" ? 8 : 4));
+    red_blocks += (uint32_t)sets;
+  }
+  if (!spill) spill_block = red_blocks = 0;
+  if (info) {
+    info->acc_words = 0;
     for (const Acc& a : J.acc)
-      if (a.kind) *acc_words += a.words;
+      if (a.kind) info->acc_words += a.words;
+    info->spill_block_bytes = spill_block;
+    info->reduce_blocks = red_blocks;
   }
   std::string o = "namespace gx {\nnamespace " + ns + " {\n\n";
   for (size_t k = 0; k < maps.size(); k++) o += map_fn(k, maps[k].second);
@@ -690,6 +712,12 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       if (a.kind == 1)
         o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
              "u, m" + K + ".data);\n";
+      else if (a.kind == 2 && spill_block)
+        o += "      if (A.spill) cache_spill<" + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+             std::to_string(a.words / kCacheSlotsPerSet) + "u, A.spill + (uint64_t)gridDim.x * " +
+             std::to_string(spill_off[k]) + "ull, blockIdx.x, gridDim.x);\n      else cache_flush<" + T + ", " +
+             a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words / kCacheSlotsPerSet) +
+             "u, " + std::to_string(a.op) + "u, m" + K + ".data);\n";
       else if (a.kind == 2)
         o += "      cache_flush<" + T + ", " + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
              std::to_string(a.words / kCacheSlotsPerSet) + "u, " + std::to_string(a.op) + "u, m" + K + ".data);\n";
@@ -717,7 +745,24 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     emit_uop(o, U[pc], pc, J, Wn);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
-  o += "  return (uint32_t)r0;\n  }\n};\n\n}  // namespace " + ns + "\n}  // namespace gx\n\n";
+  o += "  return (uint32_t)r0;\n  }\n};\n\n";
+  if (spill_block) {
+    // one block of gx_j_reduce per cache set
+    o += "__device__ __forceinline__ void reduce(const RunArgs& A, uint32_t nb) {\n  uint32_t b = blockIdx.x;\n";
+    for (size_t k = 0; k < maps.size(); k++) {
+      const Acc& a = J.acc[k];
+      if (a.kind != 2) continue;
+      const uint64_t sets = a.words / kCacheSlotsPerSet;
+      const uint64_t words = (uint64_t)maps[k].second.max_entries * maps[k].second.vstride / (a.sc == 3 ? 8 : 4);
+      const std::string S = std::to_string(sets) + "u", K = std::to_string(k);
+      o += "  if (b < " + S + ") {\n    cache_reduce<" + a.word_type() + ", " + a.slot_type() + ", " +
+           std::to_string((words + sets - 1) / sets) + "u>(A.spill + (uint64_t)nb * " + std::to_string(spill_off[k]) +
+           "ull, " + S + ", b, nb, " + std::to_string(a.op) + "u, gx_map" + K + "(A).data, " + std::to_string(words) +
+           "u);\n    return;\n  }\n  b -= " + S + ";\n";
+    }
+    o += "}\n\n";
+  }
+  o += "}  // namespace " + ns + "\n}  // namespace gx\n\n";
   return o;
 }
 
@@ -729,7 +774,7 @@ int ring_count(const JitProg& P) {
 
 }  // namespace
 
-std::string jit_source(const JitProg& P, uint64_t* acc_words) {
+std::string jit_source(const JitProg& P, JitInfo* info) {
   const uint32_t nw = jit_waves(P.stack_bytes, P.event_parallel);
   const uint32_t lds = P.stack_bytes ? nw * 64u * P.stack_bytes : 16u;
   const int nr = std::max(ring_count(P), 1);
@@ -738,7 +783,9 @@ std::string jit_source(const JitProg& P, uint64_t* acc_words) {
   o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
   o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
-  o += emit_prog(P, "p0", true, lds + 16ull * nw * nr, acc_words);
+  JitInfo ji;
+  o += emit_prog(P, "p0", true, lds + 16ull * nw * nr, &ji);
+  if (info) *info = ji;
   const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
   if (P.event_parallel)
     o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
@@ -747,7 +794,10 @@ std::string jit_source(const JitProg& P, uint64_t* acc_words) {
        "u + threadIdx.x};\n"
        "  gx::p0::Prog<true> P{wave};\n  P.begin(A);\n"
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
-       "  P.end(A);\n}\n\n";
+       "  P.end(A);\n}\n\n" +
+       (ji.spill_block_bytes ? std::string("extern \"C\" __global__ void __launch_bounds__(256) gx_j_reduce(gx::RunArgs A, "
+                                           "uint32_t nb) {\n  gx::p0::reduce(A, nb);\n}\n\n")
+                             : std::string());
   else
     o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"

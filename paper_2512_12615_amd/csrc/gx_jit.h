@@ -39,9 +39,22 @@ struct JitProg {
 // LDS array; each wave carves ring records from its own chunk of reserved
 // ring space.  The source holds no map address (those come from
 // RunArgs::maptab), so instances with same-shaped maps share it.
-// *acc_words receives the LDS accumulator words a block flushes at its end
-// (0: none), which the launch uses to size its grid.
-std::string jit_source(const JitProg& p, uint64_t* acc_words = nullptr);
+// *info receives what the launch needs to know: the LDS accumulator words a
+// block flushes at its end (0: none), which sizes the grid; and, when the
+// program has LDS caches, the spill bytes per block and the blocks of the
+// reduce kernel gx_j_reduce (see JitInfo).
+struct JitInfo {
+  uint64_t acc_words = 0;
+  // Event-parallel programs with LDS caches: at its end each block writes
+  // its caches to a spill area (spill_block_bytes per block of the launch,
+  // RunArgs::spill) instead of applying every slot to the map with a device
+  // atomic; gx_j_reduce(A, blocks) then sums each cache set over all blocks
+  // in LDS and applies one atomic per word (reduce_blocks blocks of 256
+  // threads).  0: no spill (caches flush directly).
+  uint64_t spill_block_bytes = 0;
+  uint32_t reduce_blocks = 0;
+};
+std::string jit_source(const JitProg& p, JitInfo* info = nullptr);
 
 // HIP source of a program set: every program in its own namespace and one
 // persistent kernel gx_j_set over the batched form's work items, which picks
