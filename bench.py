@@ -269,13 +269,13 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
             list(ex.map(lambda k: rt.jit_program_set([tenants[t][1] for t in range(64) if (t % 32) % 4 == k]),
                         range(4)))
         log(f"serving: compiled 32 programs and 4 program sets in {time.perf_counter() - t0:.1f} s")
-    n_req = int(20000 * (seconds + warm_s))
-    arrival, tenant, _, n_ev = W.serving_trace(n_req)
     slices = 64
     pool = torch.from_numpy(W.gen_mem_uniform(slices << 18, 1004).view(np.uint8)).pin_memory()
     base = pool.data_ptr()
-    out = {}
-    for mode, name in ((G.SERVE_CONTINUOUS, "continuous"), (G.SERVE_PER_REQUEST, "per_request")):
+
+    def serve(rate, secs, mode):
+        n_req = int(rate * (secs + warm_s))
+        arrival, tenant, _, n_ev = W.serving_trace(n_req, rate_per_s=rate)
         for fds, _ in tenants:
             for fd in fds:
                 rt.map_clear(fd)
@@ -303,13 +303,28 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
         end = max(done[i][0] for i in range(n_req))
         ev = float(n_ev[keep].sum())
         span = end - (t0 + warm_s)
-        out[name] = {
+        return {
             "p50_ms": _pct(lat, 50) * 1e3,
             "p99_ms": _pct(lat, 99) * 1e3,
             "events_per_s": ev / span,
+            "offered_events_per_s": ev / (arrival[-1] - warm_s),
             "requests": int(keep.sum()),
             "errors": int(sum(1 for i in range(n_req) if done[i][1] != 0)),
         }
+
+    out = {}
+    modes = ((G.SERVE_CONTINUOUS, "continuous"), (G.SERVE_PER_REQUEST, "per_request"))
+    # the configured load (20k requests/s, beyond what the device sustains
+    # for these programs: latency there is queueing), then a load of 60 % of
+    # the continuous server's measured rate, the same for both modes
+    for mode, name in modes:
+        out[name] = serve(20000.0, seconds, mode)
+    mean_ev = float(np.mean(W.serving_trace(100000)[3]))
+    rate = 0.6 * out["continuous"]["events_per_s"] / mean_ev
+    out["at_60pct_of_continuous"] = {"requests_per_s": rate}
+    for mode, name in modes:
+        out["at_60pct_of_continuous"][name] = serve(rate, 2.0 * seconds, mode)
+    n_req = int(20000 * (seconds + warm_s))
     out["workload"] = (f"{n_req} requests, Poisson 20k/s, 64 tenants x 256 MiB resident hash map, 32 generated "
                        f"programs, 2^8..2^18 events per request, 4 GiB admission budget, first {warm_s}s excluded")
     out["engine"] = "jit" if jit else "interp"

@@ -254,14 +254,17 @@ int gx_profile_read(gx_rt* rt, double* vm_ms, uint64_t* vm_launches);
 /* ---------------------------------------------------------------------------
  * Served form: continuous batching of tenant requests (multi-tenant policy
  * coordination, paper sections 3 and 6.3).  A request is (tenant, program,
- * host event batch).  Requests of one tenant run one at a time in submission
- * order (a tenant's programs own its maps); requests of different tenants
- * are admitted whenever device memory for their buffers (events + return
- * codes) fits in the budget, and everything admitted at one moment is run as
- * one batched launch on one of ``streams`` HIP streams, so newly admitted
- * work overlaps with work already on the device.  GX_SERVE_PER_REQUEST runs
- * every request as its own plain launch on one stream, in arrival order (the
- * baseline the continuous mode is compared with).  The server drives the
+ * host event batch).  Requests of one tenant run in submission order (a
+ * tenant's programs own its maps): all of them go to one of ``streams`` HIP
+ * streams (tenant mod streams).  Requests are admitted whenever device
+ * memory for their buffers (events + return codes) fits in the budget; a
+ * stream with fewer than four unfinished launches takes the head request of
+ * each of its tenants as one batched launch, so a tenant's next request is
+ * queued on the device before its previous one is done, requests gather
+ * into larger launches while the device is busy, and launches on different
+ * streams overlap.  GX_SERVE_PER_REQUEST
+ * runs every request as its own plain launch, one request per tenant in
+ * flight (the baseline the continuous mode is compared with).  The server drives the
  * runtime from its own host thread: while a server exists, make no other
  * calls on its runtime except map snapshots after gx_server_drain. */
 typedef struct gx_server gx_server;

@@ -213,7 +213,11 @@ struct gx_rt {
   uint32_t n_cu = 256;  // compute units of the device
   std::vector<JitSet> sets;
   static constexpr int kSide = kExecSide;
-  Exec ex;  // execution resources of runs (a captured graph swaps in its own)
+  // execution resources per launch stream: runs on different streams share
+  // no workspace, staging, side streams or spill area, so they overlap; a
+  // graph being built uses its own set (cap_ex)
+  std::vector<std::pair<hipStream_t, Exec*>> execs;
+  Exec* cap_ex = nullptr;
   std::vector<MapObj> maps;
   std::vector<ProgObj> progs;
   uint64_t* d_err = nullptr;
@@ -284,6 +288,22 @@ void note_stream(gx_rt* rt, hipStream_t s) {
   if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
   (void)hipEventRecord(e, s);
   rt->stream_events.push_back({s, e});
+}
+
+// Execution resources of runs launched on stream s (created on first use).
+Exec* exec_for(gx_rt* rt, hipStream_t s) {
+  if (rt->cap_ex) return rt->cap_ex;
+  for (auto& e : rt->execs)
+    if (e.first == s) return e.second;
+  Exec* x = new (std::nothrow) Exec();
+  if (!x) return nullptr;
+  if (exec_init(*x)) {
+    exec_free(*x);
+    delete x;
+    return nullptr;
+  }
+  rt->execs.push_back({s, x});
+  return x;
 }
 
 int wait_all(gx_rt* rt) {
@@ -414,7 +434,7 @@ std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const s
   return U;
 }
 
-int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
+int ensure_ws(Exec& X, size_t counts, size_t sums, size_t order) {
   auto grow = [](uint32_t** p, size_t* cap, size_t need) -> int {
     if (*cap >= need) return 0;
     if (*p) (void)hipFree(*p);
@@ -426,16 +446,15 @@ int ensure_ws(gx_rt* rt, size_t counts, size_t sums, size_t order) {
     return 0;
   };
   int r;
-  if ((r = grow(&rt->ex.d_counts, &rt->ex.counts_cap, counts))) return r;
-  if ((r = grow(&rt->ex.d_sums, &rt->ex.sums_cap, sums))) return r;
-  if ((r = grow(&rt->ex.d_order, &rt->ex.order_cap, order))) return r;
+  if ((r = grow(&X.d_counts, &X.counts_cap, counts))) return r;
+  if ((r = grow(&X.d_sums, &X.sums_cap, sums))) return r;
+  if ((r = grow(&X.d_order, &X.order_cap, order))) return r;
   // the queue-ordered records: kSortedStride bytes per event (u32 units)
-  if ((r = grow((uint32_t**)&rt->ex.d_sorted, &rt->ex.sorted_cap, order * (kSortedStride / 4)))) return r;
+  if ((r = grow((uint32_t**)&X.d_sorted, &X.sorted_cap, order * (kSortedStride / 4)))) return r;
   return 0;
 }
 
-int ensure_spill(gx_rt* rt, size_t bytes) {
-  Exec& X = rt->ex;
+int ensure_spill(Exec& X, size_t bytes) {
   if (X.spill_cap >= bytes) return 0;
   if (X.d_spill) (void)hipFree(X.d_spill);
   X.d_spill = nullptr;
@@ -491,6 +510,9 @@ hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes
 // One plain run of a program with launch shape k (validated arguments).
 int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint32_t* d_rc, hipStream_t s,
             const Knobs& k) {
+  Exec* Xp = exec_for(rt, s);
+  if (!Xp) return -ENOMEM;
+  Exec& X = *Xp;
   RunArgs A{};
   A.uops = p->d_uops;
   A.events = (const uint8_t*)d_events;
@@ -516,15 +538,15 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
       const uint64_t need = jit_spill_bytes(p, n_events, k.blocks);
       uint8_t* sp = nullptr;
       if (need) {
-        int r = ensure_spill(rt, need);
+        int r = ensure_spill(X, need);
         if (r) return r;
-        if (rt->ex.spill_used) (void)hipStreamWaitEvent(s, rt->ex.spill_ev, 0);
-        sp = rt->ex.d_spill;
+        if (X.spill_used) (void)hipStreamWaitEvent(s, X.spill_ev, 0);
+        sp = X.d_spill;
       }
       e = launch_jit(p, A, 0, 0, 0, 0, k.blocks, sp, s);
       if (sp) {
-        (void)hipEventRecord(rt->ex.spill_ev, s);
-        rt->ex.spill_used = true;
+        (void)hipEventRecord(X.spill_ev, s);
+        X.spill_used = true;
         rt->stats.launches += 1;
       }
     } else {
@@ -538,15 +560,15 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
     uint64_t tile = std::max<uint64_t>(4096, next_pow2((n_events + 255) / 256));
     uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
     uint64_t m = (uint64_t)L * nt;
-    int r = ensure_ws(rt, m, (m + 4095) / 4096 + 1, n_events);
+    int r = ensure_ws(X, m, (m + 4095) / 4096 + 1, n_events);
     if (r) return r;
-    if (rt->ex.ws_used) (void)hipStreamWaitEvent(s, rt->ex.ws_event, 0);
+    if (X.ws_used) (void)hipStreamWaitEvent(s, X.ws_event, 0);
     A.step_limit = per_event * n_events;
-    e = launch_partition(A, lbits, (uint32_t)tile, nt, rt->ex.d_counts, rt->ex.d_sums, rt->ex.d_order, rt->ex.d_sorted, s);
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, X.d_counts, X.d_sums, X.d_order, X.d_sorted, s);
     if (e == hipSuccess) {
-      A.order = rt->ex.d_order;
-      A.sorted = rt->ex.d_sorted;
-      A.qstart = rt->ex.d_counts;
+      A.order = X.d_order;
+      A.sorted = X.d_sorted;
+      A.qstart = X.d_counts;
       A.n_queues = L;
       if (pe.first) (void)hipEventRecord(pe.first, s);
       if (p->jf_seq) {
@@ -556,8 +578,8 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
       }
       if (pe.second) (void)hipEventRecord(pe.second, s);
     }
-    (void)hipEventRecord(rt->ex.ws_event, s);
-    rt->ex.ws_used = true;
+    (void)hipEventRecord(X.ws_event, s);
+    X.ws_used = true;
     rt->stats.launches += 6;
   }
   if (pe.first) rt->prof_pending.push_back(pe);
@@ -674,7 +696,7 @@ int gx_open(int hip_device, gx_rt** out) {
     rt->n_cu = (uint32_t)ncu;
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
-      vm_init() != hipSuccess || exec_init(rt->ex) != 0) {
+      vm_init() != hipSuccess) {
     gx_close(rt);
     return -ENOMEM;
   }
@@ -703,7 +725,10 @@ void gx_close(gx_rt* rt) {
       (void)hipEventDestroy(pe.first);
       (void)hipEventDestroy(pe.second);
     }
-  exec_free(rt->ex);
+  for (auto& e : rt->execs) {
+    exec_free(*e.second);
+    delete e.second;
+  }
   for (void* p : {(void*)rt->d_err, (void*)rt->d_stage})
     if (p) (void)hipFree(p);
   if (rt->internal) (void)hipStreamDestroy(rt->internal);
@@ -1263,6 +1288,9 @@ bool shares_map(ProgObj* a, ProgObj* b, const std::vector<MapObj>& maps) {
 // runs of interpreted programs and, side by side with it, one launch per
 // run of a compiled program.
 int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
+  Exec* Xp = exec_for(rt, s);
+  if (!Xp) return -ENOMEM;
+  Exec& X = *Xp;
   std::vector<BatchDev> B;
   std::vector<PartJob> J;
   std::vector<uint2> tiles, items;
@@ -1314,14 +1342,14 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   }
   if (B.empty()) return 0;
   if (order_total >= (1ull << 32) || counts_total >= (1ull << 32)) return -E2BIG;
-  int r = ensure_ws(rt, counts_total + 1, (counts_total + 4095) / 4096 + 1, order_total + 1);
+  int r = ensure_ws(X, counts_total + 1, (counts_total + 4095) / 4096 + 1, order_total + 1);
   if (r) return r;
   for (auto& bd : B)
     if (bd.mode == 1) {
       const PartJob& pj = J[bd.A.pad2 - 1];
-      bd.A.qstart = rt->ex.d_counts + pj.cbase;
-      bd.A.order = rt->ex.d_order;
-      bd.A.sorted = rt->ex.d_sorted;
+      bd.A.qstart = X.d_counts + pj.cbase;
+      bd.A.order = X.d_order;
+      bd.A.sorted = X.d_sorted;
       bd.A.pad2 = 0;
     }
   // items, largest runs first
@@ -1363,7 +1391,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
       spill_total += (need + 255) & ~255ull;
     }
   if (spill_total) {
-    int rs = ensure_spill(rt, spill_total);
+    int rs = ensure_spill(X, spill_total);
     if (rs) return rs;
   }
   // pack the tables: batches | items | jobs | tiles (each 64-byte aligned)
@@ -1377,7 +1405,6 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   size_t oj = os_, ot = al(oj + J.size() * sizeof(PartJob)), total = al(ot + tiles.size() * sizeof(uint2));
   // a staging slot whose previous copy has long completed; a capture takes
   // a fresh slot per phase, which the graph then owns
-  Exec& X = rt->ex;
   size_t k;
   if (X.per_phase) {
     k = X.stage_cursor++;
@@ -1402,7 +1429,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   }
   uint8_t* h_stage = st.h;
   uint8_t* d_tables = st.d;
-  if (rt->ex.ws_used) (void)hipStreamWaitEvent(s, rt->ex.ws_event, 0);
+  if (X.ws_used) (void)hipStreamWaitEvent(s, X.ws_event, 0);
   std::memcpy(h_stage + ob, B.data(), B.size() * sizeof(BatchDev));
   std::memcpy(h_stage + oi, items.data(), items.size() * sizeof(uint2));
   for (auto& so : set_off) {
@@ -1417,7 +1444,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (!J.empty())
     e = launch_partition_jobs((const PartJob*)(d_tables + oj), (const uint2*)(d_tables + ot), (uint32_t)tiles.size(),
-                              max_lbits, counts_total, rt->ex.d_counts, rt->ex.d_sums, rt->ex.d_order, rt->ex.d_sorted, s);
+                              max_lbits, counts_total, X.d_counts, X.d_sums, X.d_order, X.d_sorted, s);
   std::pair<hipEvent_t, hipEvent_t> pe{nullptr, nullptr};
   if (rt->profile) pe = prof_pair(rt);
   if (pe.first) (void)hipEventRecord(pe.first, s);
@@ -1426,16 +1453,16 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   int used_side = 0;
   size_t x = 0;  // launches handed to side streams so far
   auto side = [&]() {
-    hipStream_t ss = rt->ex.side[x % kExecSide];
+    hipStream_t ss = X.side[x % kExecSide];
     if ((int)x < kExecSide) {
-      (void)hipStreamWaitEvent(ss, rt->ex.fork_ev, 0);
+      (void)hipStreamWaitEvent(ss, X.fork_ev, 0);
       used_side++;
     }
     x++;
     return ss;
   };
-  if (spill_total && rt->ex.spill_used) (void)hipStreamWaitEvent(s, rt->ex.spill_ev, 0);
-  if (e == hipSuccess && (!jit_runs.empty() || !set_off.empty())) (void)hipEventRecord(rt->ex.fork_ev, s);
+  if (spill_total && X.spill_used) (void)hipStreamWaitEvent(s, X.spill_ev, 0);
+  if (e == hipSuccess && (!jit_runs.empty() || !set_off.empty())) (void)hipEventRecord(X.fork_ev, s);
   // program sets: one persistent launch each, with a counter of its own
   for (size_t k = 0; k < set_off.size() && e == hipSuccess; k++) {
     hipStream_t ss = side();
@@ -1443,7 +1470,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     const BatchDev* db = (const BatchDev*)(d_tables + ob);
     const uint2* di = (const uint2*)(d_tables + set_off[k].second);
     uint32_t ni = (uint32_t)v.size();
-    uint32_t* next = rt->ex.d_next + 1 + k;
+    uint32_t* next = X.d_next + 1 + k;
     // as many waves as the device holds at once: the items are chains of
     // dependent memory accesses, so throughput comes from concurrency
     const gx_rt::JitSet& js = rt->sets[set_off[k].first];
@@ -1458,25 +1485,25 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
   for (size_t y = 0; y < jit_runs.size() && e == hipSuccess; y++) {
     const uint32_t b = jit_runs[y];
     e = launch_jit(bprog[b], B[b].A, B[b].mode, B[b].lanes, B[b].qstride, B[b].qend_last, knobs_of(bprog[b]).blocks,
-                   spill_at[b] != UINT64_MAX ? rt->ex.d_spill + spill_at[b] : nullptr, side());
+                   spill_at[b] != UINT64_MAX ? X.d_spill + spill_at[b] : nullptr, side());
   }
   if (e == hipSuccess && !items.empty()) {
     uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
     uint32_t waves = (uint32_t)std::min<size_t>(items.size(), 256 * per_cu);
     e = launch_batched((const BatchDev*)(d_tables + ob), (const uint2*)(d_tables + oi), (uint32_t)items.size(),
-                       rt->ex.d_next, waves, stack_max, s);
+                       X.d_next, waves, stack_max, s);
   }
   for (int x = 0; x < used_side; x++) {
-    (void)hipEventRecord(rt->ex.join_ev[x], rt->ex.side[x]);
-    (void)hipStreamWaitEvent(s, rt->ex.join_ev[x], 0);
+    (void)hipEventRecord(X.join_ev[x], X.side[x]);
+    (void)hipStreamWaitEvent(s, X.join_ev[x], 0);
   }
   if (pe.second) (void)hipEventRecord(pe.second, s);
   if (pe.first) rt->prof_pending.push_back(pe);
-  (void)hipEventRecord(rt->ex.ws_event, s);
-  rt->ex.ws_used = true;
+  (void)hipEventRecord(X.ws_event, s);
+  X.ws_used = true;
   if (spill_total) {
-    (void)hipEventRecord(rt->ex.spill_ev, s);
-    rt->ex.spill_used = true;
+    (void)hipEventRecord(X.spill_ev, s);
+    X.spill_used = true;
   }
   if (e != hipSuccess) return to_errno(e);
   if (X.capturing) return 0;  // a graph's launches are counted when it is launched
@@ -1571,30 +1598,30 @@ int gx_graph_create(gx_rt* rt, const gx_batch* descs, uint32_t n, gx_graph** out
   const bool prof = rt->profile;
   const gx_stats st = rt->stats;
   rt->profile = false;
-  std::swap(rt->ex, G->ex);
-  rt->ex.per_phase = true;
-  rt->ex.stage_cursor = 0;
+  rt->cap_ex = &G->ex;
+  G->ex.per_phase = true;
+  G->ex.stage_cursor = 0;
   r = run_batches_impl(rt, descs, n, G->cs);
   if (!r) {
     snap.restore(G->cs);
     if (hipStreamSynchronize(G->cs) != hipSuccess) r = -EIO;
   }
   if (!r) {
-    rt->ex.capturing = true;
+    G->ex.capturing = true;
     // events recorded outside the capture may not be waited on inside it
-    rt->ex.ws_used = false;
-    rt->ex.spill_used = false;
-    rt->ex.stage_cursor = 0;
+    G->ex.ws_used = false;
+    G->ex.spill_used = false;
+    G->ex.stage_cursor = 0;
     if (hipStreamBeginCapture(G->cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
       r = -EIO;
     } else {
       r = run_batches_impl(rt, descs, n, G->cs);
       if (hipStreamEndCapture(G->cs, &G->graph) != hipSuccess && !r) r = -EIO;
     }
-    rt->ex.capturing = false;
-    G->phases = (uint32_t)rt->ex.stage_cursor;
+    G->ex.capturing = false;
+    G->phases = (uint32_t)G->ex.stage_cursor;
   }
-  std::swap(rt->ex, G->ex);
+  rt->cap_ex = nullptr;
   rt->profile = prof;
   rt->stats = st;
   if (r) return fail(r);

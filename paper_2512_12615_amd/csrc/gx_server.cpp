@@ -94,6 +94,7 @@ struct Req {
 struct Group {
   std::vector<Req*> reqs;
   hipEvent_t done = nullptr;
+  uint32_t stream = 0;
 };
 
 }  // namespace
@@ -108,6 +109,7 @@ struct gx_server {
   RangeAlloc* pin_alloc = nullptr;
   std::mutex pin_mu;  // pinned pool: submit allocates, the thread frees
   std::vector<hipStream_t> streams;
+  std::vector<uint32_t> inflight;  // unfinished groups per stream
   std::vector<hipEvent_t> free_events;
   uint32_t next_stream = 0;
   // queues
@@ -160,8 +162,8 @@ void finish(gx_server* s, Req* r, int status) {
   s->cv_done.notify_all();
 }
 
-void launch(gx_server* s, std::vector<Req*>& grp) {
-  hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
+void launch(gx_server* s, std::vector<Req*>& grp, uint32_t k) {
+  hipStream_t st = s->streams[k];
   std::vector<gx_batch> descs;
   int status = 0;
   for (Req* r : grp) {
@@ -191,6 +193,7 @@ void launch(gx_server* s, std::vector<Req*>& grp) {
   }
   Group g;
   g.reqs = grp;
+  g.stream = k;
   g.done = take_event(s);
   (void)hipEventRecord(g.done, st);
   if (status) {
@@ -199,6 +202,7 @@ void launch(gx_server* s, std::vector<Req*>& grp) {
     s->free_events.push_back(g.done);
     return;
   }
+  s->inflight[k]++;
   s->groups.push_back(std::move(g));
 }
 
@@ -230,36 +234,70 @@ void thread_main(gx_server* s) {
           finish(s, r, r->status);
         }
         s->free_events.push_back(g.done);
+        s->inflight[g.stream]--;
         s->groups.erase(s->groups.begin() + i);
       } else {
         i++;
       }
     }
-    // admission: every idle tenant's head request whose buffers fit
-    std::vector<Req*> grp;
-    size_t nt = s->tenants.size();
-    uint32_t cap = s->cfg.max_group ? s->cfg.max_group : 0xffffffffu;
-    for (size_t k = 0; k < nt && grp.size() < cap; k++) {
-      int32_t t = s->tenants[(s->rr + k) % nt];
-      auto& q = s->fifo[t];
-      if (s->busy[t] || q.empty()) continue;
-      Req* r = q.front();
-      if (!s->dev_alloc->alloc(r->dev_len, &r->dev_off)) continue;
-      q.pop_front();
-      s->busy[t] = true;
-      r->t_admit = now_s();
-      grp.push_back(r);
+    if (s->cfg.mode == GX_SERVE_PER_REQUEST) {
+      // baseline: every idle tenant's head request whose buffers fit, each
+      // its own plain launch
+      std::vector<Req*> grp;
+      const size_t nt = s->tenants.size();
+      for (size_t k = 0; k < nt; k++) {
+        int32_t t = s->tenants[(s->rr + k) % nt];
+        auto& q = s->fifo[t];
+        if (s->busy[t] || q.empty()) continue;
+        Req* r = q.front();
+        if (!s->dev_alloc->alloc(r->dev_len, &r->dev_off)) continue;
+        q.pop_front();
+        s->busy[t] = true;
+        r->t_admit = now_s();
+        grp.push_back(r);
+      }
+      if (nt) s->rr = (s->rr + 1) % nt;
+      if (grp.empty() && !s->groups.empty()) std::this_thread::yield();
+      for (Req* r : grp) {
+        std::vector<Req*> one{r};
+        launch(s, one, s->next_stream++ % (uint32_t)s->streams.size());
+      }
+      continue;
+    }
+    // continuous batching: tenant t's requests all go to stream t mod S, so
+    // they run in submission order across launches (the stream orders them)
+    // and a tenant's next request can be queued on the device before its
+    // previous one is done.  A stream with fewer than kStreamDepth
+    // unfinished launches takes the head request of each of its tenants
+    // (buffers fitting) as one batched launch: one request per tenant keeps
+    // the launch one phase wide, and while the stream is busy requests
+    // gather into the next launch.
+    constexpr uint32_t kStreamDepth = 4;
+    bool launched = false;
+    const uint32_t S = (uint32_t)s->streams.size();
+    const uint32_t cap = s->cfg.max_group ? s->cfg.max_group : 0xffffffffu;
+    const size_t nt = s->tenants.size();
+    for (uint32_t k = 0; k < S; k++) {
+      if (s->inflight[k] >= kStreamDepth) continue;
+      std::vector<Req*> grp;
+      for (size_t j = 0; j < nt && grp.size() < cap; j++) {
+        const int32_t t = s->tenants[(s->rr + j) % nt];
+        if ((uint32_t)t % S != k) continue;
+        auto& q = s->fifo[t];
+        if (q.empty()) continue;
+        Req* r = q.front();
+        if (!s->dev_alloc->alloc(r->dev_len, &r->dev_off)) continue;
+        q.pop_front();
+        r->t_admit = now_s();
+        grp.push_back(r);
+      }
+      if (!grp.empty()) {
+        launch(s, grp, k);
+        launched = true;
+      }
     }
     if (nt) s->rr = (s->rr + 1) % nt;
-    if (grp.empty() && !s->groups.empty()) std::this_thread::yield();
-    if (s->cfg.mode == GX_SERVE_PER_REQUEST) {
-      for (Req* r : grp) {  // every request is its own plain launch
-        std::vector<Req*> one{r};
-        launch(s, one);
-      }
-    } else if (!grp.empty()) {
-      launch(s, grp);
-    }
+    if (!launched && !s->groups.empty()) std::this_thread::yield();
   }
 }
 
@@ -294,6 +332,7 @@ int gx_server_create(gx_rt* rt, const gx_server_cfg* cfg, gx_server** out) {
     }
     s->streams.push_back(st);
   }
+  s->inflight.assign(s->streams.size(), 0);
   s->th = std::thread(thread_main, s);
   *out = s;
   return 0;
