@@ -346,6 +346,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the memory-bound policies, the batched and the served forms")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--only-form", choices=["memory_bound", "batched", "serving"],
+                    help="run only this form and print its JSON (profiling one form)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel that "
                          "scales the HBM byte counters of a profile)")
@@ -368,6 +370,15 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_calib_mib} MiB device to device")
         del src, dst
+
+    if args.only_form:
+        rt = G.Runtime(0)
+        fn = {"memory_bound": lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit"),
+              "batched": lambda: bench_batched(G, W, rt, 2),
+              "serving": lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit")}
+        print(json.dumps({args.only_form: fn[args.only_form]()}))
+        rt.close()
+        return
 
     n = 1 << args.events_log2
     pol = W.stride_prefetch_policy()
