@@ -170,6 +170,11 @@ def bench_memory_bound(G, W, rt, steps, jit=True):
     out["access_counter"] = bench_event_parallel(
         G, W, rt, "access counter, 2^20 x 24 B records, ARRAY 4096 x u64 shared", W.access_counter_policy(), acc,
         steps * 20, jit=jit)
+    if jit:
+        # the plain single-program configuration names the interpreter
+        out["access_counter_interpreted"] = bench_event_parallel(
+            G, W, rt, "access counter, 2^20 x 24 B records, ARRAY 4096 x u64 shared", W.access_counter_policy(),
+            acc, steps * 20, jit=False)
     del acc
     hosts = [W.gen_timing(1 << 26, 1002 + k) for k in range(2)]
     init = [[(1, b"\0\0\0\0", np.uint64(W.p99_threshold(h["lat"])).tobytes())] for h in hosts]
