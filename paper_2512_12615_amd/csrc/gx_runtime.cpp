@@ -434,6 +434,11 @@ std::vector<Uop> predecode(const std::vector<Insn>& P, const Verdict& V, const s
   return U;
 }
 
+// Events per partition tile (one wave each): at least 4096, and about 2048
+// tiles for large runs, so that the partition's waves fill the device (its
+// per-queue counts then take 2^qbits x tiles words).
+uint64_t part_tile(uint64_t n_events) { return std::max<uint64_t>(4096, next_pow2((n_events + 2047) / 2048)); }
+
 int ensure_ws(Exec& X, size_t counts, size_t sums, size_t order) {
   auto grow = [](uint32_t** p, size_t* cap, size_t need) -> int {
     if (*cap >= need) return 0;
@@ -557,7 +562,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   } else {
     const uint32_t lbits = k.qbits;
     const uint32_t L = 1u << lbits;
-    uint64_t tile = std::max<uint64_t>(4096, next_pow2((n_events + 255) / 256));
+    uint64_t tile = part_tile(n_events);
     uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
     uint64_t m = (uint64_t)L * nt;
     int r = ensure_ws(X, m, (m + 4095) / 4096 + 1, n_events);
@@ -1314,7 +1319,7 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
     } else {
       uint32_t lbits = qbits;
       uint32_t L = 1u << lbits;
-      uint64_t tile = std::max<uint64_t>(4096, next_pow2((d[i].n_events + 255) / 256));
+      uint64_t tile = part_tile(d[i].n_events);
       uint32_t nt = (uint32_t)((d[i].n_events + tile - 1) / tile);
       PartJob pj{A.events, A.n_events, A.record_size, A.stream_off, lbits, (uint32_t)tile, nt, 0, counts_total};
       for (uint32_t t = 0; t < nt; t++) tiles.push_back(make_uint2((uint32_t)J.size(), t));
