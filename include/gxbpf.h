@@ -239,6 +239,17 @@ void gx_graph_destroy(gx_graph* g);
 int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_bytes,
                          uint64_t* n_records);
 
+/* As gx_drain_ringbuf without the copy into caller memory: *view points at
+ * the drained range in the runtime's pinned staging buffer for this ring
+ * (*view_bytes bytes, valid until the next drain of this ring or
+ * gx_destroy_map), which still holds the discard records (flags bit 0; len
+ * bytes of padding) that close unused chunk space; readers skip them.
+ * Returns the bytes of the kept records (headers included) and their
+ * count in *n_records; releases the whole range.  Errors as
+ * gx_drain_ringbuf. */
+int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
+                              uint64_t* n_records);
+
 /* Counters accumulated since gx_open (synchronises the device). */
 int gx_stats_get(gx_rt* rt, gx_stats* out);
 

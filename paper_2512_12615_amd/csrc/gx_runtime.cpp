@@ -1725,6 +1725,63 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   return (int64_t)out;
 }
 
+int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
+                              uint64_t* n_records) {
+  MapObj* m = get_map(rt, ring_fd);
+  if (!m || m->h.type != MAP_RINGBUF || !view || !view_bytes) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  uint64_t ctrl[4];
+  if (hipMemcpy(ctrl, m->h.ctrl, 32, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
+  const bool cut = ctrl[3] != 0;
+  if (cut && ~ctrl[3] < head) head = ~ctrl[3];
+  *view = nullptr;
+  *view_bytes = 0;
+  if (n_records) *n_records = 0;
+  const uint64_t avail = head - tail;
+  uint64_t pos = 0, kept = 0, nrec = 0;
+  if (avail) {
+    if (m->pin_cap < avail) {
+      if (m->h_pin) (void)hipHostFree(m->h_pin);
+      m->h_pin = nullptr;
+      m->pin_cap = 0;
+      if (hipHostMalloc((void**)&m->h_pin, avail, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+      m->pin_cap = avail;
+    }
+    uint8_t* buf = m->h_pin;
+    const uint64_t t0 = tail & (cap - 1);
+    const uint64_t first = std::min(avail, cap - t0);
+    if (hipMemcpy(buf, m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+    if (first < avail && hipMemcpy(buf + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
+      return -EIO;
+    while (pos + 8 <= avail) {
+      uint32_t len, flags;
+      std::memcpy(&len, buf + pos, 4);
+      std::memcpy(&flags, buf + pos + 4, 4);
+      if (len == 0 && flags == 0) break;
+      const uint64_t need = 8 + ((len + 7ull) & ~7ull);
+      if (pos + need > avail) break;
+      if (!(flags & RING_DISCARD)) {
+        kept += need;
+        nrec++;
+      }
+      pos += need;
+    }
+    *view = buf;
+    *view_bytes = pos;
+  }
+  if (pos || cut) {
+    uint64_t nc[4] = {head, tail + pos, ctrl[2], 0};
+    const bool ok = cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
+                        : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return -EIO;
+  }
+  rt->stats.bytes_drained += kept;
+  if (n_records) *n_records = nrec;
+  return (int64_t)kept;
+}
+
 int gx_profile_enable(gx_rt* rt, int on) {
   if (!rt) return -EINVAL;
   rt->profile = on != 0;

@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
+           "gx_run_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
@@ -101,6 +101,8 @@ def lib():
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_graph_create.argtypes = [vp, C.POINTER(Batch), u32, C.POINTER(vp)]
+    L.gx_drain_ringbuf_view.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(u64), C.POINTER(u64)]
+    L.gx_drain_ringbuf_view.restype = C.c_int64
     L.gx_graph_launch.argtypes = [vp, vp]
     L.gx_graph_destroy.argtypes = [vp]
     L.gx_graph_destroy.restype = None
@@ -332,6 +334,18 @@ class Runtime:
         return Graph(self, descs)
 
     # ring buffers -----------------------------------------------------------
+    def drain_ringbuf_view(self, fd):
+        """Drain without a host copy (gx_drain_ringbuf_view): returns (view,
+        kept_bytes, n_records), view a uint8 array over the runtime's pinned
+        staging buffer, valid until the next drain of this ring, which also
+        holds discard records (parse_ring skips them)."""
+        view, vb, n = C.c_void_p(), C.c_uint64(0), C.c_uint64(0)
+        kept = _check(lib().gx_drain_ringbuf_view(self._h, fd, C.byref(view), C.byref(vb), C.byref(n)),
+                      "gx_drain_ringbuf_view")
+        if not vb.value:
+            return np.empty(0, np.uint8), kept, n.value
+        return np.ctypeslib.as_array(C.cast(view, C.POINTER(C.c_uint8)), shape=(vb.value,)), kept, n.value
+
     def drain_ringbuf(self, fd, cap=None, copy=True):
         """Returns (records, n_records): the committed records as bytes, or
         (copy=False) as a view of a buffer the next drain of this ring
@@ -398,10 +412,14 @@ class Graph:
 
 
 def parse_ring(buf: bytes):
+    """Payloads of the records {u32 len; u32 flags; payload padded to 8};
+    discard records (flags bit 0) are skipped."""
     out, pos = [], 0
     while pos + 8 <= len(buf):
         ln = int.from_bytes(buf[pos:pos + 4], "little")
-        out.append(bytes(buf[pos + 8:pos + 8 + ln]))
+        flags = int.from_bytes(buf[pos + 4:pos + 8], "little")
+        if not flags & 1:
+            out.append(bytes(buf[pos + 8:pos + 8 + ln]))
         pos += 8 + ((ln + 7) & ~7)
     return out
 

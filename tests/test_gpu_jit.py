@@ -294,3 +294,30 @@ def test_jit_instances_share_code_keep_their_maps(rt):
     for j, (fds, prog, ev, d, rc) in enumerate(runs):
         g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
         assert_same(g, oracle_run(pol, ev), f"instance {j}")
+
+
+def test_jit_ring_drain_view(rt):
+    """The drain without a host copy hands out the pinned range with its
+    discard records; the records in it are the oracle's, and the range is
+    released like a copying drain's."""
+    import torch
+    from paper_2512_12615_amd import gxbpf as G
+    _log("jit ring drain view")
+    pol = W.stride_prefetch_policy()
+    fds, prog = setup(rt, pol, jit=True)
+    seen, want = [], []
+    o_ev = []
+    for b in range(2):
+        ev = W.gen_mem_stride(40000, 91 + b, streams=64)
+        o_ev.append(ev)
+        rc = torch.zeros(len(ev), dtype=torch.int32, device="cuda")
+        rt.run_batch(prog, to_device(ev), n_events=len(ev), record_size=24, rc=rc)
+        view, kept, n = rt.drain_ringbuf_view(fds[1])
+        recs = G.parse_ring(bytes(view))
+        assert n == len(recs)
+        assert kept == sum(8 + ((len(r) + 7) & ~7) for r in recs)
+        seen += recs
+    want = oracle_run(pol, np.concatenate(o_ev)).rings[1]
+    assert sorted(seen) == want
+    view, kept, n = rt.drain_ringbuf_view(fds[1])
+    assert kept == 0 and n == 0 and len(view) == 0
