@@ -936,6 +936,8 @@ struct Checker {
       for (size_t m = 0; m < maps.size(); m++)
         if (map_used[m] && maps[m].type != MAP_RINGBUF && !(maps[m].flags & (F_SHARED | F_READ_ONLY)))
           ep = false;
+      if (hook == HOOK_WAVE_MEM && !ep)
+        throw Reject{"a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers"};
       res.event_parallel = ep;
       res.log = "accepted";
     } catch (const Reject& r) {

@@ -24,7 +24,10 @@ namespace gxo {
 
 enum : int { MAP_HASH = 1, MAP_ARRAY = 2, MAP_RINGBUF = 27 };
 enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2 };
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2 };
+// HOOK_WAVE_MEM: the warp-leader hook (section 4.4, warp-level execution):
+// one invocation per tile of 64 consecutive memory-access records, whose
+// context is the tile's aggregate (see hook_info).
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3 };
 enum : int { H_LOOKUP = 1, H_UPDATE = 2, H_DELETE = 3, H_RINGBUF_OUTPUT = 130 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 

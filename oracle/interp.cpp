@@ -39,7 +39,33 @@ bool hook_info(int hook, HookInfo* out) {
     *out = {16, 0, 4, {{0, 4}, {8, 8}}};
     return true;
   }
+  if (hook == HOOK_WAVE_MEM) {
+    // input: memory-access records (24 B); context of one invocation:
+    // {u64 lo = smallest addr @0, u64 hi = largest addr @8, u32 n = records
+    // @16, u32 stream of the tile's first record @20}
+    *out = {24, 8, 4, {{0, 8}, {8, 8}, {16, 4}, {20, 4}}};
+    return true;
+  }
   return false;
+}
+
+// Context of a warp-leader invocation for records [b, e) (24-byte
+// memory-access records), laid out as hook_info(HOOK_WAVE_MEM) states.
+static void wave_context(const uint8_t* events, uint64_t b, uint64_t e, uint8_t* ctx) {
+  uint64_t lo = ~0ull, hi = 0;
+  for (uint64_t i = b; i < e; i++) {
+    uint64_t a = 0;
+    std::memcpy(&a, events + i * 24, 8);
+    lo = a < lo ? a : lo;
+    hi = a > hi ? a : hi;
+  }
+  const uint32_t n = (uint32_t)(e - b);
+  uint32_t s0 = 0;
+  std::memcpy(&s0, events + b * 24 + 8, 4);
+  std::memcpy(ctx, &lo, 8);
+  std::memcpy(ctx + 8, &hi, 8);
+  std::memcpy(ctx + 16, &n, 4);
+  std::memcpy(ctx + 20, &s0, 4);
 }
 
 static uint64_t load_le(const uint8_t* p, int size) {
@@ -702,6 +728,40 @@ int Oracle::run(const Program& prog, const uint8_t* events, uint64_t n, int orde
   if (!hook_info(prog.hook, &hi)) return -E_INVAL;
   for (int id : prog.map_table)
     if (id < 0 || id >= (int)maps.size()) return -E_INVAL;
+  if (prog.hook == HOOK_WAVE_MEM) {
+    // one invocation per tile of 64 consecutive records, its return code
+    // given to every record of the tile; tiles in index order or shuffled
+    const uint64_t tiles = (n + 63) / 64;
+    std::vector<uint64_t> tix(tiles);
+    std::iota(tix.begin(), tix.end(), 0);
+    if (order == 2) {
+      uint64_t s = seed;
+      for (uint64_t i = tiles; i > 1; i--) {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        std::swap(tix[i - 1], tix[z % i]);
+      }
+    }
+    Exec ex(*this, prog, hi);
+    for (uint64_t t : tix) {
+      const uint64_t b = t * 64, e = b + 64 < n ? b + 64 : n;
+      uint8_t ctx[24];
+      wave_context(events, b, e, ctx);
+      uint32_t rc = 0;
+      try {
+        rc = ex.run_event(ctx);
+      } catch (const Fault& f) {
+        stats.faults++;
+        if (stats.fault_msg.empty()) stats.fault_msg = "tile " + std::to_string(t) + ": " + f.msg;
+      }
+      if (rc_out)
+        for (uint64_t i = b; i < e; i++) rc_out[i] = rc;
+    }
+    return 0;
+  }
   std::vector<uint64_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   auto key = [&](uint64_t i) { return load_le(events + i * hi.record_size + hi.stream_off, hi.stream_size); };

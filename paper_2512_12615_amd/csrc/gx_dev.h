@@ -891,13 +891,49 @@ __device__ __forceinline__ Ctx load_record(const RunArgs& A, uint64_t i) {
 }
 
 // One wave-tile of an event-parallel run: lane l runs event first + l.
+// Warp-leader hook (section 4.4's warp-level execution): the context of one
+// invocation for the wave's tile of memory-access records, from every
+// lane's record - the smallest and largest address (butterfly exchanges
+// over the 64 lanes), the number of records, the stream of the tile's first
+// record (lane 0's) - identical in every lane.
+__device__ __forceinline__ Ctx wave_context(const Ctx& c, bool live) {
+  uint64_t lo = live ? c.c0 : ~0ull, hi = live ? c.c0 : 0;
+  auto xchg = [](uint64_t v, uint32_t off) {  // v of lane (this lane ^ off)
+    const int a = (int)((lane_id() ^ off) << 2);
+    const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)h << 32) | l;
+  };
+#pragma unroll
+  for (uint32_t off = 32; off >= 1; off >>= 1) {
+    const uint64_t l2 = xchg(lo, off), h2 = xchg(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  const uint32_t n = popc64(ballot(live));
+  const uint32_t s0 = __builtin_amdgcn_readlane((uint32_t)c.c1, 0);
+  return Ctx{lo, hi, (uint64_t)n | ((uint64_t)s0 << 32)};
+}
+
+// One tile of an event-parallel run: every lane runs its record, or, for the
+// warp-leader hook, lane 0 runs the tile's aggregate and every record of the
+// tile receives its return code.
+template <class Run>
+__device__ __forceinline__ uint32_t tile_run(Run& R, const RunArgs& A, bool live, const Ctx& c, const Stk& stk,
+                                             uint64_t& steps) {
+  if (!A.leader) return R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
+  const Ctx w = wave_context(c, live);
+  const uint32_t rc = R.run(A, lane_id() == 0 && live, w.c0, w.c1, w.c2, stk, steps);
+  return __builtin_amdgcn_readlane(rc, 0);
+}
+
 template <class Run>
 __device__ __forceinline__ void event_tile(Run& R, const RunArgs& A, uint64_t first, const Stk& stk, uint64_t& steps) {
   const uint64_t i = first + lane_id();
   const bool live = i < A.n_events;
   Ctx c{0, 0, 0};
   if (live) c = load_record(A, i);
-  uint32_t rc = R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
+  uint32_t rc = tile_run(R, A, live, c, stk, steps);
   if (live && A.rc) A.rc[i] = rc;
 }
 
@@ -917,7 +953,7 @@ __device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0
     const bool ln = tn < tiles && in < A.n_events;
     Ctx cn{0, 0, 0};
     if (ln) cn = load_record(A, in);
-    const uint32_t rc = R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
+    const uint32_t rc = tile_run(R, A, live, c, stk, steps);
     if (live && A.rc) A.rc[i] = rc;
     t = tn;
     i = in;

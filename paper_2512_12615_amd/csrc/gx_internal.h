@@ -15,7 +15,10 @@ constexpr uint64_t kMaxRingBytes = 4096;
 
 enum : int { MAP_HASH = 1, MAP_ARRAY = 2, MAP_RINGBUF = 27 };
 enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2 };
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2 };
+// HOOK_WAVE_MEM: the warp-leader hook (section 4.4, warp-level execution):
+// one invocation per wave tile of 64 memory-access records, with the tile's
+// aggregate as context {u64 lo, u64 hi, u32 n, u32 stream of the first}.
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 
 // ---------------------------------------------------------------------------
@@ -105,6 +108,8 @@ struct RunArgs {
   const uint8_t* sorted;   // stream-sequential: the records in queue order, kSortedStride apart
   const uint64_t* maptab;  // device addresses of the program's map descriptors, in its map-table order
   uint8_t* spill;          // compiled event-parallel runs: LDS cache spill area (null: caches flush directly)
+  uint32_t leader;         // 1: warp-leader hook (one invocation per wave tile)
+  uint32_t pad3;
 };
 
 // Stride of the queue-ordered record copy (the largest record).

@@ -530,6 +530,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   A.err = rt->d_err;
   A.guards = p->d_guards;
   A.maptab = p->d_maptab;
+  A.leader = p->hook == HOOK_WAVE_MEM ? 1u : 0u;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
@@ -1273,6 +1274,7 @@ RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events
   A.err = rt->d_err;
   A.guards = p->d_guards;
   A.maptab = p->d_maptab;
+  A.leader = p->hook == HOOK_WAVE_MEM ? 1u : 0u;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;

@@ -46,6 +46,12 @@ bool hook_layout(int hook, uint32_t* record_size, uint32_t* stream_off, uint32_t
     *stream_size = 4;
     return true;
   }
+  if (hook == HOOK_WAVE_MEM) {  // input records as HOOK_MEM_ACCESS
+    *record_size = 24;
+    *stream_off = 8;
+    *stream_size = 4;
+    return true;
+  }
   return false;
 }
 
@@ -56,6 +62,8 @@ bool ctx_field(int hook, int64_t off, int size) {
   if (hook == HOOK_MEM_ACCESS)
     return (off == 0 && size == 8) || (off == 8 && size == 4) || (off == 16 && size == 8);
   if (hook == HOOK_KERNEL_TIMING) return (off == 0 && size == 4) || (off == 8 && size == 8);
+  if (hook == HOOK_WAVE_MEM)
+    return (off == 0 && size == 8) || (off == 8 && size == 8) || (off == 16 && size == 4) || (off == 20 && size == 4);
   return false;
 }
 
@@ -295,6 +303,8 @@ class Verifier {
       for (size_t i = 0; i < maps_.size(); i++)
         if (used_[i] && maps_[i].type != MAP_RINGBUF && !(maps_[i].flags & (F_SHARED | F_READ_ONLY)))
           V.event_parallel = false;
+      if (hook_ == HOOK_WAVE_MEM && !V.event_parallel)
+        fail(0, "a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers");
     } catch (const Fail& f) {
       Verdict bad;
       bad.ok = false;

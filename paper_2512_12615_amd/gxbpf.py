@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libgxbpf.so")
 
 MAP_HASH, MAP_ARRAY, MAP_RINGBUF = 1, 2, 27
 F_SHARED, F_READ_ONLY = 1, 2
-HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING = 1, 2
+HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING, HOOK_WAVE_MEM = 1, 2, 3
 MODE_EVENT_PARALLEL, MODE_STREAM_SEQUENTIAL = 0, 1
-RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16}
+RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16, HOOK_WAVE_MEM: 24}
 
 
 class GxError(OSError):

@@ -34,6 +34,9 @@ M2 = np.uint64(0x94D049BB133111EB)
 # hook types and record layouts (little endian, packed)
 HOOK_MEM_ACCESS = 1
 HOOK_KERNEL_TIMING = 2
+# warp-leader hook: one invocation per tile of 64 memory-access records, on
+# the tile's aggregate {u64 lo @0, u64 hi @8, u32 n @16, u32 stream @20}
+HOOK_WAVE_MEM = 3
 MEM_DTYPE = np.dtype([("addr", "<u8"), ("stream", "<u4"), ("pad", "<u4"), ("ts", "<u8")])
 TIMING_DTYPE = np.dtype([("kernel_id", "<u4"), ("pad", "<u4"), ("lat", "<u8")])
 assert MEM_DTYPE.itemsize == 24 and TIMING_DTYPE.itemsize == 16
@@ -145,6 +148,25 @@ def gen_mem_stride(n: int, seed: int, streams: int = 1024, pages_log2: int = 18,
     return ev
 
 
+def gen_mem_wave(n: int, seed: int, coalesced: float = 0.75, streams: int = 1024) -> np.ndarray:
+    """Memory-access records as the lanes of waves issue them: records come
+    in tiles of 64 (one wave's access); a fraction ``coalesced`` of the
+    tiles read consecutive 8-byte words from a uniform base (u64-aligned in
+    [0, 8 GiB)), the others 64 uniform addresses.  The tile's stream is
+    uniform in [0, streams); timestamps strictly increase."""
+    ev = np.zeros(n, dtype=MEM_DTYPE)
+    tiles = (n + 63) // 64
+    tile = np.arange(n, dtype=np.uint64) // np.uint64(64)
+    lane = np.arange(n, dtype=np.uint64) % np.uint64(64)
+    co = u01(splitmix(subseed(seed, 1), tiles)) < coalesced
+    base = (splitmix(subseed(seed, 2), tiles) >> np.uint64(31)) & ~np.uint64(7)
+    rand = (splitmix(subseed(seed, 3), n) >> np.uint64(31))
+    ev["addr"] = np.where(co[tile.astype(np.int64)], base[tile.astype(np.int64)] + lane * np.uint64(8), rand)
+    ev["stream"] = (u01(splitmix(subseed(seed, 4), tiles)) * streams).astype(np.uint32)[tile.astype(np.int64)]
+    ev["ts"] = np.cumsum(np.uint64(1) + (splitmix(subseed(seed, 5), n) >> np.uint64(58)))
+    return ev
+
+
 def gen_timing(n: int, seed: int, kernels: int = 4096, zipf_s: float = 1.2,
                mu: float = 10.0, sigma: float = 1.5) -> np.ndarray:
     """Kernel-timing records: kernel_id = Zipf(zipf_s) rank scattered by an odd
@@ -193,7 +215,7 @@ class Policy:
 
     @property
     def record_size(self) -> int:
-        return 24 if self.hook == HOOK_MEM_ACCESS else 16
+        return 16 if self.hook == HOOK_KERNEL_TIMING else 24
 
 
 # Access counter: per 2 MiB region counts in a shared array; rc = region & 1.
@@ -423,6 +445,74 @@ done:
     mov64 r0, r9
     exit
 """
+
+
+# Warp-leader access monitor: once per wave tile, on the tile's aggregate.
+# A tile within one 4 KiB page counts its records in the page's 2 MiB region
+# (coalesced); a wider tile counts once as scattered, and a tile spanning
+# more than 4 GiB also sends {lo, hi, n | stream << 32} to the ring.  The
+# return code is the number of 4 KiB pages the tile spans.
+WAVE_MONITOR = """
+    ldxdw r6, [r1+0]          ; lo
+    ldxdw r7, [r1+8]          ; hi
+    ldxw r8, [r1+16]          ; n
+    ldxw r9, [r1+20]          ; stream of the first record
+    mov64 r2, r6
+    rsh64 r2, 21
+    and64 r2, 4095            ; region of lo
+    stxw [r10-4], r2
+    mov64 r3, r7
+    sub64 r3, r6
+    jgt r3, 4095, wide
+    lddw r1, map:coal
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, pages
+    aadd64 [r0+0], r8
+    ja pages
+wide:
+    lddw r1, map:scat
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, far
+    mov64 r1, 1
+    aadd64 [r0+0], r1
+far:
+    mov64 r3, r7
+    sub64 r3, r6
+    rsh64 r3, 32
+    jeq r3, 0, pages
+    stxdw [r10-32], r6
+    stxdw [r10-24], r7
+    mov64 r1, r9
+    lsh64 r1, 32
+    or64 r1, r8
+    stxdw [r10-16], r1
+    lddw r1, map:ring
+    mov64 r2, r10
+    add64 r2, -32
+    mov64 r3, 24
+    mov64 r4, 0
+    call ringbuf_output
+pages:
+    mov64 r0, r7
+    rsh64 r0, 12
+    mov64 r1, r6
+    rsh64 r1, 12
+    sub64 r0, r1
+    add64 r0, 1
+    exit
+"""
+
+
+def wave_monitor_policy(ring_bytes: int = 64 << 20) -> Policy:
+    return Policy("wave_monitor", HOOK_WAVE_MEM, WAVE_MONITOR, [
+        MapSpec("coal", MAP_ARRAY, 4, 8, 4096, F_SHARED),
+        MapSpec("scat", MAP_ARRAY, 4, 8, 4096, F_SHARED),
+        MapSpec("ring", MAP_RINGBUF, 0, 0, ring_bytes, 0),
+    ])
 
 
 def latency_hist_policy(kernels: int = 4096, ring_bytes: int = 64 << 20) -> Policy:

@@ -74,3 +74,36 @@ def stride_prefetch(ev):
 def percentile_threshold(lat):
     k = math.ceil(0.99 * len(lat)) - 1
     return int(np.sort(lat)[k])
+
+
+def wave_tiles(ev):
+    """Per tile of 64 consecutive records: (lo, hi, n, stream of the first
+    record), by plain Python loops."""
+    out = []
+    addr = ev["addr"].tolist()
+    stream = ev["stream"].tolist()
+    for b in range(0, len(ev), 64):
+        a = addr[b:b + 64]
+        out.append((min(a), max(a), len(a), stream[b]))
+    return out
+
+
+def wave_monitor(ev):
+    """The warp-leader monitor as described in prose: per tile, coalesced
+    tiles (hi - lo < 4096) add n to coal[(lo >> 21) & 4095], others add 1 to
+    scat[...] and, spanning more than 4 GiB, emit (lo, hi, n | stream << 32);
+    every record of the tile gets the tile's page span."""
+    coal = np.zeros(4096, np.uint64)
+    scat = np.zeros(4096, np.uint64)
+    ring, rc = [], np.zeros(len(ev), np.uint32)
+    for t, (lo, hi, n, s0) in enumerate(wave_tiles(ev)):
+        reg = (lo >> 21) & 4095
+        if hi - lo < 4096:
+            coal[reg] += np.uint64(n)
+        else:
+            scat[reg] += np.uint64(1)
+            if (hi - lo) >> 32:
+                ring.append(int(lo).to_bytes(8, "little") + int(hi).to_bytes(8, "little") +
+                            ((s0 << 32) | n).to_bytes(8, "little"))
+        rc[t * 64:t * 64 + n] = ((hi >> 12) - (lo >> 12) + 1) & 0xffffffff
+    return coal, scat, sorted(ring), rc
