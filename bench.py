@@ -188,6 +188,28 @@ def bench_memory_bound(G, W, rt, steps, jit=True):
     return out
 
 
+def bench_warp_leader(G, W, rt, steps, jit=True):
+    """Warp-level execution (the warp-leader hook) against per-record
+    execution on the same records: the wave monitor runs once per tile of 64
+    records on the tile's aggregate; the access counter runs once per
+    record.  2^24 wave-shaped records, 2 rotated batches."""
+    import numpy as np
+    import torch
+    hosts = [W.gen_mem_wave(1 << 24, 1005 + k) for k in range(2)]
+    dev = [torch.from_numpy(h.view(np.uint8)).cuda() for h in hosts]
+    del hosts
+    out = {
+        "warp_leader": bench_event_parallel(G, W, rt, "wave monitor (warp-leader hook), 2^24 x 24 B records",
+                                            W.wave_monitor_policy(), dev, steps, ring_fd=2, jit=jit),
+        "per_record": bench_event_parallel(G, W, rt, "access counter (per-record hook), same records",
+                                           W.access_counter_policy(), dev, steps, jit=jit),
+    }
+    out["speedup"] = out["warp_leader"]["vm_events_per_s"] / out["per_record"]["vm_events_per_s"]
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(G, W, rt, reps):
     """256 generated programs over their own batches (2^10..2^20 events):
     one batched launch against 256 plain launches in order, same outputs."""
@@ -351,7 +373,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the memory-bound policies, the batched and the served forms")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
-    ap.add_argument("--only-form", choices=["memory_bound", "batched", "serving"],
+    ap.add_argument("--only-form", choices=["memory_bound", "warp_leader", "batched", "serving"],
                     help="run only this form and print its JSON (profiling one form)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel that "
@@ -379,6 +401,7 @@ def main():
     if args.only_form:
         rt = G.Runtime(0)
         fn = {"memory_bound": lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit"),
+              "warp_leader": lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit"),
               "batched": lambda: bench_batched(G, W, rt, 2),
               "serving": lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit")}
         print(json.dumps({args.only_form: fn[args.only_form]()}))
@@ -445,6 +468,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit")),
+                        ("warp_leader", lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit")),
                         ("batched", lambda: bench_batched(G, W, rt, 2)),
                         ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit"))):
             log(f"form: {key}")

@@ -792,7 +792,7 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
        "  const uint32_t wave = threadIdx.x >> 6;\n"
        "  gx::Stk stk{wave * 64u * " + std::to_string(P.stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
        "u + threadIdx.x};\n"
-       "  gx::p0::Prog<true> P{wave};\n  P.begin(A);\n"
+       "  gx::p0::Prog<true" + std::string(P.leader ? ", true" : "") + "> P{wave};\n  P.begin(A);\n"
        "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
        "  P.end(A);\n}\n\n" +
        (ji.spill_block_bytes ? std::string("extern \"C\" __global__ void __launch_bounds__(256) gx_j_reduce(gx::RunArgs A, "
@@ -834,7 +834,7 @@ std::string jit_set_source(const std::vector<JitProg>& progs) {
   for (size_t k = 0; k < progs.size(); k++) {
     const std::string K = std::to_string(k);
     const bool ep = progs[k].event_parallel;
-    o += "      case " + K + "u: {\n        gx::p" + K + "::Prog<false" + (ep ? "" : ", true") +
+    o += "      case " + K + "u: {\n        gx::p" + K + "::Prog<false" + (ep && !progs[k].leader ? "" : ", true") +
          "> P{0u};\n        P.begin(bd.A);\n";
     if (ep)
       o += "        gx::event_tile(P, bd.A, (uint64_t)chunk * 64u, stk, steps);\n";

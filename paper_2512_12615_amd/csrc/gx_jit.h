@@ -28,6 +28,7 @@ struct JitProg {
   const std::vector<int>* mem_map;
   const std::vector<int>* ld_map;
   bool event_parallel;
+  bool leader = false;  // warp-leader hook: one lane runs each tile, on wave-uniform values
 };
 
 // HIP source of one program: its micro-ops written out as straight-line

@@ -602,7 +602,10 @@ struct StandIn {
   std::vector<Uop> U;
   std::vector<std::pair<uint64_t, MapDev>> maps;
   std::string log;
-  JitProg prog() const { return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel}; }
+  int hook = 0;
+  JitProg prog() const {
+    return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel, hook == HOOK_WAVE_MEM};
+  }
 };
 
 int stand_in(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const uint32_t* map_shapes, uint32_t n_maps,
@@ -635,6 +638,7 @@ int stand_in(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const 
     out->maps.push_back({refs[i].desc, d});
   }
   std::vector<Insn> P = decode_insns(insns, n_insns);
+  out->hook = (int)hook_type;
   out->v = verify(P, (int)hook_type, shapes, fds);
   if (!out->v.ok) {
     out->log = out->v.log;
@@ -1072,7 +1076,8 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   }
   JitInfo info;
   const std::string src =
-      jit_source(JitProg{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel},
+      jit_source(JitProg{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
+                         p->hook == HOOK_WAVE_MEM},
                  &info);
   auto adopt = [&](const gx_rt::JitMod& jm) {
     p->jf_ep = jm.fe;
@@ -1140,7 +1145,7 @@ int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, ui
   std::map<std::string, uint32_t> uniq;
   for (uint32_t i = 0; i < n; i++) {
     const JitProg q{&ps[i]->uops, ps[i]->v.stack_bytes, &maps[i], &ps[i]->v.mem_map, &ps[i]->v.ld_map,
-                    ps[i]->v.event_parallel};
+                    ps[i]->v.event_parallel, ps[i]->hook == HOOK_WAVE_MEM};
     auto ins = uniq.emplace(jit_source(q), (uint32_t)jp.size());
     if (ins.second) jp.push_back(q);
     slot[i] = ins.first->second;
