@@ -51,10 +51,20 @@ enum {
  *   GX_HOOK_KERNEL_TIMING 16 B {u32 kernel_id; u32 pad; u64 latency_ns}
  *                         stream key = kernel_id (modelled on the paper's
  *                         device observability tools, Table 2)
- * The record is the program's read-only ctx (r1). */
+ *   GX_HOOK_WAVE_MEM      warp-leader hook (section 4.4, "Warp-level
+ *                         Execution Optimizations"): input records as
+ *                         GX_HOOK_MEM_ACCESS, but the program runs once per
+ *                         tile of 64 consecutive records (one wave) on the
+ *                         tile's aggregate ctx {u64 lo = smallest addr;
+ *                         u64 hi = largest addr; u32 n = records; u32
+ *                         stream_id of the tile's first record}, and every
+ *                         record of the tile gets its return code.  Its
+ *                         maps must be shared, read-only or ring buffers.
+ * The record (or aggregate) is the program's read-only ctx (r1). */
 enum {
   GX_HOOK_MEM_ACCESS = 1,
   GX_HOOK_KERNEL_TIMING = 2,
+  GX_HOOK_WAVE_MEM = 3,
 };
 
 /* Execution modes chosen by the verifier (section 4.4's deterministic
@@ -137,7 +147,7 @@ int gx_verify(const uint64_t* insns, uint32_t n_insns, uint32_t hook_type, const
               uint32_t n_maps, char* log, uint32_t log_size, gx_prog_info* info);
 
 /* Compile a loaded program to native gfx950 code (the paper lowers verified
- * bytecode through LLVM and inlines helpers and map accesses: section 5.1,
+ * bytecode through LLVM and inlines helpers and map accesses: sections 5.1, 5.3,
  * section 4.4 "Warp-level Execution Optimizations").  The micro-ops become
  * HIP source compiled with hipRTC; later gx_run_batch calls of this program
  * launch the compiled kernels (gx_run_batches keeps interpreting).  Results
@@ -198,15 +208,18 @@ int64_t gx_jit_set_source(const uint64_t* insns, const uint32_t* n_insns, const 
                           uint64_t cap);
 
 /* Run a program over n_events records at d_events (device memory, record
- * size given by the hook) asynchronously on ``stream``; writes the u32 return
+ * size given by the hook; the hook's invocation of section 4.3.1, one per
+ * event, here one GPU lane per event) asynchronously on ``stream``; writes the u32 return
  * code of event i to d_rc[i] if d_rc is not NULL.  Maps change in place.
  * The caller keeps d_events / d_rc alive until the stream reaches this point.
  * Errors: -EINVAL (bad fd, record_size mismatch), -ENOMEM. */
 int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
                  uint32_t record_size, uint32_t* d_rc, void* stream);
 
-/* Batched form: the work of n gx_run_batch calls in one persistent launch.
- * The results are those of the n calls made in order. */
+/* Batched form: the work of n gx_run_batch calls in one persistent launch
+ * (persistent workers claiming work units, as the paper's device scheduler
+ * policies use them, section 5.3).  The results are those of the n calls
+ * made in order. */
 typedef struct gx_batch {
   int32_t prog_fd;
   uint32_t record_size;

@@ -1,7 +1,7 @@
 // Compilation of verified programs to native gfx950 code.
 //
 // The paper lowers verified bytecode through LLVM to the GPU's own ISA and
-// inlines the helpers and map accesses (section 5.1, section 4.4
+// inlines the helpers and map accesses (sections 5.1 and 5.3, section 4.4
 // "Warp-level Execution Optimizations").  Here the pre-decoded micro-ops of
 // a verified program are written out as HIP source, one statement per
 // instruction with a label at every jump target, and compiled at load time
