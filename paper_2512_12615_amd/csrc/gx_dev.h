@@ -918,13 +918,19 @@ __device__ __forceinline__ Ctx wave_context(const Ctx& c, bool live) {
 // One tile of an event-parallel run: every lane runs its record, or, for the
 // warp-leader hook, lane 0 runs the tile's aggregate and every record of the
 // tile receives its return code.
+// (One call of R.run: the interpreter's body is large, and a second inlined
+// copy of it would crowd the instruction cache.)
 template <class Run>
 __device__ __forceinline__ uint32_t tile_run(Run& R, const RunArgs& A, bool live, const Ctx& c, const Stk& stk,
                                              uint64_t& steps) {
-  if (!A.leader) return R.run(A, live, c.c0, c.c1, c.c2, stk, steps);
-  const Ctx w = wave_context(c, live);
-  const uint32_t rc = R.run(A, lane_id() == 0 && live, w.c0, w.c1, w.c2, stk, steps);
-  return __builtin_amdgcn_readlane(rc, 0);
+  Ctx w = c;
+  bool go = live;
+  if (A.leader) {
+    w = wave_context(c, live);
+    go = lane_id() == 0 && live;
+  }
+  const uint32_t rc = R.run(A, go, w.c0, w.c1, w.c2, stk, steps);
+  return A.leader ? __builtin_amdgcn_readlane(rc, 0) : rc;
 }
 
 template <class Run>
