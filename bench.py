@@ -240,6 +240,9 @@ def bench_batched(G, W, rt, reps):
 
     res = {}
     rcs = {}
+    # the batched form's autotuner picks the persistent launch's waves per CU
+    reset()
+    tune = rt.autotune_batches([(prog, ev, n, 24, rc) for prog, _, ev, n, rc in runs], stream=stream)
     for name, fn in (("plain", plain), ("batched", batched)):
         ts = []
         for r in range(reps + 1):
@@ -260,6 +263,7 @@ def bench_batched(G, W, rt, reps):
         "batched_events_per_s": res["batched"],
         "speedup": res["batched"] / res["plain"],
         "same_rc": same,
+        "waves_per_cu": tune["waves_per_cu"],
     }
 
 

@@ -229,6 +229,14 @@ typedef struct gx_batch {
 } gx_batch;
 int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream);
 
+/* Autotuner of the batched form (the persistent launch's waves per compute
+ * unit, 2-32): times gx_run_batches over ``descs`` with each candidate, maps
+ * saved and restored as gx_autotune does, and keeps the fastest (the default
+ * unless a candidate is at least 3 % faster) for later batched launches of
+ * this runtime.  *out: blocks = the chosen waves per CU, trials, best_ms,
+ * default_ms.  Synchronous.  Errors as gx_run_batches, -ENOMEM. */
+int gx_autotune_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream, gx_tune* out);
+
 /* A batch captured into a HIP graph (the batched form's launches, replayed
  * without host work).  gx_graph_create runs the batch once to size a
  * workspace of the graph's own (the maps it touches are saved first and put

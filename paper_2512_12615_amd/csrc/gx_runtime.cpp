@@ -225,6 +225,7 @@ struct gx_rt {
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
   uint32_t epoch = 0;  // launch counter for hash tombstone reuse
+  uint32_t batch_per_cu = 0;  // waves per CU of the batched interpreter launch (gx_autotune_batches; 0: default)
   // measurement: event pairs bracketing VM kernels
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending, prof_free;
@@ -1500,7 +1501,8 @@ int run_phase(gx_rt* rt, const gx_batch* d, uint32_t n, hipStream_t s) {
                    spill_at[b] != UINT64_MAX ? X.d_spill + spill_at[b] : nullptr, side());
   }
   if (e == hipSuccess && !items.empty()) {
-    uint32_t per_cu = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
+    uint32_t per_cu = rt->batch_per_cu ? rt->batch_per_cu
+                                       : (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
     uint32_t waves = (uint32_t)std::min<size_t>(items.size(), 256 * per_cu);
     e = launch_batched((const BatchDev*)(d_tables + ob), (const uint2*)(d_tables + oi), (uint32_t)items.size(),
                        X.d_next, waves, stack_max, s);
@@ -1567,6 +1569,72 @@ int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
   if (r) return r;
   DevGuard g(rt->dev);
   return run_batches_impl(rt, descs, n, (hipStream_t)stream);
+}
+
+int gx_autotune_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream, gx_tune* out) {
+  int r = check_batches(rt, descs, n);
+  if (r) return r;
+  if (!n) return -EINVAL;
+  DevGuard g(rt->dev);
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t def = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
+  std::vector<uint32_t> cand{def};
+  for (uint32_t w : {2u, 4u, 8u, 16u, 32u})
+    if (w != def) cand.push_back(w);
+  std::vector<int> fds;
+  for (uint32_t i = 0; i < n; i++)
+    for (int fd : get_prog(rt, descs[i].prog_fd)->fds) fds.push_back(fd);
+  if (wait_all(rt)) return -EIO;
+  MapSnapshot snap;
+  if (snap.take(rt, fds, s)) return -ENOMEM;
+  const bool prof = rt->profile;
+  const gx_stats st = rt->stats;
+  const uint32_t saved = rt->batch_per_cu;
+  rt->profile = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = -ENOMEM;
+  double best = 1e300, def_ms = 0;
+  uint32_t bestw = def;
+  if (!r) {  // one untimed run first
+    snap.restore(s);
+    rt->batch_per_cu = def;
+    r = run_batches_impl(rt, descs, n, s);
+  }
+  for (size_t c = 0; c < cand.size() && !r; c++) {
+    snap.restore(s);
+    rt->batch_per_cu = cand[c];
+    (void)hipEventRecord(e0, s);
+    r = run_batches_impl(rt, descs, n, s);
+    (void)hipEventRecord(e1, s);
+    if (r) break;
+    float ms = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      r = -EIO;
+      break;
+    }
+    if (c == 0) def_ms = ms;
+    if (c == 0 ? ms < best : ms < best && ms < 0.97 * def_ms) {
+      best = ms;
+      bestw = cand[c];
+    }
+  }
+  snap.restore(s);
+  (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  rt->profile = prof;
+  rt->stats = st;
+  rt->batch_per_cu = r ? saved : bestw;
+  if (r) return r;
+  if (out) {
+    out->lanes = 0;
+    out->qbits = 0;
+    out->blocks = bestw;
+    out->trials = (uint32_t)cand.size();
+    out->best_ms = best;
+    out->default_ms = def_ms;
+  }
+  return 0;
 }
 
 struct gx_graph {

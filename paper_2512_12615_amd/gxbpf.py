@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
-           "gx_run_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
+           "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
@@ -101,6 +101,7 @@ def lib():
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_graph_create.argtypes = [vp, C.POINTER(Batch), u32, C.POINTER(vp)]
+    L.gx_autotune_batches.argtypes = [vp, C.POINTER(Batch), u32, vp, C.POINTER(Tune)]
     L.gx_drain_ringbuf_view.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(u64), C.POINTER(u64)]
     L.gx_drain_ringbuf_view.restype = C.c_int64
     L.gx_graph_launch.argtypes = [vp, vp]
@@ -328,6 +329,14 @@ class Runtime:
     def run_batches(self, descs, stream=None):
         """descs: list of (prog_fd, events tensor, n_events, record_size, rc tensor or None)."""
         _check(lib().gx_run_batches(self._h, _batch_array(descs), len(descs), _stream_handle(stream)), "gx_run_batches")
+
+    def autotune_batches(self, descs, stream=None) -> dict:
+        """Choose the batched launch's waves per CU by timing ``descs`` (map
+        contents restored afterwards)."""
+        t = Tune()
+        _check(lib().gx_autotune_batches(self._h, _batch_array(descs), len(descs), _stream_handle(stream),
+                                         C.byref(t)), "gx_autotune_batches")
+        return {"waves_per_cu": t.blocks, "trials": t.trials, "best_ms": t.best_ms, "default_ms": t.default_ms}
 
     def graph_create(self, descs) -> "Graph":
         """Capture a batch (descs as for run_batches) into a replayable graph."""

@@ -74,3 +74,35 @@ def test_autotune_event_parallel_compiled(rt):
     torch.cuda.synchronize()
     g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
     assert_same(g, oracle_run(pol, ev), "access_counter tuned")
+
+
+def test_autotune_batches_leaves_no_trace(rt):
+    """The batched form's tuner times the batch with each waves-per-CU
+    candidate; the maps are as before it, and the next batched run (with the
+    choice) matches the oracle."""
+    import torch
+    print("autotune batches", flush=True)
+    progs, sizes = W.batched_workload(12, seed=77, min_log2=8, max_log2=13)
+    runs = [(p, W.gen_mem_uniform(int(n), 700 + i)) for i, (p, n) in enumerate(zip(progs, sizes))]
+    runs.append((W.access_counter_policy(), W.gen_mem_uniform(9000, 71)))
+    descs, keep = [], []
+    for pol, ev in runs:
+        fds, prog = setup(rt, pol)
+        rc = torch.zeros(len(ev), dtype=torch.int32, device="cuda")
+        descs.append((prog, to_device(ev), len(ev), pol.record_size, rc))
+        keep.append((pol, ev, fds, rc))
+    before = [[rt.map_dump(fd) if m.type != W.MAP_RINGBUF else None for fd, m in zip(fds, pol.maps)]
+              for pol, ev, fds, rc in keep]
+    t = rt.autotune_batches(descs)
+    assert t["waves_per_cu"] in (2, 4, 8, 16, 32) and t["trials"] == 5 and t["best_ms"] > 0
+    after = [[rt.map_dump(fd) if m.type != W.MAP_RINGBUF else None for fd, m in zip(fds, pol.maps)]
+             for pol, ev, fds, rc in keep]
+    for b, a in zip(before, after):
+        for x, y in zip(b, a):
+            if x is not None:
+                assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    rt.run_batches(descs)
+    torch.cuda.synchronize()
+    for pol, ev, fds, rc in keep:
+        g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
+        assert_same(g, oracle_run(pol, ev), pol.name)
