@@ -890,29 +890,45 @@ __device__ __forceinline__ Ctx load_record(const RunArgs& A, uint64_t i) {
   return c;
 }
 
+// One row-level DPP step of a wave-wide 64-bit min and max: every lane whose
+// source lane (row shift, or row broadcast into the rows ROWS enables) exists
+// combines that lane's values with its own; the others keep their own.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const int l = (int)(uint32_t)v, h = (int)(uint32_t)(v >> 32);
+  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(l, l, CTRL, ROWS, 0xf, false);
+  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(h, h, CTRL, ROWS, 0xf, false);
+  return ((uint64_t)h2 << 32) | l2;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void minmax_step(uint64_t& lo, uint64_t& hi) {
+  const uint64_t a = dpp_u64<CTRL, ROWS>(lo), b = dpp_u64<CTRL, ROWS>(hi);
+  lo = a < lo ? a : lo;
+  hi = b > hi ? b : hi;
+}
+
 // One wave-tile of an event-parallel run: lane l runs event first + l.
 // Warp-leader hook (section 4.4's warp-level execution): the context of one
 // invocation for the wave's tile of memory-access records, from every
-// lane's record - the smallest and largest address (butterfly exchanges
-// over the 64 lanes), the number of records, the stream of the tile's first
-// record (lane 0's) - identical in every lane.
+// lane's record - the smallest and largest address, the number of records,
+// the stream of the tile's first record (lane 0's) - identical in every
+// lane.  The extremes take four row shifts (1, 2, 4, 8 lanes: the last lane
+// of each 16-lane row then holds its row's) and two row broadcasts (row 0
+// into row 1, row 1 into rows 2 and 3: lane 63 then holds the wave's), all
+// in the vector ALU, and one read of lane 63.
 __device__ __forceinline__ Ctx wave_context(const Ctx& c, bool live) {
   uint64_t lo = live ? c.c0 : ~0ull, hi = live ? c.c0 : 0;
-  auto xchg = [](uint64_t v, uint32_t off) {  // v of lane (this lane ^ off)
-    const int a = (int)((lane_id() ^ off) << 2);
-    const uint32_t l = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
-    const uint32_t h = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)(v >> 32));
-    return ((uint64_t)h << 32) | l;
-  };
-#pragma unroll
-  for (uint32_t off = 32; off >= 1; off >>= 1) {
-    const uint64_t l2 = xchg(lo, off), h2 = xchg(hi, off);
-    lo = l2 < lo ? l2 : lo;
-    hi = h2 > hi ? h2 : hi;
-  }
+  minmax_step<0x111, 0xf>(lo, hi);  // row_shr:1
+  minmax_step<0x112, 0xf>(lo, hi);  // row_shr:2
+  minmax_step<0x114, 0xf>(lo, hi);  // row_shr:4
+  minmax_step<0x118, 0xf>(lo, hi);  // row_shr:8
+  minmax_step<0x142, 0xa>(lo, hi);  // row_bcast:15 into rows 1 and 3
+  minmax_step<0x143, 0xc>(lo, hi);  // row_bcast:31 into rows 2 and 3
+  const uint64_t wlo = ((uint64_t)rdlane((uint32_t)(lo >> 32), 63) << 32) | rdlane((uint32_t)lo, 63);
+  const uint64_t whi = ((uint64_t)rdlane((uint32_t)(hi >> 32), 63) << 32) | rdlane((uint32_t)hi, 63);
   const uint32_t n = popc64(ballot(live));
   const uint32_t s0 = __builtin_amdgcn_readlane((uint32_t)c.c1, 0);
-  return Ctx{lo, hi, (uint64_t)n | ((uint64_t)s0 << 32)};
+  return Ctx{wlo, whi, (uint64_t)n | ((uint64_t)s0 << 32)};
 }
 
 // One tile of an event-parallel run: every lane runs its record, or, for the
@@ -943,28 +959,22 @@ __device__ __forceinline__ void event_tile(Run& R, const RunArgs& A, uint64_t fi
   if (live && A.rc) A.rc[i] = rc;
 }
 
-// A wave's share of an event-parallel run: tiles t0, t0 + tstep, ... with
-// the next tile's records loaded while the current one runs.
+// A wave's share of an event-parallel run: tiles t0, t0 + tstep, ...
+// (Loading the next tile's records, or a group of tiles, ahead of the
+// current one measured slower: the many resident waves already keep the
+// loads in flight, and the extra live registers cost more than they hid.)
 template <class Run>
 __device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0, uint64_t tstep, const Stk& stk) {
   uint64_t steps = 0;
   const uint64_t tiles = (A.n_events + 63) / 64;
   const uint32_t l = lane_id();
-  uint64_t t = t0, i = t0 * 64 + l;
-  bool live = t < tiles && i < A.n_events;
-  Ctx c{0, 0, 0};
-  if (live) c = load_record(A, i);
-  while (t < tiles) {
-    const uint64_t tn = t + tstep, in = tn * 64 + l;
-    const bool ln = tn < tiles && in < A.n_events;
-    Ctx cn{0, 0, 0};
-    if (ln) cn = load_record(A, in);
+  for (uint64_t t = t0; t < tiles; t += tstep) {
+    const uint64_t i = t * 64 + l;
+    const bool live = i < A.n_events;
+    Ctx c{0, 0, 0};
+    if (live) c = load_record(A, i);
     const uint32_t rc = tile_run(R, A, live, c, stk, steps);
     if (live && A.rc) A.rc[i] = rc;
-    t = tn;
-    i = in;
-    live = ln;
-    c = cn;
   }
 }
 
