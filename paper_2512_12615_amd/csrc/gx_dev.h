@@ -1059,67 +1059,59 @@ __device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q
 }
 
 // One queue of a stream-sequential run, by lane 0 of the wave with
-// wave-uniform values (compiled programs, one queue per wave).  The queue
-// bounds, queue-ordered records and event indices are constant for the
-// launch (the partition wrote them before it), so they are read with scalar
-// loads, which do not wait behind the wave's outstanding vector accesses;
-// the next block of records is fetched while this one runs.
-constexpr uint32_t kUniBlock = 4;  // records held in scalar registers
+// wave-uniform values (compiled programs, one queue per wave; the kernels
+// that call this have one wave per block).  The other 63 lanes fetch the
+// queue's records: each lane loads one record of the next block of 64 with
+// vector loads while lane 0 runs the current block, and at the start of a
+// block the wave copies the block it loaded into LDS, from where lane 0
+// reads each event's record.  The wait for a block's records thus comes
+// once per 64 events, long after they were requested.  (Holding records in
+// scalar registers, the earlier design, ran out of scalar registers: the
+// compiler spilled them as soon as they arrived, which made every record
+// fetch a full memory round trip on the event chain.)  Return codes are
+// gathered in LDS and stored by the whole wave after each block.
+struct UniStage {
+  uint64_t c0[64], c1[64], c2[64];
+  uint32_t idx[64], rc[64];
+};
 
 template <class Run>
 __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q, uint32_t qstride,
                                            uint32_t qend_last, const Stk& stk, uint64_t& steps) {
   typedef const __attribute__((address_space(4))) uint32_t cu32;
-  typedef const __attribute__((address_space(4))) uint64_t cu64;
-  constexpr uint32_t B = kUniBlock;
-  if (lane_id() != 0 || q >= A.n_queues) return;
+  __shared__ __attribute__((aligned(16))) UniStage st;
+  if (q >= A.n_queues) return;
   const uint32_t beg = ((const cu32*)A.qstart)[(uint64_t)q * qstride];
   const uint32_t end = q + 1 < A.n_queues ? ((const cu32*)A.qstart)[(uint64_t)(q + 1) * qstride] : qend_last;
   const bool wide = A.record_size > 16;
-  auto fetch = [&](uint32_t k, Ctx& c, uint32_t& idx) {
-    const cu64* p = (const cu64*)(A.sorted + (uint64_t)k * kSortedStride);
-    c.c0 = p[0];
-    c.c1 = p[1];
-    c.c2 = wide ? p[2] : 0;
-    idx = ((const cu32*)A.order)[k];
+  const uint32_t l = lane_id();
+  Ctx nc{0, 0, 0};
+  uint32_t ni = 0;
+  auto fetch = [&](uint64_t k0) {  // lane l: record k0 + l
+    const uint64_t k = k0 + l;
+    if (k < end) {
+      const GX_GLOBAL uint64_t* p = (const GX_GLOBAL uint64_t*)(A.sorted + (uint64_t)k * kSortedStride);
+      nc.c0 = p[0];
+      nc.c1 = p[1];
+      nc.c2 = wide ? p[2] : 0;
+      ni = ((const GX_GLOBAL uint32_t*)A.order)[k];
+    }
   };
-  Ctx nx[B];
-  uint32_t ni[B];
-#pragma unroll
-  for (uint32_t j = 0; j < B; j++) {
-    nx[j] = Ctx{0, 0, 0};
-    ni[j] = 0;
-    if (beg + j < end) fetch(beg + j, nx[j], ni[j]);
-  }
-  for (uint32_t k0 = beg; k0 < end; k0 += B) {
-    Ctx cu[B];
-    uint32_t si[B], crc[B];
-#pragma unroll
-    for (uint32_t j = 0; j < B; j++) {
-      cu[j] = nx[j];
-      si[j] = ni[j];
-      crc[j] = 0;
+  fetch(beg);
+  for (uint64_t k0 = beg; k0 < end; k0 += 64) {
+    st.c0[l] = nc.c0;
+    st.c1[l] = nc.c1;
+    st.c2[l] = nc.c2;
+    st.idx[l] = ni;
+    fetch(k0 + 64);
+    const uint32_t n = end - k0 < 64 ? (uint32_t)(end - k0) : 64u;
+    if (l == 0) {
+      for (uint32_t j = 0; j < n; j++)
+        st.rc[j] = (uint32_t)uni<true>(R.run(A, true, st.c0[j], st.c1[j], st.c2[j], stk, steps));
     }
-#pragma unroll
-    for (uint32_t j = 0; j < B; j++)
-      if (k0 + B + j < end) fetch(k0 + B + j, nx[j], ni[j]);
-    const uint32_t n = end - k0 < B ? end - k0 : B;
-    for (uint32_t j = 0; j < B; j++) {
-      const Ctx c = cu[0];
-#pragma unroll
-      for (uint32_t x = 0; x + 1 < B; x++) cu[x] = cu[x + 1];
-      uint32_t rc = 0;
-      if (j < n) rc = (uint32_t)uni<true>(R.run(A, true, c.c0, c.c1, c.c2, stk, steps));
-#pragma unroll
-      for (uint32_t x = 0; x + 1 < B; x++) crc[x] = crc[x + 1];
-      crc[B - 1] = rc;
-    }
-    if (A.rc) {
-#pragma unroll
-      for (uint32_t j = 0; j < B; j++)
-        if (j < n) A.rc[si[j]] = crc[j];
-    }
-    if (steps > A.step_limit) break;
+    if (A.rc && l < n) A.rc[st.idx[l]] = st.rc[l];
+    const uint64_t s0 = ((uint64_t)rdlane((uint32_t)(steps >> 32), 0) << 32) | rdlane((uint32_t)steps, 0);
+    if (s0 > A.step_limit) break;
   }
 }
 

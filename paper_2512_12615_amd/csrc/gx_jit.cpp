@@ -151,6 +151,8 @@ struct Windows {
   std::vector<int> site;     // window of each lookup site, by slot (-1 none)
   std::vector<int> acc;      // window of each map access, by slot (-1 none)
   std::vector<int32_t> off;  // its byte offset in the value
+  std::vector<char> memo;    // per window: its key, pointer and words kept across events
+  std::vector<uint64_t> inval;  // per slot: memo windows a slot's write may make stale
 };
 
 Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
@@ -340,6 +342,47 @@ Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
   return R;
 }
 
+// Lookup memos: a hash lookup site whose window belongs to a map of keys of
+// at most 8 bytes keeps, across the events of a run, the last key it found,
+// the value's address and the window's words.  When the next event looks up
+// the same key, the probe and the window load are skipped.  This holds for
+// the same reason as the windows themselves: a key's values are written by
+// the one lane that owns the key (its stream's events run in order on that
+// lane), a live slot never moves (deletes leave tombstones), and every write
+// of this program that may reach the value without going through the window
+// - a store or atomic through another pointer, an update or delete of the
+// map - clears the memo first.
+void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R) {
+  R.memo.assign(R.win.size(), 0);
+  R.inval.assign(U.size(), 0);
+  bool any = false;
+  for (size_t w = 0; w < R.win.size(); w++) {
+    const MapDev& md = J.m[R.win[w].map].second;
+    if ((U[R.win[w].pc].w0 & 0xff) == H_LOOKUP_HASH && md.type == MAP_HASH && md.key_size <= 8 && md.sstride == 16)
+      R.memo[w] = any = 1;
+  }
+  if (!any) return;
+  for (uint32_t pc = 0; pc < U.size(); pc++) {
+    const uint32_t h = U[pc].w0 & 0xff;
+    if (h == H_LDIMM) {
+      pc++;
+      continue;
+    }
+    int k;  // map whose values the slot may write (-1: any)
+    if (h == H_ST_MAP || h == H_STX_MAP || h == H_ATOMIC_MAP)
+      k = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+    else if (h == H_UPDATE_ARRAY || h == H_UPDATE_HASH || h == H_DELETE_HASH)
+      k = J.index(U[pc].imm);
+    else
+      continue;
+    for (size_t w = 0; w < R.win.size(); w++) {
+      if (!R.memo[w] || (k >= 0 && R.win[w].map != k)) continue;
+      if ((h == H_ST_MAP || h == H_STX_MAP) && R.acc[pc] == (int)w) continue;  // through the window
+      R.inval[pc] |= 1ull << w;
+    }
+  }
+}
+
 std::string map_name(const JMaps& J, uint64_t desc) {
   int k = J.index(desc);
   return k >= 0 ? "&M" + std::to_string(k) : "(const MapDev*)" + lit(desc);
@@ -396,6 +439,10 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
     o += " }\n";
   };
   const std::string sa32 = "(int32_t)" + xa, sb32 = "(int32_t)" + xb;
+  // a write that may reach a memo's value other than through its window
+  if (pc < Wn.inval.size() && Wn.inval[pc])
+    for (size_t w = 0; w < Wn.win.size(); w++)
+      if ((Wn.inval[pc] >> w) & 1) o += "  mv" + std::to_string(w) + " = false;\n";
   switch (h) {
     case H_ADD64: set(D + " + " + B); break;
     case H_SUB64: set(D + " - " + B); break;
@@ -558,10 +605,23 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
       o += "  r0 = uni<UNI>(array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk));\n";
       window_load();
       break;
-    case H_LOOKUP_HASH:
-      o += "  r0 = uni<UNI>(hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));\n";
-      window_load();
+    case H_LOOKUP_HASH: {
+      const int w = pc < Wn.site.size() ? Wn.site[pc] : -1;
+      const std::string call = "r0 = uni<UNI>(hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));";
+      if (w >= 0 && Wn.memo[w]) {
+        const std::string W = std::to_string(w);
+        const int km = J.index(u.imm);
+        o += "  { const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) + ", r2, 0, " +
+             std::to_string(J.m[km].second.key_size) + "u, stk));\n";
+        o += "    if (mv" + W + " && mk == mk" + W + ") {\n      r0 = mp" + W + ";\n    } else {\n    " + call + "\n  ";
+        window_load();
+        o += "    mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n    }\n  }\n";
+      } else {
+        o += "  " + call + "\n";
+        window_load();
+      }
       break;
+    }
     case H_UPDATE_ARRAY:
       o += "  r0 = uni<UNI>((uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
            std::to_string((a8 >> 1) & 1) + ", r3, r4, stk));\n";
@@ -664,6 +724,15 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   // the maps' descriptors, read from the map table once per run (they stay
   // in scalar registers instead of being reloaded for every event)
   for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
+  Windows Wn = plan_windows(U, J);
+  plan_memo(U, J, Wn);
+  // lookup memos: last key found, its value's address, the window's words
+  for (size_t w = 0; w < Wn.win.size(); w++) {
+    if (!Wn.memo[w]) continue;
+    const std::string W = std::to_string(w);
+    o += "  uint64_t mk" + W + " = 0, mp" + W + " = 0;\n  bool mv" + W + " = false;\n";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++) o += "  uint64_t w" + W + "_" + std::to_string(j) + " = 0;\n";
+  }
   o += "\n";
   // begin / end: open and close the wave's and the block's ring chunks and
   // the block's accumulators (wave 0 sets up the block's part; the barrier
@@ -734,9 +803,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   for (size_t k = 0; k < maps.size(); k++)
     o += "  const MapDev& M" + std::to_string(k) + " = m" + std::to_string(k) + ";\n";
   o += "  (void)r1; (void)r3; (void)r4; (void)r5; (void)r6; (void)r7; (void)r8; (void)r9; (void)r10;\n";
-  const Windows Wn = plan_windows(U, J);
   for (size_t w = 0; w < Wn.win.size(); w++)
-    for (uint32_t j = 0; j < Wn.win[w].words; j++) {
+    for (uint32_t j = 0; j < Wn.win[w].words && !Wn.memo[w]; j++) {
       const std::string nm = "w" + std::to_string(w) + "_" + std::to_string(j);
       o += "  uint64_t " + nm + " = 0; (void)" + nm + ";\n";
     }
