@@ -1109,6 +1109,7 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
       for (uint32_t j = 0; j < n; j++)
         st.rc[j] = (uint32_t)uni<true>(R.run(A, true, st.c0[j], st.c1[j], st.c2[j], stk, steps));
     }
+    R.uniformize();  // state lane 0 carries from event to event, back to wave-uniform
     if (A.rc && l < n) A.rc[st.idx[l]] = st.rc[l];
     const uint64_t s0 = ((uint64_t)rdlane((uint32_t)(steps >> 32), 0) << 32) | rdlane((uint32_t)steps, 0);
     if (s0 > A.step_limit) break;

@@ -794,6 +794,20 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "    }\n";
   }
   o += "  }\n\n";
+  // after lane 0 ran a block of events with the other lanes idle: its memo
+  // state, read from lane 0, so that the compiler keeps it wave-uniform
+  o += "  __device__ __forceinline__ void uniformize() {\n";
+  for (size_t w = 0; w < Wn.win.size(); w++) {
+    if (!Wn.memo[w]) continue;
+    const std::string W = std::to_string(w);
+    o += "    mk" + W + " = rfl64(mk" + W + ");\n    mp" + W + " = rfl64(mp" + W + ");\n    mv" + W +
+         " = __builtin_amdgcn_readfirstlane((int)mv" + W + ") != 0;\n";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++) {
+      const std::string nm = "w" + W + "_" + std::to_string(j);
+      o += "    " + nm + " = rfl64(" + nm + ");\n";
+    }
+  }
+  o += "  }\n\n";
   o += "  __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2, "
        "const Stk stk, uint64_t& steps) {\n";
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
