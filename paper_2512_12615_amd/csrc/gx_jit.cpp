@@ -61,6 +61,7 @@ constexpr uint64_t kLdsMax = 150 << 10;
 constexpr uint64_t kCacheMax = 80 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
+constexpr uint32_t kMemoEntries = 64;      // LDS lookup-memo entries per site (one queue per wave)
 
 // Cap on each cache in KiB from the environment (tuning experiments).
 int env_int_jit(const char* name, int dflt) {
@@ -351,10 +352,16 @@ Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
 // lane), a live slot never moves (deletes leave tombstones), and every write
 // of this program that may reach the value without going through the window
 // - a store or atomic through another pointer, an update or delete of the
-// map - clears the memo first.
-void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R) {
+// map - clears the memo first.  With one queue per wave (lane 0 runs it)
+// the memo is a table of kMemoEntries entries in LDS, indexed by the key's
+// two 32-bit halves xor-ed: {key, value address, generation, window
+// words}; an entry counts only while its generation is the site's current
+// one, so clearing the memo is one increment.  With several queues per wave
+// each lane keeps one entry in registers.
+void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R, bool event_parallel) {
   R.memo.assign(R.win.size(), 0);
   R.inval.assign(U.size(), 0);
+  if (event_parallel) return;  // lanes run different streams' events in turn
   bool any = false;
   for (size_t w = 0; w < R.win.size(); w++) {
     const MapDev& md = J.m[R.win[w].map].second;
@@ -442,7 +449,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
   // a write that may reach a memo's value other than through its window
   if (pc < Wn.inval.size() && Wn.inval[pc])
     for (size_t w = 0; w < Wn.win.size(); w++)
-      if ((Wn.inval[pc] >> w) & 1) o += "  mv" + std::to_string(w) + " = false;\n";
+      if ((Wn.inval[pc] >> w) & 1) o += "  mv" + std::to_string(w) + " = false; gen" + std::to_string(w) + "++;\n";
   switch (h) {
     case H_ADD64: set(D + " + " + B); break;
     case H_SUB64: set(D + " - " + B); break;
@@ -557,6 +564,10 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         body += sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
                         : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + wsh +
                               ")) | ((uint64_t)" + val + " << " + wsh + ");";
+      if (wa >= 0 && Wn.memo[wa])  // the memo entry follows the window
+        body += " if (UNI) g_memo" + std::to_string(wa) + "[cur" + std::to_string(wa) + " * " +
+                std::to_string(3 + Wn.win[wa].words) + "u + " + std::to_string(3 + Wn.off[pc] / 8) + "u] = " + wword +
+                ";";
       guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, body);
       break;
     }
@@ -611,11 +622,27 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
       if (w >= 0 && Wn.memo[w]) {
         const std::string W = std::to_string(w);
         const int km = J.index(u.imm);
+        const uint32_t nw = Wn.win[w].words;
+        const std::string S = std::to_string(3 + nw);
         o += "  { const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) + ", r2, 0, " +
              std::to_string(J.m[km].second.key_size) + "u, stk));\n";
+        // one queue per wave: the LDS table
+        o += "    if (UNI) {\n      const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " +
+             std::to_string(kMemoEntries - 1) + "u;\n      uint64_t* ent = &g_memo" + W + "[me * " + S +
+             "u];\n      cur" + W + " = me;\n";
+        o += "      if (uni<UNI>(ent[2]) == gen" + W + " && uni<UNI>(ent[0]) == mk) {\n        r0 = uni<UNI>(ent[1]);";
+        for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+          o += " w" + W + "_" + std::to_string(j) + " = uni<UNI>(ent[" + std::to_string(3 + j) + "]);";
+        o += "\n      } else {\n      " + call + "\n    ";
+        window_load();
+        o += "        ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
+        for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+          o += " ent[" + std::to_string(3 + j) + "] = w" + W + "_" + std::to_string(j) + ";";
+        o += "\n      }\n    } else {\n";
+        // several queues per wave: one entry per lane, in registers
         o += "    if (mv" + W + " && mk == mk" + W + ") {\n      r0 = mp" + W + ";\n    } else {\n    " + call + "\n  ";
         window_load();
-        o += "    mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n    }\n  }\n";
+        o += "    mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n    }\n    }\n  }\n";
       } else {
         o += "  " + call + "\n";
         window_load();
@@ -716,6 +743,12 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       o += "__shared__ __attribute__((aligned(16))) uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + a.slot_type() +
            " g_val" + K + "[" + N + "];\n";
   }
+  Windows Wn = plan_windows(U, J);
+  plan_memo(U, J, Wn, P.event_parallel);
+  for (size_t w = 0; w < Wn.win.size(); w++)
+    if (Wn.memo[w])
+      o += "__shared__ __attribute__((aligned(16))) uint64_t g_memo" + std::to_string(w) + "[" +
+           std::to_string(kMemoEntries * (3 + Wn.win[w].words)) + "];\n";
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
   // UNI: run by one lane with wave-uniform values (one queue per wave)
   o += "\ntemplate <bool PRIV, bool UNI = false>\nstruct Prog {\n  uint32_t wave;  // wave index in the block: selects its ring chunks\n"
@@ -724,13 +757,13 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   // the maps' descriptors, read from the map table once per run (they stay
   // in scalar registers instead of being reloaded for every event)
   for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
-  Windows Wn = plan_windows(U, J);
-  plan_memo(U, J, Wn);
-  // lookup memos: last key found, its value's address, the window's words
+  // lookup memos: last key found, its value's address, the window's words;
+  // with one queue per wave, the LDS table's generation and current entry
   for (size_t w = 0; w < Wn.win.size(); w++) {
     if (!Wn.memo[w]) continue;
     const std::string W = std::to_string(w);
-    o += "  uint64_t mk" + W + " = 0, mp" + W + " = 0;\n  bool mv" + W + " = false;\n";
+    o += "  uint64_t mk" + W + " = 0, mp" + W + " = 0, gen" + W + " = 1;\n  bool mv" + W + " = false;\n  uint32_t cur" +
+         W + " = 0;\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) o += "  uint64_t w" + W + "_" + std::to_string(j) + " = 0;\n";
   }
   o += "\n";
@@ -749,6 +782,10 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "    ring_chunk_init(wave * GX_NRINGS + " + std::to_string(r) + "u);\n    if (wave == 0) ring_block_init(" +
          std::to_string(r) + "u);\n";
   if (J.n_rings) o += "    __syncthreads();\n";
+  for (size_t w = 0; w < Wn.win.size(); w++)
+    if (Wn.memo[w])
+      o += "    if (UNI) g_memo" + std::to_string(w) + "[lane_id() * " + std::to_string(3 + Wn.win[w].words) +
+           "u + 2u] = 0;  // no entry is current\n";
   if (any_acc) {
     o += "    if (PRIV) {\n";
     for (size_t k = 0; k < maps.size(); k++) {
@@ -800,8 +837,9 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   for (size_t w = 0; w < Wn.win.size(); w++) {
     if (!Wn.memo[w]) continue;
     const std::string W = std::to_string(w);
-    o += "    mk" + W + " = rfl64(mk" + W + ");\n    mp" + W + " = rfl64(mp" + W + ");\n    mv" + W +
-         " = __builtin_amdgcn_readfirstlane((int)mv" + W + ") != 0;\n";
+    o += "    mk" + W + " = rfl64(mk" + W + ");\n    mp" + W + " = rfl64(mp" + W + ");\n    gen" + W + " = rfl64(gen" +
+         W + ");\n    mv" + W + " = __builtin_amdgcn_readfirstlane((int)mv" + W + ") != 0;\n    cur" + W +
+         " = __builtin_amdgcn_readfirstlane(cur" + W + ");\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) {
       const std::string nm = "w" + W + "_" + std::to_string(j);
       o += "    " + nm + " = rfl64(" + nm + ");\n";

@@ -39,7 +39,9 @@ def test_generated_programs_compile(G, i):
 def test_source_structure(G):
     pol = W.stride_prefetch_policy()
     src = G.jit_source(pol.code, pol.hook, _shapes(pol))
-    assert src.count("hash_lookup(") == 1 and src.count("hash_update(") == 1
+    # the lookup is emitted twice: through the LDS memo table (one queue per
+    # wave) and through the per-lane register memo (several queues per wave)
+    assert src.count("hash_lookup(") == 2 and src.count("hash_update(") == 1
     assert src.count("ring_output_chunked(") == 1
     labels = set(re.findall(r"^L(\d+):;", src, re.M))
     gotos = set(re.findall(r"goto L(\d+);", src))
@@ -111,7 +113,7 @@ def test_map_value_windows(G):
     import jit_window_programs as P
     pol = W.stride_prefetch_policy()
     src = G.jit_source(pol.code, pol.hook, _shapes(pol))
-    assert src.count("if (r0) { w0_0 = ") == 1
+    assert src.count("if (r0) { w0_0 = ") == 2  # both memo forms
     # no value load through a pointer is left: every LDX reads the window
     assert "r1 = uni<UNI>((uint64_t)(*(const GX_GLOBAL" not in src
     assert src.count("(w0_0 >> 0)") == 1 and src.count("(w0_1 >> 0)") == 1 and src.count("(w0_2 >> 0)") == 1
@@ -127,3 +129,31 @@ def test_map_value_windows(G):
         if name in ("atomic", "update"):
             i = next(k for k, l in enumerate(lines) if "atomic_global(" in l or "array_update(" in l)
             assert all(" >> " not in l for l in lines[i:])
+
+
+def test_lookup_memo(G):
+    """The stride policy's one lookup site keeps its key, value address and
+    window across events; the insert (an update of the map) clears every
+    memo entry, and each store through the window also writes the current
+    entry.  In the memo test program the delete and the in-place update
+    clear it too, and the second lookup site is a memo of its own."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import jit_window_programs as P
+    pol = W.stride_prefetch_policy()
+    src = G.jit_source(pol.code, pol.hook, _shapes(pol))
+    assert "__shared__ __attribute__((aligned(16))) uint64_t g_memo0[384];" in src  # 64 entries x 6 words
+    assert src.count("gen0++") == 1
+    i_gen, i_upd = src.index("gen0++"), src.index("hash_update(")
+    assert i_gen < i_upd and "hash_lookup(" not in src[i_gen:i_upd]
+    for j in range(3):
+        assert f"g_memo0[cur0 * 6u + {3 + j}u] = w0_{j};" in src
+    p = P.policy("memo")
+    s = G.jit_source(p.code, p.hook, _shapes(p), compile=True)
+    assert "g_memo0[" in s and "g_memo1[" in s
+    for call in ("hash_delete(", "hash_update("):
+        head = s[:s.index(call)]
+        assert head.rstrip().splitlines()[-1].strip().startswith("mv0 = false; gen0++;") or "gen0++" in head[-400:]
+    # an event-parallel program has no memo (its lanes take other streams' events)
+    hist = W.latency_hist_policy()
+    assert "g_memo" not in G.jit_source(hist.code, hist.hook, _shapes(hist))
