@@ -62,6 +62,7 @@ constexpr uint64_t kCacheMax = 80 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
 constexpr uint32_t kMemoEntries = 64;      // LDS lookup-memo entries per site (one queue per wave)
+constexpr uint32_t kMemoLds = 4096;        // LDS bytes of a program's memo tables (the rest keep one entry)
 
 // Cap on each cache in KiB from the environment (tuning experiments).
 int env_int_jit(const char* name, int dflt) {
@@ -153,6 +154,7 @@ struct Windows {
   std::vector<int> acc;      // window of each map access, by slot (-1 none)
   std::vector<int32_t> off;  // its byte offset in the value
   std::vector<char> memo;    // per window: its key, pointer and words kept across events
+  std::vector<char> table;   // per memo: an LDS table when one queue runs per wave
   std::vector<uint64_t> inval;  // per slot: memo windows a slot's write may make stale
 };
 
@@ -356,17 +358,28 @@ Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
 // the memo is a table of kMemoEntries entries in LDS, indexed by the key's
 // two 32-bit halves xor-ed: {key, value address, generation, window
 // words}; an entry counts only while its generation is the site's current
-// one, so clearing the memo is one increment.  With several queues per wave
-// each lane keeps one entry in registers.
-void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R, bool event_parallel) {
+// one, so clearing the memo is one increment.  Tables go to a program's
+// sites while they fit kMemoLds; with several queues per wave, and at the
+// other sites, each lane keeps one entry in registers.
+void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R, bool event_parallel, bool tables) {
   R.memo.assign(R.win.size(), 0);
+  R.table.assign(R.win.size(), 0);
   R.inval.assign(U.size(), 0);
   if (event_parallel) return;  // lanes run different streams' events in turn
   bool any = false;
+  uint32_t lds = 0;
   for (size_t w = 0; w < R.win.size(); w++) {
     const MapDev& md = J.m[R.win[w].map].second;
-    if ((U[R.win[w].pc].w0 & 0xff) == H_LOOKUP_HASH && md.type == MAP_HASH && md.key_size <= 8 && md.sstride == 16)
+    if ((U[R.win[w].pc].w0 & 0xff) == H_LOOKUP_HASH && md.type == MAP_HASH && md.key_size <= 8 && md.sstride == 16) {
       R.memo[w] = any = 1;
+      // tables while they fit the budget: LDS taken from the one-wave
+      // blocks would cost the kernel resident waves
+      const uint32_t bytes = kMemoEntries * 8 * (3 + R.win[w].words);
+      if (tables && lds + bytes <= kMemoLds) {
+        R.table[w] = 1;
+        lds += bytes;
+      }
+    }
   }
   if (!any) return;
   for (uint32_t pc = 0; pc < U.size(); pc++) {
@@ -564,7 +577,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         body += sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
                         : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + wsh +
                               ")) | ((uint64_t)" + val + " << " + wsh + ");";
-      if (wa >= 0 && Wn.memo[wa])  // the memo entry follows the window
+      if (wa >= 0 && Wn.table[wa])  // the memo entry follows the window
         body += " if (UNI) g_memo" + std::to_string(wa) + "[cur" + std::to_string(wa) + " * " +
                 std::to_string(3 + Wn.win[wa].words) + "u + " + std::to_string(3 + Wn.off[pc] / 8) + "u] = " + wword +
                 ";";
@@ -627,22 +640,25 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         o += "  { const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) + ", r2, 0, " +
              std::to_string(J.m[km].second.key_size) + "u, stk));\n";
         // one queue per wave: the LDS table
-        o += "    if (UNI) {\n      const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " +
-             std::to_string(kMemoEntries - 1) + "u;\n      uint64_t* ent = &g_memo" + W + "[me * " + S +
-             "u];\n      cur" + W + " = me;\n";
-        o += "      if (uni<UNI>(ent[2]) == gen" + W + " && uni<UNI>(ent[0]) == mk) {\n        r0 = uni<UNI>(ent[1]);";
-        for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
-          o += " w" + W + "_" + std::to_string(j) + " = uni<UNI>(ent[" + std::to_string(3 + j) + "]);";
-        o += "\n      } else {\n      " + call + "\n    ";
-        window_load();
-        o += "        ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
-        for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
-          o += " ent[" + std::to_string(3 + j) + "] = w" + W + "_" + std::to_string(j) + ";";
-        o += "\n      }\n    } else {\n";
-        // several queues per wave: one entry per lane, in registers
+        if (Wn.table[w]) {
+          o += "    if (UNI) {\n      const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " +
+               std::to_string(kMemoEntries - 1) + "u;\n      uint64_t* ent = &g_memo" + W + "[me * " + S +
+               "u];\n      cur" + W + " = me;\n";
+          o += "      if (uni<UNI>(ent[2]) == gen" + W + " && uni<UNI>(ent[0]) == mk) {\n        r0 = uni<UNI>(ent[1]);";
+          for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+            o += " w" + W + "_" + std::to_string(j) + " = uni<UNI>(ent[" + std::to_string(3 + j) + "]);";
+          o += "\n      } else {\n      " + call + "\n    ";
+          window_load();
+          o += "        ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
+          for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+            o += " ent[" + std::to_string(3 + j) + "] = w" + W + "_" + std::to_string(j) + ";";
+          o += "\n      }\n    } else {\n";
+        }
+        // several queues per wave, or no table: one entry per lane, in registers
         o += "    if (mv" + W + " && mk == mk" + W + ") {\n      r0 = mp" + W + ";\n    } else {\n    " + call + "\n  ";
         window_load();
-        o += "    mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n    }\n    }\n  }\n";
+        o += "    mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n    }\n" +
+             std::string(Wn.table[w] ? "    }\n" : "") + "  }\n";
       } else {
         o += "  " + call + "\n";
         window_load();
@@ -744,9 +760,11 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
            " g_val" + K + "[" + N + "];\n";
   }
   Windows Wn = plan_windows(U, J);
-  plan_memo(U, J, Wn, P.event_parallel);
+  // a program set's kernel would hold every member's tables at once: there
+  // each lane keeps one entry in registers
+  plan_memo(U, J, Wn, P.event_parallel, allow_acc);
   for (size_t w = 0; w < Wn.win.size(); w++)
-    if (Wn.memo[w])
+    if (Wn.table[w])
       o += "__shared__ __attribute__((aligned(16))) uint64_t g_memo" + std::to_string(w) + "[" +
            std::to_string(kMemoEntries * (3 + Wn.win[w].words)) + "];\n";
   // PRIV: the event-parallel kernel sums shared-map atomics in LDS
@@ -783,7 +801,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
          std::to_string(r) + "u);\n";
   if (J.n_rings) o += "    __syncthreads();\n";
   for (size_t w = 0; w < Wn.win.size(); w++)
-    if (Wn.memo[w])
+    if (Wn.table[w])
       o += "    if (UNI) g_memo" + std::to_string(w) + "[lane_id() * " + std::to_string(3 + Wn.win[w].words) +
            "u + 2u] = 0;  // no entry is current\n";
   if (any_acc) {

@@ -150,7 +150,9 @@ def test_lookup_memo(G):
         assert f"g_memo0[cur0 * 6u + {3 + j}u] = w0_{j};" in src
     p = P.policy("memo")
     s = G.jit_source(p.code, p.hook, _shapes(p), compile=True)
-    assert "g_memo0[" in s and "g_memo1[" in s
+    # the first site's table takes 3 KiB of the 4 KiB budget: the second
+    # site keeps one entry in registers
+    assert "g_memo0[" in s and "g_memo1[" not in s and "mk1 = mk;" in s
     for call in ("hash_delete(", "hash_update("):
         head = s[:s.index(call)]
         assert head.rstrip().splitlines()[-1].strip().startswith("mv0 = false; gen0++;") or "gen0++" in head[-400:]
