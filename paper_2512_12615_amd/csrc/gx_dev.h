@@ -1062,18 +1062,21 @@ __device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q
 // wave-uniform values (compiled programs, one queue per wave; the kernels
 // that call this have one wave per block).  The other 63 lanes fetch the
 // queue's records: each lane loads one record of the next block of 64 with
-// vector loads while lane 0 runs the current block, and at the start of a
-// block the wave copies the block it loaded into LDS, from where lane 0
-// reads each event's record.  The wait for a block's records thus comes
-// once per 64 events, long after they were requested.  (Holding records in
-// scalar registers, the earlier design, ran out of scalar registers: the
-// compiler spilled them as soon as they arrived, which made every record
-// fetch a full memory round trip on the event chain.)  Return codes are
-// gathered in LDS and stored by the whole wave after each block.
+// vector loads while lane 0 runs the current block, and lane 0 takes event
+// j's record from lane j's registers (cross-lane reads: no memory access on
+// the event chain).  The wait for a block's records thus comes once per 64
+// events, long after they were requested.  (Holding records in scalar
+// registers, the earlier design, ran out of scalar registers: the compiler
+// spilled them as soon as they arrived, which made every record fetch a
+// full memory round trip on the event chain.)  Return codes are gathered
+// in LDS and stored by the whole wave after each block.
 struct UniStage {
-  uint64_t c0[64], c1[64], c2[64];
-  uint32_t idx[64], rc[64];
+  uint32_t rc[64];
 };
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t x, uint32_t j) {
+  return ((uint64_t)rdlane((uint32_t)(x >> 32), j) << 32) | rdlane((uint32_t)x, j);
+}
 
 template <class Run>
 __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q, uint32_t qstride,
@@ -1099,18 +1102,17 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
   };
   fetch(beg);
   for (uint64_t k0 = beg; k0 < end; k0 += 64) {
-    st.c0[l] = nc.c0;
-    st.c1[l] = nc.c1;
-    st.c2[l] = nc.c2;
-    st.idx[l] = ni;
+    const Ctx cc = nc;  // this block's records, one per lane
+    const uint32_t ci = ni;
     fetch(k0 + 64);
     const uint32_t n = end - k0 < 64 ? (uint32_t)(end - k0) : 64u;
     if (l == 0) {
       for (uint32_t j = 0; j < n; j++)
-        st.rc[j] = (uint32_t)uni<true>(R.run(A, true, st.c0[j], st.c1[j], st.c2[j], stk, steps));
+        st.rc[j] = (uint32_t)uni<true>(
+            R.run(A, true, rdlane64(cc.c0, j), rdlane64(cc.c1, j), rdlane64(cc.c2, j), stk, steps));
     }
     R.uniformize();  // state lane 0 carries from event to event, back to wave-uniform
-    if (A.rc && l < n) A.rc[st.idx[l]] = st.rc[l];
+    if (A.rc && l < n) A.rc[ci] = st.rc[l];
     const uint64_t s0 = ((uint64_t)rdlane((uint32_t)(steps >> 32), 0) << 32) | rdlane((uint32_t)steps, 0);
     if (s0 > A.step_limit) break;
   }

@@ -644,9 +644,13 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
           o += "    if (UNI) {\n      const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " +
                std::to_string(kMemoEntries - 1) + "u;\n      uint64_t* ent = &g_memo" + W + "[me * " + S +
                "u];\n      cur" + W + " = me;\n";
-          o += "      if (uni<UNI>(ent[2]) == gen" + W + " && uni<UNI>(ent[0]) == mk) {\n        r0 = uni<UNI>(ent[1]);";
+          // the whole entry in one burst of LDS reads, then the checks
+          const uint32_t rd = Wn.win[w].used ? 3 + nw : 3;
+          o += "      uint64_t ev[" + std::to_string(rd) + "];\n      for (uint32_t i = 0; i < " + std::to_string(rd) +
+               "u; i++) ev[i] = uni<UNI>(ent[i]);\n";
+          o += "      if (ev[2] == gen" + W + " && ev[0] == mk) {\n        r0 = ev[1];";
           for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
-            o += " w" + W + "_" + std::to_string(j) + " = uni<UNI>(ent[" + std::to_string(3 + j) + "]);";
+            o += " w" + W + "_" + std::to_string(j) + " = ev[" + std::to_string(3 + j) + "];";
           o += "\n      } else {\n      " + call + "\n    ";
           window_load();
           o += "        ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
