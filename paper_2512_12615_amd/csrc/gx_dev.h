@@ -356,7 +356,10 @@ GX_HELPER int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkin
 
 // Ring space.  ctrl[0] head (bytes reserved so far), ctrl[1] tail (bytes
 // the host consumed), ctrl[2] drops, ctrl[3] = ~(start of the first
-// reservation that overflowed), 0 if none.  A reservation is one fetch-add
+// reservation that overflowed), 0 if none; ctrl[4] bytes of discard
+// records and ctrl[5] records written since the last drain (ctrl[6], set
+// by the host only, marks them unknown), so that a drain that takes the
+// whole range need not walk it.  A reservation is one fetch-add
 // on the head (no compare-and-swap retries under contention); the head
 // and tail are read first, so a request that cannot fit moves nothing.
 // When two requests race past the end, the late one finds its range beyond
@@ -408,6 +411,7 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
     base_lo = (uint32_t)b;
     base_hi = (uint32_t)(b >> 32);
     if (!ok) __hip_atomic_fetch_add(gl(&m->ctrl[2]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_fetch_add(gl(&m->ctrl[5]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   ok = rdlane(ok, leader);
   uint64_t base = ((uint64_t)rdlane(base_hi, leader) << 32) | rdlane(base_lo, leader);
@@ -431,9 +435,12 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
 // per (block, ring): a wave's lanes may reach a ring output under
 // different EXEC masks, and LDS keeps one copy that every lane sees.
 // Unused rest of a chunk becomes one discarded record when it is closed.
+// A wave's chunk counts the records carved from it and adds them to the
+// ring's record count when it is closed or replaced.
 struct RingChunk {
   uint64_t pos;
   uint64_t left;
+  uint64_t recs;
 };
 
 #ifdef GX_RING_SLOTS
@@ -456,28 +463,37 @@ __device__ __forceinline__ uint64_t ring_block_bytes(uint64_t cap, uint64_t bloc
 }
 
 __device__ __forceinline__ void ring_chunk_init(uint32_t slot) {
-  if (lane_id() == 0) g_rchunk[slot] = RingChunk{0, 0};
+  if (lane_id() == 0) g_rchunk[slot] = RingChunk{0, 0, 0};
 }
 // by one wave of the block, before any wave uses the ring
 __device__ __forceinline__ void ring_block_init(uint32_t r) {
   if (lane_id() == 0) {
-    g_rblock[r] = RingChunk{0, 0};
+    g_rblock[r] = RingChunk{0, 0, 0};
     g_rlock[r] = 0;
   }
 }
 
+// (one lane) the unused rest of a chunk as a discard record
 __device__ __forceinline__ void ring_discard(const MapDev* m, uint64_t pos, uint64_t left) {
-  if (left >= 8)
+  if (left >= 8) {
     *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
+    __hip_atomic_fetch_add(gl(&m->ctrl[4]), left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+// (one lane) records carved from a wave's chunk, into the ring's count
+__device__ __forceinline__ void ring_count(const MapDev* m, uint64_t recs) {
+  if (recs) __hip_atomic_fetch_add(gl(&m->ctrl[5]), recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Close a wave's chunk (every wave) / the block's chunk (one wave, after
 // every wave of the block has closed its own).
 __device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
-  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos;
+  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos, recs = g_rchunk[slot].recs;
   if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
     ring_discard(m, pos, left);
+    ring_count(m, recs);
     g_rchunk[slot].left = 0;
+    g_rchunk[slot].recs = 0;
   }
 }
 __device__ __forceinline__ void ring_block_close(const MapDev* m, uint32_t r) {
@@ -501,12 +517,12 @@ __device__ __forceinline__ bool ring_block_take(const MapDev* m, uint32_t r, uin
     const uint64_t bask = ask > block_bytes ? ask : block_bytes;
     if (ring_reserve(m, bask, &base)) {
       ring_discard(m, b.pos, b.left);
-      b = RingChunk{base, bask};
+      b = RingChunk{base, bask, 0};
     } else if (b.left >= need) {
       ask = need;  // the ring is nearly full: finish the block's chunk
     } else if (ring_reserve(m, need, &base)) {
       ring_discard(m, b.pos, b.left);
-      b = RingChunk{base, need};
+      b = RingChunk{base, need, 0};
       ask = need;
     } else {
       ok = false;
@@ -541,11 +557,12 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
   const uint32_t need = 8 + ((size + 7) & ~7u);
   const uint32_t cnt = popc64(wm);
   const uint64_t total = (uint64_t)need * cnt;
-  uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left;
+  uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left, recs = g_rchunk[slot].recs;
   if (total > left) {
     uint32_t ok = 0, lo = 0, hi = 0, glo = 0, ghi = 0;
     if (lane_id() == leader) {
       ring_discard(m, pos, left);
+      ring_count(m, recs);
       uint64_t b = 0, got = 0;
       ok = ring_block_take(m, r, block_bytes, total > chunk_bytes ? total : chunk_bytes, total, &b, &got) ? 1u : 0u;
       lo = (uint32_t)b;
@@ -556,17 +573,18 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
     }
     ok = rdlane(ok, leader);
     if (!ok) {
-      if (lane_id() == leader) g_rchunk[slot].left = 0;
+      if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos, 0, 0};
       return want ? (uint64_t)-E_AGAIN : res;
     }
     pos = ((uint64_t)rdlane(hi, leader) << 32) | rdlane(lo, leader);
     left = ((uint64_t)rdlane(ghi, leader) << 32) | rdlane(glo, leader);
+    recs = 0;
   }
   if (want) {
     ring_put(m, pos + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
     res = 0;
   }
-  if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos + total, left - total};
+  if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos + total, left - total, recs + cnt};
   return res;
 }
 #endif

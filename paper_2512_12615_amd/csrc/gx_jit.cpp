@@ -926,7 +926,7 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
   o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
   JitInfo ji;
-  o += emit_prog(P, "p0", true, lds + 16ull * nw * nr, &ji);
+  o += emit_prog(P, "p0", true, lds + (uint64_t)sizeof(uint64_t) * 3 * nw * nr, &ji);  // + the ring chunks
   if (info) *info = ji;
   const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
   if (P.event_parallel)

@@ -1738,8 +1738,8 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   if (!m || m->h.type != MAP_RINGBUF || (!host_buf && buf_bytes)) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  uint64_t ctrl[4];
-  if (hipMemcpy(ctrl, m->h.ctrl, 32, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  uint64_t ctrl[7];
+  if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
   uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
   // a reservation that overflowed ended the committed data at its start
   const bool cut = ctrl[3] != 0;
@@ -1789,11 +1789,11 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
     flush(pos);
   }
   if (pos || cut) {
-    // publish the new tail (and, after an overflow, the cut-back head)
-    uint64_t nc[4] = {head, tail + pos, ctrl[2], 0};
-    const bool ok = cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
-                        : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) return -EIO;
+    // publish the new tail (and, after an overflow, the cut-back head); the
+    // device's counts of discards and records cover what remains only when
+    // nothing remains
+    uint64_t nc[7] = {head, tail + pos, ctrl[2], 0, 0, 0, pos == avail ? 0ull : 1ull};
+    if (hipMemcpy(m->h.ctrl, nc, sizeof nc, hipMemcpyHostToDevice) != hipSuccess) return -EIO;
   }
   rt->stats.bytes_drained += out;
   if (n_records) *n_records = nrec;
@@ -1806,8 +1806,8 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
   if (!m || m->h.type != MAP_RINGBUF || !view || !view_bytes) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  uint64_t ctrl[4];
-  if (hipMemcpy(ctrl, m->h.ctrl, 32, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  uint64_t ctrl[7];
+  if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
   uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
   const bool cut = ctrl[3] != 0;
   if (cut && ~ctrl[3] < head) head = ~ctrl[3];
@@ -1830,27 +1830,33 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
     if (hipMemcpy(buf, m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
     if (first < avail && hipMemcpy(buf + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
       return -EIO;
-    while (pos + 8 <= avail) {
-      uint32_t len, flags;
-      std::memcpy(&len, buf + pos, 4);
-      std::memcpy(&flags, buf + pos + 4, 4);
-      if (len == 0 && flags == 0) break;
-      const uint64_t need = 8 + ((len + 7ull) & ~7ull);
-      if (pos + need > avail) break;
-      if (!(flags & RING_DISCARD)) {
-        kept += need;
-        nrec++;
+    if (!cut && !ctrl[6] && ctrl[4] <= avail) {
+      // every byte of the range is a record or a discard record (no launch
+      // is running), and the device counted both: no walk over the range
+      pos = avail;
+      kept = avail - ctrl[4];
+      nrec = ctrl[5];
+    } else {
+      while (pos + 8 <= avail) {
+        uint32_t len, flags;
+        std::memcpy(&len, buf + pos, 4);
+        std::memcpy(&flags, buf + pos + 4, 4);
+        if (len == 0 && flags == 0) break;
+        const uint64_t need = 8 + ((len + 7ull) & ~7ull);
+        if (pos + need > avail) break;
+        if (!(flags & RING_DISCARD)) {
+          kept += need;
+          nrec++;
+        }
+        pos += need;
       }
-      pos += need;
     }
     *view = buf;
     *view_bytes = pos;
   }
   if (pos || cut) {
-    uint64_t nc[4] = {head, tail + pos, ctrl[2], 0};
-    const bool ok = cut ? hipMemcpy(m->h.ctrl, nc, 32, hipMemcpyHostToDevice) == hipSuccess
-                        : hipMemcpy(m->h.ctrl + 1, nc + 1, 8, hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) return -EIO;
+    uint64_t nc[7] = {head, tail + pos, ctrl[2], 0, 0, 0, pos == avail ? 0ull : 1ull};
+    if (hipMemcpy(m->h.ctrl, nc, sizeof nc, hipMemcpyHostToDevice) != hipSuccess) return -EIO;
   }
   rt->stats.bytes_drained += kept;
   if (n_records) *n_records = nrec;
