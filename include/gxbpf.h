@@ -266,8 +266,10 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
  * gx_destroy_map), which still holds the discard records (flags bit 0; len
  * bytes of padding) that close unused chunk space; readers skip them.
  * Returns the bytes of the kept records (headers included) and their
- * count in *n_records; releases the whole range.  Errors as
- * gx_drain_ringbuf. */
+ * count in *n_records; releases the whole range.  When the previous drain
+ * took its whole range, both figures come from counts the device keeps
+ * (discard bytes and records written), without a host pass over the
+ * records.  Errors as gx_drain_ringbuf. */
 int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
                               uint64_t* n_records);
 
