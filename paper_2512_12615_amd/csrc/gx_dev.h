@@ -356,10 +356,11 @@ GX_HELPER int64_t array_update(const MapDev* m, int kkind, uint64_t kp, int vkin
 
 // Ring space.  ctrl[0] head (bytes reserved so far), ctrl[1] tail (bytes
 // the host consumed), ctrl[2] drops, ctrl[3] = ~(start of the first
-// reservation that overflowed), 0 if none; ctrl[4] bytes of discard
-// records and ctrl[5] records written since the last drain (ctrl[6], set
-// by the host only, marks them unknown), so that a drain that takes the
-// whole range need not walk it.  A reservation is one fetch-add
+// reservation that overflowed), 0 if none; from ctrl[kRingCount] on, the
+// bytes of discard records and the records written since the last drain
+// (summed per block in LDS, added once per block), so that a drain that
+// takes the whole range need not walk it; ctrl[kRingUnknown] = 1 when a
+// writer did not count (the interpreter's per-wave outputs).  A reservation is one fetch-add
 // on the head (no compare-and-swap retries under contention); the head
 // and tail are read first, so a request that cannot fit moves nothing.
 // When two requests race past the end, the late one finds its range beyond
@@ -411,7 +412,7 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
     base_lo = (uint32_t)b;
     base_hi = (uint32_t)(b >> 32);
     if (!ok) __hip_atomic_fetch_add(gl(&m->ctrl[2]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else __hip_atomic_fetch_add(gl(&m->ctrl[5]), (uint64_t)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *gl(&m->ctrl[kRingUnknown]) = 1;  // records not counted: the drain walks them
   }
   ok = rdlane(ok, leader);
   uint64_t base = ((uint64_t)rdlane(base_hi, leader) << 32) | rdlane(base_lo, leader);
@@ -447,6 +448,7 @@ struct RingChunk {
 __shared__ RingChunk g_rchunk[GX_RING_SLOTS];
 __shared__ RingChunk g_rblock[GX_NRINGS];
 __shared__ uint32_t g_rlock[GX_NRINGS];
+__shared__ uint64_t g_rcount[2 * GX_NRINGS];  // the block's discard bytes and records, per ring
 
 // Chunk sizes: blocks' chunks and waves' chunks in flight each hold at most
 // an eighth of the ring, so reserved-but-unused space never exceeds a
@@ -470,36 +472,46 @@ __device__ __forceinline__ void ring_block_init(uint32_t r) {
   if (lane_id() == 0) {
     g_rblock[r] = RingChunk{0, 0, 0};
     g_rlock[r] = 0;
+    g_rcount[2 * r] = 0;
+    g_rcount[2 * r + 1] = 0;
   }
 }
 
-// (one lane) the unused rest of a chunk as a discard record
-__device__ __forceinline__ void ring_discard(const MapDev* m, uint64_t pos, uint64_t left) {
+// (one lane) the unused rest of a chunk of ring r as a discard record
+__device__ __forceinline__ void ring_discard(const MapDev* m, uint32_t r, uint64_t pos, uint64_t left) {
   if (left >= 8) {
     *gl((uint64_t*)(m->data + (pos & (uint64_t)m->slot_mask))) = (uint64_t)(left - 8) | ((uint64_t)RING_DISCARD << 32);
-    __hip_atomic_fetch_add(gl(&m->ctrl[4]), left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&g_rcount[2 * r], left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
-// (one lane) records carved from a wave's chunk, into the ring's count
-__device__ __forceinline__ void ring_count(const MapDev* m, uint64_t recs) {
-  if (recs) __hip_atomic_fetch_add(gl(&m->ctrl[5]), recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// (one lane) records carved from a wave's chunk of ring r
+__device__ __forceinline__ void ring_count(uint32_t r, uint64_t recs) {
+  if (recs) __hip_atomic_fetch_add(&g_rcount[2 * r + 1], recs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Close a wave's chunk (every wave) / the block's chunk (one wave, after
-// every wave of the block has closed its own).
+// every wave of the block has closed its own), which also adds the block's
+// counts to the ring's.
 __device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
+  const uint32_t r = slot % GX_NRINGS;
   const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos, recs = g_rchunk[slot].recs;
   if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
-    ring_discard(m, pos, left);
-    ring_count(m, recs);
+    ring_discard(m, r, pos, left);
+    ring_count(r, recs);
     g_rchunk[slot].left = 0;
     g_rchunk[slot].recs = 0;
   }
 }
 __device__ __forceinline__ void ring_block_close(const MapDev* m, uint32_t r) {
   if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
-    ring_discard(m, g_rblock[r].pos, g_rblock[r].left);
+    ring_discard(m, r, g_rblock[r].pos, g_rblock[r].left);
     g_rblock[r].left = 0;
+    const uint64_t d = g_rcount[2 * r], n = g_rcount[2 * r + 1];
+    uint64_t* c = m->ctrl + kRingCount + 2 * (blockIdx.x % kRingCountSlots);
+    if (d) __hip_atomic_fetch_add(gl(c), d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (n) __hip_atomic_fetch_add(gl(c + 1), n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    g_rcount[2 * r] = 0;
+    g_rcount[2 * r + 1] = 0;
   }
 }
 
@@ -516,12 +528,12 @@ __device__ __forceinline__ bool ring_block_take(const MapDev* m, uint32_t r, uin
     uint64_t base = 0;
     const uint64_t bask = ask > block_bytes ? ask : block_bytes;
     if (ring_reserve(m, bask, &base)) {
-      ring_discard(m, b.pos, b.left);
+      ring_discard(m, r, b.pos, b.left);
       b = RingChunk{base, bask, 0};
     } else if (b.left >= need) {
       ask = need;  // the ring is nearly full: finish the block's chunk
     } else if (ring_reserve(m, need, &base)) {
-      ring_discard(m, b.pos, b.left);
+      ring_discard(m, r, b.pos, b.left);
       b = RingChunk{base, need, 0};
       ask = need;
     } else {
@@ -561,8 +573,8 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
   if (total > left) {
     uint32_t ok = 0, lo = 0, hi = 0, glo = 0, ghi = 0;
     if (lane_id() == leader) {
-      ring_discard(m, pos, left);
-      ring_count(m, recs);
+      ring_discard(m, r, pos, left);
+      ring_count(r, recs);
       uint64_t b = 0, got = 0;
       ok = ring_block_take(m, r, block_bytes, total > chunk_bytes ? total : chunk_bytes, total, &b, &got) ? 1u : 0u;
       lo = (uint32_t)b;

@@ -74,9 +74,18 @@ struct __attribute__((aligned(64))) MapDev {
   uint8_t* data;        // array / hash: values; ring: data area
   uint8_t* slots;       // hash: slot headers {u32 state; u32 pad; key bytes}
   uint64_t* ctrl;       // hash: [0] live, [1] e2big; ring: [0] head, [1] tail, [2] drops,
-                        // [3] ~(start of the first overflowing reservation) or 0
+                        // [3] ~(start of the first overflowing reservation) or 0,
+                        // [kRingUnknown], [kRingCount...]: see below
   uint64_t pad;
 };
+
+// Ring counts of discard bytes and records: kRingCountSlots pairs from word
+// kRingCount on (a block adds its totals to pair blockIdx mod the slot
+// count, so that blocks rarely add to one address), apart from the head's
+// cache line; ctrl[kRingUnknown] = 1 marks them incomplete.  Control area
+// bytes per map.
+constexpr uint32_t kRingUnknown = 16, kRingCount = 32, kRingCountSlots = 64;
+constexpr uint32_t kCtrlBytes = 2048;
 
 // Ring record header word: {u32 len, u32 flags}; a header of 0 marks space
 // that is reserved but not yet written.  Padding that closes a chunk of

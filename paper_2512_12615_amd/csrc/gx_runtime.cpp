@@ -667,7 +667,7 @@ struct MapSnapshot {
       MapObj* m = get_map(rt, fd);
       if (!m) continue;
       for (auto pr : {std::make_pair((void*)m->h.data, m->data_bytes), std::make_pair((void*)m->h.slots, m->slot_bytes),
-                      std::make_pair((void*)m->h.ctrl, (size_t)64)}) {
+                      std::make_pair((void*)m->h.ctrl, (size_t)kCtrlBytes)}) {
         if (!pr.first || !pr.second) continue;
         Part pt{pr.first, nullptr, pr.second};
         if (hipMalloc(&pt.tmp, pt.bytes) != hipSuccess) return -ENOMEM;
@@ -779,14 +779,14 @@ int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_si
   }
   DevGuard g(rt->dev);
   bool ok = hipMalloc((void**)&m.h.data, m.data_bytes) == hipSuccess &&
-            hipMalloc((void**)&m.h.ctrl, 64) == hipSuccess && hipMalloc((void**)&m.d_desc, sizeof(MapDev)) == hipSuccess;
+            hipMalloc((void**)&m.h.ctrl, kCtrlBytes) == hipSuccess && hipMalloc((void**)&m.d_desc, sizeof(MapDev)) == hipSuccess;
   if (ok && m.slot_bytes) ok = hipMalloc((void**)&m.h.slots, m.slot_bytes) == hipSuccess;
   if (!ok) {
     free_map(m);
     return -ENOMEM;
   }
   ok = hipMemsetAsync(m.h.data, 0, m.data_bytes, rt->internal) == hipSuccess &&
-       hipMemsetAsync(m.h.ctrl, 0, 64, rt->internal) == hipSuccess &&
+       hipMemsetAsync(m.h.ctrl, 0, kCtrlBytes, rt->internal) == hipSuccess &&
        (!m.slot_bytes || hipMemsetAsync(m.h.slots, 0, m.slot_bytes, rt->internal) == hipSuccess) &&
        hipMemcpyAsync(m.d_desc, &m.h, sizeof(MapDev), hipMemcpyHostToDevice, rt->internal) == hipSuccess &&
        hipStreamSynchronize(rt->internal) == hipSuccess;
@@ -876,7 +876,7 @@ int gx_map_clear(gx_rt* rt, int map_fd) {
   if (!m) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  bool ok = hipMemset(m->h.data, 0, m->data_bytes) == hipSuccess && hipMemset(m->h.ctrl, 0, 64) == hipSuccess &&
+  bool ok = hipMemset(m->h.data, 0, m->data_bytes) == hipSuccess && hipMemset(m->h.ctrl, 0, kCtrlBytes) == hipSuccess &&
             (!m->slot_bytes || hipMemset(m->h.slots, 0, m->slot_bytes) == hipSuccess) &&
             hipDeviceSynchronize() == hipSuccess;
   return ok ? 0 : -EIO;
@@ -1738,7 +1738,7 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
   if (!m || m->h.type != MAP_RINGBUF || (!host_buf && buf_bytes)) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  uint64_t ctrl[7];
+  uint64_t ctrl[kRingCount + 2 * kRingCountSlots];
   if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
   uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
   // a reservation that overflowed ended the committed data at its start
@@ -1792,7 +1792,8 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
     // publish the new tail (and, after an overflow, the cut-back head); the
     // device's counts of discards and records cover what remains only when
     // nothing remains
-    uint64_t nc[7] = {head, tail + pos, ctrl[2], 0, 0, 0, pos == avail ? 0ull : 1ull};
+    uint64_t nc[kRingCount + 2 * kRingCountSlots] = {head, tail + pos, ctrl[2], 0};
+    nc[kRingUnknown] = pos == avail ? 0 : 1;
     if (hipMemcpy(m->h.ctrl, nc, sizeof nc, hipMemcpyHostToDevice) != hipSuccess) return -EIO;
   }
   rt->stats.bytes_drained += out;
@@ -1806,7 +1807,7 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
   if (!m || m->h.type != MAP_RINGBUF || !view || !view_bytes) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  uint64_t ctrl[7];
+  uint64_t ctrl[kRingCount + 2 * kRingCountSlots];
   if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
   uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1;
   const bool cut = ctrl[3] != 0;
@@ -1830,12 +1831,17 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
     if (hipMemcpy(buf, m->h.data + t0, first, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
     if (first < avail && hipMemcpy(buf + first, m->h.data, avail - first, hipMemcpyDeviceToHost) != hipSuccess)
       return -EIO;
-    if (!cut && !ctrl[6] && ctrl[4] <= avail) {
+    uint64_t disc = 0, recs = 0;
+    for (uint32_t k = 0; k < kRingCountSlots; k++) {
+      disc += ctrl[kRingCount + 2 * k];
+      recs += ctrl[kRingCount + 2 * k + 1];
+    }
+    if (!cut && !ctrl[kRingUnknown] && disc <= avail) {
       // every byte of the range is a record or a discard record (no launch
       // is running), and the device counted both: no walk over the range
       pos = avail;
-      kept = avail - ctrl[4];
-      nrec = ctrl[5];
+      kept = avail - disc;
+      nrec = recs;
     } else {
       while (pos + 8 <= avail) {
         uint32_t len, flags;
@@ -1855,7 +1861,8 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
     *view_bytes = pos;
   }
   if (pos || cut) {
-    uint64_t nc[7] = {head, tail + pos, ctrl[2], 0, 0, 0, pos == avail ? 0ull : 1ull};
+    uint64_t nc[kRingCount + 2 * kRingCountSlots] = {head, tail + pos, ctrl[2], 0};
+    nc[kRingUnknown] = pos == avail ? 0 : 1;
     if (hipMemcpy(m->h.ctrl, nc, sizeof nc, hipMemcpyHostToDevice) != hipSuccess) return -EIO;
   }
   rt->stats.bytes_drained += kept;
