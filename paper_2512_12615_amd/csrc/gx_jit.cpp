@@ -577,10 +577,6 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         body += sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
                         : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + wsh +
                               ")) | ((uint64_t)" + val + " << " + wsh + ");";
-      if (wa >= 0 && Wn.table[wa])  // the memo entry follows the window
-        body += " if (UNI) g_memo" + std::to_string(wa) + "[cur" + std::to_string(wa) + " * " +
-                std::to_string(3 + Wn.win[wa].words) + "u + " + std::to_string(3 + Wn.off[pc] / 8) + "u] = " + wword +
-                ";";
       guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, body);
       break;
     }
@@ -639,24 +635,34 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         const std::string S = std::to_string(3 + nw);
         o += "  { const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) + ", r2, 0, " +
              std::to_string(J.m[km].second.key_size) + "u, stk));\n";
-        // one queue per wave: the LDS table
+        // one queue per wave: the last key's entry in registers, in front of
+        // the LDS table; the table entry of a key is written back when the
+        // registers move on to another key (window stores touch registers only)
         if (Wn.table[w]) {
-          o += "    if (UNI) {\n      const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " +
-               std::to_string(kMemoEntries - 1) + "u;\n      uint64_t* ent = &g_memo" + W + "[me * " + S +
-               "u];\n      cur" + W + " = me;\n";
+          const bool used = Wn.win[w].used;
+          o += "    if (UNI) {\n      if (mv" + W + " && mk == mk" + W + ") {\n        r0 = mp" + W + ";\n      } else {\n";
+          if (used) {
+            o += "        if (mv" + W + ") {";
+            for (uint32_t j = 0; j < nw; j++)
+              o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" +
+                   std::to_string(j) + ";";
+            o += " }\n";
+          }
+          o += "        const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " + std::to_string(kMemoEntries - 1) +
+               "u;\n        uint64_t* ent = &g_memo" + W + "[me * " + S + "u];\n        cur" + W + " = me;\n";
           // the whole entry in one burst of LDS reads, then the checks
-          const uint32_t rd = Wn.win[w].used ? 3 + nw : 3;
-          o += "      uint64_t ev[" + std::to_string(rd) + "];\n      for (uint32_t i = 0; i < " + std::to_string(rd) +
+          const uint32_t rd = used ? 3 + nw : 3;
+          o += "        uint64_t ev[" + std::to_string(rd) + "];\n        for (uint32_t i = 0; i < " + std::to_string(rd) +
                "u; i++) ev[i] = uni<UNI>(ent[i]);\n";
-          o += "      if (ev[2] == gen" + W + " && ev[0] == mk) {\n        r0 = ev[1];";
-          for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+          o += "        if (ev[2] == gen" + W + " && ev[0] == mk) {\n          r0 = ev[1];";
+          for (uint32_t j = 0; j < nw && used; j++)
             o += " w" + W + "_" + std::to_string(j) + " = ev[" + std::to_string(3 + j) + "];";
-          o += "\n      } else {\n      " + call + "\n    ";
+          o += "\n        } else {\n        " + call + "\n      ";
           window_load();
-          o += "        ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
-          for (uint32_t j = 0; j < nw && Wn.win[w].used; j++)
+          o += "          ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
+          for (uint32_t j = 0; j < nw && used; j++)
             o += " ent[" + std::to_string(3 + j) + "] = w" + W + "_" + std::to_string(j) + ";";
-          o += "\n      }\n    } else {\n";
+          o += "\n        }\n        mk" + W + " = mk; mp" + W + " = r0; mv" + W + " = r0 != 0;\n      }\n    } else {\n";
         }
         // several queues per wave, or no table: one entry per lane, in registers
         o += "    if (mv" + W + " && mk == mk" + W + ") {\n      r0 = mp" + W + ";\n    } else {\n    " + call + "\n  ";

@@ -134,9 +134,10 @@ def test_map_value_windows(G):
 def test_lookup_memo(G):
     """The stride policy's one lookup site keeps its key, value address and
     window across events; the insert (an update of the map) clears every
-    memo entry, and each store through the window also writes the current
-    entry.  In the memo test program the delete and the in-place update
-    clear it too, and the second lookup site is a memo of its own."""
+    memo entry, and the entry of the key held in registers is written back
+    to the LDS table when the registers move on to another key.  In the
+    memo test program the delete and the in-place update clear it too, and
+    the second lookup site is a memo of its own."""
     import sys, os
     sys.path.insert(0, os.path.dirname(__file__))
     import jit_window_programs as P
