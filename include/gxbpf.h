@@ -273,6 +273,14 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
 int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
                               uint64_t* n_records);
 
+/* Position of a ring: *head = bytes reserved since the ring was created
+ * (records, their padding and discard records), *tail = bytes drained.
+ * Both only grow; head - tail is the backlog a drain would read, and
+ * head / capacity the number of times the writers went round the ring.
+ * Waits for the runtime's launches like a drain; -EINVAL if ring_fd is not
+ * a ring or an output pointer is null. */
+int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail);
+
 /* Counters accumulated since gx_open (synchronises the device). */
 int gx_stats_get(gx_rt* rt, gx_stats* out);
 

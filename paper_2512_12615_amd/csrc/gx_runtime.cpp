@@ -1870,6 +1870,19 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
   return (int64_t)kept;
 }
 
+int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail) {
+  MapObj* m = get_map(rt, ring_fd);
+  if (!m || m->h.type != MAP_RINGBUF || !head || !tail) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  uint64_t ctrl[4];
+  if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  // an overflowed reservation's start, once a drain has cut the head back
+  *head = ctrl[3] != 0 && ~ctrl[3] < ctrl[0] ? ~ctrl[3] : ctrl[0];
+  *tail = ctrl[1];
+  return 0;
+}
+
 int gx_profile_enable(gx_rt* rt, int on) {
   if (!rt) return -EINVAL;
   rt->profile = on != 0;

@@ -44,7 +44,7 @@ class Batch(C.Structure):
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
            "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
-           "gx_jit_set_source", "gx_drain_ringbuf", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
@@ -115,6 +115,7 @@ def lib():
     L.gx_jit_set_source.restype = i64
     L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.gx_drain_ringbuf.restype = i64
+    L.gx_ringbuf_pos.argtypes = [vp, C.c_int, C.POINTER(u64), C.POINTER(u64)]
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
     L.gx_profile_enable.argtypes = [vp, C.c_int]
     L.gx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64)]
@@ -369,6 +370,13 @@ class Runtime:
         nb = _check(lib().gx_drain_ringbuf(self._h, fd, buf.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
                     "gx_drain_ringbuf")
         return (buf[:nb].tobytes() if copy else buf[:nb]), n.value
+
+    def ringbuf_pos(self, fd):
+        """(head, tail): bytes the ring's writers reserved and the host
+        drained since the ring was created (gx_ringbuf_pos)."""
+        h, t = C.c_uint64(0), C.c_uint64(0)
+        _check(lib().gx_ringbuf_pos(self._h, fd, C.byref(h), C.byref(t)), "gx_ringbuf_pos")
+        return h.value, t.value
 
     def profile_enable(self, on=True):
         _check(lib().gx_profile_enable(self._h, int(on)), "gx_profile_enable")

@@ -1,0 +1,232 @@
+"""Parity at the sizes and launch shapes the benchmark times.
+
+The benchmark's kernels run at sizes where behaviour that small tests never
+reach takes over: the stride policy's lookup memo turns over many times per
+queue (about 16 k events per stream), the 64 MiB ring wraps on every second
+step, the latency histogram's LDS caches spill to the reduce kernel, and the
+access counter's blocks flush their mirrors.  Each test here builds the
+same inputs (same generators and seeds), the same maps, the same launch
+shape (autotuned as the benchmark does, checked mode off) and the same
+launch sequence (maps persisting across rotated batches, a ring drain after
+each launch), then compares with the oracle or with closed forms that the
+CPU tests pin to the oracle.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_runner import setup, to_device
+from runners import normalise_hash
+
+from paper_2512_12615_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def rt():
+    from paper_2512_12615_amd import gxbpf as G
+    r = G.Runtime(0)
+    yield r
+    r.close()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _payloads(buf):
+    from paper_2512_12615_amd import gxbpf as G
+    return G.parse_ring(buf)
+
+
+def _records32(payloads):
+    """Sorted (n, 4) u64 view of 32-byte payloads (the multiset, ordered)."""
+    assert all(len(p) == 32 for p in payloads)
+    a = np.frombuffer(b"".join(payloads), dtype="<u8").reshape(-1, 4)
+    return a[np.lexsort(a.T[::-1])]
+
+
+def test_stride_prefetch_compiled_at_bench_size(rt, monkeypatch):
+    """2^24 events over 1024 streams, two rotated batches on persisting
+    maps, compiled one-queue kernel in the tuned launch shape; a view drain
+    after the first launch and a copying drain after the second (the 64 MiB
+    ring wraps during the second).  Return codes, the whole hash map and
+    the ring multisets equal the oracle's."""
+    import torch
+    from oracle import oracle as O
+    monkeypatch.setenv("GX_CHECKED", "0")
+    n = 1 << 24
+    pol = W.stride_prefetch_policy()
+    hosts = [W.gen_mem_stride(n, 1001 + 7 * b) for b in range(2)]
+    fds, prog = setup(rt, pol, jit=True)
+    dev = [to_device(h) for h in hosts]
+    rc = torch.empty(n, dtype=torch.int32, device="cuda")
+    tune = rt.autotune(prog, dev[0], n_events=n, record_size=24, rc=rc)
+    _log(f"stride full size: tuned shape {tune}")
+    o = O.Oracle()
+    o.set_tracking(False)
+    for m in pol.maps:
+        o.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags)
+    ring_fd = fds[1]
+    cap = pol.maps[1].max_entries
+    for b in range(2):
+        rt.run_batch(prog, dev[b], n_events=n, record_size=24, rc=rc)
+        torch.cuda.synchronize()
+        if b == 0:
+            view, kept, nrec = rt.drain_ringbuf_view(ring_fd)
+            got = _payloads(view.tobytes())
+        else:
+            buf, nrec = rt.drain_ringbuf(ring_fd)
+            got = _payloads(buf)
+        assert len(got) == nrec
+        want_rc = o.run(pol.code, pol.hook, hosts[b])
+        g_rc = rc.cpu().numpy().view(np.uint32)
+        bad = np.nonzero(g_rc != want_rc)[0]
+        assert len(bad) == 0, f"batch {b}: rc differs at {bad[:8]}"
+        want = o.drain(1)
+        assert len(got) == len(want), f"batch {b}: {len(got)} records vs {len(want)}"
+        assert np.array_equal(_records32(got), _records32(want)), f"batch {b}: ring multiset differs"
+        _log(f"stride full size: batch {b} matches ({len(got)} records)")
+    head, tail = rt.ringbuf_pos(ring_fd)
+    assert head == tail and head > cap, "the ring did not wrap"
+    k, v = rt.map_dump(fds[0])
+    ko, vo = o.dump(0)
+    assert normalise_hash(k, v) == normalise_hash(ko, vo)
+    st = rt.stats()
+    assert st["hash_e2big"] == 0 and st["ring_drops"] == 0 and st["vm_errors"] == 0
+
+
+def _floor_log2(lat):
+    # exact for lat < 2^53 (every such integer is a double)
+    assert int(lat.max()) < (1 << 53)
+    e = np.frexp(lat.astype(np.float64))[1].astype(np.int64) - 1
+    return np.where(lat > 0, e, 0)
+
+
+@pytest.mark.parametrize("jit", [True, False], ids=["compiled", "interpreted"])
+def test_latency_hist_at_bench_size(rt, monkeypatch, jit):
+    """2^26 timing records, two rotated batches with the threshold rewritten
+    before each (the benchmark's sequence), tuned launch shape (compiled: LDS
+    caches spilled to the reduce kernel).  Histogram, return codes and tail
+    records equal the closed form; the first 2^20 return codes also equal
+    the oracle's."""
+    import torch
+    from oracle import oracle as O
+    monkeypatch.setenv("GX_CHECKED", "0")
+    n = 1 << 26
+    pol = W.latency_hist_policy()
+    fds, prog = setup(rt, pol, jit=jit)
+    hist = np.zeros(4096 * 64, np.uint64)
+    rc = torch.empty(n, dtype=torch.int32, device="cuda")
+    for b in range(2):
+        h = W.gen_timing(n, 1002 + b)
+        T = W.p99_threshold(h["lat"])
+        assert rt.map_update(fds[1], b"\0\0\0\0", np.uint64(T).tobytes()) == 0
+        d = to_device(h)
+        if b == 0 and jit:
+            _log(f"latency hist full size: tuned {rt.autotune(prog, d, n_events=n, record_size=16, rc=rc)}")
+        rt.run_batch(prog, d, n_events=n, record_size=16, rc=rc)
+        torch.cuda.synchronize()
+        view, kept, nrec = rt.drain_ringbuf_view(fds[2])
+        got = _payloads(view.tobytes())
+        del d
+        bk = _floor_log2(h["lat"])
+        kid = h["kernel_id"].astype(np.int64)
+        g_rc = rc.cpu().numpy().view(np.uint32)
+        assert np.array_equal(g_rc, bk.astype(np.uint32)), f"batch {b}: rc differs"
+        hist += np.bincount(kid * 64 + bk, minlength=4096 * 64).astype(np.uint64)
+        sel = h["lat"] > np.uint64(T)
+        want = np.zeros((int(sel.sum()), 4), np.uint64)
+        want[:, 0] = kid[sel].astype(np.uint64) | (bk[sel].astype(np.uint64) << np.uint64(32))
+        want[:, 1] = h["lat"][sel]
+        want[:, 2] = np.uint64(T)
+        want = want[np.lexsort(want.T[::-1])]
+        assert len(got) == len(want)
+        assert np.array_equal(_records32(got), want), f"batch {b}: tail records differ"
+        if b == 0:
+            o = O.Oracle()
+            o.set_tracking(False)
+            for m in pol.maps:
+                o.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags)
+            assert o.update(1, b"\0\0\0\0", np.uint64(T).tobytes()) == 0
+            m = 1 << 20
+            assert np.array_equal(o.run(pol.code, pol.hook, h[:m]), g_rc[:m])
+        _log(f"latency hist full size: batch {b} matches ({len(got)} tail records)")
+        del h
+    _, vals = rt.map_dump(fds[0])
+    assert np.array_equal(np.frombuffer(vals.tobytes(), "<u8"), hist)
+    st = rt.stats()
+    assert st["ring_drops"] == 0 and st["vm_errors"] == 0
+
+
+@pytest.mark.parametrize("jit", [True, False], ids=["compiled", "interpreted"])
+def test_access_counter_at_bench_size(rt, monkeypatch, jit):
+    """2^20 records, 48 rotated batches as the benchmark's form, 20 launches
+    on one map: the map is the summed closed form, rc the last batch's."""
+    import torch
+    monkeypatch.setenv("GX_CHECKED", "0")
+    n = 1 << 20
+    pol = W.access_counter_policy()
+    fds, prog = setup(rt, pol, jit=jit)
+    hosts = [W.gen_mem_uniform(n, 1000 + k) for k in range(4)]
+    dev = [to_device(h) for h in hosts]
+    rc = torch.empty(n, dtype=torch.int32, device="cuda")
+    if jit:
+        rt.autotune(prog, dev[0], n_events=n, record_size=24, rc=rc)
+    want = np.zeros(4096, np.uint64)
+    for k in range(20):
+        rt.run_batch(prog, dev[k % 4], n_events=n, record_size=24, rc=rc)
+        want += np.bincount((hosts[k % 4]["addr"] >> np.uint64(21)).astype(np.int64), minlength=4096).astype(np.uint64)
+    torch.cuda.synchronize()
+    last = hosts[19 % 4]
+    assert np.array_equal(rc.cpu().numpy().view(np.uint32), ((last["addr"] >> np.uint64(21)) & np.uint64(1)).astype(np.uint32))
+    _, vals = rt.map_dump(fds[0])
+    assert np.array_equal(np.frombuffer(vals.tobytes(), "<u8"), want)
+    assert int(want.sum()) == 20 * n
+
+
+def test_batched_256_programs_against_oracle(rt):
+    """The batched form's workload (256 generated programs over their own
+    batches of 2^10..2^20 records, about 35 M events) in one run_batches
+    call; return codes and maps of 16 sampled programs (the smallest, the
+    largest and 14 seeded picks) equal the oracle's, and every program's
+    return codes equal a plain launch's."""
+    import torch
+    from oracle import oracle as O
+    progs, sizes = W.batched_workload(256)
+    runs = []
+    for i, (pol, n) in enumerate(zip(progs, sizes)):
+        fds, prog = setup(rt, pol)
+        h = W.gen_mem_uniform(int(n), W.subseed(1003, 1000 + i))
+        runs.append((pol, fds, prog, h, to_device(h), torch.zeros(int(n), dtype=torch.int32, device="cuda")))
+    rt.autotune_batches([(p, d, len(h), 24, rc) for _, _, p, h, d, rc in runs])
+    rt.run_batches([(p, d, len(h), 24, rc) for _, _, p, h, d, rc in runs])
+    torch.cuda.synchronize()
+    pick = set(np.random.default_rng(1003).choice(256, 14, replace=False).tolist())
+    pick |= {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    batched_rc = [rc.cpu().numpy().view(np.uint32).copy() for *_, rc in runs]
+    for i in sorted(pick):
+        pol, fds, prog, h, d, rc = runs[i]
+        o = O.Oracle()
+        for m in pol.maps:
+            o.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags)
+        assert np.array_equal(batched_rc[i], o.run(pol.code, pol.hook, h)), f"program {i}: rc"
+        for mi, m in enumerate(pol.maps):
+            k, v = rt.map_dump(fds[mi])
+            ko, vo = o.dump(mi)
+            if m.type == W.MAP_ARRAY:
+                assert v.tobytes() == vo.tobytes(), f"program {i}: map {mi}"
+            else:
+                assert normalise_hash(k, v) == normalise_hash(ko, vo), f"program {i}: map {mi}"
+        _log(f"batched program {i} ({len(h)} events) matches the oracle")
+    # plain launches of every program on cleared maps give the same rc
+    for pol, fds, prog, h, d, rc in runs:
+        for fd in fds:
+            rt.map_clear(fd)
+        rt.run_batch(prog, d, n_events=len(h), record_size=24, rc=rc)
+    torch.cuda.synchronize()
+    for i, (*_, rc) in enumerate(runs):
+        assert np.array_equal(rc.cpu().numpy().view(np.uint32), batched_rc[i]), f"program {i}: plain vs batched"
+    st = rt.stats()
+    assert st["hash_e2big"] == 0 and st["vm_errors"] == 0

@@ -57,6 +57,19 @@ def test_jit_stride_prefetch(rt, n, streams):
     assert g.stats["hash_e2big"] == 0 and g.stats["ring_drops"] == 0 and g.stats["vm_errors"] == 0
 
 
+def test_jit_stride_prefetch_shared_queues(rt, monkeypatch):
+    """64 queues for 1024 streams: 16 streams per queue, whose keys collide
+    in the lookup memo of the one-queue kernel."""
+    _log("jit stride_prefetch on 64 queues")
+    monkeypatch.setenv("GX_SEQ_LANES", "1")
+    monkeypatch.setenv("GX_QUEUE_BITS", "6")
+    pol = W.stride_prefetch_policy()
+    ev = W.gen_mem_stride(1 << 17, 4242)
+    g = gpu_run(rt, pol, ev, jit=True)
+    assert_same(g, oracle_run(pol, ev), "stride_prefetch")
+    assert g.stats["hash_e2big"] == 0 and g.stats["ring_drops"] == 0 and g.stats["vm_errors"] == 0
+
+
 @pytest.mark.parametrize("i", range(8))
 def test_jit_generated_programs(rt, i):
     pol = W.gen_program(W.subseed(1003, 100 + i))

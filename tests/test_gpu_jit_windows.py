@@ -57,3 +57,19 @@ def test_window_programs_in_a_set(rt):
         g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
         assert_same(g, oracle_run(pol, ev), pol.name)
     assert rt.stats()["vm_errors"] == 0
+
+
+@pytest.mark.parametrize("name", sorted(P.PROGRAMS))
+def test_window_programs_with_shared_queues(rt, monkeypatch, name):
+    """One queue per wave over 64 queues: streams s and s + 64 share a queue,
+    and their keys (stream << 32 | page & 7) fall on the same entry of the
+    64-entry lookup memo, so entries are evicted by a colliding key and the
+    first key is looked up again after stores through its window."""
+    print(f"window program {name} on shared queues", flush=True)
+    monkeypatch.setenv("GX_SEQ_LANES", "1")
+    monkeypatch.setenv("GX_QUEUE_BITS", "6")
+    pol = P.policy(name)
+    ev = W.gen_mem_uniform(1 << 15, 9, streams=128)
+    g = gpu_run(rt, pol, ev, jit=True)
+    assert_same(g, oracle_run(pol, ev), name)
+    assert g.stats["vm_errors"] == 0 and g.stats["hash_e2big"] == 0
