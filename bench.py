@@ -69,31 +69,40 @@ def measured_traffic(fingerprint):
     return None, None
 
 
-def cpu_baseline(pol, ev, streams_in_sample):
-    """The oracle, single-threaded, on the events of a subset of streams (a
-    valid sub-run: streams are independent)."""
-    import numpy as np
-    from oracle import oracle as O
-    sel = np.isin(ev["stream"], np.arange(streams_in_sample, dtype=np.uint32))
-    sample = np.ascontiguousarray(ev[sel])
-    o = O.Oracle()
-    for m in pol.maps:
-        o.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags)
-    t0 = time.perf_counter()
-    o.run(pol.code, pol.hook, sample)
-    dt = time.perf_counter() - t0
-    st = o.stats()
-    return {
-        "value": len(sample) / dt,
-        "unit": "events/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"stride-prefetch events of streams 0..{streams_in_sample - 1} "
-                  f"({len(sample)} of {len(ev)} events, one batch), single thread",
-        "seconds": dt,
-        "insns_per_event": st["insns"] / max(len(sample), 1),
-        "insns_per_s": st["insns"] / dt,
-    }
+def cpu_trials(code, hook, shapes, ev, event_parallel, threads, trials=10, init=None):
+    """The oracle on ``threads`` host threads over one whole batch (split by
+    stream, or by event range for event-parallel programs), ``trials``
+    times from fresh maps: median and geometric mean of events/s and
+    eBPF instructions/s."""
+    from oracle import parallel as P
+
+    def trial():
+        dt, oracles, _, _ = P.run_parallel(code, hook, shapes, ev, event_parallel, threads, init)
+        return dt, len(ev), P.insns(oracles)
+    return P.trials(trial, trials)
+
+
+def cpu_line(r, threads, sample):
+    """A cpu_baseline object from cpu_trials' figures."""
+    from oracle import parallel as P
+    return {"value": r["median"], "unit": "events/s", "cores": threads, "kind": "oracle", "sample": sample,
+            "geomean": r["geomean"], "insns_per_s": r["insns_median"], "insns_per_s_geomean": r["insns_geomean"],
+            "trials": r["trials"], "cpu": P.host_cpu_model()}
+
+
+def cpu_baseline(pol, ev, threads, trials=10):
+    """Headline baseline: the stride-prefetch batch on ``threads`` threads."""
+    shapes = [(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+    r = cpu_trials(pol.code, pol.hook, shapes, ev, False, threads, trials)
+    line = cpu_line(r, threads, f"one whole stride-prefetch batch ({len(ev)} events, 1024 streams) split by "
+                                f"stream over {threads} threads, each with its own oracle and maps; "
+                                f"median of {trials} trials")
+    line["insns_per_event"] = r["insns_median"] / r["median"]
+    return line
+
+
+def _shapes(pol):
+    return [(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
 
 
 def _pct(x, q):
@@ -102,10 +111,11 @@ def _pct(x, q):
 
 
 def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=None, ring_fd=None, jit=True,
-                         tuned=True):
+                         tuned=True, cpu=None):
     """Back-to-back plain launches of an event-parallel policy over rotated
     resident batches; events/s from the wall clock, HBM fraction from the VM
-    kernel's own time (record + rc + ring bytes per event)."""
+    kernel's own time (record + rc + ring bytes per event).  ``cpu``:
+    (host events, map init, threads, sample text) for the oracle baseline."""
     import torch
     fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
     prog = rt.load_program(pol.code, pol.hook, fds)
@@ -146,7 +156,13 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     rt.profile_enable(False)
     vm_s = vm_ms / 1000 / max(launches, 1)
     alg = n * (pol.record_size + 4) + ring[0] / steps
+    cpu_out = None
+    if cpu is not None and cpu[2]:
+        ev_h, init_h, threads, sample = cpu
+        cpu_out = cpu_line(cpu_trials(pol.code, pol.hook, _shapes(pol), ev_h, True, threads, 10, init_h), threads,
+                           sample)
     return {
+        "cpu_baseline": cpu_out,
         "workload": name,
         "engine": "jit" if jit else "interp",
         "blocks": (tune["blocks"] or "sized per run") if tune else "default",
@@ -159,7 +175,7 @@ def bench_event_parallel(G, W, rt, name, pol, batches, steps, init_per_batch=Non
     }
 
 
-def bench_memory_bound(G, W, rt, steps, jit=True):
+def bench_memory_bound(G, W, rt, steps, jit=True, threads=0):
     """The two event-parallel policies: access counter (2^20 records, 48
     rotated batches = 1.1 GiB) and latency histogram (2^26 records, 2 rotated
     batches = 2 GiB, ring drained every launch)."""
@@ -167,9 +183,12 @@ def bench_memory_bound(G, W, rt, steps, jit=True):
     import torch
     out = {}
     acc = [torch.from_numpy(W.gen_mem_uniform(1 << 20, 1000 + k).view(np.uint8)).cuda() for k in range(48)]
+    acc_cpu = (np.concatenate([W.gen_mem_uniform(1 << 20, 1000 + k) for k in range(8)]), None, threads,
+               f"8 access-counter batches (2^23 events) split by event range over {threads} threads, each with its "
+               "own oracle and maps (summed); median of 10 trials")
     out["access_counter"] = bench_event_parallel(
         G, W, rt, "access counter, 2^20 x 24 B records, ARRAY 4096 x u64 shared", W.access_counter_policy(), acc,
-        steps * 20, jit=jit)
+        steps * 20, jit=jit, cpu=acc_cpu)
     if jit:
         # the plain single-program configuration names the interpreter
         out["access_counter_interpreted"] = bench_event_parallel(
@@ -179,51 +198,121 @@ def bench_memory_bound(G, W, rt, steps, jit=True):
     hosts = [W.gen_timing(1 << 26, 1002 + k) for k in range(2)]
     init = [[(1, b"\0\0\0\0", np.uint64(W.p99_threshold(h["lat"])).tobytes())] for h in hosts]
     lat = [torch.from_numpy(h.view(np.uint8)).cuda() for h in hosts]
+    lat_cpu = (np.ascontiguousarray(hosts[0][:1 << 24]), init[0], threads,
+               f"the first 2^24 events of a latency-histogram batch split by event range over {threads} threads "
+               "(own oracles and maps, summed); median of 10 trials")
     del hosts
     out["latency_hist"] = bench_event_parallel(
         G, W, rt, "latency histogram + p99 tail records, 2^26 x 16 B records, ARRAY 4096 x 64 x u64 shared, "
-        "64 MiB ring", W.latency_hist_policy(), lat, steps, init_per_batch=init, ring_fd=2, jit=jit)
+        "64 MiB ring", W.latency_hist_policy(), lat, steps, init_per_batch=init, ring_fd=2, jit=jit, cpu=lat_cpu)
     del lat
     torch.cuda.empty_cache()
     return out
 
 
-def bench_warp_leader(G, W, rt, steps, jit=True):
-    """Warp-level execution (the warp-leader hook) against per-record
-    execution on the same records: the wave monitor runs once per tile of 64
-    records on the tile's aggregate; the access counter runs once per
-    record.  2^24 wave-shaped records, 2 rotated batches."""
+def bench_warp_leader(G, W, rt, steps, jit=True, threads=0):
+    """Warp-level execution (section 4.4) on 2^24 wave-shaped records, two
+    rotated batches: the same counting handler once per tile of 64 records
+    (warp-leader hook, on the tile's aggregate) and once per record (SIMT
+    hook: verified warp-uniform, each lane's +1 combined into one update per
+    wave), checked to give the same return codes and maps."""
     import numpy as np
     import torch
     hosts = [W.gen_mem_wave(1 << 24, 1005 + k) for k in range(2)]
     dev = [torch.from_numpy(h.view(np.uint8)).cuda() for h in hosts]
+    sample = (hosts[0], None, threads, f"one batch of 2^24 records split at tile boundaries over {threads} threads "
+                                       "(own oracles and maps); median of 10 trials")
     del hosts
     out = {
-        "warp_leader": bench_event_parallel(G, W, rt, "wave monitor (warp-leader hook), 2^24 x 24 B records",
-                                            W.wave_monitor_policy(), dev, steps, ring_fd=2, jit=jit),
-        "per_record": bench_event_parallel(G, W, rt, "access counter (per-record hook), same records",
-                                           W.access_counter_policy(), dev, steps, jit=jit),
+        "warp_leader": bench_event_parallel(G, W, rt, "wave counts, warp-leader hook (once per tile), 2^24 x 24 B "
+                                            "records", W.wave_counts_policy(False), dev, steps, jit=jit, cpu=sample),
+        "per_lane_simt": bench_event_parallel(G, W, rt, "the same counting per record, SIMT hook", W.wave_counts_policy(True),
+                                              dev, steps, jit=jit, cpu=sample),
     }
-    out["speedup"] = out["warp_leader"]["vm_events_per_s"] / out["per_record"]["vm_events_per_s"]
+    # equal output: each handler once over the same batch on fresh maps
+    res = []
+    n = dev[0].numel() // 24
+    for simt in (False, True):
+        pol = W.wave_counts_policy(simt)
+        fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+        prog = rt.load_program(pol.code, pol.hook, fds)
+        if jit:
+            rt.jit_program(prog)
+        rc = torch.zeros(n, dtype=torch.int32, device="cuda")
+        rt.run_batch(prog, dev[0], n_events=n, record_size=24, rc=rc)
+        torch.cuda.synchronize()
+        res.append((rc.cpu().numpy().tobytes(), [rt.map_dump(fd)[1].tobytes() for fd in fds]))
+    out["same_output"] = res[0] == res[1]
+    out["per_lane_over_leader_time"] = out["per_lane_simt"]["vm_kernel_us"] / out["warp_leader"]["vm_kernel_us"]
     del dev
     torch.cuda.empty_cache()
     return out
 
 
-def bench_batched(G, W, rt, reps):
+def cpu_runs(items, threads, trials=10, budget_s=20.0):
+    """Independent runs (policy, events) on ``threads`` threads, each run on
+    a fresh oracle, runs handed to the least-loaded thread largest first:
+    median and geometric mean of events/s and insns/s over ``trials``."""
+    from oracle import parallel as P
+    load = [0] * threads
+    mine = [[] for _ in range(threads)]
+    for it in sorted(items, key=lambda it: -len(it[1])):
+        t = load.index(min(load))
+        mine[t].append(it[:2])
+        load[t] += len(it[1])
+    total = sum(len(it[1]) for it in items)
+    shapes = {id(it[0]): (it[2] if len(it) > 2 else _shapes(it[0])) for it in items}
+
+    def trial():
+        oracles = [[P.new_oracle(shapes[id(pol)]) for pol, _ in m] for m in mine]
+
+        def work(t):
+            for o, (pol, ev) in zip(oracles[t], mine[t]):
+                o.run(pol.code, pol.hook, ev)
+        t0 = time.perf_counter()
+        P.run_threads([lambda t=t: work(t) for t in range(threads)])
+        dt = time.perf_counter() - t0
+        return dt, total, sum(P.insns(os_) for os_ in oracles)
+    return P.trials(trial, trials, budget_s)
+
+
+def _digest(rt, fds_list):
+    """sha256 over the contents of every map of every run (hash maps as
+    sorted pairs: their slot layout is not part of the result)."""
+    import hashlib
+    h = hashlib.sha256()
+    for fds in fds_list:
+        for fd in fds:
+            k, v = rt.map_dump(fd)
+            if rt.maps[fd].type == 1:
+                for a, b in sorted(zip(map(bytes, k), map(bytes, v))):
+                    h.update(a + b)
+            else:
+                h.update(v.tobytes())
+    return h.hexdigest()
+
+
+def bench_batched(G, W, rt, reps, threads=0):
     """256 generated programs over their own batches (2^10..2^20 events):
-    one batched launch against 256 plain launches in order, same outputs."""
+    256 plain launches in order against one batched call, interpreted; then
+    the same batched call with the programs compiled into four program sets
+    (one persistent launch per set), and its replay as a HIP graph.  Every
+    form gives the same return codes and maps."""
     import numpy as np
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     progs, sizes = W.batched_workload(256)
     stream = torch.cuda.current_stream()
-    runs = []
+    runs, hosts = [], []
     for i, (pol, n) in enumerate(zip(progs, sizes)):
         fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
         prog = rt.load_program(pol.code, pol.hook, fds)
-        ev = torch.from_numpy(W.gen_mem_uniform(int(n), W.subseed(1003, 1000 + i)).view(np.uint8)).cuda()
+        h = W.gen_mem_uniform(int(n), W.subseed(1003, 1000 + i))
+        hosts.append(h)
+        ev = torch.from_numpy(h.view(np.uint8)).cuda()
         runs.append((prog, fds, ev, int(n), torch.zeros(int(n), dtype=torch.int32, device="cuda")))
     total = int(sizes.sum())
+    descs = [(prog, ev, n, 24, rc) for prog, _, ev, n, rc in runs]
 
     def reset():
         for _, fds, _, _, _ in runs:
@@ -236,14 +325,11 @@ def bench_batched(G, W, rt, reps):
             rt.run_batch(prog, ev, n_events=n, record_size=24, rc=rc, stream=stream)
 
     def batched():
-        rt.run_batches([(prog, ev, n, 24, rc) for prog, _, ev, n, rc in runs], stream=stream)
+        rt.run_batches(descs, stream=stream)
 
-    res = {}
-    rcs = {}
-    # the batched form's autotuner picks the persistent launch's waves per CU
-    reset()
-    tune = rt.autotune_batches([(prog, ev, n, 24, rc) for prog, _, ev, n, rc in runs], stream=stream)
-    for name, fn in (("plain", plain), ("batched", batched)):
+    res, rcs, maps = {}, {}, {}
+
+    def timed(name, fn):
         ts = []
         for r in range(reps + 1):
             reset()
@@ -254,20 +340,53 @@ def bench_batched(G, W, rt, reps):
                 ts.append(time.perf_counter() - t0)
         res[name] = total / float(np.median(ts))
         rcs[name] = torch.cat([rc for *_, rc in runs]).clone()
-    same = bool(torch.equal(rcs["plain"], rcs["batched"]))
-    del runs
+        maps[name] = _digest(rt, [fds for _, fds, *_ in runs])
+
+    # the batched form's autotuner picks the persistent launch's waves per CU
+    reset()
+    tune = rt.autotune_batches(descs, stream=stream)
+    timed("plain", plain)
+    timed("batched", batched)
+    # the same programs compiled: four program sets of 64 (one persistent
+    # kernel each); plain runs keep interpreting
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(4) as ex:
+        list(ex.map(lambda k: rt.jit_program_set([runs[i][0] for i in range(k, 256, 4)]), range(4)))
+    compile_s = time.perf_counter() - t0
+    log(f"batched: compiled 4 program sets of 64 in {compile_s:.1f} s")
+    timed("batched_sets", batched)
+    graph = rt.graph_create(descs)
+    timed("graph_sets", lambda: graph.launch(stream))
+    graph.close()
+    names = ["plain", "batched", "batched_sets", "graph_sets"]
+    same_rc = all(bool(torch.equal(rcs["plain"], rcs[k])) for k in names)
+    same_maps = all(maps["plain"] == maps[k] for k in names)
+    cpu_out = None
+    if threads:
+        items = [(progs[i], hosts[i]) for i in range(0, 256, 8)]
+        n_s = sum(len(h) for _, h in items)
+        cpu_out = cpu_line(cpu_runs(items, threads), threads,
+                           f"32 of the 256 programs (every 8th, {n_s} events) on {threads} threads, one oracle per "
+                           "program, largest first to the least-loaded thread; median of up to 10 trials (20 s)")
+    del runs, hosts
     torch.cuda.empty_cache()
     return {
         "workload": f"256 generated programs (16-512 slots), own batches of 2^10..2^20 records, {total} events",
         "plain_events_per_s": res["plain"],
         "batched_events_per_s": res["batched"],
         "speedup": res["batched"] / res["plain"],
-        "same_rc": same,
+        "batched_sets_events_per_s": res["batched_sets"],
+        "graph_sets_events_per_s": res["graph_sets"],
+        "speedup_sets": res["batched_sets"] / res["plain"],
+        "set_compile_s": compile_s,
+        "same_rc": same_rc,
+        "same_maps": same_maps,
         "waves_per_cu": tune["waves_per_cu"],
+        "cpu_baseline": cpu_out,
     }
 
 
-def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
+def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True, threads=0, sustained_s=10.0, sustained_warm_s=1.0):
     """Open-loop Poisson trace (20k requests/s, 64 tenants, 32 programs,
     2^8..2^18 events per request, 256 MiB of hash map per tenant = 16 GiB
     resident) through the continuous server and the per-request baseline.
@@ -304,7 +423,7 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
     pool = torch.from_numpy(W.gen_mem_uniform(slices << 18, 1004).view(np.uint8)).pin_memory()
     base = pool.data_ptr()
 
-    def serve(rate, secs, mode):
+    def serve(rate, secs, mode, warm_s=warm_s):
         n_req = int(rate * (secs + warm_s))
         arrival, tenant, _, n_ev = W.serving_trace(n_req, rate_per_s=rate)
         for fds, _ in tenants:
@@ -352,13 +471,30 @@ def bench_serving(G, W, rt, seconds, warm_s=0.2, jit=True):
         out[name] = serve(20000.0, seconds, mode)
     mean_ev = float(np.mean(W.serving_trace(100000)[3]))
     rate = 0.6 * out["continuous"]["events_per_s"] / mean_ev
-    out["at_60pct_of_continuous"] = {"requests_per_s": rate}
+    # a load the device sustains, run for the measurement's full length
+    out["at_60pct_of_continuous"] = {"requests_per_s": rate, "seconds": sustained_s, "warmup_s": sustained_warm_s}
     for mode, name in modes:
-        out["at_60pct_of_continuous"][name] = serve(rate, 2.0 * seconds, mode)
+        out["at_60pct_of_continuous"][name] = serve(rate, sustained_s, mode, sustained_warm_s)
     n_req = int(20000 * (seconds + warm_s))
     out["workload"] = (f"{n_req} requests, Poisson 20k/s, 64 tenants x 256 MiB resident hash map, 32 generated "
                        f"programs, 2^8..2^18 events per request, 4 GiB admission budget, first {warm_s}s excluded")
     out["engine"] = "jit" if jit else "interp"
+    if threads:
+        # the oracle over the trace's first requests: each tenant's requests
+        # in order on its own oracle (maps), tenants spread over the threads
+        n_s = 400
+        _, tenant, _, n_ev = W.serving_trace(n_s)
+        pool_h = pool.numpy().view(W.MEM_DTYPE)
+        per = {}
+        for i in range(n_s):
+            per.setdefault(int(tenant[i]), []).append(pool_h[(i % slices) << 18:((i % slices) << 18) + int(n_ev[i])])
+        items = [(progs[t % 32], np.concatenate(v),
+                  [(m.type, m.key_size, m.value_size, (1 << 22) if m.type == W.MAP_HASH else m.max_entries, m.flags)
+                   for m in progs[t % 32].maps]) for t, v in per.items()]
+        out["cpu_baseline"] = cpu_line(cpu_runs(items, threads), threads,
+                                       f"the trace's first {n_s} requests ({int(n_ev.sum())} events): each tenant's "
+                                       f"requests in order on its own oracle, tenants over {threads} threads; "
+                                       "median of up to 10 trials (20 s)")
     return out
 
 
@@ -369,7 +505,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events-log2", type=int, default=24)
     ap.add_argument("--batches", type=int, default=2)
-    ap.add_argument("--cpu-streams", type=int, default=192)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle baselines (0: the CPUs available, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--engine", choices=["jit", "interp"], default="jit",
                     help="run the program compiled to native code (jit) or interpreted")
@@ -402,12 +539,17 @@ def main():
         log(f"copied {args.copy_calib_mib} MiB device to device")
         del src, dst
 
+    threads = 0
+    if not args.no_cpu:
+        from oracle import parallel as P
+        threads = args.cpu_threads or P.host_threads()
+
     if args.only_form:
         rt = G.Runtime(0)
-        fn = {"memory_bound": lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit"),
-              "warp_leader": lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit"),
-              "batched": lambda: bench_batched(G, W, rt, 2),
-              "serving": lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit")}
+        fn = {"memory_bound": lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit", threads),
+              "warp_leader": lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit", threads),
+              "batched": lambda: bench_batched(G, W, rt, 2, threads),
+              "serving": lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit", threads=threads)}
         print(json.dumps({args.only_form: fn[args.only_form]()}))
         rt.close()
         return
@@ -471,10 +613,11 @@ def main():
     forms = None
     if not args.no_forms:
         forms = {}
-        for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit")),
-                        ("warp_leader", lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit")),
-                        ("batched", lambda: bench_batched(G, W, rt, 2)),
-                        ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit"))):
+        for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit", threads)),
+                        ("warp_leader", lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit", threads)),
+                        ("batched", lambda: bench_batched(G, W, rt, 2, threads)),
+                        ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit",
+                                                           threads=threads))):
             log(f"form: {key}")
             try:
                 forms[key] = fn()
@@ -486,7 +629,7 @@ def main():
     insns_per_event = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(pol, host_batches[0], args.cpu_streams)
+        cpu = cpu_baseline(pol, host_batches[0], threads)
         insns_per_event = cpu["insns_per_event"]
 
     tune_lanes = tune["lanes"] if tune else int(os.environ.get("GX_SEQ_LANES", "1"))
@@ -542,8 +685,7 @@ def main():
         # chain (map state carried from event to event), run one after another
         "chain": {"streams": 1024, "events_per_stream": n / 1024,
                   "ns_per_event": vm_avg_s * 1e9 / (n / 1024)},
-        "cpu_baseline": {k: v for k, v in cpu.items() if k in ("value", "unit", "cores", "kind", "sample")}
-        if cpu else None,
+        "cpu_baseline": {k: v for k, v in cpu.items() if k != "insns_per_event"} if cpu else None,
         "stats": st,
         "forms": forms,
     }

@@ -42,6 +42,11 @@ enum {
   GX_F_SHARED = 1u,
   /* Written by the host only: lookups and loads only. */
   GX_F_READ_ONLY = 2u,
+  /* With GX_F_READ_ONLY: the map lives in host memory (pinned, mapped into
+   * the device's address space) instead of device memory: the cold tier of
+   * section 4.4's hierarchical maps, for large host-written state that the
+   * device reads rarely (each device read crosses the host link). */
+  GX_F_HOST = 4u,
 };
 
 /* Hook types: select the event record layout and the stream key.
@@ -60,16 +65,34 @@ enum {
  *                         stream_id of the tile's first record}, and every
  *                         record of the tile gets its return code.  Its
  *                         maps must be shared, read-only or ring buffers.
+ *   GX_HOOK_SIMT_MEM      SIMT-aware per-lane hook (section 4.4, "SIMT-aware
+ *                         Verification"): input records as
+ *                         GX_HOOK_MEM_ACCESS, one invocation per record,
+ *                         whose ctx is the record (bytes 0..23, lane-
+ *                         varying) followed by its tile's aggregate as for
+ *                         GX_HOOK_WAVE_MEM (bytes 24..47, warp-uniform).
+ *                         The verifier tracks uniformity from these fields
+ *                         and rejects lane-varying branch conditions (loop
+ *                         exits included), map keys, ring records and
+ *                         flags, map-update addresses and fetching map
+ *                         atomics; maps must be shared, read-only or ring
+ *                         buffers.  Waves then never split, and a wave's
+ *                         shared-map updates (one word) are combined into
+ *                         one.
  * The record (or aggregate) is the program's read-only ctx (r1). */
 enum {
   GX_HOOK_MEM_ACCESS = 1,
   GX_HOOK_KERNEL_TIMING = 2,
   GX_HOOK_WAVE_MEM = 3,
+  GX_HOOK_SIMT_MEM = 4,
 };
 
-/* Execution modes chosen by the verifier (section 4.4's deterministic
- * reading): a program that touches only shared, read-only and ring maps is
- * event-parallel; any other program runs each stream's events in order. */
+/* Execution modes chosen by the verifier.  They follow from this runtime's
+ * deterministic map contract, which replaces the relaxed, eventually
+ * consistent maps of section 4.4 (each stream's events run in index order;
+ * shared maps take commutative atomics only): a program that touches only
+ * shared, read-only and ring maps is event-parallel; any other program
+ * runs each stream's events in order. */
 enum {
   GX_MODE_EVENT_PARALLEL = 0,
   GX_MODE_STREAM_SEQUENTIAL = 1,
@@ -100,14 +123,16 @@ int gx_open(int hip_device, gx_rt** out);
 /* Free every map and program of the runtime, then the runtime. */
 void gx_close(gx_rt* rt);
 
-/* Create a map (section 4.4, "Hierarchical Cross-layer Maps"; here every map
- * lives in device memory).  Returns a map fd >= 0.
+/* Create a map (section 4.4, "Hierarchical Cross-layer Maps": device memory,
+ * or host memory for GX_F_HOST; LDS shards are the kernels' own, and host
+ * snapshots are gx_snapshot_*).  Returns a map fd >= 0.
  *   ARRAY:   key_size 4 (u32 index), value_size 1..4096, max_entries >= 1;
  *            values start zeroed.
  *   HASH:    key_size 1..64, value_size 1..4096, max_entries >= 1.
  *   RINGBUF: key_size = value_size = 0, max_entries = data bytes, a power of
  *            two >= 4096.
- * flags: GX_F_SHARED or GX_F_READ_ONLY (not both; not on a ring).
+ * flags: GX_F_SHARED or GX_F_READ_ONLY (not both; not on a ring);
+ * GX_F_HOST only together with GX_F_READ_ONLY, on arrays and hashes.
  * Errors: -EINVAL bad sizes or flags; -ENOMEM. */
 int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_size,
                   uint32_t max_entries, uint32_t flags);
@@ -280,6 +305,35 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
  * Waits for the runtime's launches like a drain; -EINVAL if ring_fd is not
  * a ring or an output pointer is null. */
 int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail);
+
+/* Host snapshots of device maps (section 4.4, "Hierarchical Cross-layer
+ * Maps": GPU-resident state flushed asynchronously to host-visible
+ * instances at kernel completion boundaries, so that host-side readers get
+ * a coherent view without synchronising with the device).
+ *
+ * gx_snapshot_start: a daemon thread copies the n maps (arrays or hashes)
+ * every interval_us microseconds into pinned host buffers.  Each copy is
+ * issued on ``stream`` (the stream the maps' runs go to) between two runs
+ * (never inside one), so a snapshot is the maps' state after some prefix
+ * of the runs issued on that stream, identical for all n maps.  One daemon
+ * per runtime: -EBUSY if one runs, -EINVAL for a bad fd or a ring, -ENOMEM.
+ *
+ * gx_snapshot_read: the latest snapshot of one map, without touching the
+ * device (relaxed consistency: up to an interval plus the runs in flight
+ * behind the exact state that gx_map_dump returns).  Same output as
+ * gx_map_dump; *version (may be NULL) is the snapshot's sequence number,
+ * 0 before the first.  -ENOENT if the map is not snapshotted.
+ *
+ * gx_snapshot_flush: take a snapshot now, after every run issued on the
+ * daemon's stream so far, and wait for it (after it, gx_snapshot_read
+ * equals gx_map_dump if nothing else ran).  -ENOENT if no daemon runs.
+ *
+ * gx_snapshot_stop: stop the daemon and free its buffers (also done by
+ * gx_close). */
+int gx_snapshot_start(gx_rt* rt, const int* map_fds, uint32_t n, uint64_t interval_us, void* stream);
+int64_t gx_snapshot_read(gx_rt* rt, int map_fd, void* keys, void* vals, uint64_t cap, uint64_t* version);
+int gx_snapshot_flush(gx_rt* rt);
+void gx_snapshot_stop(gx_rt* rt);
 
 /* Counters accumulated since gx_open (synchronises the device). */
 int gx_stats_get(gx_rt* rt, gx_stats* out);

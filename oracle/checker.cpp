@@ -24,7 +24,15 @@
 //     read-only maps take only lookups and loads; value pointers into a hash
 //     map die at the next update or delete of that map;
 //   * budgets: 65536 dynamic instructions, 64 helper calls and 4096 ring
-//     bytes per invocation.
+//     bytes per invocation;
+//   * SIMT hook: every value is warp-uniform or lane-varying (the record's
+//     fields vary, its tile's aggregate is uniform; results vary if an
+//     operand does; stack bytes carry the kind of what was stored); branch
+//     conditions (loop bounds included), map keys, ring records and their
+//     flags, and the addresses of map atomics must be uniform; the maps must
+//     be shared, read-only or ring buffers; fetching atomics on maps are
+//     refused; an atomic's operand may vary (the device combines a wave's
+//     operands into one update).
 #include <algorithm>
 #include <functional>
 #include <map>
@@ -48,6 +56,7 @@ struct AV {
   uint64_t lo = 0, hi = 0;  // scalar: unsigned range; pointer: signed offset range
   int tz = 0;               // known trailing zero bits
   int map = -1;
+  bool var = false;         // lane-varying (SIMT hook)
 };
 
 int ctz64(uint64_t v) { return v ? __builtin_ctzll(v) : 64; }
@@ -60,6 +69,7 @@ struct AState {
   bool live = false;
   AV r[11];
   uint8_t stk[STACK_BYTES];
+  uint8_t stkvar[STACK_BYTES];  // byte holds a lane-varying value (SIMT hook)
   uint64_t steps = 0, calls = 0, ring = 0;
 };
 
@@ -83,6 +93,7 @@ AV join_v(const AV& a, const AV& b) {
     r.hi = (uint64_t)std::max((int64_t)a.hi, (int64_t)b.hi);
   }
   r.tz = std::min(a.tz, b.tz);
+  r.var = a.var || b.var;
   return r;
 }
 
@@ -94,6 +105,7 @@ void join_into(AState& dst, const AState& src) {
   }
   for (int i = 0; i < 11; i++) dst.r[i] = join_v(dst.r[i], src.r[i]);
   for (int i = 0; i < STACK_BYTES; i++) dst.stk[i] = dst.stk[i] && src.stk[i];
+  for (int i = 0; i < STACK_BYTES; i++) dst.stkvar[i] = dst.stkvar[i] || src.stkvar[i];
   dst.steps = std::max(dst.steps, src.steps);
   dst.calls = std::max(dst.calls, src.calls);
   dst.ring = std::max(dst.ring, src.ring);
@@ -256,6 +268,7 @@ struct Checker {
   const std::vector<Insn>& ins;
   int n;
   int hook;
+  bool simt;  // SIMT hook: uniformity rules apply
   HookInfo hi;
   const std::vector<MapShape>& maps;
   const std::vector<int>& table;
@@ -267,7 +280,7 @@ struct Checker {
   std::vector<int> shared_op;  // per shared map: the one (atomic op, size) it takes, or -1
 
   Checker(const std::vector<Insn>& i, int h, const std::vector<MapShape>& m, const std::vector<int>& t)
-      : ins(i), n((int)i.size()), hook(h), maps(m), table(t) {}
+      : ins(i), n((int)i.size()), hook(h), simt(h == HOOK_SIMT_MEM), maps(m), table(t) {}
 
   [[noreturn]] void rej(int pc, const std::string& m) {
     std::ostringstream os;
@@ -498,12 +511,13 @@ struct Checker {
   }
 
   // Check an access of ``size`` bytes at base + off; mode 0 load, 1 store,
-  // 2 commutative atomic, 3 fetching atomic.
-  void access(AState& s, int pc, const AV& b, int64_t off, int size, int mode) {
+  // 2 commutative atomic, 3 fetching atomic.  ``sv``: whether the stored
+  // value is lane-varying.  Returns whether the bytes read are.
+  bool access(AState& s, int pc, const AV& b, int64_t off, int size, int mode, bool sv = false) {
     if (b.k == A_CTX) {
       if (mode != 0) rej(pc, "write to ctx");
       for (auto& f : hi.fields)
-        if ((int64_t)f.first == off && (int)f.second == size) return;
+        if ((int64_t)f.first == off && (int)f.second == size) return simt && (uint64_t)off < hi.uniform_off;
       rej(pc, "bad ctx access");
     }
     if (b.k == A_STACK) {
@@ -514,10 +528,16 @@ struct Checker {
       if (mode != 1)
         for (int i = 0; i < size; i++)
           if (!s.stk[o + i]) rej(pc, "read of uninitialised stack");
+      bool v = false;
+      if (mode != 1)
+        for (int i = 0; i < size; i++) v = v || s.stkvar[o + i];
       if (mode != 0)
-        for (int i = 0; i < size; i++) s.stk[o + i] = 1;
+        for (int i = 0; i < size; i++) {
+          s.stk[o + i] = 1;
+          s.stkvar[o + i] = mode == 1 ? sv : (s.stkvar[o + i] || sv);
+        }
       min_stack = std::min<int>(min_stack, (int)o);
-      return;
+      return v;
     }
     if (b.k == A_MAPVAL) {
       const MapShape& m = maps[b.map];
@@ -525,6 +545,8 @@ struct Checker {
       if (lo < 0 || hi2 + size > (int64_t)m.value_size) rej(pc, "map value access out of bounds");
       if (lo % size) rej(pc, "misaligned map value access");
       if (b.lo != b.hi && b.tz < __builtin_ctz(size)) rej(pc, "possibly misaligned map value access");
+      if (simt && mode != 0 && b.var) rej(pc, "lane-varying map address of an update (SIMT hook)");
+      if (simt && mode == 3) rej(pc, "fetching atomic on a map (SIMT hook: non-uniform atomic)");
       if ((m.flags & F_READ_ONLY) && mode != 0) rej(pc, "write to read-only map");
       if ((m.flags & F_SHARED) && mode != 2) rej(pc, "shared map takes only commutative atomics");
       if (m.flags & F_SHARED) {
@@ -534,13 +556,15 @@ struct Checker {
         if (shared_op[b.map] < 0) shared_op[b.map] = key;
         else if (shared_op[b.map] != key) rej(pc, "shared map updated with different atomic operations");
       }
-      return;
+      return b.var;
     }
     if (b.k == A_MAPVAL_OR_NULL) rej(pc, "map value access without null check");
     rej(pc, "memory access through non-pointer");
   }
 
-  void arg_mem(AState& s, int pc, int reg, uint32_t nbytes) {
+  // A helper's memory argument; ``what`` names it when the SIMT hook needs
+  // it warp-uniform (nullptr: it may vary).
+  void arg_mem(AState& s, int pc, int reg, uint32_t nbytes, const char* what = nullptr) {
     const AV& b = rd(s, pc, reg);
     if (b.k == A_STACK) {
       if (b.lo != b.hi) rej(pc, "variable-offset stack argument");
@@ -548,6 +572,9 @@ struct Checker {
       if (o < 0 || o + (int64_t)nbytes > STACK_BYTES) rej(pc, "stack argument out of bounds");
       for (uint32_t i = 0; i < nbytes; i++)
         if (!s.stk[o + i]) rej(pc, "helper reads uninitialised stack");
+      if (simt && what)
+        for (uint32_t i = 0; i < nbytes; i++)
+          if (s.stkvar[o + i]) rej(pc, std::string("lane-varying ") + what + " (SIMT hook)");
       min_stack = std::min<int>(min_stack, (int)o);
       return;
     }
@@ -556,6 +583,7 @@ struct Checker {
       if ((int64_t)b.lo < 0 || (int64_t)b.hi + (int64_t)nbytes > (int64_t)m.value_size)
         rej(pc, "map value argument out of bounds");
       if (m.flags & F_SHARED) rej(pc, "shared map value used as helper input");
+      if (simt && what && b.var) rej(pc, std::string("lane-varying ") + what + " (SIMT hook)");
       return;
     }
     rej(pc, "helper memory argument must point to stack or a map value");
@@ -572,15 +600,15 @@ struct Checker {
     if (id == H_LOOKUP) {
       int m = map_arg(s, pc, 1);
       if (maps[m].type == MAP_RINGBUF) rej(pc, "lookup on a ring buffer");
-      arg_mem(s, pc, 2, maps[m].key_size);
+      arg_mem(s, pc, 2, maps[m].key_size, "map key");
       s.r[0] = AV{A_MAPVAL_OR_NULL, 0, 0, 64, m};
     } else if (id == H_UPDATE || id == H_DELETE) {
       int m = map_arg(s, pc, 1);
       if (maps[m].type == MAP_RINGBUF) rej(pc, "update/delete on a ring buffer");
       if (maps[m].flags & (F_SHARED | F_READ_ONLY)) rej(pc, "update/delete on a shared or read-only map");
-      arg_mem(s, pc, 2, maps[m].key_size);
+      arg_mem(s, pc, 2, maps[m].key_size, "map key");
       if (id == H_UPDATE) {
-        arg_mem(s, pc, 3, maps[m].value_size);
+        arg_mem(s, pc, 3, maps[m].value_size, "map update value");
         if (rd(s, pc, 4).k != A_SCALAR) rej(pc, "update flags must be a scalar");
       }
       if (maps[m].type == MAP_HASH)
@@ -593,8 +621,9 @@ struct Checker {
       const AV& sz = rd(s, pc, 3);
       if (sz.k != A_SCALAR || sz.lo != sz.hi) rej(pc, "ringbuf_output size must be a constant");
       if (sz.lo == 0 || sz.lo > 4096) rej(pc, "ringbuf_output size out of range");
-      arg_mem(s, pc, 2, (uint32_t)sz.lo);
+      arg_mem(s, pc, 2, (uint32_t)sz.lo, "ring record");
       if (rd(s, pc, 4).k != A_SCALAR) rej(pc, "ringbuf_output flags must be a scalar");
+      if (simt && rd(s, pc, 4).var) rej(pc, "lane-varying ringbuf_output flags (SIMT hook)");
       s.ring += 8 + ((sz.lo + 7) & ~7ull);
       if (s.ring > kMaxRing) rej(pc, "ring byte budget exceeded");
       s.r[0] = unknown();
@@ -721,7 +750,9 @@ struct Checker {
         if (code == 0xd0 || code == 0x80) {
           const AV& a = rd(s, pc, in.dst);
           if (a.k != A_SCALAR) rej(pc, "ALU on a pointer");
+          const bool v = a.var;
           s.r[in.dst] = alu_scalar(is64, code, in.off, x, in.imm, a, exact(0));
+          s.r[in.dst].var = v;
           break;
         }
         AV b = x ? rd(s, pc, in.src) : exact(is64 ? (uint64_t)(int64_t)in.imm : (uint64_t)(uint32_t)in.imm);
@@ -731,13 +762,17 @@ struct Checker {
         }
         if (code == 0xb0) {
           if (b.k != A_SCALAR) rej(pc, "pointer leaked through 32-bit or sign-extending move");
+          const bool v = b.var;
           s.r[in.dst] = alu_scalar(is64, code, in.off, x, in.imm, exact(0), b);
+          s.r[in.dst].var = v;
           break;
         }
         const AV& a = rd(s, pc, in.dst);
         (void)a0;
+        const bool var = a.var || b.var;
         if (a.k == A_SCALAR && b.k == A_SCALAR) {
           s.r[in.dst] = alu_scalar(is64, code, in.off, x, in.imm, a, b);
+          s.r[in.dst].var = var;
           break;
         }
         if (!is64 || b.k != A_SCALAR || (code != 0x00 && code != 0x10) || (a.k != A_STACK && a.k != A_MAPVAL))
@@ -763,6 +798,7 @@ struct Checker {
           rej(pc, "unbounded pointer arithmetic");
         }
         if ((int64_t)r.lo < -(1ll << 40) || (int64_t)r.hi > (1ll << 40)) rej(pc, "pointer offset out of range");
+        r.var = var;
         s.r[in.dst] = r;
         break;
       }
@@ -787,6 +823,7 @@ struct Checker {
         }
         const AV& a = rd(s, pc, in.dst);
         AV b = x ? rd(s, pc, in.src) : exact(is32 ? (uint64_t)(uint32_t)in.imm : (uint64_t)(int64_t)in.imm);
+        if (simt && (a.var || b.var)) rej(pc, "lane-varying branch condition (SIMT hook)");
         if (a.k == A_MAPVAL_OR_NULL || a.k == A_MAPVAL) {
           if (is32 || x || in.imm != 0 || (code != 0x10 && code != 0x50))
             rej(pc, "pointer comparison other than a null check");
@@ -819,9 +856,10 @@ struct Checker {
       case 1: {
         int size = kSz[(in.op >> 3) & 3];
         const AV& b = rd(s, pc, in.src);
-        access(s, pc, b, in.off, size, 0);
+        const bool v = access(s, pc, b, in.off, size, 0);
         bool sx = (in.op & 0xe0) == 0x80;
         s.r[in.dst] = (size == 8 || sx) ? unknown() : range(0, (1ull << (8 * size)) - 1, 0);
+        s.r[in.dst].var = v;
         break;
       }
       case 2: {
@@ -836,16 +874,19 @@ struct Checker {
         const AV& v = rd(s, pc, in.src);
         if (v.k != A_SCALAR) rej(pc, "pointer stored to memory");
         if ((in.op & 0xe0) == 0x60) {
-          access(s, pc, b, in.off, size, 1);
+          access(s, pc, b, in.off, size, 1, v.var);
           break;
         }
         bool fetch = in.imm & 1;
         if (in.imm == 0xf1 && rd(s, pc, 0).k != A_SCALAR) rej(pc, "cmpxchg needs a scalar r0");
-        access(s, pc, b, in.off, size, fetch ? 3 : 2);
-        if (in.imm == 0xf1)
+        const bool ov = access(s, pc, b, in.off, size, fetch ? 3 : 2, v.var || (in.imm == 0xf1 && s.r[0].var));
+        if (in.imm == 0xf1) {
           s.r[0] = size == 8 ? unknown() : range(0, 0xffffffffull, 0);
-        else if (fetch)
+          s.r[0].var = ov;
+        } else if (fetch) {
           s.r[in.src] = size == 8 ? unknown() : range(0, 0xffffffffull, 0);
+          s.r[in.src].var = ov;
+        }
         break;
       }
       case 0: {
@@ -927,6 +968,7 @@ struct Checker {
       s.r[1] = AV{A_CTX, 0, 0, 64, -1};
       s.r[10] = AV{A_STACK, (uint64_t)STACK_BYTES, (uint64_t)STACK_BYTES, 9, -1};
       std::fill(std::begin(s.stk), std::end(s.stk), 0);
+      std::fill(std::begin(s.stkvar), std::end(s.stkvar), 0);
       std::map<int, AState> outer;
       region(0, n - 1, s, outer, nullptr);
       if (!outer.empty()) rej(outer.begin()->first, "edge leaves the program");
@@ -938,6 +980,8 @@ struct Checker {
           ep = false;
       if (hook == HOOK_WAVE_MEM && !ep)
         throw Reject{"a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers"};
+      if (simt && !ep)
+        throw Reject{"a SIMT hook's lanes run one wave's events together: its maps must be shared, read-only or ring buffers"};
       res.event_parallel = ep;
       res.log = "accepted";
     } catch (const Reject& r) {

@@ -27,7 +27,12 @@ enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2 };
 // HOOK_WAVE_MEM: the warp-leader hook (section 4.4, warp-level execution):
 // one invocation per tile of 64 consecutive memory-access records, whose
 // context is the tile's aggregate (see hook_info).
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3 };
+// HOOK_SIMT_MEM: one invocation per memory-access record, whose context is
+// the record followed by its tile's aggregate; the aggregate's fields are
+// warp-uniform, the record's lane-varying, and the checker holds the program
+// to warp-uniform control flow, map keys and side effects (section 4.4,
+// "SIMT-aware Verification").
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4 };
 enum : int { H_LOOKUP = 1, H_UPDATE = 2, H_DELETE = 3, H_RINGBUF_OUTPUT = 130 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 
@@ -48,6 +53,7 @@ struct HookInfo {
   uint32_t record_size;
   uint32_t stream_off, stream_size;  // stream key field
   std::vector<std::pair<uint32_t, uint32_t>> fields;
+  uint32_t uniform_off = ~0u;  // ctx bytes from here on are warp-uniform (SIMT hook)
 };
 bool hook_info(int hook, HookInfo* out);
 

@@ -46,6 +46,13 @@ bool hook_info(int hook, HookInfo* out) {
     *out = {24, 8, 4, {{0, 8}, {8, 8}, {16, 4}, {20, 4}}};
     return true;
   }
+  if (hook == HOOK_SIMT_MEM) {
+    // input: memory-access records (24 B); context of one invocation: the
+    // record's fields, then its tile's aggregate as HOOK_WAVE_MEM's context
+    // at offset 24 (warp-uniform)
+    *out = {24, 8, 4, {{0, 8}, {8, 4}, {16, 8}, {24, 8}, {32, 8}, {40, 4}, {44, 4}}, 24};
+    return true;
+  }
   return false;
 }
 
@@ -759,6 +766,40 @@ int Oracle::run(const Program& prog, const uint8_t* events, uint64_t n, int orde
       }
       if (rc_out)
         for (uint64_t i = b; i < e; i++) rc_out[i] = rc;
+    }
+    return 0;
+  }
+  if (prog.hook == HOOK_SIMT_MEM) {
+    // one invocation per record on {record, its tile's aggregate}; records
+    // in index order or shuffled (the program is event-parallel)
+    std::vector<uint64_t> ix(n);
+    std::iota(ix.begin(), ix.end(), 0);
+    if (order == 2) {
+      uint64_t s = seed;
+      for (uint64_t i = n; i > 1; i--) {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        std::swap(ix[i - 1], ix[z % i]);
+      }
+    }
+    std::vector<uint8_t> agg(((n + 63) / 64) * 24);
+    for (uint64_t t = 0; t * 64 < n; t++) wave_context(events, t * 64, std::min(n, t * 64 + 64), &agg[t * 24]);
+    Exec ex(*this, prog, hi);
+    for (uint64_t i : ix) {
+      uint8_t ctx[48];
+      std::memcpy(ctx, events + i * 24, 24);
+      std::memcpy(ctx + 24, &agg[(i / 64) * 24], 24);
+      uint32_t rc = 0;
+      try {
+        rc = ex.run_event(ctx);
+      } catch (const Fault& f) {
+        stats.faults++;
+        if (stats.fault_msg.empty()) stats.fault_msg = "event " + std::to_string(i) + ": " + f.msg;
+      }
+      if (rc_out) rc_out[i] = rc;
     }
     return 0;
   }

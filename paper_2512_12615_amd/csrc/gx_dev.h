@@ -64,26 +64,14 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Wave reductions over the active lanes.  Older device compilers (such as
-// the run-time compiler some PyTorch builds bundle) lack the builtins; they
-// then get a lane loop here and per-lane map atomics without aggregation.
-#if __has_builtin(__builtin_amdgcn_wave_reduce_add_u64) && __has_builtin(__builtin_amdgcn_wave_reduce_max_u32)
-#define GX_HAS_WAVE_REDUCE 1
-#else
-#define GX_HAS_WAVE_REDUCE 0
-#endif
-
+// Largest x over the active lanes (read lane by lane: used once per queue).
 __device__ __forceinline__ uint32_t wave_max_active(uint32_t x) {
-#if GX_HAS_WAVE_REDUCE
-  return __builtin_amdgcn_wave_reduce_max_u32(x, 0);
-#else
   uint32_t m = 0;
   for (uint64_t b = ballot(true); b; b &= b - 1) {
     const uint32_t v = __builtin_amdgcn_readlane(x, (uint32_t)__builtin_ctzll(b));
     m = v > m ? v : m;
   }
   return m;
-#endif
 }
 
 // Map memory is device memory.  Its pointers come from descriptors, not
@@ -278,6 +266,24 @@ GX_HELPER int64_t hash_find(const MapDev* m, uint64_t h, int kind, uint64_t kp, 
   return -1;
 }
 
+// Lookup of a key of at most 8 bytes given as a value (compiled programs
+// whose key lies in a register of the private frame); slots of 16 bytes.
+GX_HELPER uint64_t hash_lookup_k(const MapDev* m, uint64_t k0, uint32_t epoch) {
+  (void)epoch;
+  const uint64_t h = hash_final(hash_step(m->key_size, k0));
+  const uint32_t mask = m->slot_mask, tag = (uint32_t)(h >> 32);
+  uint32_t i = (uint32_t)h & mask;
+  for (uint32_t probe = 0; probe <= mask; probe++) {
+    uint64_t st, sk;
+    load_slot16(m->slots + (uint64_t)i * 16u, &st, &sk);
+    const uint32_t state = (uint32_t)st & 0xff;
+    if (state == SLOT_EMPTY) break;
+    if (state == SLOT_LIVE && (uint32_t)(st >> 32) == tag && sk == k0) return (uint64_t)(m->data + (uint64_t)i * m->vstride);
+    i = (i + 1) & mask;
+  }
+  return 0;
+}
+
 GX_HELPER uint64_t hash_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk, uint32_t epoch) {
   uint64_t h = key_hash(m, kind, kp, stk);
   int64_t s = hash_find(m, h, kind, kp, stk, epoch, nullptr);
@@ -337,6 +343,10 @@ GX_HELPER int64_t hash_delete(const MapDev* m, int kind, uint64_t kp, const Stk&
                      hdr_word(SLOT_TOMB, epoch, stk.owner), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_add(gl(&m->ctrl[0]), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
+}
+
+__device__ __forceinline__ uint64_t array_lookup_idx(const MapDev* m, uint32_t idx) {
+  return idx < m->max_entries ? (uint64_t)(m->data + (uint64_t)idx * m->vstride) : 0;
 }
 
 __device__ __forceinline__ uint64_t array_lookup(const MapDev* m, int kind, uint64_t kp, const Stk& stk) {
@@ -551,15 +561,16 @@ __device__ __forceinline__ bool ring_block_take(const MapDev* m, uint32_t r, uin
   return ok;
 }
 
-// ringbuf_output carving from the wave's chunk; a new chunk of
-// ``chunk_bytes`` (or the wave's whole request, if larger) is taken from the
-// block's chunk when this one is short.  Same results as ring_output while
-// space lasts; near a full ring a request may fail a little earlier (the
-// unused parts of chunks count as used until the drain).
-__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint32_t r,
-                                                         uint64_t chunk_bytes, uint64_t block_bytes, int kind,
-                                                         uint64_t dp, uint32_t size, uint64_t flags,
-                                                         const Stk& stk) {
+// ringbuf_output carving from the wave's chunk, for active lanes that all
+// pass one ring slot and one size; a new chunk of ``chunk_bytes`` (or the
+// wave's whole request, if larger) is taken from the block's chunk when
+// this one is short.  Same results as ring_output while space lasts; near a
+// full ring a request may fail a little earlier (the unused parts of chunks
+// count as used until the drain).
+__device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t slot, uint32_t r,
+                                                       uint64_t chunk_bytes, uint64_t block_bytes, int kind,
+                                                       uint64_t dp, uint32_t size, uint64_t flags,
+                                                       const Stk& stk) {
   uint64_t res = 0;
   const bool want = flags == 0;
   if (!want) res = (uint64_t)-E_INVAL;
@@ -599,31 +610,141 @@ __device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_
   if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos + total, left - total, recs + cnt};
   return res;
 }
+
+// ringbuf_output of compiled programs.  The compiler may merge call sites
+// that differ in record size or ring (their arguments then vary by lane),
+// so the active lanes are served one (slot, size) group at a time; each
+// group's records are carved as one wave request.
+__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint32_t r,
+                                                         uint64_t chunk_bytes, uint64_t block_bytes, int kind,
+                                                         uint64_t dp, uint32_t size, uint64_t flags,
+                                                         const Stk& stk) {
+  uint64_t res = 0;
+  for (uint64_t todo = ballot(true); todo;) {
+    const uint32_t l0 = (uint32_t)__builtin_ctzll(todo);
+    const bool mine = slot == rdlane(slot, l0) && size == rdlane(size, l0);
+    todo &= ~ballot(mine);
+    if (mine) res = ring_output_group(m, slot, r, chunk_bytes, block_bytes, kind, dp, size, flags, stk);
+  }
+  return res;
+}
 #endif
 
-// Atomic read-modify-write on global memory; commutative non-fetching forms
-// are reduced across the active lanes when they all hit one address.
+// ---------------------------------------------------------------------------
+// Wave aggregation of commutative map updates by distinct address (section
+// 4.4: duplicate map updates that SIMT execution causes).  The active lanes
+// are taken group by group: the lowest remaining lane's address and every
+// lane that shares it.  A group of two or more lanes is combined into one
+// value, which its lowest lane applies once; the first singleton group ends
+// the search (the addresses are then mostly distinct: uniformly spread
+// updates pay one comparison), and so does the 8th group.  Combining equal
+// addends takes a closed form (n * v for add, v for or/and, v or 0 for
+// xor); unequal addends over a full wave take a DPP reduction; otherwise
+// they are read lane by lane.
+
+constexpr int kAggGroups = 8;
+
+__device__ __forceinline__ uint64_t agg_identity(uint32_t op) { return op == 0x50 ? ~0ull : 0ull; }
+__device__ __forceinline__ uint64_t agg_apply(uint64_t a, uint64_t b, uint32_t op) {
+  switch (op) {
+    case 0x00: return a + b;
+    case 0x40: return a | b;
+    case 0x50: return a & b;
+    default: return a ^ b;
+  }
+}
+
+__device__ __forceinline__ uint64_t rdlane_u64(uint64_t x, uint32_t j) {
+  return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(x >> 32), j) << 32) |
+         __builtin_amdgcn_readlane((uint32_t)x, j);
+}
+
+// One DPP step of a wave reduction: every lane combines its value with the
+// source lane's (row shift, or a row broadcast into the rows ROWS enables);
+// lanes without a source combine with the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_combine(uint64_t x, uint32_t op) {
+  const uint64_t id = agg_identity(op);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)id, (int)(uint32_t)x, CTRL, ROWS, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(id >> 32), (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, false);
+  return agg_apply(x, ((uint64_t)hi << 32) | lo, op);
+}
+
+// op over all 64 lanes (every lane active): inclusive scans of the rows of
+// 16 by shifts of 1, 2, 4 and 8 lanes, then row 0 broadcast into row 1 and
+// row 2 into row 3, then rows 0-1 into rows 2-3: lane 63 holds the total.
+__device__ __forceinline__ uint64_t wave_reduce_full(uint64_t x, uint32_t op) {
+  x = dpp_combine<0x111, 0xf>(x, op);  // row_shr:1
+  x = dpp_combine<0x112, 0xf>(x, op);  // row_shr:2
+  x = dpp_combine<0x114, 0xf>(x, op);  // row_shr:4
+  x = dpp_combine<0x118, 0xf>(x, op);  // row_shr:8
+  x = dpp_combine<0x142, 0xa>(x, op);  // row_bcast:15
+  x = dpp_combine<0x143, 0xc>(x, op);  // row_bcast:31
+  return rdlane_u64(x, 63);
+}
+
+// op over the lanes of group ``grp`` (active lanes, lowest lane l0).
+__device__ __forceinline__ uint64_t group_combine(uint64_t v, uint32_t op, uint64_t grp, uint32_t l0) {
+  const uint64_t v0 = rdlane_u64(v, l0);
+  if ((ballot(v != v0) & grp) == 0) {
+    const uint32_t n = popc64(grp);
+    return op == 0x00 ? v0 * n : op == 0xa0 ? ((n & 1) ? v0 : 0) : v0;
+  }
+  if (grp == ~0ull) return wave_reduce_full(v, op);
+  uint64_t acc = agg_identity(op);
+  for (uint64_t m = grp; m; m &= m - 1) acc = agg_apply(acc, rdlane_u64(v, (uint32_t)__builtin_ctzll(m)), op);
+  return acc;
+}
+
+// Aggregate this wave's commutative updates (op, addend v at addr): group
+// leaders call apply(addr, combined) for their groups.  Returns true for a
+// lane whose update is still its own to apply.
+template <class F>
+__device__ __forceinline__ bool wave_aggregate(uint64_t addr, uint64_t v, uint32_t op, F&& apply) {
+  uint64_t todo = ballot(true);
+  const uint32_t me = lane_id();
+  for (int g = 0; g < kAggGroups && todo; g++) {
+    const uint32_t l0 = (uint32_t)__builtin_ctzll(todo);
+    const uint64_t grp = ballot(addr == rdlane_u64(addr, l0)) & todo;
+    if (grp == (1ull << l0)) break;
+    const uint64_t agg = group_combine(v, op, grp, l0);
+    if (me == l0) apply(addr, agg);
+    todo &= ~grp;
+  }
+  return (todo >> me) & 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void global_rmw_op(uint64_t addr, T v, uint32_t op) {
+  GX_GLOBAL T* p = (GX_GLOBAL T*)addr;
+  switch (op) {
+    case 0x00: __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    case 0x40: __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    case 0x50: __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+    default: __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+  }
+}
+
+// The wave aggregation of a commutative non-fetching atomic on global
+// memory; true for a lane whose update is still its own.  (Kept inline: a
+// call out of the interpreter's dispatch loop costs register saves around
+// every call, measured far worse than the grouping's own registers.)
+__device__ __forceinline__ bool atomic_aggregate(uint64_t addr, uint64_t v, uint32_t op, int sc) {
+  const bool w64 = sc == 3;
+  return wave_aggregate(addr, v, op, [&](uint64_t a, uint64_t x) {
+    if (w64)
+      global_rmw_op<uint64_t>(a, x, op);
+    else
+      global_rmw_op<uint32_t>(a, (uint32_t)x, op);
+  });
+}
+
+// Atomic read-modify-write on global memory; the commutative non-fetching
+// forms are aggregated per wave by distinct address first.
 __device__ __forceinline__ uint64_t atomic_global(uint64_t addr, uint64_t v, uint32_t op, int sc, uint64_t r0) {
   bool w64 = sc == 3;
-#if GX_HAS_WAVE_REDUCE
-  if (!(op & 1)) {  // ADD / OR / AND / XOR without fetch
-    uint64_t first = rfl64(addr);
-    if (ballot(addr == first) == ballot(true)) {
-      uint64_t agg;
-      switch (op) {
-        case 0x00: agg = w64 ? __builtin_amdgcn_wave_reduce_add_u64(v, 0) : __builtin_amdgcn_wave_reduce_add_u32((uint32_t)v, 0); break;
-        case 0x40: agg = w64 ? __builtin_amdgcn_wave_reduce_or_b64(v, 0) : __builtin_amdgcn_wave_reduce_or_b32((uint32_t)v, 0); break;
-        case 0x50: agg = w64 ? __builtin_amdgcn_wave_reduce_and_b64(v, 0) : __builtin_amdgcn_wave_reduce_and_b32((uint32_t)v, 0); break;
-        default: agg = w64 ? __builtin_amdgcn_wave_reduce_xor_b64(v, 0) : __builtin_amdgcn_wave_reduce_xor_b32((uint32_t)v, 0); break;
-      }
-      if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
-        v = agg;
-      } else {
-        return 0;
-      }
-    }
-  }
-#endif
+  if (!(op & 1) && !atomic_aggregate(addr, v, op, sc)) return 0;  // ADD / OR / AND / XOR without fetch
   if (w64) {
     GX_GLOBAL uint64_t* p = (GX_GLOBAL uint64_t*)addr;
     switch (op) {
@@ -853,6 +974,28 @@ __device__ __forceinline__ void cache_reduce(const uint8_t* spill, uint32_t sets
   }
 }
 
+// Lookup-memo table entries of compiled programs: the generation word's top
+// bit marks an entry whose window words are newer than the map's memory.
+constexpr uint64_t kMemoGen = ~0ull >> 1;
+
+// Read-modify-write of the bytes at bit shift sh of a private-frame word
+// (compiled programs; the frame is the lane's own): returns the old value.
+__device__ __forceinline__ uint64_t frame_rmw(uint64_t& w, uint32_t sh, uint64_t v, uint32_t op, int sc, uint64_t r0) {
+  const uint64_t mask = sc == 3 ? ~0ull : ((1ull << (8u << sc)) - 1);
+  const uint64_t old = (w >> sh) & mask;
+  uint64_t nv;
+  switch (op & 0xf0) {
+    case 0x00: nv = old + v; break;
+    case 0x40: nv = old | v; break;
+    case 0x50: nv = old & v; break;
+    case 0xa0: nv = old ^ v; break;
+    case 0xe0: nv = v; break;
+    default: nv = ((sc == 3 ? r0 : (uint32_t)r0) == old) ? v : old; break;
+  }
+  w = (w & ~(mask << sh)) | ((nv & mask) << sh);
+  return old;
+}
+
 // Read-modify-write on the lane's own stack (private: no atomicity needed).
 __device__ __forceinline__ uint64_t atomic_stack(uint8_t* p, uint64_t v, uint32_t op, int sc, uint64_t r0) {
   uint64_t old = load_sized(p, sc), nv;
@@ -904,8 +1047,9 @@ __device__ __forceinline__ bool guard_ok(const RunArgs& A, uint32_t pc, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// event loops.  ``R.run(A, live, c0, c1, c2, stk, steps)`` executes one
-// invocation per live lane and returns its rc.
+// event loops.  ``R.run(A, live, c0, c1, c2, g, stk, steps)`` executes one
+// invocation per live lane and returns its rc; c0..c2 are the lane's
+// context words, g the tile aggregate's (SIMT hook; zero otherwise).
 
 struct Ctx {
   uint64_t c0, c1, c2;  // event record words
@@ -969,13 +1113,15 @@ __device__ __forceinline__ Ctx wave_context(const Ctx& c, bool live) {
 template <class Run>
 __device__ __forceinline__ uint32_t tile_run(Run& R, const RunArgs& A, bool live, const Ctx& c, const Stk& stk,
                                              uint64_t& steps) {
-  Ctx w = c;
+  Ctx w = c, g{0, 0, 0};
   bool go = live;
   if (A.leader) {
     w = wave_context(c, live);
     go = lane_id() == 0 && live;
+  } else if (A.simt) {
+    g = wave_context(c, live);  // every lane runs its record, with the tile's aggregate
   }
-  const uint32_t rc = R.run(A, go, w.c0, w.c1, w.c2, stk, steps);
+  const uint32_t rc = R.run(A, go, w.c0, w.c1, w.c2, g, stk, steps);
   return A.leader ? __builtin_amdgcn_readlane(rc, 0) : rc;
 }
 
@@ -1074,7 +1220,7 @@ __device__ __forceinline__ void stream_wave(Run& R, const RunArgs& A, uint32_t q
 #pragma unroll
       for (uint32_t x = 0; x + 1 < B; x++) cu[x] = cu[x + 1];
       uint32_t rc = 0;
-      if (k0 + j < rounds) rc = R.run(A, k0 + j < cnt, c.c0, c.c1, c.c2, stk, steps);
+      if (k0 + j < rounds) rc = R.run(A, k0 + j < cnt, c.c0, c.c1, c.c2, Ctx{0, 0, 0}, stk, steps);
 #pragma unroll
       for (uint32_t x = 0; x + 1 < B; x++) crc[x] = crc[x + 1];
       crc[B - 1] = rc;
@@ -1139,7 +1285,7 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
     if (l == 0) {
       for (uint32_t j = 0; j < n; j++)
         st.rc[j] = (uint32_t)uni<true>(
-            R.run(A, true, rdlane64(cc.c0, j), rdlane64(cc.c1, j), rdlane64(cc.c2, j), stk, steps));
+            R.run(A, true, rdlane64(cc.c0, j), rdlane64(cc.c1, j), rdlane64(cc.c2, j), Ctx{0, 0, 0}, stk, steps));
     }
     R.uniformize();  // state lane 0 carries from event to event, back to wave-uniform
     if (A.rc && l < n) A.rc[ci] = st.rc[l];

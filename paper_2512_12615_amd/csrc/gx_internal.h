@@ -9,16 +9,26 @@ namespace gx {
 // own, independently of any other component).
 constexpr int kMaxInsns = 4096;
 constexpr int kStackMax = 512;
+// LDS an interpreted event-parallel block may take for its stack frames and
+// the mirror of one shared map, and the largest mirrored value area
+constexpr uint32_t kAccLdsMax = 128u << 10;
+constexpr uint32_t kAccMirrorMax = 32u << 10;
 constexpr uint64_t kMaxDynInsns = 65536;
 constexpr uint64_t kMaxCalls = 64;
 constexpr uint64_t kMaxRingBytes = 4096;
 
 enum : int { MAP_HASH = 1, MAP_ARRAY = 2, MAP_RINGBUF = 27 };
-enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2 };
+// F_HOST: a read-only map kept in host memory (the cold tier), read by the
+// device through its mapped address.
+enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2, F_HOST = 4 };
 // HOOK_WAVE_MEM: the warp-leader hook (section 4.4, warp-level execution):
 // one invocation per wave tile of 64 memory-access records, with the tile's
 // aggregate as context {u64 lo, u64 hi, u32 n, u32 stream of the first}.
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3 };
+// HOOK_SIMT_MEM: one invocation per memory-access record (one lane each),
+// whose context is the record {u64 addr, u32 stream, u32 pad, u64 ts}
+// followed by its wave tile's aggregate as above at byte 24; the verifier
+// holds the program to warp-uniform control flow, keys and side effects.
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 
 // ---------------------------------------------------------------------------
@@ -119,6 +129,13 @@ struct RunArgs {
   uint8_t* spill;          // compiled event-parallel runs: LDS cache spill area (null: caches flush directly)
   uint32_t leader;         // 1: warp-leader hook (one invocation per wave tile)
   uint32_t pad3;
+  // interpreted event-parallel runs: a shared array map whose atomics the
+  // block sums in an LDS mirror (value area [acc_lo, acc_hi); mirror at LDS
+  // byte acc_lds; operation acc_op at width 2^acc_sc bytes); acc_hi == acc_lo
+  // when none
+  uint64_t acc_lo, acc_hi;
+  uint32_t acc_lds, acc_op, acc_sc;
+  uint32_t simt;           // 1: SIMT hook (each lane's context carries its tile's aggregate)
 };
 
 // Stride of the queue-ordered record copy (the largest record).

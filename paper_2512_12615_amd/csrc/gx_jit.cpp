@@ -63,6 +63,15 @@ constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
 constexpr uint32_t kMemoEntries = 64;      // LDS lookup-memo entries per site (one queue per wave)
 constexpr uint32_t kMemoLds = 4096;        // LDS bytes of a program's memo tables (the rest keep one entry)
+// Shared-map updates of event-parallel kernels may be aggregated per wave
+// by distinct word before the LDS accumulator (GX_AGG_LDS=1).  Off by
+// default: measured on the access counter (2^20 events, 16.2 -> 21.2 us)
+// and the latency histogram (2^26 events, 581 -> 641 us), the grouping
+// costs more than the LDS atomics it saves.
+bool agg_lds() {
+  const char* v = std::getenv("GX_AGG_LDS");
+  return v && *v && std::atoi(v) != 0;
+}
 
 // Cap on each cache in KiB from the environment (tuning experiments).
 int env_int_jit(const char* name, int dflt) {
@@ -78,6 +87,7 @@ struct JMaps {
   std::vector<int> ring;  // ring index per map (-1 if not a ring)
   int n_rings = 0;
   std::vector<Acc> acc;   // per map
+  bool simt = false;      // SIMT hook: a wave's shared-map updates hit one word, combined first
   JMaps(const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mm, const std::vector<int>& lm)
       : m(maps), mem_map(mm), ld_map(lm) {
     for (auto& e : maps) ring.push_back(e.second.type == MAP_RINGBUF ? n_rings++ : -1);
@@ -156,6 +166,11 @@ struct Windows {
   std::vector<char> memo;    // per window: its key, pointer and words kept across events
   std::vector<char> table;   // per memo: an LDS table when one queue runs per wave
   std::vector<uint64_t> inval;  // per slot: memo windows a slot's write may make stale
+  // per memo table: written back (window stores stay in the table until the
+  // entry is evicted, the memo is cleared or the run ends) instead of
+  // written through; for a map with one memo site, in the one-queue kernel
+  std::vector<char> wb;
+  std::vector<uint64_t> sync;  // per slot: written-back tables a slot's read of map memory must flush first
 };
 
 Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
@@ -345,6 +360,185 @@ Windows plan_windows(const std::vector<Uop>& U, const JMaps& J) {
   return R;
 }
 
+// Private frames: when every stack access and every stack argument of a
+// helper call has a base register whose offset from the frame pointer r10
+// is known (r10 itself, or r10 moved and shifted by constants), the frame's
+// 8-byte words become locals of the generated code (registers: scalar ones
+// in the wave-uniform kernel), and the accesses become shifts and masks of
+// those locals.  The LDS frame stays as the place helpers read their stack
+// arguments from: the words a helper reads are stored there right before
+// the call (helpers only read the stack).  A forward data-flow pass over the
+// micro-ops finds each access's byte in the frame; any unknown base leaves
+// the program on the LDS frame.
+struct Frame {
+  bool priv = false;
+  std::vector<int32_t> at;   // per slot: frame byte of the stack access, or of the helper's r2 argument
+  std::vector<int32_t> at3;  // per slot: frame byte of an update's r3 (value) argument
+};
+
+Frame plan_frame(const std::vector<Uop>& U, uint32_t stack_bytes) {
+  Frame F;
+  const uint32_t n = (uint32_t)U.size();
+  F.at.assign(n, -1);
+  F.at3.assign(n, -1);
+  if (!stack_bytes || stack_bytes > 512) return F;
+  struct St {
+    bool reached = false;
+    bool k[11];
+    int64_t d[11];
+  };
+  std::vector<St> in(n);
+  bool ok = true;
+  auto step = [&](uint32_t pc, St s, std::vector<uint32_t>& succ, bool mark) {
+    const Uop& u = U[pc];
+    const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, src = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
+    const bool K = (u.w0 >> 24) & 1;
+    auto kill = [&](uint32_t r) {
+      if (r < 10) s.k[r] = false;
+    };
+    // frame byte of base register r plus offset o (-1 if unknown or outside)
+    auto byte = [&](uint32_t r, int64_t o) -> int32_t {
+      if (r > 10 || !s.k[r]) return -1;
+      const int64_t b = (int64_t)stack_bytes + s.d[r] + o;
+      return b >= 0 && b < (int64_t)stack_bytes ? (int32_t)b : -1;
+    };
+    auto need = [&](std::vector<int32_t>& v, uint32_t r, int64_t o) {
+      const int32_t b = byte(r, o);
+      if (b < 0) ok = false;
+      if (mark) v[pc] = b;
+    };
+    uint32_t next = pc + 1;
+    if (h <= H_TRUNC) {
+      if (h == H_MOV64 && !K && src <= 10 && d < 10) {
+        s.k[d] = s.k[src];
+        s.d[d] = s.d[src];
+      } else if ((h == H_ADD64 || h == H_SUB64) && K && d < 10 && s.k[d]) {
+        s.d[d] += h == H_ADD64 ? (int64_t)u.imm : -(int64_t)u.imm;
+      } else {
+        kill(d);
+      }
+      succ.push_back(next);
+      return s;
+    }
+    if (h >= H_JA && h <= H_JSLE32) {
+      if (h != H_JA) succ.push_back(next);
+      succ.push_back((uint32_t)u.aux);
+      return s;
+    }
+    switch (h) {
+      case H_LDX_STACK:
+        need(F.at, src, u.aux);
+        kill(d);
+        break;
+      case H_ST_STACK:
+      case H_STX_STACK:
+        need(F.at, d, u.aux);
+        break;
+      case H_ATOMIC_STACK:
+        need(F.at, d, u.aux);
+        if ((uint32_t)u.imm == 0xf1) kill(0);
+        else if (u.imm & 1) kill(src);
+        break;
+      case H_ATOMIC_MAP:
+        if ((uint32_t)u.imm == 0xf1) kill(0);
+        else if (u.imm & 1) kill(src);
+        break;
+      case H_LDIMM:
+        kill(d);
+        next = pc + 2;
+        break;
+      case H_LOOKUP_ARRAY:
+      case H_LOOKUP_HASH:
+      case H_DELETE_HASH:
+      case H_RINGBUF_OUTPUT:
+        if ((a8 & 1) == PK_STACK) need(F.at, 2, 0);
+        for (uint32_t r = 0; r <= 5; r++) kill(r);
+        break;
+      case H_RET_EINVAL:
+        for (uint32_t r = 0; r <= 5; r++) kill(r);
+        break;
+      case H_UPDATE_ARRAY:
+      case H_UPDATE_HASH:
+        if ((a8 & 1) == PK_STACK) need(F.at, 2, 0);
+        if (((a8 >> 1) & 1) == PK_STACK) need(F.at3, 3, 0);
+        for (uint32_t r = 0; r <= 5; r++) kill(r);
+        break;
+      case H_EXIT:
+        return s;
+      default:
+        if (h == H_LDX_CTX || h == H_LDX_MAP) kill(d);
+        break;
+    }
+    succ.push_back(next);
+    return s;
+  };
+  St entry;
+  entry.reached = true;
+  for (int r = 0; r < 11; r++) {
+    entry.k[r] = r == 10;
+    entry.d[r] = 0;
+  }
+  if (n) in[0] = entry;
+  std::vector<uint32_t> work;
+  if (n) work.push_back(0);
+  std::vector<char> queued(n, 0);
+  if (n) queued[0] = 1;
+  while (!work.empty()) {
+    const uint32_t pc = work.back();
+    work.pop_back();
+    queued[pc] = 0;
+    std::vector<uint32_t> succ;
+    const St out = step(pc, in[pc], succ, false);
+    for (uint32_t t : succ) {
+      if (t >= n) continue;
+      St& dst = in[t];
+      bool changed = false;
+      if (!dst.reached) {
+        dst = out;
+        changed = true;
+      } else {
+        for (int r = 0; r < 10; r++)
+          if (dst.k[r] && (!out.k[r] || dst.d[r] != out.d[r])) {
+            dst.k[r] = false;
+            changed = true;
+          }
+      }
+      if (changed && !queued[t]) {
+        queued[t] = 1;
+        work.push_back(t);
+      }
+    }
+  }
+  for (uint32_t pc = 0; pc < n; pc++) {
+    if (!in[pc].reached) continue;
+    std::vector<uint32_t> succ;
+    (void)step(pc, in[pc], succ, true);
+  }
+  F.priv = ok && std::getenv("GX_LDS_FRAME") == nullptr;
+  return F;
+}
+
+// Statements storing the frame words that bytes [b, b + len) of the frame
+// occupy into the LDS frame (before a helper reads them there).
+std::string frame_spill(int32_t b, uint32_t len) {
+  std::string o;
+  for (uint32_t w = (uint32_t)b / 8; w < ((uint32_t)b + len + 7) / 8; w++)
+    o += "*(uint64_t*)saddr(stk, " + std::to_string(8 * w) + "u) = f" + std::to_string(w) + "; ";
+  return o;
+}
+
+// Expression for the first min(8, len) bytes at frame byte b, when they lie
+// in one frame word; "" otherwise.
+std::string frame_bytes(int32_t b, uint32_t len) {
+  const uint32_t n = len < 8 ? len : 8;
+  if ((uint32_t)b % 8 + n > 8) return "";
+  const std::string w = "f" + std::to_string(b / 8);
+  const uint32_t sh = 8 * ((uint32_t)b % 8);
+  std::string e = sh ? "(" + w + " >> " + std::to_string(sh) + ")" : w;
+  if (n < 8) e = "(" + e + " & " + lit((1ull << (8 * n)) - 1) + ")";
+  return e;
+}
+
 // Lookup memos: a hash lookup site whose window belongs to a map of keys of
 // at most 8 bytes keeps, across the events of a run, the last key it found,
 // the value's address and the window's words.  When the next event looks up
@@ -365,6 +559,8 @@ void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R, bool event
   R.memo.assign(R.win.size(), 0);
   R.table.assign(R.win.size(), 0);
   R.inval.assign(U.size(), 0);
+  R.wb.assign(R.win.size(), 0);
+  R.sync.assign(U.size(), 0);
   if (event_parallel) return;  // lanes run different streams' events in turn
   bool any = false;
   uint32_t lds = 0;
@@ -401,6 +597,31 @@ void plan_memo(const std::vector<Uop>& U, const JMaps& J, Windows& R, bool event
       R.inval[pc] |= 1ull << w;
     }
   }
+  // write-back tables: the only memo site of their map; every other read of
+  // map memory that may reach its values - a load not through the window, a
+  // helper reading a map-value argument - writes the table back first
+  for (size_t w = 0; w < R.win.size(); w++) {
+    if (!R.table[w]) continue;
+    int sites = 0;
+    for (size_t x = 0; x < R.win.size(); x++) sites += R.memo[x] && R.win[x].map == R.win[w].map;
+    R.wb[w] = sites == 1 && std::getenv("GX_WRITE_THROUGH") == nullptr;
+  }
+  for (uint32_t pc = 0; pc < U.size(); pc++) {
+    const uint32_t h = U[pc].w0 & 0xff, a8 = (U[pc].w0 >> 16) & 0xff;
+    if (h == H_LDIMM) {
+      pc++;
+      continue;
+    }
+    for (size_t w = 0; w < R.win.size(); w++) {
+      if (!R.wb[w]) continue;
+      if (h == H_LDX_MAP) {
+        const int k = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+        if ((k < 0 || k == R.win[w].map) && R.acc[pc] != (int)w) R.sync[pc] |= 1ull << w;
+      } else if (h >= H_LOOKUP_ARRAY && h <= H_RINGBUF_OUTPUT && ((a8 & 1) == PK_MAPVAL || ((a8 >> 1) & 1) == PK_MAPVAL)) {
+        R.sync[pc] |= 1ull << w;
+      }
+    }
+  }
 }
 
 std::string map_name(const JMaps& J, uint64_t desc) {
@@ -424,7 +645,7 @@ std::string map_fn(size_t k, const MapDev& m) {
   return b;
 }
 
-void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const Windows& Wn) {
+void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const Windows& Wn, const Frame& Fr) {
   const uint32_t h = u.w0 & 0xff, d = (u.w0 >> 8) & 15, s = (u.w0 >> 12) & 15, a8 = (u.w0 >> 16) & 0xff;
   const bool K = (u.w0 >> 24) & 1;
   const std::string D = reg(d), S = reg(s);
@@ -459,10 +680,34 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
     o += " }\n";
   };
   const std::string sa32 = "(int32_t)" + xa, sb32 = "(int32_t)" + xb;
+  // private frame: the frame word and bit shift of this slot's stack access
+  const int32_t fb = Fr.priv && pc < Fr.at.size() ? Fr.at[pc] : -1;
+  const std::string fw = fb >= 0 ? "f" + std::to_string(fb / 8) : std::string();
+  const std::string fsh = fb >= 0 ? std::to_string(8 * (fb % 8)) : std::string();
+  // a helper's stack arguments stored to the LDS frame first (key at r2 of
+  // klen bytes, an update's value at r3 of vlen bytes)
+  const int hk = J.index(u.imm);
+  const uint32_t klen = hk >= 0 ? J.m[hk].second.key_size : 0, vlen = hk >= 0 ? J.m[hk].second.value_size : 0;
+  auto spill_args = [&](uint32_t len2, uint32_t len3) {
+    std::string t;
+    if (Fr.priv && (a8 & 1) == PK_STACK && pc < Fr.at.size() && Fr.at[pc] >= 0) t += frame_spill(Fr.at[pc], len2);
+    if (Fr.priv && len3 && ((a8 >> 1) & 1) == PK_STACK && pc < Fr.at3.size() && Fr.at3[pc] >= 0)
+      t += frame_spill(Fr.at3[pc], len3);
+    return t;
+  };
+  // the helper's r2 key as a value, when it is a frame word's bytes
+  const std::string kval = Fr.priv && (a8 & 1) == PK_STACK && fb >= 0 ? frame_bytes(fb, klen) : std::string();
   // a write that may reach a memo's value other than through its window
+  // (a written-back table is written back first), or a read of map memory
+  // that a written-back table may hold newer words of
   if (pc < Wn.inval.size() && Wn.inval[pc])
     for (size_t w = 0; w < Wn.win.size(); w++)
-      if ((Wn.inval[pc] >> w) & 1) o += "  mv" + std::to_string(w) + " = false; gen" + std::to_string(w) + "++;\n";
+      if ((Wn.inval[pc] >> w) & 1)
+        o += std::string(Wn.wb[w] ? "  if (UNI) memo_flush" + std::to_string(w) + "();\n" : "") + "  mv" +
+             std::to_string(w) + " = false; gen" + std::to_string(w) + "++;\n";
+  if (pc < Wn.sync.size() && Wn.sync[pc])
+    for (size_t w = 0; w < Wn.win.size(); w++)
+      if ((Wn.sync[pc] >> w) & 1) o += "  if (UNI) memo_flush" + std::to_string(w) + "();\n";
   switch (h) {
     case H_ADD64: set(D + " + " + B); break;
     case H_SUB64: set(D + " - " + B); break;
@@ -540,12 +785,17 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
     case H_JSLE32: jmp(sa32 + " <= " + sb32); break;
     case H_LDX_CTX: {
       const uint32_t wi = (uint32_t)u.aux >> 3, sh = 8 * ((uint32_t)u.aux & 7);
-      std::string w = "(c" + std::to_string(wi) + " >> " + std::to_string(sh) + ")";
+      // words 3..5: the tile's aggregate (SIMT hook), wave-uniform
+      std::string w = wi < 3 ? "(c" + std::to_string(wi) + " >> " + std::to_string(sh) + ")"
+                             : "(uni<true>(g.c" + std::to_string(wi - 3) + ") >> " + std::to_string(sh) + ")";
       set(extend(std::string("(") + kTy[sc] + ")" + w, sc, sxf));
       break;
     }
     case H_LDX_STACK:
-      set("uni<UNI>(" + extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf) + ")");
+      if (fb >= 0)
+        set(extend(std::string("(") + kTy[sc] + ")(" + fw + " >> " + fsh + ")", sc, sxf));
+      else
+        set("uni<UNI>(" + extend(std::string("*(const ") + kTy[sc] + "*)saddr(stk, (uint32_t)" + S + " + " + off + ")", sc, sxf) + ")");
       break;
     case H_LDX_MAP: {
       const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
@@ -565,18 +815,28 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
       break;
     }
     case H_ST_STACK:
-    case H_STX_STACK:
-      o += std::string("  *(") + kTy[sc] + "*)saddr(stk, (uint32_t)" + D + " + " + off + ") = (" + kTy[sc] + ")" +
-           (h == H_ST_STACK ? lit(u.imm) : S) + ";\n";
+    case H_STX_STACK: {
+      const std::string val = std::string("(") + kTy[sc] + ")" + (h == H_ST_STACK ? lit(u.imm) : S);
+      if (fb >= 0)
+        o += sc == 3 ? "  " + fw + " = (uint64_t)" + val + ";\n"
+                     : "  " + fw + " = (" + fw + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + fsh + ")) | ((uint64_t)" +
+                           val + " << " + fsh + ");\n";
+      else
+        o += std::string("  *(") + kTy[sc] + "*)saddr(stk, (uint32_t)" + D + " + " + off + ") = " + val + ";\n";
       break;
+    }
     case H_ST_MAP:
     case H_STX_MAP: {
       const std::string val = std::string("(") + kTy[sc] + ")" + (h == H_ST_MAP ? lit(u.imm) : S);
       std::string body = std::string("*(GX_GLOBAL ") + kTy[sc] + "*)ad = " + val + ";";
-      if (wa >= 0)
-        body += sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
-                        : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] + ")~0ull << " + wsh +
-                              ")) | ((uint64_t)" + val + " << " + wsh + ");";
+      if (wa >= 0) {
+        const std::string local = sc == 3 ? " " + wword + " = (uint64_t)" + val + ";"
+                                          : " " + wword + " = (" + wword + " & ~((uint64_t)(" + kTy[sc] +
+                                                ")~0ull << " + wsh + ")) | ((uint64_t)" + val + " << " + wsh + ");";
+        // a written-back table: the window's words are the value's newest
+        body = Wn.wb[wa] ? "if (UNI) {" + local + " dy" + std::to_string(wa) + " = true; } else { " + body + local + " }"
+                         : body + local;
+      }
       guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, body);
       break;
     }
@@ -591,22 +851,30 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
       std::string wb = op == 0xf1 ? "r0 = t;" : (op & 1) ? S + " = t;" : "(void)t;";
       const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
       const Acc* ac = (h == H_ATOMIC_MAP && mk >= 0 && mk < (int)J.acc.size() && J.acc[mk].kind) ? &J.acc[mk] : nullptr;
-      if (h == H_ATOMIC_STACK) {
+      if (h == H_ATOMIC_STACK && fb >= 0) {
+        o += "  { const uint64_t t = frame_rmw(" + fw + ", " + fsh + "u, " + S + ", " + std::to_string(op) + "u, " +
+             std::to_string(sc) + ", r0); " + wb + " }\n";
+      } else if (h == H_ATOMIC_STACK) {
         o += "  { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }\n";
       } else if (ac) {
         // shared map: summed in LDS by the event-parallel kernel
         const std::string T = ac->word_type(), K = std::to_string(mk);
         const std::string ops = std::to_string(ac->op) + "u";
         const std::string sets = std::to_string(ac->words / kCacheSlotsPerSet) + "u";
+        // the update of word a_ by x_ in the block's LDS accumulator
         const std::string lds =
-            ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(ad - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
-                                std::to_string(ac->sc) + "], (" + T + ")" + S + ", " + ops + ");"
-            : ac->narrow ? "cache_add_narrow(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, ad, (uint64_t)" +
-                               S + ");"
-                         : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, ad, (" +
-                               T + ")" + S + ", " + ops + ");";
+            ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(a_ - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
+                                std::to_string(ac->sc) + "], (" + T + ")x_, " + ops + ");"
+            : ac->narrow ? "cache_add_narrow(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, a_, x_);"
+                         : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, a_, (" +
+                               T + ")x_, " + ops + ");";
+        // lanes of the wave that update one word are combined first (one
+        // LDS atomic per distinct word instead of one per lane)
+        const std::string fn = "auto acc_ = [&](uint64_t a_, uint64_t x_) { " + lds + " }; ";
+        const std::string priv = agg_lds() || J.simt ? fn + "if (wave_aggregate(ad, (uint64_t)" + S + ", " + ops + ", acc_)) acc_(ad, (uint64_t)" + S + ");"
+                                         : fn + "acc_(ad, (uint64_t)" + S + ");";
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
-                "if (PRIV) { " + lds + " } else { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
+                "if (PRIV) { " + priv + " } else { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
       } else {
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = uni<UNI>(" + call + "); " + wb);
       }
@@ -622,30 +890,42 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         set(lit(u.imm));
       break;
     case H_LOOKUP_ARRAY:
-      o += "  r0 = uni<UNI>(array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk));\n";
+      if (!kval.empty())
+        o += "  r0 = uni<UNI>(array_lookup_idx(" + M + ", (uint32_t)" + kval + "));\n";
+      else
+        o += "  " + spill_args(4, 0) + "r0 = uni<UNI>(array_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk));\n";
       window_load();
       break;
     case H_LOOKUP_HASH: {
       const int w = pc < Wn.site.size() ? Wn.site[pc] : -1;
-      const std::string call = "r0 = uni<UNI>(hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));";
+      const bool kv = !kval.empty() && klen <= 8 && hk >= 0 && J.m[hk].second.sstride == 16;
+      const std::string call =
+          kv ? "r0 = uni<UNI>(hash_lookup_k(" + M + ", " + kval + ", A.epoch));"
+             : spill_args(klen, 0) + "r0 = uni<UNI>(hash_lookup(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));";
       if (w >= 0 && Wn.memo[w]) {
         const std::string W = std::to_string(w);
         const int km = J.index(u.imm);
         const uint32_t nw = Wn.win[w].words;
         const std::string S = std::to_string(3 + nw);
-        o += "  { const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) + ", r2, 0, " +
-             std::to_string(J.m[km].second.key_size) + "u, stk));\n";
+        if (!kval.empty())
+          o += "  { const uint64_t mk = uni<UNI>(" + kval + ");\n";
+        else
+          o += "  { " + spill_args(klen, 0) + "const uint64_t mk = uni<UNI>(gx::chunk(" + std::to_string(a8 & 1) +
+               ", r2, 0, " + std::to_string(J.m[km].second.key_size) + "u, stk));\n";
         // one queue per wave: the last key's entry in registers, in front of
         // the LDS table; the table entry of a key is written back when the
         // registers move on to another key (window stores touch registers only)
         if (Wn.table[w]) {
           const bool used = Wn.win[w].used;
           o += "    if (UNI) {\n      if (mv" + W + " && mk == mk" + W + ") {\n        r0 = mp" + W + ";\n      } else {\n";
+          const bool wbk = Wn.wb[w];
           if (used) {
             o += "        if (mv" + W + ") {";
             for (uint32_t j = 0; j < nw; j++)
               o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" +
                    std::to_string(j) + ";";
+            if (wbk)
+              o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63);";
             o += " }\n";
           }
           o += "        const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " + std::to_string(kMemoEntries - 1) +
@@ -654,10 +934,20 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
           const uint32_t rd = used ? 3 + nw : 3;
           o += "        uint64_t ev[" + std::to_string(rd) + "];\n        for (uint32_t i = 0; i < " + std::to_string(rd) +
                "u; i++) ev[i] = uni<UNI>(ent[i]);\n";
-          o += "        if (ev[2] == gen" + W + " && ev[0] == mk) {\n          r0 = ev[1];";
+          const std::string g2 = wbk ? "(ev[2] & kMemoGen)" : "ev[2]";
+          o += "        if (" + g2 + " == gen" + W + " && ev[0] == mk) {\n          r0 = ev[1];";
           for (uint32_t j = 0; j < nw && used; j++)
             o += " w" + W + "_" + std::to_string(j) + " = ev[" + std::to_string(3 + j) + "];";
-          o += "\n        } else {\n        " + call + "\n      ";
+          if (wbk) o += " dy" + W + " = (ev[2] >> 63) != 0;";
+          o += "\n        } else {\n";
+          if (wbk) {
+            // the entry's current key, if its words are newer than memory
+            o += "        if ((ev[2] & kMemoGen) == gen" + W + " && (ev[2] >> 63)) {";
+            for (uint32_t j = 0; j < nw; j++)
+              o += " *(GX_GLOBAL uint64_t*)(ev[1] + " + std::to_string(8 * j) + "ull) = ev[" + std::to_string(3 + j) + "];";
+            o += " }\n        dy" + W + " = false;\n";
+          }
+          o += "        " + call + "\n      ";
           window_load();
           o += "          ent[0] = mk; ent[1] = r0; ent[2] = r0 ? gen" + W + " : 0;";
           for (uint32_t j = 0; j < nw && used; j++)
@@ -676,19 +966,21 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
       break;
     }
     case H_UPDATE_ARRAY:
-      o += "  r0 = uni<UNI>((uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
-           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk));\n";
+      o += "  " + spill_args(4, vlen) + "r0 = uni<UNI>((uint64_t)array_update(" + M + ", " + std::to_string(a8 & 1) +
+           ", r2, " + std::to_string((a8 >> 1) & 1) + ", r3, r4, stk));\n";
       break;
     case H_UPDATE_HASH:
-      o += "  r0 = uni<UNI>((uint64_t)hash_update(" + M + ", " + std::to_string(a8 & 1) + ", r2, " +
-           std::to_string((a8 >> 1) & 1) + ", r3, r4, stk, A.epoch));\n";
+      o += "  " + spill_args(klen, vlen) + "r0 = uni<UNI>((uint64_t)hash_update(" + M + ", " + std::to_string(a8 & 1) +
+           ", r2, " + std::to_string((a8 >> 1) & 1) + ", r3, r4, stk, A.epoch));\n";
       break;
     case H_DELETE_HASH:
-      o += "  r0 = uni<UNI>((uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) + ", r2, stk, A.epoch));\n";
+      o += "  " + spill_args(klen, 0) + "r0 = uni<UNI>((uint64_t)hash_delete(" + M + ", " + std::to_string(a8 & 1) +
+           ", r2, stk, A.epoch));\n";
       break;
     case H_RET_EINVAL: o += "  r0 = (uint64_t)-22ll;\n"; break;
     case H_RINGBUF_OUTPUT: {
       const int k = J.index(u.imm);
+      o += "  " + spill_args((uint32_t)u.aux, 0) + "\n";
       if (k >= 0 && J.ring[k] >= 0)
         o += "  r0 = uni<UNI>(ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, " +
              std::to_string(J.ring[k]) + "u, chunk[" + std::to_string(J.ring[k]) + "], bchunk[" +
@@ -725,6 +1017,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   const std::vector<Uop>& U = *P.U;
   const auto& maps = *P.maps;
   JMaps J(maps, *P.mem_map, *P.ld_map);
+  J.simt = P.simt;
   std::vector<char> target(U.size() + 1, 0);
   for (const Uop& u : U)
     if (is_jump(u.w0 & 0xff) && (uint32_t)u.aux < target.size()) target[(uint32_t)u.aux] = 1;
@@ -770,6 +1063,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
            " g_val" + K + "[" + N + "];\n";
   }
   Windows Wn = plan_windows(U, J);
+  const Frame Fr = plan_frame(U, P.stack_bytes);
   // a program set's kernel would hold every member's tables at once: there
   // each lane keeps one entry in registers
   plan_memo(U, J, Wn, P.event_parallel, allow_acc);
@@ -792,9 +1086,29 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     const std::string W = std::to_string(w);
     o += "  uint64_t mk" + W + " = 0, mp" + W + " = 0, gen" + W + " = 1;\n  bool mv" + W + " = false;\n  uint32_t cur" +
          W + " = 0;\n";
+    if (Wn.wb[w]) o += "  bool dy" + W + " = false;  // the registers' window is newer than memory\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) o += "  uint64_t w" + W + "_" + std::to_string(j) + " = 0;\n";
   }
   o += "\n";
+  // write-back tables: write every entry whose words are newer than memory
+  // back to the map (one lane, in the middle of a run; end() does it with
+  // one lane per entry)
+  for (size_t w = 0; w < Wn.win.size(); w++) {
+    if (!Wn.wb[w]) continue;
+    const std::string W = std::to_string(w), S = std::to_string(3 + Wn.win[w].words);
+    o += "  __device__ __forceinline__ void memo_flush" + W + "() {\n    if (mv" + W + ") {";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++)
+      o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" + std::to_string(j) + ";";
+    o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63); }\n    dy" + W +
+         " = false;\n    for (uint32_t e = 0; e < " + std::to_string(kMemoEntries) + "u; e++) memo_writeback" + W +
+         "(e);\n  }\n";
+    o += "  __device__ __forceinline__ void memo_writeback" + W + "(uint32_t e) {\n    uint64_t* ent = &g_memo" + W +
+         "[e * " + S + "u];\n    const uint64_t g = ent[2];\n    if ((g & kMemoGen) == gen" + W +
+         " && (g >> 63)) {\n";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++)
+      o += "      *(GX_GLOBAL uint64_t*)(ent[1] + " + std::to_string(8 * j) + "ull) = ent[" + std::to_string(3 + j) + "];\n";
+    o += "      ent[2] = g & kMemoGen;\n    }\n  }\n";
+  }
   // begin / end: open and close the wave's and the block's ring chunks and
   // the block's accumulators (wave 0 sets up the block's part; the barrier
   // makes it visible to the other waves).
@@ -829,6 +1143,17 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "      __syncthreads();\n    }\n";
   }
   o += "  }\n  __device__ __forceinline__ void end(const RunArgs& A) {\n    (void)A;\n";
+  // the one-queue kernel's written-back tables: the registers' entry into
+  // its table slot, then each lane writes back one slot
+  for (size_t w = 0; w < Wn.win.size(); w++) {
+    if (!Wn.wb[w]) continue;
+    const std::string W = std::to_string(w), S = std::to_string(3 + Wn.win[w].words);
+    o += "    if (UNI) {\n      if (mv" + W + ") {";
+    for (uint32_t j = 0; j < Wn.win[w].words; j++)
+      o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" + std::to_string(j) + ";";
+    o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63); }\n      memo_writeback" +
+         W + "(lane_id());\n    }\n";
+  }
   for (size_t k = 0; k < maps.size(); k++)
     if (J.ring[k] >= 0)
       o += "    ring_chunk_close(&m" + std::to_string(k) + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u);\n";
@@ -868,6 +1193,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "    mk" + W + " = rfl64(mk" + W + ");\n    mp" + W + " = rfl64(mp" + W + ");\n    gen" + W + " = rfl64(gen" +
          W + ");\n    mv" + W + " = __builtin_amdgcn_readfirstlane((int)mv" + W + ") != 0;\n    cur" + W +
          " = __builtin_amdgcn_readfirstlane(cur" + W + ");\n";
+    if (Wn.wb[w]) o += "    dy" + W + " = __builtin_amdgcn_readfirstlane((int)dy" + W + ") != 0;\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) {
       const std::string nm = "w" + W + "_" + std::to_string(j);
       o += "    " + nm + " = rfl64(" + nm + ");\n";
@@ -875,7 +1201,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   }
   o += "  }\n\n";
   o += "  __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2, "
-       "const Stk stk, uint64_t& steps) {\n";
+       "const Ctx& g, const Stk stk, uint64_t& steps) {\n  (void)g;\n";
   o += "  (void)c0; (void)c1; (void)c2; (void)steps;\n  if (!live) return 0;\n";
   o += "  if (UNI) { c0 = rfl64(c0); c1 = rfl64(c1); c2 = rfl64(c2); }\n";
   o += "  uint64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0, r5 = 0, r6 = 0, r7 = 0, r8 = 0, r9 = 0;\n";
@@ -888,9 +1214,14 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       const std::string nm = "w" + std::to_string(w) + "_" + std::to_string(j);
       o += "  uint64_t " + nm + " = 0; (void)" + nm + ";\n";
     }
+  if (Fr.priv) {
+    o += "  uint64_t";
+    for (uint32_t w = 0; w < P.stack_bytes / 8; w++) o += std::string(w ? "," : "") + " f" + std::to_string(w) + " = 0";
+    o += ";  // the frame's words (private frame)\n";
+  }
   for (uint32_t pc = 0; pc < U.size(); pc++) {
     if (target[pc]) o += "L" + std::to_string(pc) + ":;\n";
-    emit_uop(o, U[pc], pc, J, Wn);
+    emit_uop(o, U[pc], pc, J, Wn, Fr);
     if ((U[pc].w0 & 0xff) == H_LDIMM) pc++;  // second slot of lddw
   }
   o += "  return (uint32_t)r0;\n  }\n};\n\n";

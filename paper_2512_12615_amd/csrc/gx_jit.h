@@ -29,6 +29,7 @@ struct JitProg {
   const std::vector<int>* ld_map;
   bool event_parallel;
   bool leader = false;  // warp-leader hook: one lane runs each tile, on wave-uniform values
+  bool simt = false;    // SIMT hook: shared-map updates are wave-uniform, combined per wave
 };
 
 // HIP source of one program: its micro-ops written out as straight-line

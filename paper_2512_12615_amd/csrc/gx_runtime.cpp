@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cerrno>
+#include <chrono>
+#include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -12,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gx_internal.h"
@@ -22,6 +26,7 @@
 namespace gx {
 hipError_t vm_init();
 hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s);
+hipError_t launch_event_parallel_acc(RunArgs A, uint32_t n_cu, hipStream_t s);
 hipError_t launch_stream_seq(const RunArgs& A, uint32_t lanes, uint32_t qstride, hipStream_t s);
 hipError_t launch_partition(const RunArgs& A, uint32_t lbits, uint32_t tile, uint32_t nt, uint32_t* counts,
                             uint32_t* sums, uint32_t* order, uint8_t* sorted, hipStream_t s);
@@ -55,6 +60,30 @@ struct MapObj {
   size_t data_bytes = 0, slot_bytes = 0;
   uint8_t* h_pin = nullptr;  // ring: pinned staging for drains
   size_t pin_cap = 0;
+  // host tier (F_HOST): the pinned host allocations behind h.data / h.slots
+  uint8_t* host_data = nullptr;
+  uint8_t* host_slots = nullptr;
+};
+
+// Host snapshots of device maps (gx_snapshot_*): pinned copies taken by a
+// daemon thread between runs on one stream; the latest complete copy is
+// published under the lock.
+struct SnapMap {
+  int fd = -1;
+  size_t data_bytes = 0, slot_bytes = 0;
+  uint8_t* pin[2] = {nullptr, nullptr};  // copy target / published copy
+  uint64_t version = 0;
+};
+struct SnapDaemon {
+  std::thread th;
+  std::mutex mu;               // the published copies and versions
+  std::mutex take_mu;          // one snapshot at a time (daemon or flush)
+  std::condition_variable cv;
+  bool stop = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  uint64_t interval_us = 0;
+  std::vector<SnapMap> maps;
 };
 
 struct ProgObj {
@@ -78,6 +107,10 @@ struct ProgObj {
   uint32_t jred_blocks = 0; // blocks of its reduce kernel
   // launch shape chosen by gx_autotune (0: default)
   uint32_t tuned_lanes = 0, tuned_qbits = 0, tuned_blocks = 0;
+  // interpreted event-parallel runs: the shared array map summed in an LDS
+  // mirror (value area [acc_lo, acc_hi), operation, width code); none if equal
+  uint64_t acc_lo = 0, acc_hi = 0;
+  uint32_t acc_op = 0, acc_sc = 0;
   // member of a compiled program set: its set and its slot there (-1: none)
   int set_id = -1;
   uint32_t set_slot = 0;
@@ -222,6 +255,10 @@ struct gx_rt {
   std::vector<ProgObj> progs;
   uint64_t* d_err = nullptr;
   uint8_t* d_stage = nullptr;  // control-plane staging (keys, values, results)
+  // host snapshot daemon; runs are issued under enq_mu while it runs, so
+  // that its copies land between runs
+  SnapDaemon* snap = nullptr;
+  std::mutex enq_mu;
   std::vector<std::pair<hipStream_t, hipEvent_t>> stream_events;
   gx_stats stats{};
   uint32_t epoch = 0;  // launch counter for hash tombstone reuse
@@ -271,8 +308,10 @@ ProgObj* get_prog(gx_rt* rt, int fd) {
 }
 
 void free_map(MapObj& m) {
-  if (m.h.data) (void)hipFree(m.h.data);
-  if (m.h.slots) (void)hipFree(m.h.slots);
+  if (m.host_data) (void)hipHostFree(m.host_data);
+  else if (m.h.data) (void)hipFree(m.h.data);
+  if (m.host_slots) (void)hipHostFree(m.host_slots);
+  else if (m.h.slots) (void)hipFree(m.h.slots);
   if (m.h.ctrl) (void)hipFree(m.h.ctrl);
   if (m.d_desc) (void)hipFree(m.d_desc);
   if (m.h_pin) (void)hipHostFree(m.h_pin);
@@ -513,6 +552,17 @@ hipError_t launch_jit(const ProgObj* p, RunArgs A, uint32_t mode, uint32_t lanes
   return hipModuleLaunchKernel(p->jf_seq, (A.n_queues + lanes - 1) / lanes, 1, 1, 64, 1, 1, 0, s, args, nullptr);
 }
 
+// The interpreter's event-parallel launch: with the block-level LDS mirror
+// when the program updates a small shared array map.
+hipError_t launch_interp_ep(gx_rt* rt, const ProgObj* p, RunArgs A, hipStream_t s) {
+  if (p->acc_hi <= p->acc_lo || !env_int("GX_INTERP_ACC", 1)) return launch_event_parallel(A, s);
+  A.acc_lo = p->acc_lo;
+  A.acc_hi = p->acc_hi;
+  A.acc_op = p->acc_op;
+  A.acc_sc = p->acc_sc;
+  return launch_event_parallel_acc(A, rt->n_cu, s);
+}
+
 // One plain run of a program with launch shape k (validated arguments).
 int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint32_t* d_rc, hipStream_t s,
             const Knobs& k) {
@@ -532,6 +582,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   A.guards = p->d_guards;
   A.maptab = p->d_maptab;
   A.leader = p->hook == HOOK_WAVE_MEM ? 1u : 0u;
+  A.simt = p->hook == HOOK_SIMT_MEM ? 1u : 0u;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
@@ -557,7 +608,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
         rt->stats.launches += 1;
       }
     } else {
-      e = launch_event_parallel(A, s);
+      e = launch_interp_ep(rt, p, A, s);
     }
     if (pe.second) (void)hipEventRecord(pe.second, s);
     rt->stats.launches += 1;
@@ -605,7 +656,8 @@ struct StandIn {
   std::string log;
   int hook = 0;
   JitProg prog() const {
-    return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel, hook == HOOK_WAVE_MEM};
+    return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel, hook == HOOK_WAVE_MEM,
+                   hook == HOOK_SIMT_MEM};
   }
 };
 
@@ -719,6 +771,7 @@ int gx_open(int hip_device, gx_rt** out) {
 
 void gx_close(gx_rt* rt) {
   if (!rt) return;
+  gx_snapshot_stop(rt);
   DevGuard g(rt->dev);
   (void)hipDeviceSynchronize();
   for (auto& m : rt->maps)
@@ -749,8 +802,9 @@ void gx_close(gx_rt* rt) {
 int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_size, uint32_t max_entries,
                   uint32_t flags) {
   if (!rt) return -EINVAL;
-  if (flags & ~(uint32_t)(F_SHARED | F_READ_ONLY)) return -EINVAL;
+  if (flags & ~(uint32_t)(F_SHARED | F_READ_ONLY | F_HOST)) return -EINVAL;
   if ((flags & F_SHARED) && (flags & F_READ_ONLY)) return -EINVAL;
+  if ((flags & F_HOST) && (!(flags & F_READ_ONLY) || (type != MAP_ARRAY && type != MAP_HASH))) return -EINVAL;
   MapObj m;
   m.h.type = type;
   m.h.key_size = key_size;
@@ -778,16 +832,28 @@ int gx_create_map(gx_rt* rt, uint32_t type, uint32_t key_size, uint32_t value_si
     return -EINVAL;
   }
   DevGuard g(rt->dev);
-  bool ok = hipMalloc((void**)&m.h.data, m.data_bytes) == hipSuccess &&
-            hipMalloc((void**)&m.h.ctrl, kCtrlBytes) == hipSuccess && hipMalloc((void**)&m.d_desc, sizeof(MapDev)) == hipSuccess;
-  if (ok && m.slot_bytes) ok = hipMalloc((void**)&m.h.slots, m.slot_bytes) == hipSuccess;
+  bool ok;
+  if (flags & F_HOST) {
+    // the cold tier: pinned host memory, mapped for the device's loads
+    auto host = [&](size_t bytes, uint8_t** hp, uint8_t** dp) {
+      if (hipHostMalloc((void**)hp, bytes, hipHostMallocMapped) != hipSuccess) return false;
+      std::memset(*hp, 0, bytes);
+      return hipHostGetDevicePointer((void**)dp, *hp, 0) == hipSuccess;
+    };
+    ok = host(m.data_bytes, &m.host_data, &m.h.data) && (!m.slot_bytes || host(m.slot_bytes, &m.host_slots, &m.h.slots));
+  } else {
+    ok = hipMalloc((void**)&m.h.data, m.data_bytes) == hipSuccess &&
+         (!m.slot_bytes || hipMalloc((void**)&m.h.slots, m.slot_bytes) == hipSuccess);
+  }
+  ok = ok && hipMalloc((void**)&m.h.ctrl, kCtrlBytes) == hipSuccess &&
+       hipMalloc((void**)&m.d_desc, sizeof(MapDev)) == hipSuccess;
   if (!ok) {
     free_map(m);
     return -ENOMEM;
   }
-  ok = hipMemsetAsync(m.h.data, 0, m.data_bytes, rt->internal) == hipSuccess &&
+  ok = (m.host_data || hipMemsetAsync(m.h.data, 0, m.data_bytes, rt->internal) == hipSuccess) &&
        hipMemsetAsync(m.h.ctrl, 0, kCtrlBytes, rt->internal) == hipSuccess &&
-       (!m.slot_bytes || hipMemsetAsync(m.h.slots, 0, m.slot_bytes, rt->internal) == hipSuccess) &&
+       (!m.slot_bytes || m.host_slots || hipMemsetAsync(m.h.slots, 0, m.slot_bytes, rt->internal) == hipSuccess) &&
        hipMemcpyAsync(m.d_desc, &m.h, sizeof(MapDev), hipMemcpyHostToDevice, rt->internal) == hipSuccess &&
        hipStreamSynchronize(rt->internal) == hipSuccess;
   if (!ok) {
@@ -876,8 +942,11 @@ int gx_map_clear(gx_rt* rt, int map_fd) {
   if (!m) return -EINVAL;
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
-  bool ok = hipMemset(m->h.data, 0, m->data_bytes) == hipSuccess && hipMemset(m->h.ctrl, 0, kCtrlBytes) == hipSuccess &&
-            (!m->slot_bytes || hipMemset(m->h.slots, 0, m->slot_bytes) == hipSuccess) &&
+  if (m->host_data) std::memset(m->host_data, 0, m->data_bytes);
+  if (m->host_slots) std::memset(m->host_slots, 0, m->slot_bytes);
+  bool ok = (m->host_data || hipMemset(m->h.data, 0, m->data_bytes) == hipSuccess) &&
+            hipMemset(m->h.ctrl, 0, kCtrlBytes) == hipSuccess &&
+            (!m->slot_bytes || m->host_slots || hipMemset(m->h.slots, 0, m->slot_bytes) == hipSuccess) &&
             hipDeviceSynchronize() == hipSuccess;
   return ok ? 0 : -EIO;
 }
@@ -954,6 +1023,21 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
       guards[2 * pc + 1] = (uint64_t)(uintptr_t)m->h.data + m->data_bytes;
     }
   ProgObj p;
+  // the first shared array map the program updates with atomics, if its
+  // value area fits an LDS mirror (the verifier allows one operation at one
+  // width per shared map)
+  for (size_t pc = 0; pc < U.size() && pc < v.mem_map.size(); pc++) {
+    if ((U[pc].w0 & 0xff) != H_ATOMIC_MAP || v.mem_map[pc] < 0) continue;
+    const MapObj* m = tab[v.mem_map[pc]];
+    if (m->h.type != MAP_ARRAY || !(m->h.flags & F_SHARED)) continue;
+    const uint64_t area = (uint64_t)m->h.max_entries * m->h.vstride;
+    if (area > kAccMirrorMax) continue;
+    p.acc_lo = (uint64_t)(uintptr_t)m->h.data;
+    p.acc_hi = p.acc_lo + area;
+    p.acc_op = (uint32_t)U[pc].imm & 0xf0;
+    p.acc_sc = (U[pc].w0 >> 16) & 3;
+    break;
+  }
   p.hook = (int)hook_type;
   p.record_size = rs;
   p.stream_off = so;
@@ -1078,7 +1162,7 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
   JitInfo info;
   const std::string src =
       jit_source(JitProg{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
-                         p->hook == HOOK_WAVE_MEM},
+                         p->hook == HOOK_WAVE_MEM, p->hook == HOOK_SIMT_MEM},
                  &info);
   auto adopt = [&](const gx_rt::JitMod& jm) {
     p->jf_ep = jm.fe;
@@ -1146,7 +1230,7 @@ int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, ui
   std::map<std::string, uint32_t> uniq;
   for (uint32_t i = 0; i < n; i++) {
     const JitProg q{&ps[i]->uops, ps[i]->v.stack_bytes, &maps[i], &ps[i]->v.mem_map, &ps[i]->v.ld_map,
-                    ps[i]->v.event_parallel, ps[i]->hook == HOOK_WAVE_MEM};
+                    ps[i]->v.event_parallel, ps[i]->hook == HOOK_WAVE_MEM, ps[i]->hook == HOOK_SIMT_MEM};
     auto ins = uniq.emplace(jit_source(q), (uint32_t)jp.size());
     if (ins.second) jp.push_back(q);
     slot[i] = ins.first->second;
@@ -1260,6 +1344,9 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
   if (!d_events) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
   DevGuard g(rt->dev);
+  // a run's launches stay together between the snapshot daemon's copies
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
   return run_one(rt, p, d_events, n_events, d_rc, (hipStream_t)stream, knobs_of(p));
 }
 
@@ -1281,6 +1368,7 @@ RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events
   A.guards = p->d_guards;
   A.maptab = p->d_maptab;
   A.leader = p->hook == HOOK_WAVE_MEM ? 1u : 0u;
+  A.simt = p->hook == HOOK_SIMT_MEM ? 1u : 0u;
   A.checked = env_int("GX_CHECKED", 0) ? 1u : 0u;
   A.epoch = ++rt->epoch;
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
@@ -1568,6 +1656,8 @@ int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
   int r = check_batches(rt, descs, n);
   if (r) return r;
   DevGuard g(rt->dev);
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
   return run_batches_impl(rt, descs, n, (hipStream_t)stream);
 }
 
@@ -1715,6 +1805,8 @@ int gx_graph_launch(gx_graph* G, void* stream) {
   gx_rt* rt = G->rt;
   DevGuard g(rt->dev);
   hipStream_t s = (hipStream_t)stream;
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
   if (hipGraphLaunch(G->exec, s) != hipSuccess) return -EIO;
   rt->stats.launches += 1;
   rt->stats.events += G->events;
@@ -1868,6 +1960,150 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
   rt->stats.bytes_drained += kept;
   if (n_records) *n_records = nrec;
   return (int64_t)kept;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One snapshot of every map of the daemon: copies issued on its stream
+// between two runs (the enqueue lock keeps runs whole), waited for, then
+// published.  Returns 0 or -EIO.
+int snap_take(gx_rt* rt, SnapDaemon* d) {
+  std::lock_guard<std::mutex> one(d->take_mu);
+  {
+    std::lock_guard<std::mutex> lk(rt->enq_mu);
+    for (SnapMap& sm : d->maps) {
+      const MapObj& m = rt->maps[sm.fd];
+      if (hipMemcpyAsync(sm.pin[0], m.h.data, sm.data_bytes, hipMemcpyDeviceToHost, d->stream) != hipSuccess ||
+          (sm.slot_bytes && hipMemcpyAsync(sm.pin[0] + sm.data_bytes, m.h.slots, sm.slot_bytes, hipMemcpyDeviceToHost,
+                                           d->stream) != hipSuccess))
+        return -EIO;
+    }
+    if (hipEventRecord(d->ev, d->stream) != hipSuccess) return -EIO;
+  }
+  if (hipEventSynchronize(d->ev) != hipSuccess) return -EIO;
+  std::lock_guard<std::mutex> lk(d->mu);
+  for (SnapMap& sm : d->maps) {
+    std::swap(sm.pin[0], sm.pin[1]);
+    sm.version++;
+  }
+  return 0;
+}
+
+void snap_free(SnapDaemon* d) {
+  for (SnapMap& sm : d->maps)
+    for (uint8_t* p : sm.pin)
+      if (p) (void)hipHostFree(p);
+  if (d->ev) (void)hipEventDestroy(d->ev);
+  delete d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gx_snapshot_start(gx_rt* rt, const int* map_fds, uint32_t n, uint64_t interval_us, void* stream) {
+  if (!rt || (!map_fds && n)) return -EINVAL;
+  if (rt->snap) return -EBUSY;
+  DevGuard g(rt->dev);
+  SnapDaemon* d = new (std::nothrow) SnapDaemon();
+  if (!d) return -ENOMEM;
+  d->stream = (hipStream_t)stream;
+  d->interval_us = std::max<uint64_t>(interval_us, 100);
+  for (uint32_t i = 0; i < n; i++) {
+    const MapObj* m = get_map(rt, map_fds[i]);
+    if (!m || m->h.type == MAP_RINGBUF) {
+      snap_free(d);
+      return -EINVAL;
+    }
+    SnapMap sm;
+    sm.fd = map_fds[i];
+    sm.data_bytes = m->data_bytes;
+    sm.slot_bytes = m->slot_bytes;
+    d->maps.push_back(sm);
+    for (uint8_t*& p : d->maps.back().pin)
+      if (hipHostMalloc((void**)&p, sm.data_bytes + sm.slot_bytes, hipHostMallocDefault) != hipSuccess) {
+        snap_free(d);
+        return -ENOMEM;
+      }
+  }
+  if (hipEventCreateWithFlags(&d->ev, hipEventDisableTiming) != hipSuccess) {
+    snap_free(d);
+    return -ENOMEM;
+  }
+  rt->snap = d;
+  const int dev = rt->dev;
+  d->th = std::thread([rt, d, dev]() {
+    (void)hipSetDevice(dev);
+    std::unique_lock<std::mutex> lk(d->mu);
+    while (!d->stop) {
+      d->cv.wait_for(lk, std::chrono::microseconds(d->interval_us), [d] { return d->stop; });
+      if (d->stop) break;
+      lk.unlock();
+      (void)snap_take(rt, d);
+      lk.lock();
+    }
+  });
+  return 0;
+}
+
+int64_t gx_snapshot_read(gx_rt* rt, int map_fd, void* keys, void* vals, uint64_t cap, uint64_t* version) {
+  if (!rt) return -EINVAL;
+  SnapDaemon* d = rt->snap;
+  if (!d) return -ENOENT;
+  const MapObj* m = get_map(rt, map_fd);
+  if (!m) return -EINVAL;
+  std::lock_guard<std::mutex> lk(d->mu);
+  for (const SnapMap& sm : d->maps) {
+    if (sm.fd != map_fd) continue;
+    if (version) *version = sm.version;
+    const MapDev& h = m->h;
+    const uint8_t* data = sm.pin[1];
+    if (h.type == MAP_ARRAY) {
+      for (uint64_t i = 0; i < h.max_entries && i < cap; i++) {
+        if (keys) std::memcpy((uint8_t*)keys + 4 * i, &i, 4);
+        if (vals) std::memcpy((uint8_t*)vals + i * h.value_size, data + i * h.vstride, h.value_size);
+      }
+      return h.max_entries;
+    }
+    const uint8_t* slots = data + sm.data_bytes;
+    uint64_t cnt = 0;
+    for (uint64_t i = 0; i <= h.slot_mask; i++) {
+      const uint8_t* hdr = slots + i * h.sstride;
+      uint32_t st;
+      std::memcpy(&st, hdr, 4);
+      if ((st & 0xff) != SLOT_LIVE) continue;
+      if (cnt < cap) {
+        if (keys) std::memcpy((uint8_t*)keys + cnt * h.key_size, hdr + 8, h.key_size);
+        if (vals) std::memcpy((uint8_t*)vals + cnt * h.value_size, data + i * h.vstride, h.value_size);
+      }
+      cnt++;
+    }
+    return (int64_t)cnt;
+  }
+  return -ENOENT;
+}
+
+int gx_snapshot_flush(gx_rt* rt) {
+  if (!rt || !rt->snap) return -ENOENT;
+  DevGuard g(rt->dev);
+  return snap_take(rt, rt->snap);
+}
+
+void gx_snapshot_stop(gx_rt* rt) {
+  if (!rt || !rt->snap) return;
+  SnapDaemon* d = rt->snap;
+  {
+    std::lock_guard<std::mutex> lk(d->mu);
+    d->stop = true;
+  }
+  d->cv.notify_all();
+  if (d->th.joinable()) d->th.join();
+  DevGuard g(rt->dev);
+  (void)hipStreamSynchronize(d->stream);
+  rt->snap = nullptr;
+  snap_free(d);
 }
 
 int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail) {

@@ -2,13 +2,17 @@
 // admission by device-memory budget (declared in include/gxbpf.h).
 //
 // A host thread owns every HIP call of the server.  Submissions land in
-// per-tenant FIFO queues; a tenant has at most one request on the device
-// (its programs own its maps, so its requests must run in order).  Whenever
-// the thread finds requests whose buffers fit in the free part of the device
-// pool, it admits them together and launches them as one batched run on the
-// next of its streams; a request whose buffers do not fit waits without
-// blocking smaller requests of other tenants.  Completion is detected with
-// HIP events, after the return codes have been copied back.
+// per-tenant FIFO queues.  A tenant's programs own its maps, so its
+// requests must run in order: they all go to stream (tenant mod streams),
+// whose order keeps them in sequence; in continuous mode a stream holds up
+// to four unfinished launches, each taking the head request of each of its
+// tenants, so one tenant may have several requests queued on the device
+// (one per launch, in order).  Only the per-request mode keeps at most one
+// request per tenant in flight.  Whenever the thread finds requests whose
+// buffers fit in the free part of the device pool, it admits them; a
+// request whose buffers do not fit waits without blocking smaller requests
+// of other tenants.  Completion is detected with HIP events, after the
+// return codes have been copied back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -46,7 +46,7 @@ bool hook_layout(int hook, uint32_t* record_size, uint32_t* stream_off, uint32_t
     *stream_size = 4;
     return true;
   }
-  if (hook == HOOK_WAVE_MEM) {  // input records as HOOK_MEM_ACCESS
+  if (hook == HOOK_WAVE_MEM || hook == HOOK_SIMT_MEM) {  // input records as HOOK_MEM_ACCESS
     *record_size = 24;
     *stream_off = 8;
     *stream_size = 4;
@@ -64,8 +64,14 @@ bool ctx_field(int hook, int64_t off, int size) {
   if (hook == HOOK_KERNEL_TIMING) return (off == 0 && size == 4) || (off == 8 && size == 8);
   if (hook == HOOK_WAVE_MEM)
     return (off == 0 && size == 8) || (off == 8 && size == 8) || (off == 16 && size == 4) || (off == 20 && size == 4);
+  if (hook == HOOK_SIMT_MEM)  // the record's fields, then the tile aggregate's at 24
+    return ctx_field(HOOK_MEM_ACCESS, off, size) || (off >= 24 && ctx_field(HOOK_WAVE_MEM, off - 24, size));
   return false;
 }
+
+// SIMT hook: ctx bytes from this offset on are warp-uniform (the tile's
+// aggregate); the record's own fields before it vary by lane.
+constexpr int64_t kSimtUniformFrom = 24;
 
 // ---------------------------------------------------------------------------
 // tracked-bits domain: bit i is known iff mask bit i is 0, then equals v bit i.
@@ -107,6 +113,7 @@ struct Val {
   Bits b = kUnknownBits;     // scalar value / pointer offset bits
   uint64_t lo = 0, hi = ~0ull;  // unsigned range (scalar) / offset range as signed (pointers)
   int map = -1;
+  bool lanes = false;        // differs between the lanes of a wave (SIMT hook)
 };
 
 Val scal(Bits b, uint64_t lo, uint64_t hi) {
@@ -140,6 +147,7 @@ Val vjoin(const Val& a, const Val& b) {
   r.t = t;
   r.map = a.map;
   r.b = bunion(a.b, b.b);
+  r.lanes = a.lanes || b.lanes;
   if (t == T_SCALAR) {
     r.lo = std::min(a.lo, b.lo);
     r.hi = std::max(a.hi, b.hi);
@@ -153,7 +161,8 @@ Val vjoin(const Val& a, const Val& b) {
 struct State {
   bool live = false;
   Val r[11];
-  uint64_t init[kStackMax / 64];  // stack byte initialised bits (byte i of the 512-byte frame)
+  uint64_t init[kStackMax / 64];   // stack byte initialised bits (byte i of the 512-byte frame)
+  uint64_t lanes[kStackMax / 64];  // stack byte holds a lane-varying value (SIMT hook)
   uint64_t steps = 0, calls = 0, ring = 0;
 };
 
@@ -165,6 +174,7 @@ void sjoin(State& d, const State& s) {
   }
   for (int i = 0; i < 11; i++) d.r[i] = vjoin(d.r[i], s.r[i]);
   for (int i = 0; i < kStackMax / 64; i++) d.init[i] &= s.init[i];
+  for (int i = 0; i < kStackMax / 64; i++) d.lanes[i] |= s.lanes[i];
   d.steps = std::max(d.steps, s.steps);
   d.calls = std::max(d.calls, s.calls);
   d.ring = std::max(d.ring, s.ring);
@@ -177,6 +187,17 @@ bool init_all(const State& s, int64_t o, int64_t n) {
 }
 void init_set(State& s, int64_t o, int64_t n) {
   for (int64_t i = o; i < o + n; i++) s.init[i >> 6] |= 1ull << (i & 63);
+}
+bool lanes_any(const State& s, int64_t o, int64_t n) {
+  for (int64_t i = o; i < o + n; i++)
+    if ((s.lanes[i >> 6] >> (i & 63)) & 1) return true;
+  return false;
+}
+void lanes_set(State& s, int64_t o, int64_t n, bool v) {
+  for (int64_t i = o; i < o + n; i++) {
+    if (v) s.lanes[i >> 6] |= 1ull << (i & 63);
+    else s.lanes[i >> 6] &= ~(1ull << (i & 63));
+  }
 }
 
 struct Fail {
@@ -262,7 +283,7 @@ uint64_t eval_alu(bool w64, int op, int16_t off, bool x, int32_t imm, uint64_t a
 class Verifier {
  public:
   Verifier(const std::vector<Insn>& p, int hook, const std::vector<MapShape>& t, const std::vector<int>& fds)
-      : P(p), N((int)p.size()), hook_(hook), maps_(t), fds_(fds) {}
+      : P(p), N((int)p.size()), hook_(hook), simt_(hook == HOOK_SIMT_MEM), maps_(t), fds_(fds) {}
 
   Verdict run() {
     Verdict& V = out_;
@@ -293,6 +314,7 @@ class Verifier {
       s.r[10].b = bconst(kStackMax);
       s.r[10].lo = s.r[10].hi = kStackMax;
       std::memset(s.init, 0, sizeof s.init);
+      std::memset(s.lanes, 0, sizeof s.lanes);
       std::map<int, State> exits;
       walk(0, N - 1, s, exits, nullptr);
       if (!exits.empty()) fail(exits.begin()->first, "control leaves the program");
@@ -305,6 +327,8 @@ class Verifier {
           V.event_parallel = false;
       if (hook_ == HOOK_WAVE_MEM && !V.event_parallel)
         fail(0, "a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers");
+      if (simt_ && !V.event_parallel)
+        fail(0, "the lanes of a SIMT hook run one wave's events at once: its maps must be shared, read-only or ring buffers");
     } catch (const Fail& f) {
       Verdict bad;
       bad.ok = false;
@@ -318,6 +342,10 @@ class Verifier {
   const std::vector<Insn>& P;
   const int N;
   const int hook_;
+  // SIMT hook (section 4.4, "SIMT-aware Verification"): values are tracked
+  // as warp-uniform or lane-varying; branches, map keys, ring records and
+  // their flags, and map-update addresses must be uniform
+  const bool simt_;
   const std::vector<MapShape>& maps_;
   const std::vector<int>& fds_;
   Verdict out_;
@@ -524,24 +552,29 @@ class Verifier {
   }
 
   // Memory access through ``base``; mode: 0 load, 1 store, 2 commutative
-  // atomic, 3 atomic that reads.
-  void access(State& s, int pc, const Val& base, int64_t off, int size, int mode) {
+  // atomic, 3 atomic that reads.  ``in_lanes``: the stored value varies by
+  // lane.  Returns whether the value read varies by lane.
+  bool access(State& s, int pc, const Val& base, int64_t off, int size, int mode, bool in_lanes = false) {
     switch (base.t) {
       case T_CTX:
         if (mode != 0) fail(pc, "ctx is read-only");
         if (base.lo != 0 || base.hi != 0 || !ctx_field(hook_, off, size)) fail(pc, "invalid ctx field access");
         fact(out_.mem_kind, pc, KIND_CTX, "memory access");
-        return;
+        return simt_ && off < kSimtUniformFrom;
       case T_STACK: {
         if (base.lo != base.hi) fail(pc, "stack access with a variable offset");
         int64_t o = (int64_t)base.lo + off;
         if (o < 0 || o + size > kStackMax) fail(pc, "stack access out of bounds");
         if (o & (size - 1)) fail(pc, "misaligned stack access");
         if (mode != 1 && !init_all(s, o, size)) fail(pc, "stack read before write");
-        if (mode != 0) init_set(s, o, size);
+        const bool was = mode != 1 && lanes_any(s, o, size);
+        if (mode != 0) {
+          init_set(s, o, size);
+          lanes_set(s, o, size, in_lanes || was);
+        }
         low_stack_ = std::min<int>(low_stack_, (int)o);
         fact(out_.mem_kind, pc, KIND_STACK, "memory access");
-        return;
+        return was;
       }
       case T_MAPVAL: {
         const MapShape& m = maps_[base.map];
@@ -549,6 +582,8 @@ class Verifier {
         if (lo < 0 || hi + size > (int64_t)m.value_size) fail(pc, "map value access out of bounds");
         uint64_t al = (uint64_t)size - 1;
         if (((base.b.v + (uint64_t)off) & al) || (base.b.m & al)) fail(pc, "map value access may be misaligned");
+        if (simt_ && mode != 0 && base.lanes) fail(pc, "SIMT hook: a map update at a lane-varying address");
+        if (simt_ && mode == 3) fail(pc, "SIMT hook: an atomic that reads a map value is not warp-uniform");
         if ((m.flags & F_READ_ONLY) && mode != 0) fail(pc, "write to a read-only map");
         if ((m.flags & F_SHARED) && mode != 2) fail(pc, "shared maps take only commutative atomics");
         if (m.flags & F_SHARED) {
@@ -559,7 +594,7 @@ class Verifier {
         }
         fact(out_.mem_kind, pc, KIND_MAPVAL, "memory access");
         fact_map(out_.mem_map, pc, base.map);
-        return;
+        return base.lanes;
       }
       case T_MAPVAL_NULL:
         fail(pc, "map value used before its null check");
@@ -568,13 +603,17 @@ class Verifier {
     }
   }
 
-  void mem_arg(State& s, int pc, int reg, uint64_t n, std::vector<int8_t>& kinds) {
+  // A helper's memory argument; ``uniform``: what it is, when the SIMT hook
+  // needs it warp-uniform (nullptr: no such need).
+  void mem_arg(State& s, int pc, int reg, uint64_t n, std::vector<int8_t>& kinds, const char* uniform = nullptr) {
     const Val& v = use(s, pc, reg);
+    if (simt_ && uniform && v.lanes) fail(pc, std::string("SIMT hook: ") + uniform + " through a lane-varying pointer");
     if (v.t == T_STACK) {
       if (v.lo != v.hi) fail(pc, "helper stack argument with a variable offset");
       int64_t o = (int64_t)v.lo;
       if (o < 0 || o + (int64_t)n > kStackMax) fail(pc, "helper stack argument out of bounds");
       if (!init_all(s, o, (int64_t)n)) fail(pc, "helper reads uninitialised stack");
+      if (simt_ && uniform && lanes_any(s, o, (int64_t)n)) fail(pc, std::string("SIMT hook: lane-varying ") + uniform);
       low_stack_ = std::min<int>(low_stack_, (int)o);
       fact(kinds, pc, KIND_STACK, "helper argument");
       return;
@@ -602,7 +641,7 @@ class Verifier {
     if (id == 1) {
       int m = map_arg(s, pc);
       if (maps_[m].type == MAP_RINGBUF) fail(pc, "lookup on a ring buffer");
-      mem_arg(s, pc, 2, maps_[m].key_size, out_.arg2_kind);
+      mem_arg(s, pc, 2, maps_[m].key_size, out_.arg2_kind, "map key");
       Val r;
       r.t = T_MAPVAL_NULL;
       r.map = m;
@@ -614,9 +653,9 @@ class Verifier {
       const MapShape& ms = maps_[m];
       if (ms.type == MAP_RINGBUF) fail(pc, "update/delete on a ring buffer");
       if (ms.flags & (F_SHARED | F_READ_ONLY)) fail(pc, "update/delete on a shared or read-only map");
-      mem_arg(s, pc, 2, ms.key_size, out_.arg2_kind);
+      mem_arg(s, pc, 2, ms.key_size, out_.arg2_kind, "map key");
       if (id == 2) {
-        mem_arg(s, pc, 3, ms.value_size, out_.arg3_kind);
+        mem_arg(s, pc, 3, ms.value_size, out_.arg3_kind, "map update value");
         if (use(s, pc, 4).t != T_SCALAR) fail(pc, "update flags must be a scalar");
       }
       if (ms.type == MAP_HASH)
@@ -630,8 +669,9 @@ class Verifier {
       if (!is_const(z) || z.lo < 1 || z.lo > 4096) fail(pc, "ringbuf_output size must be a constant in [1, 4096]");
       if (out_.ring_size[pc] && out_.ring_size[pc] != z.lo) fail(pc, "ringbuf_output size differs between paths");
       out_.ring_size[pc] = (uint32_t)z.lo;
-      mem_arg(s, pc, 2, z.lo, out_.arg2_kind);
+      mem_arg(s, pc, 2, z.lo, out_.arg2_kind, "ring record");
       if (use(s, pc, 4).t != T_SCALAR) fail(pc, "ringbuf_output flags must be a scalar");
+      if (simt_ && use(s, pc, 4).lanes) fail(pc, "SIMT hook: lane-varying ringbuf_output flags");
       s.ring += 8 + ((z.lo + 7) & ~7ull);
       if (s.ring > kMaxRingBytes) fail(pc, "ring-byte budget exceeded");
       s.r[0] = sany();
@@ -812,7 +852,9 @@ class Verifier {
         if (o == 0x80 || o == 0xd0) {
           const Val& a = use(s, pc, in.dst);
           if (a.t != T_SCALAR) fail(pc, "arithmetic on a pointer");
+          const bool ln = a.lanes;
           s.r[in.dst] = alu(pc, w64, in, a, sconst(0));
+          s.r[in.dst].lanes = ln;
           break;
         }
         Val b = x ? use(s, pc, in.src) : sconst(w64 ? (uint64_t)(int64_t)in.imm : (uint64_t)(uint32_t)in.imm);
@@ -823,11 +865,13 @@ class Verifier {
         if (o == 0xb0) {
           if (b.t != T_SCALAR) fail(pc, "pointer truncated or sign-extended");
           s.r[in.dst] = alu(pc, w64, in, sconst(0), b);
+          s.r[in.dst].lanes = b.lanes;
           break;
         }
         const Val a = use(s, pc, in.dst);
         if (a.t == T_SCALAR && b.t == T_SCALAR) {
           s.r[in.dst] = alu(pc, w64, in, a, b);
+          s.r[in.dst].lanes = a.lanes || b.lanes;
           break;
         }
         if (!w64 || b.t != T_SCALAR || (o != 0x00 && o != 0x10) || (a.t != T_STACK && a.t != T_MAPVAL))
@@ -853,6 +897,7 @@ class Verifier {
           fail(pc, "pointer offset is unbounded");
         }
         if ((int64_t)r.lo < -(1ll << 32) || (int64_t)r.hi > (1ll << 32)) fail(pc, "pointer offset out of range");
+        r.lanes = a.lanes || b.lanes;
         s.r[in.dst] = r;
         break;
       }
@@ -877,6 +922,7 @@ class Verifier {
         }
         const Val& a = use(s, pc, in.dst);
         Val b = x ? use(s, pc, in.src) : sconst(w32 ? (uint64_t)(uint32_t)in.imm : (uint64_t)(int64_t)in.imm);
+        if (simt_ && (a.lanes || b.lanes)) fail(pc, "SIMT hook: the branch condition varies by lane");
         if (a.t == T_MAPVAL || a.t == T_MAPVAL_NULL) {
           if (w32 || x || in.imm || (o != 0x10 && o != 0x50)) fail(pc, "only a null check may compare a pointer");
           State nonnull = s, null = s;
@@ -909,9 +955,10 @@ class Verifier {
       case 1: {
         int sz = kSize[(in.op >> 3) & 3];
         Val base = use(s, pc, in.src);
-        access(s, pc, base, in.off, sz, 0);
+        const bool ln = access(s, pc, base, in.off, sz, 0);
         bool sx = (in.op & 0xe0) == 0x80;
         s.r[in.dst] = (sz == 8 || sx) ? sany() : scal(Bits{0, (1ull << (8 * sz)) - 1}, 0, (1ull << (8 * sz)) - 1);
+        s.r[in.dst].lanes = ln;
         break;
       }
       case 2: {
@@ -923,15 +970,18 @@ class Verifier {
       case 3: {
         int sz = kSize[(in.op >> 3) & 3];
         Val base = use(s, pc, in.dst);
-        if (use(s, pc, in.src).t != T_SCALAR) fail(pc, "pointers cannot be stored to memory");
+        const Val& sv = use(s, pc, in.src);
+        if (sv.t != T_SCALAR) fail(pc, "pointers cannot be stored to memory");
+        const bool sl = sv.lanes;
         if ((in.op & 0xe0) == 0x60) {
-          access(s, pc, base, in.off, sz, 1);
+          access(s, pc, base, in.off, sz, 1, sl);
           break;
         }
         bool reads = in.imm & 1;
         if (in.imm == 0xf1 && use(s, pc, 0).t != T_SCALAR) fail(pc, "cmpxchg compares against a scalar r0");
-        access(s, pc, base, in.off, sz, reads ? 3 : 2);
+        const bool ol = access(s, pc, base, in.off, sz, reads ? 3 : 2, sl || (in.imm == 0xf1 && s.r[0].lanes));
         Val old = sz == 8 ? sany() : s32any();
+        old.lanes = ol;
         if (in.imm == 0xf1) s.r[0] = old;
         else if (reads) s.r[in.src] = old;
         break;

@@ -19,8 +19,20 @@ typedef uint64_t rf_t __attribute__((ext_vector_type(16)));
 // ---------------------------------------------------------------------------
 // The interpreter: runs one invocation per live lane and returns rc.
 
+// A shared map's commutative atomic into the block's LDS mirror (only
+// commutative non-fetching operations reach a shared map, all of one
+// operation at one width, so the old value is never needed).
+__device__ __forceinline__ void acc_rmw(const RunArgs& A, uint64_t ad, uint64_t v) {
+  uint8_t* base = g_lds + A.acc_lds;
+  const uint64_t i = (ad - A.acc_lo) >> A.acc_sc;
+  if (A.acc_sc == 3)
+    lds_rmw<uint64_t>((uint64_t*)base + i, v, A.acc_op);
+  else
+    lds_rmw<uint32_t>((uint32_t*)base + i, (uint32_t)v, A.acc_op);
+}
+
 __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2,
-                                           const Stk stk, uint64_t& steps) {
+                                           const Ctx& g, const Stk stk, uint64_t& steps) {
   const Uop* __restrict__ U = A.uops;
   rf_t r = (rf_t)(0);
   r[10] = A.stack_bytes;
@@ -135,6 +147,9 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
         uint64_t wv = c0;
         if (wi == 1) wv = c1;
         if (wi == 2) wv = c2;
+        if (wi == 3) wv = g.c0;  // the tile's aggregate (SIMT hook)
+        if (wi == 4) wv = g.c1;
+        if (wi == 5) wv = g.c2;
         wv >>= 8 * ((uint32_t)aux & 7);
         uint64_t v = sc == 3 ? wv : (wv & ((1ull << (8 << sc)) - 1));
         res = (a8 & 4) ? sx(v, sc) : v;
@@ -173,10 +188,13 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
         uint64_t old = 0;
         if (A.checked && h == H_ATOMIC_MAP) act = act && guard_ok(A, pc, a + (int64_t)aux, 1u << sc);
         if (act) {
+          const uint64_t ad = a + (int64_t)aux;
           if (h == H_ATOMIC_STACK)
             old = atomic_stack(saddr(stk, (uint32_t)a + aux), v, op, sc, r0);
+          else if (ad - A.acc_lo < A.acc_hi - A.acc_lo)
+            acc_rmw(A, ad, v);  // the block's LDS mirror of a shared map
           else
-            old = atomic_global(a + (int64_t)aux, v, op, sc, r0);
+            old = atomic_global(ad, v, op, sc, r0);
         }
         if (op == 0xf1) {
           res = old;
@@ -290,8 +308,8 @@ __device__ __forceinline__ uint32_t vm_run(const RunArgs& A, bool live, uint64_t
 
 struct Interp {
   __device__ __forceinline__ uint32_t run(const RunArgs& A, bool live, uint64_t c0, uint64_t c1, uint64_t c2,
-                                          const Stk stk, uint64_t& steps) {
-    return vm_run(A, live, c0, c1, c2, stk, steps);
+                                          const Ctx& g, const Stk stk, uint64_t& steps) {
+    return vm_run(A, live, c0, c1, c2, g, stk, steps);
   }
 };
 
@@ -302,6 +320,31 @@ extern "C" __global__ void __launch_bounds__(256) gx_k_event_parallel(RunArgs A)
   uint64_t steps = 0;
   Interp I;
   event_tile(I, A, (uint64_t)blockIdx.x * blockDim.x + wave * 64u, stk, steps);
+}
+
+// Event-parallel mode with a shared map summed in LDS: each block mirrors
+// the map's value area (starting at the operation's identity), its waves
+// take tiles t, t + stride, ... of the run, and the block applies its sums
+// to the map once at the end (consecutive threads, consecutive words: one
+// coalesced device atomic per word it touched).  The grid is sized so that
+// each block runs at least as many events as the mirror has words.
+extern "C" __global__ void __launch_bounds__(1024) gx_k_event_parallel_acc(RunArgs A) {
+  const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
+  const uint32_t words = (uint32_t)((A.acc_hi - A.acc_lo) >> A.acc_sc);
+  uint8_t* mirror = g_lds + A.acc_lds;
+  if (A.acc_sc == 3)
+    mirror_init<uint64_t>((uint64_t*)mirror, words, A.acc_op);
+  else
+    mirror_init<uint32_t>((uint32_t*)mirror, words, A.acc_op);
+  __syncthreads();
+  Interp I;
+  event_loop(I, A, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, stk);
+  __syncthreads();
+  if (A.acc_sc == 3)
+    mirror_flush<uint64_t>((const uint64_t*)mirror, words, A.acc_op, (uint8_t*)A.acc_lo);
+  else
+    mirror_flush<uint32_t>((const uint32_t*)mirror, words, A.acc_op, (uint8_t*)A.acc_lo);
 }
 
 // Stream-sequential mode: ``lanes`` lanes of each one-wave block own queues.
@@ -525,6 +568,9 @@ hipError_t vm_init() {
   hipError_t e = hipFuncSetAttribute((const void*)gx_k_event_parallel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      256 * kStackMax);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gx_k_event_parallel_acc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          kAccLdsMax);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)gx_k_stream_seq, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)gx_k_batched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
@@ -533,6 +579,24 @@ hipError_t vm_init() {
 hipError_t launch_event_parallel(const RunArgs& A, hipStream_t s) {
   uint64_t blocks = (A.n_events + 255) / 256;
   hipLaunchKernelGGL(gx_k_event_parallel, dim3((uint32_t)blocks), dim3(256), 256 * A.stack_bytes, s, A);
+  return hipGetLastError();
+}
+
+// The mirrored form: as many waves per block (up to 16) as the LDS holds
+// next to the mirror, and blocks enough to fill the device but no more
+// than one per ``words`` events.
+hipError_t launch_event_parallel_acc(RunArgs A, uint32_t n_cu, hipStream_t s) {
+  const uint64_t acc_bytes = A.acc_hi - A.acc_lo;
+  uint32_t nw = 16;
+  while (nw > 1 && (uint64_t)nw * 64 * A.stack_bytes + acc_bytes > kAccLdsMax) nw /= 2;
+  A.acc_lds = nw * 64u * A.stack_bytes;
+  const uint64_t words = acc_bytes >> A.acc_sc;
+  const uint64_t tiles = (A.n_events + 63) / 64;
+  const uint64_t per_words = A.n_events / words > n_cu ? A.n_events / words : n_cu;
+  uint64_t nb = (tiles + nw - 1) / nw;
+  if (nb > per_words) nb = per_words;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(gx_k_event_parallel_acc, dim3((uint32_t)nb), dim3(64 * nw), A.acc_lds + acc_bytes, s, A);
   return hipGetLastError();
 }
 

@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libgxbpf.so")
 
 MAP_HASH, MAP_ARRAY, MAP_RINGBUF = 1, 2, 27
 F_SHARED, F_READ_ONLY = 1, 2
-HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING, HOOK_WAVE_MEM = 1, 2, 3
+HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING, HOOK_WAVE_MEM, HOOK_SIMT_MEM = 1, 2, 3, 4
 MODE_EVENT_PARALLEL, MODE_STREAM_SEQUENTIAL = 0, 1
-RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16, HOOK_WAVE_MEM: 24}
+RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16, HOOK_WAVE_MEM: 24, HOOK_SIMT_MEM: 24}
 
 
 class GxError(OSError):
@@ -44,7 +44,8 @@ class Batch(C.Structure):
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
            "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
-           "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
+           "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_snapshot_start", "gx_snapshot_read",
+           "gx_snapshot_flush", "gx_snapshot_stop", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
            "gx_server_release", "gx_server_drain", "gx_server_destroy"]
 SERVE_CONTINUOUS, SERVE_PER_REQUEST = 0, 1
@@ -116,6 +117,12 @@ def lib():
     L.gx_drain_ringbuf.argtypes = [vp, C.c_int, vp, u64, C.POINTER(u64)]
     L.gx_drain_ringbuf.restype = i64
     L.gx_ringbuf_pos.argtypes = [vp, C.c_int, C.POINTER(u64), C.POINTER(u64)]
+    L.gx_snapshot_start.argtypes = [vp, vp, u32, u64, vp]
+    L.gx_snapshot_read.argtypes = [vp, C.c_int, vp, vp, u64, C.POINTER(u64)]
+    L.gx_snapshot_read.restype = i64
+    L.gx_snapshot_flush.argtypes = [vp]
+    L.gx_snapshot_stop.argtypes = [vp]
+    L.gx_snapshot_stop.restype = None
     L.gx_stats_get.argtypes = [vp, C.POINTER(Stats)]
     L.gx_profile_enable.argtypes = [vp, C.c_int]
     L.gx_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(u64)]
@@ -377,6 +384,32 @@ class Runtime:
         h, t = C.c_uint64(0), C.c_uint64(0)
         _check(lib().gx_ringbuf_pos(self._h, fd, C.byref(h), C.byref(t)), "gx_ringbuf_pos")
         return h.value, t.value
+
+    # host snapshots ---------------------------------------------------------
+    def snapshot_start(self, fds, interval_us=1000, stream=None):
+        """Start the snapshot daemon over maps ``fds`` (gx_snapshot_start)."""
+        arr = np.array(list(fds), dtype=np.int32)
+        _check(lib().gx_snapshot_start(self._h, arr.ctypes.data_as(C.c_void_p), len(arr), int(interval_us),
+                                       _stream_handle(stream)), "gx_snapshot_start")
+
+    def snapshot_read(self, fd):
+        """(keys, values, version) of the latest host snapshot of a map,
+        without touching the device (shapes as map_dump)."""
+        m = self.maps[fd]
+        ver = C.c_uint64(0)
+        n = _check(lib().gx_snapshot_read(self._h, fd, None, None, 0, C.byref(ver)), "gx_snapshot_read")
+        keys = np.zeros((max(n, 1), m.key_size), np.uint8)
+        vals = np.zeros((max(n, 1), m.value_size), np.uint8)
+        n2 = _check(lib().gx_snapshot_read(self._h, fd, keys.ctypes.data_as(C.c_void_p),
+                                           vals.ctypes.data_as(C.c_void_p), n, C.byref(ver)), "gx_snapshot_read")
+        n = min(n, n2)
+        return keys[:n], vals[:n], ver.value
+
+    def snapshot_flush(self):
+        _check(lib().gx_snapshot_flush(self._h), "gx_snapshot_flush")
+
+    def snapshot_stop(self):
+        lib().gx_snapshot_stop(self._h)
 
     def profile_enable(self, on=True):
         _check(lib().gx_profile_enable(self._h, int(on)), "gx_profile_enable")

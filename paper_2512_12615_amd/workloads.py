@@ -37,6 +37,10 @@ HOOK_KERNEL_TIMING = 2
 # warp-leader hook: one invocation per tile of 64 memory-access records, on
 # the tile's aggregate {u64 lo @0, u64 hi @8, u32 n @16, u32 stream @20}
 HOOK_WAVE_MEM = 3
+# SIMT hook: one invocation per memory-access record, on the record followed
+# by its tile's aggregate at byte 24 (warp-uniform); the verifier holds the
+# program to warp-uniform branches, keys and side effects
+HOOK_SIMT_MEM = 4
 MEM_DTYPE = np.dtype([("addr", "<u8"), ("stream", "<u4"), ("pad", "<u4"), ("ts", "<u8")])
 TIMING_DTYPE = np.dtype([("kernel_id", "<u4"), ("pad", "<u4"), ("lat", "<u8")])
 assert MEM_DTYPE.itemsize == 24 and TIMING_DTYPE.itemsize == 16
@@ -513,6 +517,80 @@ def wave_monitor_policy(ring_bytes: int = 64 << 20) -> Policy:
         MapSpec("scat", MAP_ARRAY, 4, 8, 4096, F_SHARED),
         MapSpec("ring", MAP_RINGBUF, 0, 0, ring_bytes, 0),
     ])
+
+
+# The wave monitor's counting part, as a warp-leader handler and as the same
+# handler run by every lane under the SIMT hook: tiles whose addresses span
+# at most 4 KiB count their records into coal[region of lo], the others
+# into scat[region of lo]; rc = the tile's highest address.  Once per tile
+# the leader adds n; per lane each record adds 1 (the device combines the
+# wave's lanes into one update), so both give the same maps and rc.
+WAVE_COUNTS_LEADER = """
+    ldxdw r6, [r1+0]          ; lo
+    ldxdw r7, [r1+8]          ; hi
+    ldxw r8, [r1+16]          ; n
+    mov64 r2, r6
+    rsh64 r2, 21
+    and64 r2, 4095
+    stxw [r10-4], r2
+    mov64 r3, r7
+    sub64 r3, r6
+    jgt r3, 4095, wide
+    lddw r1, map:coal
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, out
+    aadd64 [r0+0], r8
+    ja out
+wide:
+    lddw r1, map:scat
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, out
+    aadd64 [r0+0], r8
+out:
+    mov64 r0, r7
+    exit
+"""
+
+WAVE_COUNTS_SIMT = """
+    ldxdw r6, [r1+24]         ; lo of the tile (uniform)
+    ldxdw r7, [r1+32]         ; hi of the tile (uniform)
+    mov64 r2, r6
+    rsh64 r2, 21
+    and64 r2, 4095
+    stxw [r10-4], r2
+    mov64 r3, r7
+    sub64 r3, r6
+    mov64 r8, 1
+    jgt r3, 4095, wide
+    lddw r1, map:coal
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, out
+    aadd64 [r0+0], r8
+    ja out
+wide:
+    lddw r1, map:scat
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, out
+    aadd64 [r0+0], r8
+out:
+    mov64 r0, r7
+    exit
+"""
+
+
+def wave_counts_policy(simt: bool) -> Policy:
+    maps = [MapSpec("coal", MAP_ARRAY, 4, 8, 4096, F_SHARED), MapSpec("scat", MAP_ARRAY, 4, 8, 4096, F_SHARED)]
+    if simt:
+        return Policy("wave_counts_simt", HOOK_SIMT_MEM, WAVE_COUNTS_SIMT, maps)
+    return Policy("wave_counts_leader", HOOK_WAVE_MEM, WAVE_COUNTS_LEADER, maps)
 
 
 def latency_hist_policy(kernels: int = 4096, ring_bytes: int = 64 << 20) -> Policy:

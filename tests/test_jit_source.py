@@ -40,8 +40,10 @@ def test_source_structure(G):
     pol = W.stride_prefetch_policy()
     src = G.jit_source(pol.code, pol.hook, _shapes(pol))
     # the lookup is emitted twice: through the LDS memo table (one queue per
-    # wave) and through the per-lane register memo (several queues per wave)
-    assert src.count("hash_lookup(") == 2 and src.count("hash_update(") == 1
+    # wave) and through the per-lane register memo (several queues per wave);
+    # its key lies in a frame word (private frame), so it is passed by value
+    assert src.count("hash_lookup_k(") == 2 and src.count("hash_update(") == 1
+    assert "saddr(stk, (uint32_t)" not in src  # no stack access left in LDS
     assert src.count("ring_output_chunked(") == 1
     labels = set(re.findall(r"^L(\d+):;", src, re.M))
     gotos = set(re.findall(r"goto L(\d+);", src))
