@@ -241,6 +241,22 @@ int64_t gx_jit_set_source(const uint64_t* insns, const uint32_t* n_insns, const 
 int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
                  uint32_t record_size, uint32_t* d_rc, void* stream);
 
+/* gx_run_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and results, but nothing is allocated - no hipMalloc,
+ * hipFree, events, streams or staging.  The run's workspace (the stream
+ * partition of a stream-sequential program; a compiled event-parallel
+ * program's cache spill, which flushes to the map directly when it does not
+ * fit) lives in a fixed 16 MiB array per device, found at gx_open and held
+ * until the process ends.  Every call on a device shares that array and
+ * nothing in it carries over between calls, so calls on one device must not
+ * overlap: issue them on one stream or order them.  No profile brackets are
+ * recorded.  Errors: as gx_run_batch, and -E2BIG when a stream-sequential
+ * run's workspace exceeds the array (about 480 k events with 4096 queues,
+ * the default launch shape). */
+int gx_run_batch_noalloc(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
+                         uint32_t record_size, uint32_t* d_rc, void* stream);
+
 /* Batched form: the work of n gx_run_batch calls in one persistent launch
  * (persistent workers claiming work units, as the paper's device scheduler
  * policies use them, section 5.3).  The results are those of the n calls

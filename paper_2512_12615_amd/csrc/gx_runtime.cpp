@@ -38,6 +38,7 @@ hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, ui
 hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
                           uint32_t waves, uint32_t stack_max, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, uint32_t n, hipStream_t s);
+hipError_t scratch_region(int dev, uint8_t** ptr, uint64_t* bytes);
 }  // namespace gx
 
 using namespace gx;
@@ -255,6 +256,12 @@ struct gx_rt {
   std::vector<ProgObj> progs;
   uint64_t* d_err = nullptr;
   uint8_t* d_stage = nullptr;  // control-plane staging (keys, values, results)
+  // gx_run_batch_noalloc: this device's scratch array (device address) and
+  // the event its latest run recorded
+  uint8_t* d_scratch = nullptr;
+  uint64_t scratch_bytes = 0;
+  hipEvent_t noalloc_ev = nullptr;
+  bool noalloc_used = false;
   // host snapshot daemon; runs are issued under enq_mu while it runs, so
   // that its copies land between runs
   SnapDaemon* snap = nullptr;
@@ -349,6 +356,7 @@ Exec* exec_for(gx_rt* rt, hipStream_t s) {
 int wait_all(gx_rt* rt) {
   for (auto& se : rt->stream_events)
     if (hipEventSynchronize(se.second) != hipSuccess) return -EIO;
+  if (rt->noalloc_used && hipEventSynchronize(rt->noalloc_ev) != hipSuccess) return -EIO;
   if (hipStreamSynchronize(rt->internal) != hipSuccess) return -EIO;
   return 0;
 }
@@ -759,7 +767,8 @@ int gx_open(int hip_device, gx_rt** out) {
     rt->n_cu = (uint32_t)ncu;
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
-      vm_init() != hipSuccess) {
+      hipEventCreateWithFlags(&rt->noalloc_ev, hipEventDisableTiming) != hipSuccess ||
+      scratch_region(hip_device, &rt->d_scratch, &rt->scratch_bytes) != hipSuccess || vm_init() != hipSuccess) {
     gx_close(rt);
     return -ENOMEM;
   }
@@ -784,6 +793,7 @@ void gx_close(gx_rt* rt) {
   for (auto& jm : rt->jit_cache)
     if (jm.second.mod) (void)hipModuleUnload(jm.second.mod);
   for (auto& se : rt->stream_events) (void)hipEventDestroy(se.second);
+  if (rt->noalloc_ev) (void)hipEventDestroy(rt->noalloc_ev);
   for (auto* v : {&rt->prof_pending, &rt->prof_free})
     for (auto& pe : *v) {
       (void)hipEventDestroy(pe.first);
@@ -1376,6 +1386,70 @@ RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events
   return A;
 }
 
+// Layout of a stream-sequential run's workspace in one region: counts,
+// sums, order, queue-ordered records, each 256-byte aligned.  Returns the
+// bytes needed.
+uint64_t seq_layout(uint64_t n_events, uint32_t lbits, uint64_t off[4]) {
+  const uint64_t tile = part_tile(n_events);
+  const uint64_t nt = (n_events + tile - 1) / tile;
+  const uint64_t m = ((uint64_t)1 << lbits) * nt;
+  const uint64_t sz[4] = {m * 4, ((m + 4095) / 4096 + 1) * 4, n_events * 4, n_events * kSortedStride};
+  uint64_t at = 0;
+  for (int i = 0; i < 4; i++) {
+    off[i] = at;
+    at += (sz[i] + 255) & ~255ull;
+  }
+  return at;
+}
+
+// One plain run that allocates nothing: the stream partition (and a
+// compiled event-parallel run's cache spill, when it fits) use the device's
+// scratch array instead of the runtime's workspace; no events, streams or
+// staging are created.  Every call on the device shares the array, so
+// calls that overlap on the device race.
+int run_noalloc(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint32_t* d_rc, hipStream_t s,
+                const Knobs& k) {
+  RunArgs A = make_args(rt, p, d_events, n_events, d_rc);
+  hipError_t e;
+  if (p->v.event_parallel) {
+    if (p->jf_ep) {
+      // a spill area beyond the array: the caches flush to the map directly
+      const uint64_t need = jit_spill_bytes(p, n_events, k.blocks);
+      uint8_t* sp = need && need <= rt->scratch_bytes ? rt->d_scratch : nullptr;
+      e = launch_jit(p, A, 0, 0, 0, 0, k.blocks, sp, s);
+      rt->stats.launches += sp ? 2 : 1;
+    } else {
+      e = launch_interp_ep(rt, p, A, s);
+      rt->stats.launches += 1;
+    }
+  } else {
+    uint64_t off[4];
+    if (seq_layout(n_events, k.qbits, off) > rt->scratch_bytes) return -E2BIG;
+    const uint64_t tile = part_tile(n_events);
+    const uint32_t nt = (uint32_t)((n_events + tile - 1) / tile);
+    uint32_t* counts = (uint32_t*)(rt->d_scratch + off[0]);
+    uint32_t* sums = (uint32_t*)(rt->d_scratch + off[1]);
+    uint32_t* order = (uint32_t*)(rt->d_scratch + off[2]);
+    uint8_t* sorted = rt->d_scratch + off[3];
+    e = launch_partition(A, k.qbits, (uint32_t)tile, nt, counts, sums, order, sorted, s);
+    if (e == hipSuccess) {
+      A.order = order;
+      A.sorted = sorted;
+      A.qstart = counts;
+      A.n_queues = 1u << k.qbits;
+      e = p->jf_seq ? launch_jit(p, A, 1, k.lanes, nt, (uint32_t)n_events, 0, nullptr, s)
+                    : launch_stream_seq(A, k.lanes, nt, s);
+    }
+    rt->stats.launches += 6;
+  }
+  if (e != hipSuccess) return to_errno(e);
+  // drains and map reads wait for this event
+  if (hipEventRecord(rt->noalloc_ev, s) != hipSuccess) return -EIO;
+  rt->noalloc_used = true;
+  rt->stats.events += n_events;
+  return 0;
+}
+
 bool shares_map(ProgObj* a, ProgObj* b, const std::vector<MapObj>& maps) {
   for (int x : a->fds)
     for (int y : b->fds)
@@ -1659,6 +1733,20 @@ int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
   std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
   if (rt->snap) lk.lock();
   return run_batches_impl(rt, descs, n, (hipStream_t)stream);
+}
+
+int gx_run_batch_noalloc(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size,
+                         uint32_t* d_rc, void* stream) {
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p) return -EINVAL;
+  if (record_size != p->record_size) return -EINVAL;
+  if (n_events == 0) return 0;
+  if (!d_events) return -EINVAL;
+  if (n_events >= (1ull << 32)) return -E2BIG;
+  DevGuard g(rt->dev);
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
+  return run_noalloc(rt, p, d_events, n_events, d_rc, (hipStream_t)stream, knobs_of(p));
 }
 
 int gx_autotune_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream, gx_tune* out) {

@@ -10,6 +10,8 @@
 // until the lanes meet again.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "gx_dev.h"
 
 namespace gx {
@@ -560,9 +562,40 @@ extern "C" __global__ void gx_k_map_op(const MapDev* m, int op, const uint8_t* k
 }  // namespace gx
 
 // ---------------------------------------------------------------------------
+// Workspace of the allocation-free run entry point (gx_run_batch_noalloc):
+// one fixed array per device, held until the process ends.  Its device
+// address is looked up once per device; host code uses that address only
+// (the array's name is a host-side stand-in, not device memory).
+
+namespace gx {
+constexpr uint64_t kScratchBytes = 16ull << 20;
+}
+
+static __device__ __align__(256) uint8_t scratch[gx::kScratchBytes];
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 
 namespace gx {
+
+// Device address of the current device's scratch array (device ``dev``),
+// looked up on the first call for that device.  0 or the HIP error.
+hipError_t scratch_region(int dev, uint8_t** ptr, uint64_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static uint8_t* addr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (uint8_t*)p;
+  }
+  *ptr = addr[dev];
+  *bytes = kScratchBytes;
+  return hipSuccess;
+}
 
 hipError_t vm_init() {
   hipError_t e = hipFuncSetAttribute((const void*)gx_k_event_parallel, hipFuncAttributeMaxDynamicSharedMemorySize,

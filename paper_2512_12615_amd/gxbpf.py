@@ -42,7 +42,7 @@ class Batch(C.Structure):
 
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
-           "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch",
+           "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch", "gx_run_batch_noalloc",
            "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_snapshot_start", "gx_snapshot_read",
            "gx_snapshot_flush", "gx_snapshot_stop", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
@@ -99,6 +99,7 @@ def lib():
     L.gx_prog_info_get.argtypes = [vp, C.c_int, C.POINTER(ProgInfo)]
     L.gx_verify.argtypes = [vp, u32, u32, vp, u32, C.c_char_p, u32, C.POINTER(ProgInfo)]
     L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
+    L.gx_run_batch_noalloc.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_graph_create.argtypes = [vp, C.POINTER(Batch), u32, C.POINTER(vp)]
@@ -333,6 +334,17 @@ class Runtime:
         r = lib().gx_run_batch(self._h, prog_fd, _dptr(events), n_events, record_size, _dptr(rc),
                                _stream_handle(stream))
         _check(r, "gx_run_batch")
+
+    def run_batch_noalloc(self, prog_fd, events, n_events=None, record_size=None, rc=None, stream=None):
+        """run_batch on the device's fixed scratch array: allocates nothing
+        (gx_run_batch_noalloc); calls on one device must not overlap."""
+        if record_size is None:
+            record_size = RECORD_SIZE[self.prog_info(prog_fd).hook]
+        if n_events is None:
+            n_events = events.numel() * events.element_size() // record_size
+        r = lib().gx_run_batch_noalloc(self._h, prog_fd, _dptr(events), n_events, record_size, _dptr(rc),
+                                       _stream_handle(stream))
+        _check(r, "gx_run_batch_noalloc")
 
     def run_batches(self, descs, stream=None):
         """descs: list of (prog_fd, events tensor, n_events, record_size, rc tensor or None)."""
