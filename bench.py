@@ -249,6 +249,122 @@ def bench_warp_leader(G, W, rt, steps, jit=True, threads=0):
     return out
 
 
+def _time_ms(fn, reps):
+    """Median wall time of fn() on the current stream between two events."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        s.record()
+        fn()
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e))
+    return _pct(ts, 50)
+
+
+def bench_app_hooks(G, W, rt, reps=10):
+    """A hook inside an application kernel (section 5.3's trampolines;
+    section 6.2.1's vector add with a stride access pattern): 2^26 doubles
+    per array, iterations visiting j = i s mod n for s = 1 (coalesced) and s
+    = 4099 (each lane on its own cache line), with no hook, with a per-lane
+    program (the access counter; the wave-counting handler under the SIMT
+    hook), and with warp-leader programs (the same counting handler; the L2
+    stride prefetch policy).  Overhead is against the kernel without a hook
+    at the same stride."""
+    import numpy as np
+    import torch
+    n = 1 << 26
+    g = torch.Generator(device="cuda").manual_seed(5)
+    a = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    c = torch.empty_like(a)
+    rc = torch.empty(n, dtype=torch.int32, device="cuda")
+    modes = [("none", None, True), ("per_lane_access_counter", W.access_counter_policy, True),
+             ("per_lane_simt_counts", lambda: W.wave_counts_policy(True), True),
+             ("warp_leader_counts", lambda: W.wave_counts_policy(False), True),
+             ("warp_leader_stride_l2", W.stride_l2_policy, True),
+             ("warp_leader_counts_interpreted", lambda: W.wave_counts_policy(False), False)]
+    out = {"workload": "vector add c[j] = a[j] + b[j], 2^26 doubles per array, j = i s mod n, hook at the load "
+                       "of a[j]", "elements": n}
+    want = a + b
+    for stride in (1, 4099):
+        res = {}
+        outputs = {}
+        for name, mk, jit in modes:
+            prog = -1
+            fds = []
+            if mk is not None:
+                pol = mk()
+                fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+                prog = rt.load_program(pol.code, pol.hook, fds)
+                if jit:
+                    rt.jit_program(prog)
+            # timed without return codes: the hint is consumed in the kernel
+            ms = _time_ms(lambda: rt.run_app_vadd(prog, a, b, c, stride=stride), reps)
+            ok = bool(torch.equal(c, want))
+            if name in ("per_lane_simt_counts", "warp_leader_counts"):
+                for fd in fds:
+                    rt.map_clear(fd)
+                rt.run_app_vadd(prog, a, b, c, stride=stride, rc=rc)
+                torch.cuda.synchronize()
+                outputs[name] = (rc.cpu().numpy().tobytes(), [rt.map_dump(fd)[1].tobytes() for fd in fds])
+            res[name] = {"ms": ms, "engine": ("jit" if jit else "interp") if mk else None, "result_ok": ok}
+        base = res["none"]["ms"]
+        for name in res:
+            res[name]["overhead_pct"] = 100.0 * (res[name]["ms"] - base) / base
+        res["none"]["gb_per_s"] = 24.0 * n / (base / 1e3) / 1e9
+        res["leader_and_simt_same_output"] = outputs["per_lane_simt_counts"] == outputs["warp_leader_counts"]
+        lead, simt = res["warp_leader_counts"]["ms"] - base, res["per_lane_simt_counts"]["ms"] - base
+        res["leader_overhead_cut_pct"] = 100.0 * (1 - lead / simt) if simt > 0 else None
+        out[f"stride_{stride}"] = res
+    del a, b, c, rc, want
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_block_scheduler(G, W, rt, reps=5):
+    """The device block scheduler (section 6.2.1): 1024 persistent workers
+    (one wave each) over 16 units each, units of 64 lanes running a 64-bit
+    generator cost[u] steps; "moderate" (costs rising linearly 1x..2x over
+    the units) and "heavy_tail" (a contiguous 10 % of the workers own units
+    100-200x costlier).  FixedWork (static ranges, no hook), Greedy (always
+    steal), MaxSteals (4 units) and LatencyBudget (steal while the worker
+    has stolen for less than a quarter of FixedWork's makespan), compiled.
+    Every run's output is checked against FixedWork's."""
+    import numpy as np
+    import torch
+    workers, upw = 1024, 16
+    out = {"workload": f"{workers} workers x {upw} units, 64 lanes per unit", "workers": workers}
+    for regime, base in (("moderate", 2000), ("heavy_tail", 200)):
+        cost = torch.from_numpy(W.sched_costs(workers, upw, regime, base, 11).view(np.int32)).cuda()
+        ref = torch.zeros(64 * cost.numel(), dtype=torch.int64, device="cuda")
+        res = {"base_steps": base}
+        fixed_ms = _time_ms(lambda: rt.run_sched(-1, cost, workers, ref), reps)
+        res["fixed"] = {"ms": fixed_ms}
+        budget_ns = int(fixed_ms * 1e6 / 4)
+        for kind, param in (("greedy", None), ("max_steals", 4), ("latency_budget", budget_ns)):
+            pol = W.sched_policy(kind)
+            fds = [rt.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags) for m in pol.maps]
+            if param is not None:
+                rt.map_update(fds[1], b"\0\0\0\0", np.uint64(param).tobytes())
+            prog = rt.load_program(pol.code, pol.hook, fds)
+            rt.jit_program(prog)
+            o = torch.zeros_like(ref)
+            log_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+            ms = _time_ms(lambda: rt.run_sched(prog, cost, workers, o, log_n=log_n), reps)
+            steals = int(np.frombuffer(rt.map_dump(fds[0])[1].tobytes(), "<u8").sum())
+            res[kind] = {"ms": ms, "speedup_vs_fixed": fixed_ms / ms, "decisions_last_run": int(log_n.item()),
+                         "yes_per_run": steals / (reps + 1), "same_output": bool(torch.equal(o, ref))}
+            if param is not None:
+                res[kind]["param"] = param
+        out[regime] = res
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_runs(items, threads, trials=10, budget_s=20.0):
     """Independent runs (policy, events) on ``threads`` threads, each run on
     a fresh oracle, runs handed to the least-loaded thread largest first:
@@ -514,7 +630,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the memory-bound policies, the batched and the served forms")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
-    ap.add_argument("--only-form", choices=["memory_bound", "warp_leader", "batched", "serving"],
+    ap.add_argument("--only-form", choices=["memory_bound", "warp_leader", "app_hooks", "block_scheduler", "batched",
+                                            "serving"],
                     help="run only this form and print its JSON (profiling one form)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel that "
@@ -548,6 +665,8 @@ def main():
         rt = G.Runtime(0)
         fn = {"memory_bound": lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit", threads),
               "warp_leader": lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit", threads),
+              "app_hooks": lambda: bench_app_hooks(G, W, rt),
+              "block_scheduler": lambda: bench_block_scheduler(G, W, rt),
               "batched": lambda: bench_batched(G, W, rt, 2, threads),
               "serving": lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit", threads=threads)}
         print(json.dumps({args.only_form: fn[args.only_form]()}))
@@ -615,6 +734,8 @@ def main():
         forms = {}
         for key, fn in (("memory_bound", lambda: bench_memory_bound(G, W, rt, 10, args.engine == "jit", threads)),
                         ("warp_leader", lambda: bench_warp_leader(G, W, rt, 10, args.engine == "jit", threads)),
+                        ("app_hooks", lambda: bench_app_hooks(G, W, rt)),
+                        ("block_scheduler", lambda: bench_block_scheduler(G, W, rt)),
                         ("batched", lambda: bench_batched(G, W, rt, 2, threads)),
                         ("serving", lambda: bench_serving(G, W, rt, args.serve_seconds, jit=args.engine == "jit",
                                                            threads=threads))):

@@ -79,12 +79,25 @@ enum {
  *                         buffers.  Waves then never split, and a wave's
  *                         shared-map updates (one word) are combined into
  *                         one.
- * The record (or aggregate) is the program's read-only ctx (r1). */
+ *   GX_HOOK_SCHED         steal decision of the device block scheduler
+ *                         (section 4.3.2, should_try_steal): run by
+ *                         gx_run_sched only, once per decision of a
+ *                         persistent worker, on 32 B {u32 worker; u32 done
+ *                         (units run so far); u64 elapsed_ns (since the
+ *                         worker started); u64 steal_ns (since it began
+ *                         stealing); u32 stolen (units stolen so far); u32
+ *                         left (units left in the victim's range)}; a
+ *                         non-zero return code takes one more unit.  Maps
+ *                         must be shared, read-only or ring buffers.
+ * The record (or aggregate) is the program's read-only ctx (r1).  The
+ * memory hooks (1, 3, 4) can also sit inside an application kernel
+ * (gx_run_app_vadd). */
 enum {
   GX_HOOK_MEM_ACCESS = 1,
   GX_HOOK_KERNEL_TIMING = 2,
   GX_HOOK_WAVE_MEM = 3,
   GX_HOOK_SIMT_MEM = 4,
+  GX_HOOK_SCHED = 5,
 };
 
 /* Execution modes chosen by the verifier.  They follow from this runtime's
@@ -218,8 +231,11 @@ int gx_jit_program_set(gx_rt* rt, const int* prog_fds, uint32_t n, char* log, ui
 
 /* The HIP source gx_jit_program would compile for a program (no device
  * needed; map descriptors get stand-in addresses).  Same program and shape
- * arguments as gx_verify.  With compile != 0 the source is also compiled
- * for gfx950.  Writes up to cap - 1 bytes of source (NUL-terminated) to
+ * arguments as gx_verify.  With bit 0 of ``compile`` set the source is also
+ * compiled for gfx950; with bit 1 set it is the source of the instrumented
+ * vector add's kernel (gx_run_app_vadd; event-parallel memory hooks only,
+ * else -EINVAL) instead of the run kernels.  A GX_HOOK_SCHED program's
+ * source holds the block scheduler's worker kernel (gx_run_sched).  Writes up to cap - 1 bytes of source (NUL-terminated) to
  * ``out`` (may be NULL) and returns the full length; -EACCES if the
  * verifier rejects (reason in out), -EIO if compilation fails (compiler log
  * in out). */
@@ -256,6 +272,51 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
  * the default launch shape). */
 int gx_run_batch_noalloc(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
                          uint32_t record_size, uint32_t* d_rc, void* stream);
+
+/* A hook inside an application kernel (section 5.3: trampolines at a
+ * kernel's memory instructions; section 6.2.1's vector add with a stride
+ * access pattern): the HIP kernel computes d_c[j] = d_a[j] + d_b[j] for j =
+ * (i * stride) mod n over iterations i < n (device arrays of n doubles; j
+ * visits every element once since gcd(stride, n) = 1), and at its load of
+ * d_a[j] runs the event-parallel memory-hook program prog_fd on the access's
+ * record {addr = 8 j (byte offset in d_a), stream_id = i / 64 (the 64-
+ * iteration tile, one wave's), ts = i}: per lane for GX_HOOK_MEM_ACCESS and
+ * GX_HOOK_SIMT_MEM (with the tile's aggregate), once per tile for
+ * GX_HOOK_WAVE_MEM.  The results equal gx_run_batch over those records in
+ * iteration order.  The return code d of iteration i goes to d_rc[i] if
+ * d_rc is not NULL and, when non-zero, is a prefetch hint: the lane also
+ * loads d_a[(j + d) mod n] ahead of its own loads (gfx950 has no data
+ * prefetch instruction).  prog_fd < 0 runs the kernel without the hook.
+ * Compiled programs run in a compiled copy of the kernel (built at the
+ * first call), others in the interpreter.  Asynchronous on ``stream``.
+ * Errors: -EINVAL (n = 0 or n > 2^32, stride >= n, gcd(stride, n) != 1,
+ * a program of another hook or a stream-sequential one), -ENOMEM, -EIO. */
+int gx_run_app_vadd(gx_rt* rt, int prog_fd, const double* d_a, const double* d_b, double* d_c, uint64_t n,
+                    uint64_t stride, uint32_t* d_rc, void* stream);
+
+/* Device block scheduler (section 4.3.2's work-stealing thread-block
+ * scheduler with persistent workers; section 6.2.1's policies): ``workers``
+ * persistent workers (one wave each) run n_units work units of d_cost[u]
+ * iterations each (d_out[64 u + l] = 64 u + l after d_cost[u] steps of the
+ * 64-bit MMIX linear congruential generator; d_out holds 64 n_units words).
+ * Worker w owns units [w n_units / workers, (w + 1) n_units / workers) and
+ * claims them in order; with a GX_HOOK_SCHED program, once its range is
+ * empty the worker asks the program before each steal whether to take one
+ * more unit from the first worker after it (cyclically) with units left,
+ * and stops at the first "no" or when no unit is left anywhere.  prog_fd <
+ * 0: static assignment (no stealing).  Every unit runs exactly once, so
+ * d_out never depends on the policy.  Each decision's 32-byte context (the
+ * GX_HOOK_SCHED record) goes to d_log[4 k .. 4 k + 3] and its return code
+ * to d_log_rc[k], k < log_cap (decision k in the order they were made; each
+ * worker's own decisions keep their order); *d_log_n (device, may be NULL)
+ * receives the number of decisions, which may exceed log_cap.  Compiled
+ * programs run in a compiled worker kernel (gx_jit_program), others in the
+ * interpreter.  Asynchronous on ``stream``; the runtime zeroes its counters
+ * on the stream.  Errors: -EINVAL (n_units or workers 0, workers > 65536,
+ * log_cap > 0 without log arrays, a program of another hook), -ENOMEM. */
+int gx_run_sched(gx_rt* rt, int prog_fd, const uint32_t* d_cost, uint32_t n_units, uint32_t workers,
+                 uint64_t* d_out, uint64_t* d_log, uint32_t* d_log_rc, uint32_t log_cap, uint32_t* d_log_n,
+                 void* stream);
 
 /* Batched form: the work of n gx_run_batch calls in one persistent launch
  * (persistent workers claiming work units, as the paper's device scheduler

@@ -980,6 +980,8 @@ struct Checker {
           ep = false;
       if (hook == HOOK_WAVE_MEM && !ep)
         throw Reject{"a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers"};
+      if (hook == HOOK_SCHED && !ep)
+        throw Reject{"a scheduling hook runs in every worker at once: its maps must be shared, read-only or ring buffers"};
       if (simt && !ep)
         throw Reject{"a SIMT hook's lanes run one wave's events together: its maps must be shared, read-only or ring buffers"};
       res.event_parallel = ep;

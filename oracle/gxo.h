@@ -32,7 +32,12 @@ enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2 };
 // warp-uniform, the record's lane-varying, and the checker holds the program
 // to warp-uniform control flow, map keys and side effects (section 4.4,
 // "SIMT-aware Verification").
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4 };
+// HOOK_SCHED: the device block scheduler's steal decision (section 4.3.2,
+// should_try_steal): one invocation per decision of a persistent worker,
+// whose context is the worker's state at that point (see hook_info); a
+// non-zero return code means "take one more work unit from another
+// worker's range".
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4, HOOK_SCHED = 5 };
 enum : int { H_LOOKUP = 1, H_UPDATE = 2, H_DELETE = 3, H_RINGBUF_OUTPUT = 130 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 

@@ -53,6 +53,13 @@ bool hook_info(int hook, HookInfo* out) {
     *out = {24, 8, 4, {{0, 8}, {8, 4}, {16, 8}, {24, 8}, {32, 8}, {40, 4}, {44, 4}}, 24};
     return true;
   }
+  if (hook == HOOK_SCHED) {
+    // {u32 worker @0, u32 units done @4, u64 ns since the worker started @8,
+    // u64 ns since it began stealing @16, u32 units stolen @24, u32 units
+    // left in the victim's range @28}
+    *out = {32, 0, 4, {{0, 4}, {4, 4}, {8, 8}, {16, 8}, {24, 4}, {28, 4}}};
+    return true;
+  }
   return false;
 }
 

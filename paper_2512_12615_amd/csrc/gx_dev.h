@@ -1319,4 +1319,149 @@ __device__ __forceinline__ void batched_items(const BatchDev* B, const uint2* it
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Hooks inside application kernels (section 5.3: trampolines at a kernel's
+// memory instructions; persistent workers that claim logical work units).
+
+// x mod n by Barrett reduction with mu = floor((2^64 - 1) / n): the quotient
+// estimate is at most two below the true one, so two corrections suffice.
+__device__ __forceinline__ uint64_t mod_n(uint64_t x, uint64_t n, uint64_t mu) {
+  const uint64_t q = (uint64_t)(((unsigned __int128)x * mu) >> 64);
+  uint64_t r = x - q * n;
+  r = r >= n ? r - n : r;
+  return r >= n ? r - n : r;
+}
+
+// One 64-iteration tile t of the instrumented vector add: lane l runs
+// iteration i = 64 t + l, c[j] = a[j] + b[j] with j = (i stride) mod n.  With
+// HOOK, a trampoline at the load of a[j] builds the access's memory-access
+// record {addr = 8 j, stream = t, ts = i} and runs the program on it (per
+// lane, once per tile on the tile's aggregate for the warp-leader hook, per
+// lane with the aggregate for the SIMT hook).  A non-zero return code d is
+// a prefetch hint for a[(j + d) mod n]: gfx950 has no data-prefetch
+// instruction, so the lane loads that element and folds it into ``sink``,
+// which only an empty asm statement at the kernel's end reads (the load is
+// issued with the tile's own and waited for with them).
+template <bool HOOK, class Run>
+__device__ __forceinline__ void app_vadd_tile(Run& R, const RunArgs& A, const AppArgs& P, uint64_t t, const Stk& stk,
+                                              uint64_t& steps, uint64_t& sink) {
+  const uint64_t i = t * 64 + lane_id();
+  const bool live = i < P.n;
+  const uint64_t j = live ? mod_n(i * P.stride, P.n, P.mu) : 0;
+  if (HOOK) {
+    const uint32_t rc = tile_run(R, A, live, Ctx{8 * j, (uint64_t)(uint32_t)t, i}, stk, steps);
+    if (live) {
+      if (rc) sink ^= __builtin_bit_cast(uint64_t, P.a[mod_n(j + rc, P.n, P.mu)]);
+      if (A.rc) A.rc[i] = rc;
+    }
+  }
+  if (live) P.c[j] = P.a[j] + P.b[j];
+}
+
+// A wave's share of the vector add: tiles t0, t0 + tstep, ...
+template <bool HOOK, class Run>
+__device__ __forceinline__ void app_vadd_loop(Run& R, const RunArgs& A, const AppArgs& P, uint64_t t0, uint64_t tstep,
+                                              const Stk& stk) {
+  uint64_t sink = 0;
+  const uint64_t tiles = (P.n + 63) / 64;
+  for (uint64_t t = t0; t < tiles; t += tstep) {
+    uint64_t steps = 0;  // the runaway guard's budget is per tile
+    app_vadd_tile<HOOK>(R, A, P, t, stk, steps, sink);
+  }
+  asm volatile("" ::"v"(sink));
+}
+
+// Work unit u of the block scheduler's workload (a stand-in for one tile of
+// an imbalanced kernel): lane l iterates a 64-bit linear congruential
+// generator (Knuth's MMIX constants) cost[u] times from 64 u + l and stores
+// the result at out[64 u + l].
+__device__ __forceinline__ void sched_unit(const SchedArgs& S, uint32_t u) {
+  uint64_t x = 64ull * u + lane_id();
+  const uint32_t k = rfl(S.cost[u]);
+  for (uint32_t m = 0; m < k; m++) x = x * 6364136223846793005ull + 1442695040888963407ull;
+  S.out[64ull * u + lane_id()] = x;
+}
+
+__device__ __forceinline__ uint64_t wall_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Persistent worker w of the block scheduler (one wave; section 4.3.2's
+// work-stealing scheduler).  Worker w owns units [w N / W, (w + 1) N / W)
+// of the N units and claims them in order from its counter.  Once its range
+// is empty, with HOOK, it asks the program before each steal whether to
+// take one more unit; the victim is the first worker after w (cyclically)
+// with units left, found 64 workers at a time.  The decision's context
+// {u32 worker, u32 units done, u64 ns since the worker started, u64 ns
+// since it began stealing, u32 units stolen, u32 units left in the
+// victim's range} and return code are appended to the log.  A claim is a
+// fetch-add on the owner's counter, so every unit runs exactly once
+// whichever worker takes it: the results never depend on the policy, only
+// the time does.  Without HOOK (static assignment) the worker stops once
+// its range is empty.
+template <bool HOOK, class Run>
+__device__ __forceinline__ void sched_worker(Run& R, const RunArgs& A, const SchedArgs& S, uint32_t w,
+                                             const Stk& stk) {
+  const uint32_t W = S.workers, l = lane_id();
+  auto first = [&](uint32_t v) { return (uint32_t)((uint64_t)v * S.n_units / W); };
+  auto claim = [&](uint32_t v) -> uint32_t {
+    uint32_t k = 0;
+    if (l == 0) k = __hip_atomic_fetch_add(gl(&S.next[v]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t u = first(v) + rdlane(k, 0);
+    return u < first(v + 1) ? u : ~0u;
+  };
+  const uint64_t t0 = wall_ticks();
+  uint32_t done = 0, stolen = 0;
+  for (uint32_t u = claim(w); u != ~0u; u = claim(w)) {
+    sched_unit(S, u);
+    done++;
+  }
+  if (!HOOK) return;
+  const uint64_t t1 = wall_ticks();
+  for (;;) {
+    uint32_t victim = ~0u, left = 0;
+    for (uint32_t d0 = 1; d0 < W && victim == ~0u; d0 += 64) {
+      const uint32_t d = d0 + l;
+      uint32_t v = 0, rem = 0;
+      if (d < W) {
+        v = w + d >= W ? w + d - W : w + d;
+        const uint32_t taken = __hip_atomic_load(gl(&S.next[v]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t size = first(v + 1) - first(v);
+        rem = taken < size ? size - taken : 0;
+      }
+      const uint64_t m = ballot(rem > 0);
+      if (m) {
+        const uint32_t f = (uint32_t)__builtin_ctzll(m);
+        victim = rdlane(v, f);
+        left = rdlane(rem, f);
+      }
+    }
+    if (victim == ~0u) break;
+    const uint64_t now = wall_ticks();
+    const uint64_t c0 = w | ((uint64_t)done << 32);
+    const uint64_t c1 = (now - t0) * S.tick_num / S.tick_den;
+    const uint64_t c2 = (now - t1) * S.tick_num / S.tick_den;
+    const uint64_t c3 = stolen | ((uint64_t)left << 32);
+    // the record's fourth word travels as the aggregate's first; the
+    // runaway guard's budget is per decision
+    uint64_t steps = 0;
+    const uint32_t rc = rdlane(R.run(A, l == 0, c0, c1, c2, Ctx{c3, 0, 0}, stk, steps), 0);
+    if (l == 0) {
+      const uint32_t at = __hip_atomic_fetch_add(gl(S.log_n), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (S.log && at < S.log_cap) {
+        S.log[4ull * at] = c0;
+        S.log[4ull * at + 1] = c1;
+        S.log[4ull * at + 2] = c2;
+        S.log[4ull * at + 3] = c3;
+        S.log_rc[at] = rc;
+      }
+    }
+    if (!rc) break;
+    const uint32_t u = claim(victim);
+    if (u != ~0u) {
+      sched_unit(S, u);
+      done++;
+      stolen++;
+    }
+  }
+}
 }  // namespace gx

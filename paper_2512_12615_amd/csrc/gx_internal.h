@@ -28,7 +28,10 @@ enum : uint32_t { F_SHARED = 1, F_READ_ONLY = 2, F_HOST = 4 };
 // whose context is the record {u64 addr, u32 stream, u32 pad, u64 ts}
 // followed by its wave tile's aggregate as above at byte 24; the verifier
 // holds the program to warp-uniform control flow, keys and side effects.
-enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4 };
+// HOOK_SCHED: the device block scheduler's steal decision (section 4.3.2's
+// should_try_steal), one invocation per decision of a persistent worker on
+// {u32 worker, u32 done, u64 elapsed_ns, u64 steal_ns, u32 stolen, u32 left}.
+enum : int { HOOK_MEM_ACCESS = 1, HOOK_KERNEL_TIMING = 2, HOOK_WAVE_MEM = 3, HOOK_SIMT_MEM = 4, HOOK_SCHED = 5 };
 enum : int64_t { E_NOENT = 2, E_2BIG = 7, E_AGAIN = 11, E_EXIST = 17, E_INVAL = 22 };
 
 // ---------------------------------------------------------------------------
@@ -140,6 +143,29 @@ struct RunArgs {
 
 // Stride of the queue-ordered record copy (the largest record).
 constexpr uint32_t kSortedStride = 24;
+
+// The instrumented vector add (a hook inside an application kernel):
+// c[j] = a[j] + b[j] for j = (i stride) mod n, iterations i < n.
+struct AppArgs {
+  const double* a;
+  const double* b;
+  double* c;
+  uint64_t n;       // 1 <= n <= 2^32
+  uint64_t stride;  // < n, coprime to n
+  uint64_t mu;      // floor((2^64 - 1) / n), for reductions mod n
+};
+
+// The device block scheduler: persistent workers over imbalanced work units.
+struct SchedArgs {
+  const uint32_t* cost;  // per unit: iterations of the unit's work
+  uint64_t* out;         // per unit: 64 results
+  uint32_t* next;        // per worker: units of its range claimed so far (zeroed by the host)
+  uint64_t* log;         // per decision: its 32-byte context record (nullable)
+  uint32_t* log_rc;      // per decision: the program's return code
+  uint32_t* log_n;       // decisions made (zeroed by the host; may exceed log_cap)
+  uint32_t n_units, workers, log_cap, pad;
+  uint64_t tick_num, tick_den;  // wall-clock ticks to ns: ticks * num / den
+};
 
 // Batched form: one entry per run in a persistent launch.
 struct BatchDev {

@@ -925,7 +925,8 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
               o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" +
                    std::to_string(j) + ";";
             if (wbk)
-              o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63);";
+              o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63); dm" +
+                   W + " = dy" + W + " ? dm" + W + " | (1ull << cur" + W + ") : dm" + W + " & ~(1ull << cur" + W + ");";
             o += " }\n";
           }
           o += "        const uint32_t me = ((uint32_t)mk ^ (uint32_t)(mk >> 32)) & " + std::to_string(kMemoEntries - 1) +
@@ -945,7 +946,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
             o += "        if ((ev[2] & kMemoGen) == gen" + W + " && (ev[2] >> 63)) {";
             for (uint32_t j = 0; j < nw; j++)
               o += " *(GX_GLOBAL uint64_t*)(ev[1] + " + std::to_string(8 * j) + "ull) = ev[" + std::to_string(3 + j) + "];";
-            o += " }\n        dy" + W + " = false;\n";
+            o += " }\n        dy" + W + " = false; dm" + W + " &= ~(1ull << me);\n";
           }
           o += "        " + call + "\n      ";
           window_load();
@@ -1086,22 +1087,25 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     const std::string W = std::to_string(w);
     o += "  uint64_t mk" + W + " = 0, mp" + W + " = 0, gen" + W + " = 1;\n  bool mv" + W + " = false;\n  uint32_t cur" +
          W + " = 0;\n";
-    if (Wn.wb[w]) o += "  bool dy" + W + " = false;  // the registers' window is newer than memory\n";
+    if (Wn.wb[w])
+      o += "  bool dy" + W + " = false;  // the registers' window is newer than memory\n  uint64_t dm" + W +
+           " = 0;  // table slots whose words are newer than memory\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) o += "  uint64_t w" + W + "_" + std::to_string(j) + " = 0;\n";
   }
   o += "\n";
   // write-back tables: write every entry whose words are newer than memory
-  // back to the map (one lane, in the middle of a run; end() does it with
-  // one lane per entry)
+  // back to the map (one lane, in the middle of a run, visiting only the
+  // slots the dirty mask names; end() does it with one lane per entry)
   for (size_t w = 0; w < Wn.win.size(); w++) {
     if (!Wn.wb[w]) continue;
     const std::string W = std::to_string(w), S = std::to_string(3 + Wn.win[w].words);
     o += "  __device__ __forceinline__ void memo_flush" + W + "() {\n    if (mv" + W + ") {";
     for (uint32_t j = 0; j < Wn.win[w].words; j++)
       o += " g_memo" + W + "[cur" + W + " * " + S + "u + " + std::to_string(3 + j) + "u] = w" + W + "_" + std::to_string(j) + ";";
-    o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63); }\n    dy" + W +
-         " = false;\n    for (uint32_t e = 0; e < " + std::to_string(kMemoEntries) + "u; e++) memo_writeback" + W +
-         "(e);\n  }\n";
+    o += " g_memo" + W + "[cur" + W + " * " + S + "u + 2u] = gen" + W + " | ((uint64_t)dy" + W + " << 63); dm" + W +
+         " = dy" + W + " ? dm" + W + " | (1ull << cur" + W + ") : dm" + W + " & ~(1ull << cur" + W + "); }\n    dy" + W +
+         " = false;\n    for (uint64_t d = dm" + W + "; d; d &= d - 1) memo_writeback" + W +
+         "((uint32_t)__builtin_ctzll(d));\n    dm" + W + " = 0;\n  }\n";
     o += "  __device__ __forceinline__ void memo_writeback" + W + "(uint32_t e) {\n    uint64_t* ent = &g_memo" + W +
          "[e * " + S + "u];\n    const uint64_t g = ent[2];\n    if ((g & kMemoGen) == gen" + W +
          " && (g >> 63)) {\n";
@@ -1193,7 +1197,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "    mk" + W + " = rfl64(mk" + W + ");\n    mp" + W + " = rfl64(mp" + W + ");\n    gen" + W + " = rfl64(gen" +
          W + ");\n    mv" + W + " = __builtin_amdgcn_readfirstlane((int)mv" + W + ") != 0;\n    cur" + W +
          " = __builtin_amdgcn_readfirstlane(cur" + W + ");\n";
-    if (Wn.wb[w]) o += "    dy" + W + " = __builtin_amdgcn_readfirstlane((int)dy" + W + ") != 0;\n";
+    if (Wn.wb[w])
+      o += "    dy" + W + " = __builtin_amdgcn_readfirstlane((int)dy" + W + ") != 0;\n    dm" + W + " = rfl64(dm" + W + ");\n";
     for (uint32_t j = 0; j < Wn.win[w].words; j++) {
       const std::string nm = "w" + W + "_" + std::to_string(j);
       o += "    " + nm + " = rfl64(" + nm + ");\n";
@@ -1254,7 +1259,10 @@ int ring_count(const JitProg& P) {
 }  // namespace
 
 std::string jit_source(const JitProg& P, JitInfo* info) {
-  const uint32_t nw = jit_waves(P.stack_bytes, P.event_parallel);
+  // the block scheduler's workers: one wave per block, no LDS accumulators
+  // (decisions are rare; their map updates go to the map directly)
+  const bool sched = P.kernel == 2;
+  const uint32_t nw = sched ? 1u : jit_waves(P.stack_bytes, P.event_parallel);
   const uint32_t lds = P.stack_bytes ? nw * 64u * P.stack_bytes : 16u;
   const int nr = std::max(ring_count(P), 1);
   std::string o;
@@ -1263,20 +1271,30 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
   o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
   JitInfo ji;
-  o += emit_prog(P, "p0", true, lds + (uint64_t)sizeof(uint64_t) * 3 * nw * nr, &ji);  // + the ring chunks
+  o += emit_prog(P, "p0", !sched, sched ? 0 : lds + (uint64_t)sizeof(uint64_t) * 3 * nw * nr, &ji);  // + the ring chunks
   if (info) *info = ji;
   const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
-  if (P.event_parallel)
-    o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n"
-       "  const uint32_t wave = threadIdx.x >> 6;\n"
-       "  gx::Stk stk{wave * 64u * " + std::to_string(P.stack_bytes) + "u, gx::lane_id() * 8u, blockIdx.x * " + T +
-       "u + threadIdx.x};\n"
-       "  gx::p0::Prog<true" + std::string(P.leader ? ", true" : "") + "> P{wave};\n  P.begin(A);\n"
-       "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
-       "  P.end(A);\n}\n\n" +
-       (ji.spill_block_bytes ? std::string("extern \"C\" __global__ void __launch_bounds__(256) gx_j_reduce(gx::RunArgs A, "
-                                           "uint32_t nb) {\n  gx::p0::reduce(A, nb);\n}\n\n")
-                             : std::string());
+  const std::string head = "  const uint32_t wave = threadIdx.x >> 6;\n"
+                           "  gx::Stk stk{wave * 64u * " + std::to_string(P.stack_bytes) +
+                           "u, gx::lane_id() * 8u, blockIdx.x * " + T + "u + threadIdx.x};\n"
+                           "  gx::p0::Prog<true" + std::string(P.leader ? ", true" : "") + "> P{wave};\n  P.begin(A);\n";
+  const std::string reduce =
+      ji.spill_block_bytes ? std::string("extern \"C\" __global__ void __launch_bounds__(256) gx_j_reduce(gx::RunArgs A, "
+                                         "uint32_t nb) {\n  gx::p0::reduce(A, nb);\n}\n\n")
+                           : std::string();
+  if (P.event_parallel && P.kernel == 1)
+    o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_app_vadd(gx::RunArgs A, gx::AppArgs Pa) {\n" +
+         head + "  gx::app_vadd_loop<true>(P, A, Pa, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " +
+         W + "u, stk);\n  P.end(A);\n}\n\n" + reduce;
+  else if (P.event_parallel && sched)
+    o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_sched(gx::RunArgs A, gx::SchedArgs S) {\n"
+         "  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"
+         "  gx::p0::Prog<false> P{0u};\n  P.begin(A);\n"
+         "  gx::sched_worker<true>(P, A, S, blockIdx.x, stk);\n  P.end(A);\n}\n\n";
+  else if (P.event_parallel)
+    o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n" + head +
+         "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
+         "  P.end(A);\n}\n\n" + reduce;
   else
     o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "
        "uint32_t qstride, uint32_t qend_last) {\n  gx::Stk stk{0, gx::lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};\n"

@@ -30,6 +30,10 @@ struct JitProg {
   bool event_parallel;
   bool leader = false;  // warp-leader hook: one lane runs each tile, on wave-uniform values
   bool simt = false;    // SIMT hook: shared-map updates are wave-uniform, combined per wave
+  // the kernel the source holds besides the program: 0, the run kernels of
+  // its mode; 1, the instrumented vector add gx_j_app_vadd (event-parallel
+  // memory hooks); 2, the block scheduler's workers gx_j_sched (HOOK_SCHED)
+  int kernel = 0;
 };
 
 // HIP source of one program: its micro-ops written out as straight-line
@@ -41,6 +45,11 @@ struct JitProg {
 // LDS array; each wave carves ring records from its own chunk of reserved
 // ring space.  The source holds no map address (those come from
 // RunArgs::maptab), so instances with same-shaped maps share it.
+// With JitProg::kernel 1 the source holds, in place of the run kernels,
+// gx_j_app_vadd(RunArgs, AppArgs) with the event-parallel kernel's block
+// shape and LDS accumulators (and gx_j_reduce when the program spills);
+// with kernel 2, gx_j_sched(RunArgs, SchedArgs): one worker (one wave) per
+// block, shared-map updates straight to the map.
 // *info receives what the launch needs to know: the LDS accumulator words a
 // block flushes at its end (0: none), which sizes the grid; and, when the
 // program has LDS caches, the spill bytes per block and the blocks of the

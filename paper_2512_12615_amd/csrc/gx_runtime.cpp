@@ -38,6 +38,10 @@ hipError_t launch_partition_jobs(const PartJob* d_jobs, const uint2* d_tiles, ui
 hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint32_t n_items, uint32_t* d_next,
                           uint32_t waves, uint32_t stack_max, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, uint32_t n, hipStream_t s);
+hipError_t launch_app_vadd(const RunArgs& A, const AppArgs& P, hipStream_t s);
+hipError_t launch_app_plain(const AppArgs& P, uint32_t n_cu, hipStream_t s);
+hipError_t launch_sched(const RunArgs& A, const SchedArgs& S, hipStream_t s);
+hipError_t launch_sched_plain(const SchedArgs& S, hipStream_t s);
 hipError_t scratch_region(int dev, uint8_t** ptr, uint64_t* bytes);
 }  // namespace gx
 
@@ -53,6 +57,8 @@ constexpr uint64_t kJitMaxBlocks = 2048;
 constexpr size_t kMaxSetsPerPhase = 15;
 // Programs one compiled set holds at most
 constexpr uint32_t kMaxSetPrograms = 64;
+// Block scheduler: workers of one launch at most
+constexpr uint32_t kMaxWorkers = 1u << 16;
 
 struct MapObj {
   bool live = false;
@@ -106,6 +112,10 @@ struct ProgObj {
   uint64_t jacc_words = 0;  // LDS accumulator words each block flushes
   uint64_t jspill = 0;      // LDS cache spill bytes per block (0: caches flush directly)
   uint32_t jred_blocks = 0; // blocks of its reduce kernel
+  // compiled kernel with the program at a hook inside an application kernel
+  // (the instrumented vector add, or the block scheduler's workers for
+  // HOOK_SCHED programs) and that module's reduce kernel
+  hipFunction_t jf_app = nullptr, jf_app_red = nullptr;
   // launch shape chosen by gx_autotune (0: default)
   uint32_t tuned_lanes = 0, tuned_qbits = 0, tuned_blocks = 0;
   // interpreted event-parallel runs: the shared array map summed in an LDS
@@ -180,6 +190,8 @@ struct Exec {
   hipEvent_t ws_event = nullptr;
   bool ws_used = false;
   uint32_t* d_next = nullptr;  // work counters of persistent launches (16)
+  uint32_t* d_wnext = nullptr;  // block scheduler: per-worker unit counters and the log count
+  size_t wnext_cap = 0;
   // LDS cache spill areas of compiled event-parallel runs (one per run of a
   // phase), free again once the reduce kernels that read them are done
   uint8_t* d_spill = nullptr;
@@ -220,7 +232,7 @@ void exec_free(Exec& x) {
   if (x.ws_event) (void)hipEventDestroy(x.ws_event);
   if (x.spill_ev) (void)hipEventDestroy(x.spill_ev);
   for (void* p : {(void*)x.d_counts, (void*)x.d_sums, (void*)x.d_order, (void*)x.d_sorted, (void*)x.d_next,
-                  (void*)x.d_spill})
+                  (void*)x.d_spill, (void*)x.d_wnext})
     if (p) (void)hipFree(p);
   x = Exec{};
 }
@@ -245,6 +257,7 @@ struct gx_rt {
     uint32_t blocks_per_cu = 0;  // resident one-wave blocks per CU (occupancy)
   };
   uint32_t n_cu = 256;  // compute units of the device
+  uint32_t wall_khz = 100000;  // frequency of the device's constant wall clock (s_memrealtime)
   std::vector<JitSet> sets;
   static constexpr int kSide = kExecSide;
   // execution resources per launch stream: runs on different streams share
@@ -746,6 +759,9 @@ struct MapSnapshot {
   }
 };
 
+int jit_app_module(gx_rt* rt, ProgObj* p, int kind, hipModule_t* mod, hipFunction_t* f, hipFunction_t* fr,
+                   JitInfo* info_out);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -765,6 +781,9 @@ int gx_open(int hip_device, gx_rt** out) {
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && ncu > 0)
     rt->n_cu = (uint32_t)ncu;
+  int wkhz = 0;
+  if (hipDeviceGetAttribute(&wkhz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && wkhz > 0)
+    rt->wall_khz = (uint32_t)wkhz;
   if (hipStreamCreateWithFlags(&rt->internal, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void**)&rt->d_err, 64) != hipSuccess || hipMalloc((void**)&rt->d_stage, 16384) != hipSuccess ||
       hipEventCreateWithFlags(&rt->noalloc_ev, hipEventDisableTiming) != hipSuccess ||
@@ -1085,7 +1104,7 @@ int gx_load_program(gx_rt* rt, const uint64_t* insns, uint32_t n_insns, uint32_t
 int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events, uint32_t record_size, uint32_t* d_rc,
                 void* stream, gx_tune* out) {
   ProgObj* p = get_prog(rt, prog_fd);
-  if (!p || record_size != p->record_size || !d_events || n_events == 0) return -EINVAL;
+  if (!p || record_size != p->record_size || p->hook == HOOK_SCHED || !d_events || n_events == 0) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
   DevGuard g(rt->dev);
   hipStream_t s = (hipStream_t)stream;
@@ -1168,6 +1187,19 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
     MapObj* m = get_map(rt, fd);
     if (!m) return -EINVAL;
     maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
+  }
+  if (p->hook == HOOK_SCHED) {
+    // the program's only kernel is the block scheduler's
+    hipModule_t mod = nullptr;
+    JitInfo ji;
+    int r = jit_app_module(rt, p, 2, &mod, &p->jf_app, &p->jf_app_red, &ji);
+    write_log(log, log_size, "");
+    if (r) return r;
+    p->jacc_words = ji.acc_words;
+    p->jspill = p->jf_app_red ? ji.spill_block_bytes : 0;
+    p->jred_blocks = ji.reduce_blocks;
+    p->jmod = mod;
+    return 0;
   }
   JitInfo info;
   const std::string src =
@@ -1324,8 +1356,11 @@ int64_t gx_jit_source(const uint64_t* insns, uint32_t n_insns, uint32_t hook_typ
     if (r == -EACCES) write_log(out, (uint32_t)std::min<uint64_t>(cap, 0xffffffffu), si.log);
     return r;
   }
-  std::string src = jit_source(si.prog());
-  if (compile) {
+  JitProg jp = si.prog();
+  jp.kernel = hook_type == HOOK_SCHED ? 2 : (compile & 2) ? 1 : 0;
+  if (jp.kernel == 1 && (!jp.event_parallel || hook_type == HOOK_KERNEL_TIMING)) return -EINVAL;
+  std::string src = jit_source(jp);
+  if (compile & 1) {
     std::vector<char> code;
     std::string lg;
     r = jit_compile(src, &code, &lg);
@@ -1349,7 +1384,7 @@ int gx_run_batch(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events
                  uint32_t* d_rc, void* stream) {
   ProgObj* p = get_prog(rt, prog_fd);
   if (!p) return -EINVAL;
-  if (record_size != p->record_size) return -EINVAL;
+  if (record_size != p->record_size || p->hook == HOOK_SCHED) return -EINVAL;
   if (n_events == 0) return 0;
   if (!d_events) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
@@ -1384,6 +1419,96 @@ RunArgs make_args(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events
   uint64_t per_event = 64 * (p->v.max_insns + 1) + 64;
   A.step_limit = p->v.event_parallel ? per_event : per_event * n_events;
   return A;
+}
+
+// ---------------------------------------------------------------------------
+// Hooks inside application kernels: the instrumented vector add and the
+// block scheduler's workers (section 5.3).
+
+// The module of a compiled program whose kernel is gx_j_app_vadd (kind 1)
+// or gx_j_sched (kind 2), built on first use and shared through the source
+// cache; *fr: its reduce kernel (null: none).
+int jit_app_module(gx_rt* rt, ProgObj* p, int kind, hipModule_t* mod, hipFunction_t* f, hipFunction_t* fr,
+                   JitInfo* info_out) {
+  std::vector<std::pair<uint64_t, MapDev>> maps;
+  for (int fd : p->fds) {
+    MapObj* m = get_map(rt, fd);
+    if (!m) return -EINVAL;
+    maps.push_back({(uint64_t)(uintptr_t)m->d_desc, m->h});
+  }
+  JitProg jp{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
+             p->hook == HOOK_WAVE_MEM, p->hook == HOOK_SIMT_MEM};
+  jp.kernel = kind;
+  JitInfo info;
+  const std::string src = jit_source(jp, &info);
+  auto adopt = [&](const gx_rt::JitMod& jm) {
+    *mod = jm.mod;
+    *f = jm.fe;
+    *fr = jm.fr;
+    *info_out = jm.info;
+  };
+  {
+    std::lock_guard<std::mutex> lk(rt->jit_mu);
+    auto it = rt->jit_cache.find(src);
+    if (it != rt->jit_cache.end()) {
+      adopt(it->second);
+      return 0;
+    }
+  }
+  std::vector<char> code;
+  std::string lg;
+  int r = jit_compile(src, &code, &lg);
+  if (r) return r;
+  DevGuard g(rt->dev);
+  gx_rt::JitMod jm;
+  jm.info = info;
+  if (hipModuleLoadData(&jm.mod, code.data()) != hipSuccess) return -EIO;
+  if (hipModuleGetFunction(&jm.fe, jm.mod, kind == 1 ? "gx_j_app_vadd" : "gx_j_sched") != hipSuccess ||
+      (kind == 1 && info.spill_block_bytes && hipModuleGetFunction(&jm.fr, jm.mod, "gx_j_reduce") != hipSuccess)) {
+    (void)hipModuleUnload(jm.mod);
+    return -EIO;
+  }
+  std::lock_guard<std::mutex> lk(rt->jit_mu);
+  auto ins = rt->jit_cache.emplace(src, jm);
+  if (!ins.second) (void)hipModuleUnload(jm.mod);  // compiled concurrently by another call
+  adopt(ins.first->second);
+  return 0;
+}
+
+// Launch a program's compiled application kernel (nb blocks of ``nw``
+// waves, RunArgs then ``x`` as arguments), then its reduce kernel when the
+// program's LDS caches spill.
+template <class X>
+int launch_jit_app(gx_rt* rt, const ProgObj* p, RunArgs A, X x, uint32_t nb, uint32_t nw, hipStream_t s) {
+  Exec* Xp = exec_for(rt, s);
+  if (!Xp) return -ENOMEM;
+  Exec& E = *Xp;
+  uint8_t* sp = nullptr;
+  if (p->jspill && p->jf_app_red) {
+    int r = ensure_spill(E, (size_t)nb * p->jspill);
+    if (r) return r;
+    if (E.spill_used) (void)hipStreamWaitEvent(s, E.spill_ev, 0);
+    sp = E.d_spill;
+  }
+  A.spill = sp;
+  void* args[] = {&A, &x};
+  hipError_t e = hipModuleLaunchKernel(p->jf_app, nb, 1, 1, 64 * nw, 1, 1, 0, s, args, nullptr);
+  if (e == hipSuccess && sp) {
+    void* rargs[] = {&A, &nb};
+    e = hipModuleLaunchKernel(p->jf_app_red, p->jred_blocks, 1, 1, 256, 1, 1, 0, s, rargs, nullptr);
+    (void)hipEventRecord(E.spill_ev, s);
+    E.spill_used = true;
+  }
+  return e == hipSuccess ? 0 : to_errno(e);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
 }
 
 // Layout of a stream-sequential run's workspace in one region: counts,
@@ -1716,7 +1841,9 @@ int check_batches(gx_rt* rt, const gx_batch* descs, uint32_t n) {
   if (!rt || (!descs && n)) return -EINVAL;
   for (uint32_t i = 0; i < n; i++) {
     ProgObj* p = get_prog(rt, descs[i].prog_fd);
-    if (!p || descs[i].record_size != p->record_size || (descs[i].n_events && !descs[i].d_events)) return -EINVAL;
+    if (!p || descs[i].record_size != p->record_size || p->hook == HOOK_SCHED ||
+        (descs[i].n_events && !descs[i].d_events))
+      return -EINVAL;
     if (descs[i].n_events >= (1ull << 32)) return -E2BIG;
   }
   return 0;
@@ -1739,7 +1866,7 @@ int gx_run_batch_noalloc(gx_rt* rt, int prog_fd, const void* d_events, uint64_t 
                          uint32_t* d_rc, void* stream) {
   ProgObj* p = get_prog(rt, prog_fd);
   if (!p) return -EINVAL;
-  if (record_size != p->record_size) return -EINVAL;
+  if (record_size != p->record_size || p->hook == HOOK_SCHED) return -EINVAL;
   if (n_events == 0) return 0;
   if (!d_events) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
@@ -2192,6 +2319,104 @@ void gx_snapshot_stop(gx_rt* rt) {
   (void)hipStreamSynchronize(d->stream);
   rt->snap = nullptr;
   snap_free(d);
+}
+
+int gx_run_app_vadd(gx_rt* rt, int prog_fd, const double* d_a, const double* d_b, double* d_c, uint64_t n,
+                    uint64_t stride, uint32_t* d_rc, void* stream) {
+  if (!rt || !d_a || !d_b || !d_c || n == 0 || n > (1ull << 32) || stride >= n || gcd64(stride, n) != 1)
+    return -EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const AppArgs P{d_a, d_b, d_c, n, stride, ~0ull / n};
+  DevGuard g(rt->dev);
+  if (prog_fd < 0) {
+    hipError_t e = launch_app_plain(P, rt->n_cu, s);
+    return e == hipSuccess ? 0 : to_errno(e);
+  }
+  ProgObj* p = get_prog(rt, prog_fd);
+  if (!p || !p->v.event_parallel ||
+      (p->hook != HOOK_MEM_ACCESS && p->hook != HOOK_WAVE_MEM && p->hook != HOOK_SIMT_MEM))
+    return -EINVAL;
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
+  RunArgs A = make_args(rt, p, nullptr, n, d_rc);
+  int r = 0;
+  if (p->jf_ep) {
+    if (!p->jf_app) {
+      hipModule_t mod = nullptr;
+      JitInfo ji;
+      r = jit_app_module(rt, p, 1, &mod, &p->jf_app, &p->jf_app_red, &ji);
+      if (r) return r;
+    }
+    r = launch_jit_app(rt, p, A, P, jit_ep_blocks(p, n, 0), jit_waves(p->v.stack_bytes, true), s);
+  } else {
+    hipError_t e = launch_app_vadd(A, P, s);
+    r = e == hipSuccess ? 0 : to_errno(e);
+  }
+  if (r) return r;
+  rt->stats.launches += 1;
+  rt->stats.events += n;
+  note_stream(rt, s);
+  return 0;
+}
+
+int gx_run_sched(gx_rt* rt, int prog_fd, const uint32_t* d_cost, uint32_t n_units, uint32_t workers,
+                 uint64_t* d_out, uint64_t* d_log, uint32_t* d_log_rc, uint32_t log_cap, uint32_t* d_log_n,
+                 void* stream) {
+  if (!rt || !d_cost || !d_out || n_units == 0 || workers == 0 || workers > kMaxWorkers ||
+      (log_cap && (!d_log || !d_log_rc)))
+    return -EINVAL;
+  ProgObj* p = nullptr;
+  if (prog_fd >= 0) {
+    p = get_prog(rt, prog_fd);
+    if (!p || p->hook != HOOK_SCHED || !p->v.event_parallel) return -EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  DevGuard g(rt->dev);
+  std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
+  if (rt->snap) lk.lock();
+  Exec* Xp = exec_for(rt, s);
+  if (!Xp) return -ENOMEM;
+  Exec& E = *Xp;
+  // per-worker counters, then the runtime's own log count
+  if (E.wnext_cap < (size_t)workers + 1) {
+    if (E.d_wnext) (void)hipFree(E.d_wnext);
+    E.d_wnext = nullptr;
+    E.wnext_cap = 0;
+    if (hipMalloc((void**)&E.d_wnext, ((size_t)workers + 1) * 4) != hipSuccess) return -ENOMEM;
+    E.wnext_cap = (size_t)workers + 1;
+  }
+  hipError_t e = launch_zero(E.d_wnext, workers + 1, s);
+  if (e == hipSuccess && d_log_n) e = launch_zero(d_log_n, 1, s);
+  if (e != hipSuccess) return to_errno(e);
+  SchedArgs S{};
+  S.cost = d_cost;
+  S.out = d_out;
+  S.next = E.d_wnext;
+  S.log = log_cap ? d_log : nullptr;
+  S.log_rc = d_log_rc;
+  S.log_n = d_log_n ? d_log_n : E.d_wnext + workers;
+  S.n_units = n_units;
+  S.workers = workers;
+  S.log_cap = log_cap;
+  S.tick_num = 1000000;  // kHz ticks to ns
+  S.tick_den = rt->wall_khz;
+  int r = 0;
+  if (!p) {
+    e = launch_sched_plain(S, s);
+    r = e == hipSuccess ? 0 : to_errno(e);
+  } else {
+    RunArgs A = make_args(rt, p, nullptr, 0, nullptr);
+    if (p->jf_app) {
+      r = launch_jit_app(rt, p, A, S, workers, 1, s);
+    } else {
+      e = launch_sched(A, S, s);
+      r = e == hipSuccess ? 0 : to_errno(e);
+    }
+  }
+  if (r) return r;
+  rt->stats.launches += 1;
+  note_stream(rt, s);
+  return 0;
 }
 
 int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail) {

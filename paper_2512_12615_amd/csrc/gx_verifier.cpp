@@ -52,6 +52,12 @@ bool hook_layout(int hook, uint32_t* record_size, uint32_t* stream_off, uint32_t
     *stream_size = 4;
     return true;
   }
+  if (hook == HOOK_SCHED) {  // the worker is the stream
+    *record_size = 32;
+    *stream_off = 0;
+    *stream_size = 4;
+    return true;
+  }
   return false;
 }
 
@@ -66,6 +72,8 @@ bool ctx_field(int hook, int64_t off, int size) {
     return (off == 0 && size == 8) || (off == 8 && size == 8) || (off == 16 && size == 4) || (off == 20 && size == 4);
   if (hook == HOOK_SIMT_MEM)  // the record's fields, then the tile aggregate's at 24
     return ctx_field(HOOK_MEM_ACCESS, off, size) || (off >= 24 && ctx_field(HOOK_WAVE_MEM, off - 24, size));
+  if (hook == HOOK_SCHED)
+    return ((off == 0 || off == 4 || off == 24 || off == 28) && size == 4) || ((off == 8 || off == 16) && size == 8);
   return false;
 }
 
@@ -327,6 +335,8 @@ class Verifier {
           V.event_parallel = false;
       if (hook_ == HOOK_WAVE_MEM && !V.event_parallel)
         fail(0, "a warp-leader hook runs once per wave: its maps must be shared, read-only or ring buffers");
+      if (hook_ == HOOK_SCHED && !V.event_parallel)
+        fail(0, "a scheduling hook runs in all workers at once: its maps must be shared, read-only or ring buffers");
       if (simt_ && !V.event_parallel)
         fail(0, "the lanes of a SIMT hook run one wave's events at once: its maps must be shared, read-only or ring buffers");
     } catch (const Fail& f) {

@@ -10,6 +10,7 @@
 // until the lanes meet again.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "gx_dev.h"
@@ -349,6 +350,39 @@ extern "C" __global__ void __launch_bounds__(1024) gx_k_event_parallel_acc(RunAr
     mirror_flush<uint32_t>((const uint32_t*)mirror, words, A.acc_op, (uint8_t*)A.acc_lo);
 }
 
+// The instrumented vector add, interpreted: one 64-iteration tile per wave.
+extern "C" __global__ void __launch_bounds__(256) gx_k_app_vadd(RunArgs A, AppArgs P) {
+  const uint32_t wave = threadIdx.x >> 6;
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
+  uint64_t steps = 0, sink = 0;
+  Interp I;
+  app_vadd_tile<true>(I, A, P, (uint64_t)blockIdx.x * 4u + wave, stk, steps, sink);
+  asm volatile("" ::"v"(sink));
+}
+
+// The vector add without a hook (grid-stride over tiles).
+extern "C" __global__ void __launch_bounds__(256) gx_k_app_plain(AppArgs P) {
+  const RunArgs A{};
+  Interp I;
+  const Stk stk{0, 0, 0};
+  app_vadd_loop<false>(I, A, P, (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6), (uint64_t)gridDim.x * 4u, stk);
+}
+
+// The block scheduler's workers, interpreted: one one-wave block per worker.
+extern "C" __global__ void __launch_bounds__(64) gx_k_sched(RunArgs A, SchedArgs S) {
+  Stk stk{0, lane_id() * 8u, blockIdx.x * 64u + threadIdx.x};
+  Interp I;
+  sched_worker<true>(I, A, S, blockIdx.x, stk);
+}
+
+// Static assignment (no scheduling hook): each worker runs its own range.
+extern "C" __global__ void __launch_bounds__(64) gx_k_sched_plain(SchedArgs S) {
+  const RunArgs A{};
+  Interp I;
+  const Stk stk{0, 0, 0};
+  sched_worker<false>(I, A, S, blockIdx.x, stk);
+}
+
 // Stream-sequential mode: ``lanes`` lanes of each one-wave block own queues.
 extern "C" __global__ void __launch_bounds__(64) gx_k_stream_seq(RunArgs A, uint32_t lanes, uint32_t qstride) {
   Stk stk{0, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
@@ -606,6 +640,10 @@ hipError_t vm_init() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)gx_k_stream_seq, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gx_k_app_vadd, hipFuncAttributeMaxDynamicSharedMemorySize, 256 * kStackMax);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gx_k_sched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)gx_k_batched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
 }
 
@@ -630,6 +668,29 @@ hipError_t launch_event_parallel_acc(RunArgs A, uint32_t n_cu, hipStream_t s) {
   if (nb > per_words) nb = per_words;
   if (nb == 0) nb = 1;
   hipLaunchKernelGGL(gx_k_event_parallel_acc, dim3((uint32_t)nb), dim3(64 * nw), A.acc_lds + acc_bytes, s, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_app_vadd(const RunArgs& A, const AppArgs& P, hipStream_t s) {
+  const uint64_t blocks = (P.n + 255) / 256;
+  hipLaunchKernelGGL(gx_k_app_vadd, dim3((uint32_t)blocks), dim3(256), 256 * A.stack_bytes, s, A, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_app_plain(const AppArgs& P, uint32_t n_cu, hipStream_t s) {
+  const uint64_t tiles = (P.n + 63) / 64;
+  const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)n_cu * 8);
+  hipLaunchKernelGGL(gx_k_app_plain, dim3((uint32_t)std::max<uint64_t>(blocks, 1)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_sched(const RunArgs& A, const SchedArgs& S, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_sched, dim3(S.workers), dim3(64), 64 * A.stack_bytes, s, A, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sched_plain(const SchedArgs& S, hipStream_t s) {
+  hipLaunchKernelGGL(gx_k_sched_plain, dim3(S.workers), dim3(64), 0, s, S);
   return hipGetLastError();
 }
 

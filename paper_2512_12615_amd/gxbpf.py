@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libgxbpf.so")
 
 MAP_HASH, MAP_ARRAY, MAP_RINGBUF = 1, 2, 27
 F_SHARED, F_READ_ONLY = 1, 2
-HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING, HOOK_WAVE_MEM, HOOK_SIMT_MEM = 1, 2, 3, 4
+HOOK_MEM_ACCESS, HOOK_KERNEL_TIMING, HOOK_WAVE_MEM, HOOK_SIMT_MEM, HOOK_SCHED = 1, 2, 3, 4, 5
 MODE_EVENT_PARALLEL, MODE_STREAM_SEQUENTIAL = 0, 1
-RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16, HOOK_WAVE_MEM: 24, HOOK_SIMT_MEM: 24}
+RECORD_SIZE = {HOOK_MEM_ACCESS: 24, HOOK_KERNEL_TIMING: 16, HOOK_WAVE_MEM: 24, HOOK_SIMT_MEM: 24, HOOK_SCHED: 32}
 
 
 class GxError(OSError):
@@ -42,7 +42,7 @@ class Batch(C.Structure):
 
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
-           "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch", "gx_run_batch_noalloc",
+           "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch", "gx_run_batch_noalloc", "gx_run_app_vadd", "gx_run_sched",
            "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_snapshot_start", "gx_snapshot_read",
            "gx_snapshot_flush", "gx_snapshot_stop", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
@@ -100,6 +100,8 @@ def lib():
     L.gx_verify.argtypes = [vp, u32, u32, vp, u32, C.c_char_p, u32, C.POINTER(ProgInfo)]
     L.gx_run_batch.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
     L.gx_run_batch_noalloc.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp]
+    L.gx_run_app_vadd.argtypes = [vp, C.c_int, vp, vp, vp, u64, u64, vp, vp]
+    L.gx_run_sched.argtypes = [vp, C.c_int, vp, u32, u32, vp, vp, vp, u32, vp, vp]
     L.gx_run_batches.argtypes = [vp, C.POINTER(Batch), u32, vp]
     L.gx_autotune.argtypes = [vp, C.c_int, vp, u64, u32, vp, vp, C.POINTER(Tune)]
     L.gx_graph_create.argtypes = [vp, C.POINTER(Batch), u32, C.POINTER(vp)]
@@ -165,16 +167,17 @@ def verify(code: bytes, hook: int, shapes):
     return r == 0, log.value.decode(), info
 
 
-def jit_source(code: bytes, hook: int, shapes, compile: bool = False) -> str:
+def jit_source(code: bytes, hook: int, shapes, compile: bool = False, app: bool = False) -> str:
     """HIP source the JIT generates for a program (no device needed); with
-    ``compile`` it is also compiled for gfx950.  Raises GxError on rejection
-    or compile failure (message holds the log)."""
+    ``compile`` it is also compiled for gfx950; with ``app`` it is the
+    instrumented vector add's kernel.  Raises GxError on rejection or
+    compile failure (message holds the log)."""
     sh = np.array(shapes, dtype=np.uint32).reshape(-1, 5) if shapes else np.zeros((0, 5), np.uint32)
     w = _words(code)
     cap = 1 << 22
     out = C.create_string_buffer(cap)
     r = lib().gx_jit_source(w.ctypes.data_as(C.c_void_p), len(code) // 8, hook, sh.ctypes.data_as(C.c_void_p),
-                            len(sh), int(compile), out, cap)
+                            len(sh), int(compile) | (2 if app else 0), out, cap)
     if r < 0:
         raise GxError(-r, f"gx_jit_source: {os.strerror(-r)}: {out.value.decode(errors='replace')}")
     return out.value.decode()
@@ -345,6 +348,35 @@ class Runtime:
         r = lib().gx_run_batch_noalloc(self._h, prog_fd, _dptr(events), n_events, record_size, _dptr(rc),
                                        _stream_handle(stream))
         _check(r, "gx_run_batch_noalloc")
+
+    def run_app_vadd(self, prog_fd, a, b, c, stride=1, rc=None, stream=None):
+        """The instrumented vector add (gx_run_app_vadd): c[j] = a[j] + b[j],
+        j = i stride mod n, with prog_fd (or none if < 0) at its load of a[j].
+        a, b, c: float64 device tensors of n elements; rc: uint32/int32
+        device tensor of n or None."""
+        n = a.numel()
+        if b.numel() != n or c.numel() != n or a.dtype != b.dtype or a.dtype != c.dtype:
+            raise ValueError("a, b and c must hold the same number of doubles")
+        if rc is not None and rc.numel() < n:
+            raise ValueError("rc holds fewer than n elements")
+        r = lib().gx_run_app_vadd(self._h, prog_fd, _dptr(a), _dptr(b), _dptr(c), n, stride, _dptr(rc),
+                                  _stream_handle(stream))
+        _check(r, "gx_run_app_vadd")
+
+    def run_sched(self, prog_fd, cost, workers, out, log=None, log_rc=None, log_n=None, stream=None):
+        """The device block scheduler (gx_run_sched): cost: uint32 device
+        tensor of units; out: 64 x units uint64 (int64) device words; log:
+        (cap, 4) uint64 words, log_rc: cap uint32, log_n: one uint32 (device
+        tensors or None)."""
+        n_units = cost.numel()
+        if out.numel() < 64 * n_units:
+            raise ValueError("out holds fewer than 64 words per unit")
+        cap = 0 if log is None else log.numel() // 4
+        if log is not None and (log_rc is None or log_rc.numel() < cap):
+            raise ValueError("log_rc must hold one code per logged decision")
+        r = lib().gx_run_sched(self._h, prog_fd, _dptr(cost), n_units, workers, _dptr(out), _dptr(log),
+                               _dptr(log_rc), cap, _dptr(log_n), _stream_handle(stream))
+        _check(r, "gx_run_sched")
 
     def run_batches(self, descs, stream=None):
         """descs: list of (prog_fd, events tensor, n_events, record_size, rc tensor or None)."""

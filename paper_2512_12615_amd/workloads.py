@@ -41,9 +41,15 @@ HOOK_WAVE_MEM = 3
 # by its tile's aggregate at byte 24 (warp-uniform); the verifier holds the
 # program to warp-uniform branches, keys and side effects
 HOOK_SIMT_MEM = 4
+# device block scheduler: one invocation per steal decision of a persistent
+# worker, on {u32 worker, u32 done, u64 elapsed_ns, u64 steal_ns, u32 stolen,
+# u32 left}; a non-zero return code means "take one more unit"
+HOOK_SCHED = 5
 MEM_DTYPE = np.dtype([("addr", "<u8"), ("stream", "<u4"), ("pad", "<u4"), ("ts", "<u8")])
 TIMING_DTYPE = np.dtype([("kernel_id", "<u4"), ("pad", "<u4"), ("lat", "<u8")])
-assert MEM_DTYPE.itemsize == 24 and TIMING_DTYPE.itemsize == 16
+SCHED_DTYPE = np.dtype([("worker", "<u4"), ("done", "<u4"), ("elapsed_ns", "<u8"), ("steal_ns", "<u8"),
+                        ("stolen", "<u4"), ("left", "<u4")])
+assert MEM_DTYPE.itemsize == 24 and TIMING_DTYPE.itemsize == 16 and SCHED_DTYPE.itemsize == 32
 
 # map types (Linux numbering) and flags
 MAP_HASH, MAP_ARRAY, MAP_RINGBUF = 1, 2, 27
@@ -219,7 +225,7 @@ class Policy:
 
     @property
     def record_size(self) -> int:
-        return 16 if self.hook == HOOK_KERNEL_TIMING else 24
+        return {HOOK_KERNEL_TIMING: 16, HOOK_SCHED: 32}.get(self.hook, 24)
 
 
 # Access counter: per 2 MiB region counts in a shared array; rc = region & 1.
@@ -599,6 +605,138 @@ def latency_hist_policy(kernels: int = 4096, ring_bytes: int = 64 << 20) -> Poli
         MapSpec("cfg", MAP_ARRAY, 4, 8, 1, F_READ_ONLY),
         MapSpec("ring", MAP_RINGBUF, 0, 0, ring_bytes, 0),
     ])
+
+
+# ---------------------------------------------------------------------------
+# policies for hooks inside application kernels
+
+# L2 stride prefetch for the instrumented vector add (warp leader, section
+# 6.2.1's device prefetch policy): the tile's lane-to-lane stride, estimated
+# from its address range, is counted into stride[min(stride in elements,
+# 4095)], and the return code asks the trampoline to prefetch, in every
+# lane, the element one tile of iterations ahead (stride x records);
+# tiles of one record return 0 (no prefetch).
+STRIDE_L2 = """
+    ldxdw r6, [r1+0]          ; lo
+    ldxdw r7, [r1+8]          ; hi
+    ldxw r8, [r1+16]          ; n
+    mov64 r0, 0
+    jlt r8, 2, out
+    mov64 r9, r7
+    sub64 r9, r6
+    mov64 r3, r8
+    sub64 r3, 1
+    div64 r9, r3              ; bytes from lane to lane
+    rsh64 r9, 3               ; in elements
+    mov64 r2, r9
+    jlt r2, 4096, keep
+    mov64 r2, 4095
+keep:
+    stxw [r10-4], r2
+    lddw r1, map:stride
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, dist
+    mov64 r1, 1
+    aadd64 [r0+0], r1
+dist:
+    mov64 r0, r9
+    mul64 r0, r8
+out:
+    exit
+"""
+
+
+def stride_l2_policy() -> Policy:
+    return Policy("stride_l2", HOOK_WAVE_MEM, STRIDE_L2, [MapSpec("stride", MAP_ARRAY, 4, 8, 4096, F_SHARED)])
+
+
+# Block-scheduler policies (section 4.3.2's should_try_steal; section
+# 6.2.1's Greedy and LatencyBudget, the support matrix's MaxSteals).  Each
+# counts its yes-decisions per worker in steals[worker mod 4096]; cfg[0] is
+# the policy's parameter.
+_SCHED_COUNT = """
+    ldxw r6, [r9+0]           ; worker
+    and64 r6, 4095
+    stxw [r10-8], r6
+    lddw r1, map:steals
+    mov64 r2, r10
+    add64 r2, -8
+    call map_lookup_elem
+    jeq r0, 0, yes
+    mov64 r1, 1
+    aadd64 [r0+0], r1
+yes:
+    mov64 r0, 1
+    exit
+"""
+
+_SCHED_CFG = """
+    mov64 r9, r1
+    stw [r10-4], 0
+    lddw r1, map:cfg
+    mov64 r2, r10
+    add64 r2, -4
+    call map_lookup_elem
+    jeq r0, 0, no
+    ldxdw r7, [r0+0]          ; the parameter
+"""
+
+# always steal while another worker has units left
+SCHED_GREEDY = "    mov64 r9, r1\n" + _SCHED_COUNT
+
+# steal while this worker has stolen fewer than cfg[0] units
+SCHED_MAX_STEALS = _SCHED_CFG + """
+    ldxw r6, [r9+24]          ; stolen
+    jge r6, r7, no
+""" + _SCHED_COUNT + """
+no:
+    mov64 r0, 0
+    exit
+"""
+
+# steal while this worker has spent less than cfg[0] ns stealing
+SCHED_LATENCY_BUDGET = _SCHED_CFG + """
+    ldxdw r6, [r9+16]         ; steal_ns
+    jge r6, r7, no
+""" + _SCHED_COUNT + """
+no:
+    mov64 r0, 0
+    exit
+"""
+
+
+def sched_policy(kind: str) -> Policy:
+    text = {"greedy": SCHED_GREEDY, "max_steals": SCHED_MAX_STEALS, "latency_budget": SCHED_LATENCY_BUDGET}[kind]
+    maps = [MapSpec("steals", MAP_ARRAY, 4, 8, 4096, F_SHARED)]
+    if kind != "greedy":
+        maps.append(MapSpec("cfg", MAP_ARRAY, 4, 8, 1, F_READ_ONLY))
+    return Policy("sched_" + kind, HOOK_SCHED, text, maps)
+
+
+def sched_costs(workers: int, units_per_worker: int, regime: str, base: int, seed: int) -> np.ndarray:
+    """Work-unit costs (iterations per unit) of the block-scheduler workload,
+    in the unit order the workers' ranges split (worker w owns units
+    [w n / W, (w + 1) n / W)).  "moderate": the cost grows linearly from
+    base to 2 base over the units, so the last workers' ranges hold twice
+    the work of the first's; "heavy_tail": a contiguous 10 % of the workers
+    own units 100-200 x costlier (section 6.2.1's clustered heavy tail), the
+    rest cost base; "uniform": every unit costs base."""
+    n = workers * units_per_worker
+    if regime == "uniform":
+        return np.full(n, base, np.uint32)
+    if regime == "moderate":
+        return (base + (np.arange(n, dtype=np.uint64) * base) // max(n - 1, 1)).astype(np.uint32)
+    if regime == "heavy_tail":
+        u = u01(splitmix(subseed(seed, 9), n))
+        cost = np.full(n, base, np.float64)
+        w = np.arange(n) * workers // n  # the owning worker
+        h0 = int(u01(splitmix(subseed(seed, 10), 1))[0] * (workers - workers // 10))
+        heavy = (w >= h0) & (w < h0 + max(1, workers // 10))
+        cost[heavy] = base * (100 + 100 * u[heavy])
+        return np.minimum(cost, 2**32 - 1).astype(np.uint32)
+    raise ValueError(regime)
 
 
 # ---------------------------------------------------------------------------
