@@ -61,6 +61,7 @@ constexpr uint64_t kLdsMax = 150 << 10;
 constexpr uint64_t kCacheMax = 80 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
+constexpr uint32_t kCombSlots = 4;         // shared-map words a one-lane run combines in registers
 constexpr uint32_t kMemoEntries = 64;      // LDS lookup-memo entries per site (one queue per wave)
 constexpr uint32_t kMemoLds = 4096;        // LDS bytes of a program's memo tables (the rest keep one entry)
 // Shared-map updates of event-parallel kernels may be aggregated per wave
@@ -88,6 +89,7 @@ struct JMaps {
   int n_rings = 0;
   std::vector<Acc> acc;   // per map
   bool simt = false;      // SIMT hook: a wave's shared-map updates hit one word, combined first
+  std::vector<std::pair<int, int>> comb;  // per map: {op, width} of its register combiner, op -1 if none
   JMaps(const std::vector<std::pair<uint64_t, MapDev>>& maps, const std::vector<int>& mm, const std::vector<int>& lm)
       : m(maps), mem_map(mm), ld_map(lm) {
     for (auto& e : maps) ring.push_back(e.second.type == MAP_RINGBUF ? n_rings++ : -1);
@@ -873,8 +875,15 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         const std::string fn = "auto acc_ = [&](uint64_t a_, uint64_t x_) { " + lds + " }; ";
         const std::string priv = agg_lds() || J.simt ? fn + "if (wave_aggregate(ad, (uint64_t)" + S + ", " + ops + ", acc_)) acc_(ad, (uint64_t)" + S + ");"
                                          : fn + "acc_(ad, (uint64_t)" + S + ");";
+        const std::string cmb = mk >= 0 && mk < (int)J.comb.size() && J.comb[mk].first >= 0
+                                    ? "if (UNI) { comb" + std::to_string(mk) + "(ad, (uint64_t)" + S + "); } else "
+                                    : std::string();
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
-                "if (PRIV) { " + priv + " } else { const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
+                "if (PRIV) { " + priv + " } else " + cmb + "{ const uint64_t t = uni<UNI>(" + call + "); " + wb + " }");
+      } else if (h == H_ATOMIC_MAP && mk >= 0 && mk < (int)J.comb.size() && J.comb[mk].first >= 0) {
+        guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc,
+                "if (UNI && !PRIV) { comb" + std::to_string(mk) + "(ad, (uint64_t)" + S + "); } else { const uint64_t t = uni<UNI>(" +
+                    call + "); " + wb + " }");
       } else {
         guarded(D + " + (uint64_t)(int64_t)" + off, 1u << sc, "const uint64_t t = uni<UNI>(" + call + "); " + wb);
       }
@@ -1065,6 +1074,21 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   }
   Windows Wn = plan_windows(U, J);
   const Frame Fr = plan_frame(U, P.stack_bytes);
+  // shared maps' atomics in one-lane (UNI) runs: combined per wave in a few
+  // registers (map -> {op, width}; -1: none)
+  std::vector<std::pair<int, int>> comb(maps.size(), {-1, 0});
+  for (uint32_t pc = 0; pc < U.size(); pc++) {
+    if ((U[pc].w0 & 0xff) == H_LDIMM) {
+      pc++;
+      continue;
+    }
+    if ((U[pc].w0 & 0xff) != H_ATOMIC_MAP) continue;
+    const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+    const uint32_t op = (uint32_t)U[pc].imm;
+    if (mk < 0 || mk >= (int)maps.size() || !(maps[mk].second.flags & F_SHARED) || (op & 1)) continue;
+    comb[mk] = {(int)(op & 0xf0), (int)((U[pc].w0 >> 16) & 3)};
+  }
+  J.comb = comb;
   // a program set's kernel would hold every member's tables at once: there
   // each lane keeps one entry in registers
   plan_memo(U, J, Wn, P.event_parallel, allow_acc);
@@ -1080,6 +1104,30 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   // the maps' descriptors, read from the map table once per run (they stay
   // in scalar registers instead of being reloaded for every event)
   for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
+  // combiners: a one-lane run's updates of a shared map word gather in
+  // registers (kCombSlots words, replaced round robin) and reach the map as
+  // one device atomic per word when replaced or at the end; only atomics
+  // touch a shared map's values, so nothing in the run can see the delay
+  for (size_t k = 0; k < maps.size(); k++) {
+    if (comb[k].first < 0) continue;
+    const std::string K = std::to_string(k), OP = std::to_string(comb[k].first) + "u",
+                      SC = std::to_string(comb[k].second);
+    for (uint32_t j = 0; j < kCombSlots; j++)
+      o += "  uint64_t ca" + K + "_" + std::to_string(j) + " = 0, cv" + K + "_" + std::to_string(j) + " = 0;\n";
+    o += "  uint32_t cr" + K + " = 0;\n";
+    o += "  __device__ __forceinline__ void comb" + K + "(uint64_t a, uint64_t x) {\n";
+    for (uint32_t j = 0; j < kCombSlots; j++) {
+      const std::string J2 = K + "_" + std::to_string(j);
+      o += "    if (a == ca" + J2 + ") { cv" + J2 + " = agg_apply(cv" + J2 + ", x, " + OP + "); return; }\n";
+    }
+    o += "    switch (cr" + K + ") {\n";
+    for (uint32_t j = 0; j < kCombSlots; j++) {
+      const std::string J2 = K + "_" + std::to_string(j);
+      o += "      case " + std::to_string(j) + "u: if (ca" + J2 + ") (void)atomic_global(ca" + J2 + ", cv" + J2 + ", " + OP +
+           ", " + SC + ", 0); ca" + J2 + " = a; cv" + J2 + " = x; break;\n";
+    }
+    o += "    }\n    cr" + K + " = (cr" + K + " + 1u) % " + std::to_string(kCombSlots) + "u;\n  }\n";
+  }
   // lookup memos: last key found, its value's address, the window's words;
   // with one queue per wave, the LDS table's generation and current entry
   for (size_t w = 0; w < Wn.win.size(); w++) {
@@ -1147,6 +1195,17 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     o += "      __syncthreads();\n    }\n";
   }
   o += "  }\n  __device__ __forceinline__ void end(const RunArgs& A) {\n    (void)A;\n";
+  for (size_t k = 0; k < maps.size(); k++) {
+    if (comb[k].first < 0) continue;
+    const std::string K = std::to_string(k);
+    o += "    if (UNI && !PRIV) {\n";
+    for (uint32_t j = 0; j < kCombSlots; j++) {
+      const std::string J2 = K + "_" + std::to_string(j);
+      o += "      { const uint64_t a = rfl64(ca" + J2 + "), x = rfl64(cv" + J2 + "); if (a && lane_id() == 0) (void)atomic_global(a, x, " +
+           std::to_string(comb[k].first) + "u, " + std::to_string(comb[k].second) + ", 0); ca" + J2 + " = 0; }\n";
+    }
+    o += "    }\n";
+  }
   // the one-queue kernel's written-back tables: the registers' entry into
   // its table slot, then each lane writes back one slot
   for (size_t w = 0; w < Wn.win.size(); w++) {
@@ -1191,6 +1250,15 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   // after lane 0 ran a block of events with the other lanes idle: its memo
   // state, read from lane 0, so that the compiler keeps it wave-uniform
   o += "  __device__ __forceinline__ void uniformize() {\n";
+  for (size_t k = 0; k < maps.size(); k++) {
+    if (comb[k].first < 0) continue;
+    const std::string K = std::to_string(k);
+    for (uint32_t j = 0; j < kCombSlots; j++) {
+      const std::string J2 = K + "_" + std::to_string(j);
+      o += "    ca" + J2 + " = rfl64(ca" + J2 + ");\n    cv" + J2 + " = rfl64(cv" + J2 + ");\n";
+    }
+    o += "    cr" + K + " = __builtin_amdgcn_readfirstlane(cr" + K + ");\n";
+  }
   for (size_t w = 0; w < Wn.win.size(); w++) {
     if (!Wn.memo[w]) continue;
     const std::string W = std::to_string(w);
