@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CLOCK_GHZ = 2.4
+INT32_PEAK = 64 * 256 * CLOCK_GHZ * 1e9
 METRIC = "events/s and eBPF insns/s on 1 MI355X; p50/p99 serving latency"
 
 
@@ -53,9 +55,10 @@ def kernel_fingerprint(G, pol, engine):
 
 
 def measured_traffic(fingerprint):
-    """HBM bytes per launch from a committed counter summary
-    (profiles/*traffic*.md: lines 'kernel_sha256: ...' and
-    'traffic_bytes_per_launch: ...'), if it was taken for this kernel."""
+    """HBM bytes per launch and machine instructions per event from a
+    committed counter summary (profiles/*traffic*.md: lines 'kernel_sha256:
+    ...', 'traffic_bytes_per_launch: ...', 'insns_per_event: ...'), if it
+    was taken for this kernel."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
         kv = {}
@@ -65,8 +68,9 @@ def measured_traffic(fingerprint):
                     k, v = line.split(":", 1)
                     kv[k.strip().strip("`* ")] = v.strip().strip("`* ")
         if kv.get("kernel_sha256") == fingerprint and "traffic_bytes_per_launch" in kv:
-            return float(kv["traffic_bytes_per_launch"]), os.path.basename(path)
-    return None, None
+            ipe = float(kv["insns_per_event"]) if "insns_per_event" in kv else None
+            return float(kv["traffic_bytes_per_launch"]), os.path.basename(path), ipe
+    return None, None, None
 
 
 def cpu_trials(code, hook, shapes, ev, event_parallel, threads, trials=10, init=None):
@@ -755,7 +759,7 @@ def main():
 
     tune_lanes = tune["lanes"] if tune else int(os.environ.get("GX_SEQ_LANES", "1"))
     fp = kernel_fingerprint(G, pol, args.engine)
-    traffic, traffic_src = measured_traffic(fp)
+    traffic, traffic_src, machine_ipe = measured_traffic(fp)
     vm_avg_s = vm_ms / 1000 / max(vm_launches, 1)
     ring_per_launch = ring_bytes[0] / args.steps
     alg_bytes = n * (24 + 4) + ring_per_launch
@@ -804,8 +808,20 @@ def main():
         },
         # the bound that holds here: each stream's events form one dependent
         # chain (map state carried from event to event), run one after another
+        # by one wave, which issues at most one instruction every 4 cycles
         "chain": {"streams": 1024, "events_per_stream": n / 1024,
-                  "ns_per_event": vm_avg_s * 1e9 / (n / 1024)},
+                  "ns_per_event": vm_avg_s * 1e9 / (n / 1024),
+                  "machine_insns_per_event": machine_ipe,
+                  "issue_bound_ns_per_event": machine_ipe * 4 / CLOCK_GHZ if machine_ipe else None,
+                  "issue_bound_frac": (machine_ipe * 4 / CLOCK_GHZ) / (vm_avg_s * 1e9 / (n / 1024))
+                  if machine_ipe else None,
+                  "model": "one wave per stream, one instruction per wave every 4 cycles at 2.4 GHz; "
+                           "machine instructions per event from the kernel's SQ_INSTS_* counters"},
+        # eBPF instructions per second against the INT32 vector peak (64
+        # lane-ops per clock per CU x 256 CUs x 2.4 GHz)
+        "alu": {"achieved_insns_per_s": events_per_s * insns_per_event if insns_per_event else None,
+                "peak_lane_ops_per_s": INT32_PEAK,
+                "frac": events_per_s * insns_per_event / INT32_PEAK if insns_per_event else None},
         "cpu_baseline": {k: v for k, v in cpu.items() if k != "insns_per_event"} if cpu else None,
         "stats": st,
         "forms": forms,
