@@ -212,6 +212,20 @@ def test_soundness_all_programs_up_to_3():
     assert _sound(progs) > 20
 
 
+# every program of four instructions over a core alphabet: the loads and
+# stores, a counter and its counted-loop jumps back, forward jumps over one
+# or two instructions, an unconditional loop and the exit
+CORE4 = ["mov64 r0, 0", "add64 r0, 1", "mov64 r1, 0", "ldxdw r0, [r1+0]", "stdw [r10-8], 1",
+         "ldxdw r0, [r10-8]", "exit", "mov64 r6, 0", "add64 r6, 1", "ja -1", "ja +1",
+         "jeq r0, 0, +1", "jgt r0, 1, +2", "jeq r0, 0, -2", "jlt r6, 3, -2", "jlt r6, 3, -3"]
+
+
+def test_soundness_all_programs_of_4_over_a_core_alphabet():
+    progs = list(itertools.product(CORE4, repeat=4))
+    assert len(progs) == 16 ** 4
+    assert _sound(progs) > 100
+
+
 def test_soundness_framed_programs():
     """Three enumerated instructions between an initialising prefix and an
     exit, so that loops and branches over initialised registers are covered."""
