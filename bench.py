@@ -415,7 +415,7 @@ def _digest(rt, fds_list):
 def bench_batched(G, W, rt, reps, threads=0):
     """256 generated programs over their own batches (2^10..2^20 events):
     256 plain launches in order against one batched call, interpreted; then
-    the same batched call with the programs compiled into four program sets
+    the same batched call with the programs compiled into eight program sets
     (one persistent launch per set), and its replay as a HIP graph.  Every
     form gives the same return codes and maps."""
     import numpy as np
@@ -467,13 +467,18 @@ def bench_batched(G, W, rt, reps, threads=0):
     tune = rt.autotune_batches(descs, stream=stream)
     timed("plain", plain)
     timed("batched", batched)
-    # the same programs compiled: four program sets of 64 (one persistent
-    # kernel each); plain runs keep interpreting
+    # the same programs compiled: eight program sets of 32 (one persistent
+    # kernel each, compiled side by side); plain runs keep interpreting
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(4) as ex:
-        list(ex.map(lambda k: rt.jit_program_set([runs[i][0] for i in range(k, 256, 4)]), range(4)))
+
+    def compile_set(k):
+        rt.jit_program_set([runs[i][0] for i in range(k, 256, 8)])
+        log(f"batched: program set {k} compiled ({time.perf_counter() - t0:.1f} s)")
+
+    with ThreadPoolExecutor(8) as ex:
+        list(ex.map(compile_set, range(8)))
     compile_s = time.perf_counter() - t0
-    log(f"batched: compiled 4 program sets of 64 in {compile_s:.1f} s")
+    log(f"batched: compiled 8 program sets of 32 in {compile_s:.1f} s")
     timed("batched_sets", batched)
     graph = rt.graph_create(descs)
     timed("graph_sets", lambda: graph.launch(stream))

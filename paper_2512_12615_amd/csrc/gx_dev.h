@@ -1266,9 +1266,25 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
   const uint32_t l = lane_id();
   Ctx nc{0, 0, 0};
   uint32_t ni = 0;
+  // With the queue-ordered copy, lane l reads record k0 + l of it and its
+  // index; without it (A.sorted null), lane l gathers event order[k0 + l]
+  // from the input: the indices are read a block earlier than the records
+  // (ni2), so neither load waits inside the loop.
+  const bool gather = A.sorted == nullptr;
+  uint32_t ni2 = 0;
+  auto index_of = [&](uint64_t k) { return k < end ? ((const GX_GLOBAL uint32_t*)A.order)[k] : 0u; };
   auto fetch = [&](uint64_t k0) {  // lane l: record k0 + l
     const uint64_t k = k0 + l;
-    if (k < end) {
+    if (gather) {
+      ni = ni2;
+      ni2 = index_of(k + 64);
+      if (k < end) {
+        const GX_GLOBAL uint64_t* p = (const GX_GLOBAL uint64_t*)(A.events + (uint64_t)ni * A.record_size);
+        nc.c0 = p[0];
+        nc.c1 = p[1];
+        nc.c2 = wide ? p[2] : 0;
+      }
+    } else if (k < end) {
       const GX_GLOBAL uint64_t* p = (const GX_GLOBAL uint64_t*)(A.sorted + (uint64_t)k * kSortedStride);
       nc.c0 = p[0];
       nc.c1 = p[1];
@@ -1276,6 +1292,7 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
       ni = ((const GX_GLOBAL uint32_t*)A.order)[k];
     }
   };
+  if (gather) ni2 = index_of((uint64_t)beg + l);
   fetch(beg);
   for (uint64_t k0 = beg; k0 < end; k0 += 64) {
     const Ctx cc = nc;  // this block's records, one per lane

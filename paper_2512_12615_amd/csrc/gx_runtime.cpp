@@ -39,6 +39,7 @@ hipError_t launch_batched(const BatchDev* d_batches, const uint2* d_items, uint3
                           uint32_t waves, uint32_t stack_max, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, uint32_t n, hipStream_t s);
 hipError_t launch_app_vadd(const RunArgs& A, const AppArgs& P, hipStream_t s);
+hipError_t launch_app_vadd_acc(RunArgs A, const AppArgs& P, uint32_t n_cu, hipStream_t s);
 hipError_t launch_app_plain(const AppArgs& P, uint32_t n_cu, hipStream_t s);
 hipError_t launch_sched(const RunArgs& A, const SchedArgs& S, hipStream_t s);
 hipError_t launch_sched_plain(const SchedArgs& S, hipStream_t s);
@@ -643,10 +644,14 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
     if (r) return r;
     if (X.ws_used) (void)hipStreamWaitEvent(s, X.ws_event, 0);
     A.step_limit = per_event * n_events;
-    e = launch_partition(A, lbits, (uint32_t)tile, nt, X.d_counts, X.d_sums, X.d_order, X.d_sorted, s);
+    // the one-queue compiled kernel gathers its records through order[], so
+    // the partition writes only the indices
+    const bool gather = p->jf_uni && k.lanes == 1;
+    e = launch_partition(A, lbits, (uint32_t)tile, nt, X.d_counts, X.d_sums, X.d_order, gather ? nullptr : X.d_sorted,
+                         s);
     if (e == hipSuccess) {
       A.order = X.d_order;
-      A.sorted = X.d_sorted;
+      A.sorted = gather ? nullptr : X.d_sorted;
       A.qstart = X.d_counts;
       A.n_queues = L;
       if (pe.first) (void)hipEventRecord(pe.first, s);
@@ -1555,7 +1560,7 @@ int run_noalloc(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, 
     uint32_t* counts = (uint32_t*)(rt->d_scratch + off[0]);
     uint32_t* sums = (uint32_t*)(rt->d_scratch + off[1]);
     uint32_t* order = (uint32_t*)(rt->d_scratch + off[2]);
-    uint8_t* sorted = rt->d_scratch + off[3];
+    uint8_t* sorted = p->jf_uni && k.lanes == 1 ? nullptr : rt->d_scratch + off[3];
     e = launch_partition(A, k.qbits, (uint32_t)tile, nt, counts, sums, order, sorted, s);
     if (e == hipSuccess) {
       A.order = order;
@@ -2348,6 +2353,14 @@ int gx_run_app_vadd(gx_rt* rt, int prog_fd, const double* d_a, const double* d_b
       if (r) return r;
     }
     r = launch_jit_app(rt, p, A, P, jit_ep_blocks(p, n, 0), jit_waves(p->v.stack_bytes, true), s);
+  } else if (p->acc_hi > p->acc_lo && env_int("GX_INTERP_ACC", 1)) {
+    // the interpreter's LDS mirror of a small shared array map
+    A.acc_lo = p->acc_lo;
+    A.acc_hi = p->acc_hi;
+    A.acc_op = p->acc_op;
+    A.acc_sc = p->acc_sc;
+    hipError_t e = launch_app_vadd_acc(A, P, rt->n_cu, s);
+    r = e == hipSuccess ? 0 : to_errno(e);
   } else {
     hipError_t e = launch_app_vadd(A, P, s);
     r = e == hipSuccess ? 0 : to_errno(e);

@@ -360,6 +360,28 @@ extern "C" __global__ void __launch_bounds__(256) gx_k_app_vadd(RunArgs A, AppAr
   asm volatile("" ::"v"(sink));
 }
 
+// The same with a shared map summed in the block's LDS mirror (as
+// gx_k_event_parallel_acc): waves loop over tiles grid-stride and the block
+// applies its sums once at the end.
+extern "C" __global__ void __launch_bounds__(1024) gx_k_app_vadd_acc(RunArgs A, AppArgs P) {
+  const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  Stk stk{wave * 64u * A.stack_bytes, lane_id() * 8u, blockIdx.x * blockDim.x + threadIdx.x};
+  const uint32_t words = (uint32_t)((A.acc_hi - A.acc_lo) >> A.acc_sc);
+  uint8_t* mirror = g_lds + A.acc_lds;
+  if (A.acc_sc == 3)
+    mirror_init<uint64_t>((uint64_t*)mirror, words, A.acc_op);
+  else
+    mirror_init<uint32_t>((uint32_t*)mirror, words, A.acc_op);
+  __syncthreads();
+  Interp I;
+  app_vadd_loop<true>(I, A, P, (uint64_t)blockIdx.x * nw + wave, (uint64_t)gridDim.x * nw, stk);
+  __syncthreads();
+  if (A.acc_sc == 3)
+    mirror_flush<uint64_t>((const uint64_t*)mirror, words, A.acc_op, (uint8_t*)A.acc_lo);
+  else
+    mirror_flush<uint32_t>((const uint32_t*)mirror, words, A.acc_op, (uint8_t*)A.acc_lo);
+}
+
 // The vector add without a hook (grid-stride over tiles).
 extern "C" __global__ void __launch_bounds__(256) gx_k_app_plain(AppArgs P) {
   const RunArgs A{};
@@ -427,8 +449,18 @@ __device__ __forceinline__ void part_count(const PartJob& J, uint32_t t, uint32_
   for (uint32_t q = l; q < L; q += 64) cnt[q] = 0;
   __syncthreads();
   uint64_t b = (uint64_t)t * J.tile, e = b + J.tile < J.n_events ? b + J.tile : J.n_events;
-  for (uint64_t i = b + l; i < e; i += 64)
-    atomicAdd(&cnt[stream_key_of(J.events, J.record_size, J.stream_off, i) & (L - 1)], 1u);
+  // four rounds of keys are loaded before their LDS counts are added
+  for (uint64_t c = b; c < e; c += 256) {
+    uint32_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = c + 64 * u + l;
+      k[u] = i < e ? stream_key_of(J.events, J.record_size, J.stream_off, i) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (c + 64 * u + l < e) atomicAdd(&cnt[k[u] & (L - 1)], 1u);
+  }
   __syncthreads();
   for (uint32_t q = l; q < L; q += 64) counts[J.cbase + (uint64_t)q * J.nt + t] = cnt[q];
 }
@@ -440,10 +472,13 @@ __device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const
   for (uint32_t q = l; q < L; q += 64) base[q] = offs[J.cbase + (uint64_t)q * J.nt + t];
   __syncthreads();
   uint64_t b = (uint64_t)t * J.tile, e = b + J.tile < J.n_events ? b + J.tile : J.n_events;
+  // the next round's keys are loaded while this round ranks and writes
+  uint32_t nkey = b + l < e ? stream_key_of(J.events, J.record_size, J.stream_off, b + l) : 0;
   for (uint64_t c = b; c < e; c += 64) {
     uint64_t i = c + l;
     bool v = i < e;
-    uint32_t key = v ? (stream_key_of(J.events, J.record_size, J.stream_off, i) & (L - 1)) : 0;
+    uint32_t key = v ? (nkey & (L - 1)) : 0;
+    if (c + 64 + l < e) nkey = stream_key_of(J.events, J.record_size, J.stream_off, c + 64 + l);
     uint64_t peers = ballot(v);
     for (uint32_t bit = 0; bit < J.lbits; bit++) {
       uint64_t m = ballot(v && ((key >> bit) & 1));
@@ -458,11 +493,14 @@ __device__ __forceinline__ void part_scatter(const PartJob& J, uint32_t t, const
       order[pos] = (uint32_t)i;
       if (rank == 0) base[key] = pos + popc64(peers);
       // the record itself, so that each queue's records lie together
-      const uint64_t* src = (const uint64_t*)(J.events + i * J.record_size);
-      uint64_t* dst = (uint64_t*)(sorted + (uint64_t)pos * kSortedStride);
-      dst[0] = src[0];
-      dst[1] = src[1];
-      if (J.record_size > 16) dst[2] = src[2];
+      // (null sorted: the consumer gathers the records through order[])
+      if (sorted) {
+        const uint64_t* src = (const uint64_t*)(J.events + i * J.record_size);
+        uint64_t* dst = (uint64_t*)(sorted + (uint64_t)pos * kSortedStride);
+        dst[0] = src[0];
+        dst[1] = src[1];
+        if (J.record_size > 16) dst[2] = src[2];
+      }
     }
   }
 }
@@ -642,6 +680,8 @@ hipError_t vm_init() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)gx_k_app_vadd, hipFuncAttributeMaxDynamicSharedMemorySize, 256 * kStackMax);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gx_k_app_vadd_acc, hipFuncAttributeMaxDynamicSharedMemorySize, kAccLdsMax);
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)gx_k_sched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)gx_k_batched, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * kStackMax);
@@ -674,6 +714,22 @@ hipError_t launch_event_parallel_acc(RunArgs A, uint32_t n_cu, hipStream_t s) {
 hipError_t launch_app_vadd(const RunArgs& A, const AppArgs& P, hipStream_t s) {
   const uint64_t blocks = (P.n + 255) / 256;
   hipLaunchKernelGGL(gx_k_app_vadd, dim3((uint32_t)blocks), dim3(256), 256 * A.stack_bytes, s, A, P);
+  return hipGetLastError();
+}
+
+// The mirrored form's shape as launch_event_parallel_acc's, over n tiles.
+hipError_t launch_app_vadd_acc(RunArgs A, const AppArgs& P, uint32_t n_cu, hipStream_t s) {
+  const uint64_t acc_bytes = A.acc_hi - A.acc_lo;
+  uint32_t nw = 16;
+  while (nw > 1 && (uint64_t)nw * 64 * A.stack_bytes + acc_bytes > kAccLdsMax) nw /= 2;
+  A.acc_lds = nw * 64u * A.stack_bytes;
+  const uint64_t words = acc_bytes >> A.acc_sc;
+  const uint64_t tiles = (P.n + 63) / 64;
+  const uint64_t per_words = P.n / words > n_cu ? P.n / words : n_cu;
+  uint64_t nb = (tiles + nw - 1) / nw;
+  if (nb > per_words) nb = per_words;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(gx_k_app_vadd_acc, dim3((uint32_t)nb), dim3(64 * nw), A.acc_lds + acc_bytes, s, A, P);
   return hipGetLastError();
 }
 
