@@ -74,6 +74,14 @@ bool agg_lds() {
   return v && *v && std::atoi(v) != 0;
 }
 
+// The checked mode's bounds checks of map-value accesses (GX_CHECKED, read
+// again by every run) are compiled in only when it is on at compile time:
+// otherwise each access would test the run's flag on the event chain.
+std::string guards_define() {
+  const char* v = std::getenv("GX_CHECKED");
+  return std::string("#define GX_GUARDS ") + (v && *v && std::atoi(v) != 0 ? "1" : "0") + "\n";
+}
+
 // Cap on each cache in KiB from the environment (tuning experiments).
 int env_int_jit(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -662,7 +670,7 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
   auto set32 = [&](const std::string& e) { o += "  " + D + " = (uint64_t)(uint32_t)(" + e + ");\n"; };
   auto jmp = [&](const std::string& c) { o += "  if (" + c + ") " + tgt + "\n"; };
   auto guarded = [&](const std::string& addr, uint32_t size, const std::string& body) {
-    o += "  { const uint64_t ad = " + addr + ";\n    if (!A.checked || guard_ok(A, " + std::to_string(pc) + "u, ad, " +
+    o += "  { const uint64_t ad = " + addr + ";\n    if (!GX_GUARDS || !A.checked || guard_ok(A, " + std::to_string(pc) + "u, ad, " +
          std::to_string(size) + "u)) { " + body + " } }\n";
   };
   const std::string sgn_a = "(int64_t)" + D, sgn_b = "(int64_t)" + B;
@@ -1335,6 +1343,7 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
   const int nr = std::max(ring_count(P), 1);
   std::string o;
   o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
+  o += guards_define();
   o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
   o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
@@ -1386,6 +1395,7 @@ std::string jit_set_source(const std::vector<JitProg>& progs) {
   }
   std::string o;
   o += "#define GX_LDS_BYTES " + std::to_string(64u * stack) + "\n";
+  o += guards_define();
   o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
   o += "#define GX_RING_SLOTS " + std::to_string(nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
