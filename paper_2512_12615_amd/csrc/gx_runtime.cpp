@@ -1119,7 +1119,7 @@ int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
   cand.push_back(def);
   if (p->v.event_parallel) {
     if (p->jf_ep)
-      for (uint32_t b : {256u, 512u, 1024u, 2048u, 4096u, 8192u}) cand.push_back(Knobs{def.lanes, def.qbits, b});
+      for (uint32_t b : {64u, 128u, 256u, 512u, 1024u, 2048u, 4096u, 8192u}) cand.push_back(Knobs{def.lanes, def.qbits, b});
   } else {
     for (uint32_t q : {10u, 12u, 14u})
       for (uint32_t l : {1u, 2u, 4u, 8u, 16u, 32u, 64u}) cand.push_back(Knobs{l, q, 0});

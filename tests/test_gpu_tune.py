@@ -67,7 +67,7 @@ def test_autotune_event_parallel_compiled(rt):
     ev = W.gen_mem_uniform(1 << 18, 9)
     d = to_device(ev)
     t = rt.autotune(prog, d, n_events=len(ev), record_size=24)
-    assert t["trials"] == 7
+    assert t["trials"] == 9  # the default and 64..8192 blocks
     assert np.frombuffer(rt.map_dump(fds[0])[1].tobytes(), "<u8").sum() == 0
     rc = torch.zeros(len(ev), dtype=torch.int32, device="cuda")
     rt.run_batch(prog, d, n_events=len(ev), record_size=24, rc=rc)
