@@ -56,9 +56,11 @@ struct Acc {
 
 // LDS a workgroup may take (gfx950: 160 KiB per CU), of which the
 // accumulators get what stacks and ring slots leave; caches are capped at
-// kCacheMax each (every slot in use costs one device atomic at the flush).
+// kCacheMax each (every slot in use costs one device atomic, or one spilled
+// slot, at the flush; the latency histogram measured 562 -> 537 us per 2^26
+// events when the cap went from 80 to 112 KiB, and slower below 64 KiB).
 constexpr uint64_t kLdsMax = 150 << 10;
-constexpr uint64_t kCacheMax = 80 << 10;
+constexpr uint64_t kCacheMax = 112 << 10;
 constexpr uint64_t kCacheSlotsPerSet = 4;  // the device cache's ways
 constexpr uint64_t kReduceMax = 8192;      // words of a reduce block's LDS sums
 constexpr uint32_t kCombSlots = 4;         // shared-map words a one-lane run combines in registers
