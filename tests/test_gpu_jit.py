@@ -334,3 +334,78 @@ def test_jit_ring_drain_view(rt):
     assert sorted(seen) == want
     view, kept, n = rt.drain_ringbuf_view(fds[1])
     assert kept == 0 and n == 0 and len(view) == 0
+
+
+def _combined_prog(op, width, words):
+    """Stream-sequential program (an owned hash entry per stream) whose loop
+    updates a shared array six times per event, cycling over ``words``
+    words: one-lane compiled runs combine these updates in registers (four
+    words, replaced round robin), so more than four words force
+    replacements within an event."""
+    mn = {"add": "aadd", "or": "aor", "and": "aand", "xor": "axor"}[op] + ("64" if width == 8 else "32")
+    text = f"""
+        ldxw r6, [r1+8]
+        ldxdw r7, [r1+16]
+        stxdw [r10-8], r6
+        stdw [r10-16], 1
+        lddw r1, map:own
+        mov64 r2, r10
+        add64 r2, -8
+        mov64 r3, r10
+        add64 r3, -16
+        mov64 r4, 0
+        call map_update_elem
+        mov64 r9, 0
+    loop:
+        mov64 r1, r7
+        add64 r1, r9
+        mod64 r1, {words}
+        stxw [r10-4], r1
+        lddw r1, map:sh
+        mov64 r2, r10
+        add64 r2, -4
+        call map_lookup_elem
+        jeq r0, 0, next
+        mov64 r1, r7
+        rsh64 r1, 7
+        {'xor64 r1, -1' if op == 'and' else 'and64 r1, 0xfffff'}
+        {mn} [r0+0], r1
+    next:
+        add64 r9, 1
+        jlt r9, 6, loop
+        mov64 r0, r6
+        and64 r0, 7
+        exit
+    """
+    return W.Policy(f"combined_{op}{width}_{words}", W.HOOK_MEM_ACCESS, text,
+                    [W.MapSpec("own", W.MAP_HASH, 8, 8, 4096, 0),
+                     W.MapSpec("sh", W.MAP_ARRAY, 4, width, 16, W.F_SHARED)])
+
+
+@pytest.mark.parametrize("op,width,words", [("add", 8, 1), ("add", 4, 3), ("or", 8, 5), ("xor", 4, 9),
+                                            ("and", 8, 16), ("add", 8, 7)])
+@pytest.mark.parametrize("batched", [False, True])
+def test_jit_one_lane_combiner(rt, op, width, words, batched):
+    """Every stream hits the same few shared words from the one-queue kernel
+    (and from a compiled program set): maps and return codes equal the
+    oracle's."""
+    import torch
+    _log(f"jit combiner {op}{width} words={words} batched={batched}")
+    pol = _combined_prog(op, width, words)
+    n = 1 << 14
+    ev = W.gen_mem_uniform(n, 300 + words)
+    ev["ts"] = W.splitmix(301 + words, n)
+    init = [(1, np.uint32(k).tobytes(), b"\xff" * width) for k in range(16)] if op == "and" else None
+    want = oracle_run(pol, ev, init)
+    if not batched:
+        g = gpu_run(rt, pol, ev, init, jit=True)
+        assert_same(g, want, pol.name)
+        assert g.stats["vm_errors"] == 0
+        return
+    fds, prog = setup(rt, pol, init)
+    rt.jit_program_set([prog])
+    rc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    rt.run_batches([(prog, to_device(ev), n, 24, rc)])
+    torch.cuda.synchronize()
+    g = collect(rt, pol, fds, rc.cpu().numpy().view(np.uint32))
+    assert_same(g, want, pol.name + " set")
