@@ -85,6 +85,15 @@ __device__ __forceinline__ GX_GLOBAL T* gl(T* p) {
   return (GX_GLOBAL T*)p;
 }
 
+// LDS words that lanes of a wave pass to each other (one lane writes, the
+// others read later): every access is volatile, so that the compiler keeps
+// no lane's own copy in a register, which would see only that lane's
+// updates.
+template <typename T>
+__device__ __forceinline__ volatile __attribute__((address_space(3))) T* lds(T* p) {
+  return (volatile __attribute__((address_space(3))) T*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(T* p) {
   return __hip_atomic_load(gl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -393,11 +402,28 @@ __device__ __forceinline__ bool ring_reserve(const MapDev* m, uint64_t total, ui
 }
 
 
-__device__ __forceinline__ void ring_put(const MapDev* m, uint64_t pos, int kind, uint64_t dp, uint32_t size,
-                                         const Stk& stk) {
+// A record's payload word w, from the stack or map memory (``kind``, ``dp``)
+// or, in compiled programs whose record lies in the private frame, from the
+// caller's registers.
+struct RecSrc {
+  int kind;
+  uint64_t dp;
+  const Stk& stk;
+  __device__ __forceinline__ uint64_t operator()(uint32_t w, uint32_t size) const { return chunk(kind, dp, w, size, stk); }
+};
+struct RecVal {
+  uint64_t w[8];  // up to 64 bytes
+  __device__ __forceinline__ uint64_t operator()(uint32_t j, uint32_t size) const {
+    const uint32_t left = size - 8 * j;
+    return left >= 8 ? w[j] : w[j] & ((1ull << (8 * left)) - 1);
+  }
+};
+
+template <class Src>
+__device__ __forceinline__ void ring_put(const MapDev* m, uint64_t pos, const Src& src, uint32_t size) {
   const uint64_t mask = m->slot_mask;
   const uint32_t nw = (size + 7) / 8;
-  for (uint32_t w = 0; w < nw; w++) *gl((uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask))) = chunk(kind, dp, w, size, stk);
+  for (uint32_t w = 0; w < nw; w++) *gl((uint64_t*)(m->data + ((pos + 8 + 8 * w) & mask))) = src(w, size);
   // records are read by the host once the producing launch has completed
   *gl((uint64_t*)(m->data + (pos & mask))) = (uint64_t)size;
 }
@@ -431,7 +457,7 @@ GX_HELPER uint64_t ring_output(const MapDev* m, int kind, uint64_t dp, uint32_t 
     return res;
   }
   if (want) {
-    ring_put(m, base + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
+    ring_put(m, base + (uint64_t)need * rank_in(wm), RecSrc{kind, dp, stk}, size);
     res = 0;
   }
   return res;
@@ -456,6 +482,11 @@ struct RingChunk {
 
 #ifdef GX_RING_SLOTS
 __shared__ RingChunk g_rchunk[GX_RING_SLOTS];
+__device__ __forceinline__ void chunk_store(uint32_t slot, uint64_t pos, uint64_t left, uint64_t recs) {
+  *lds(&g_rchunk[slot].pos) = pos;
+  *lds(&g_rchunk[slot].left) = left;
+  *lds(&g_rchunk[slot].recs) = recs;
+}
 __shared__ RingChunk g_rblock[GX_NRINGS];
 __shared__ uint32_t g_rlock[GX_NRINGS];
 __shared__ uint64_t g_rcount[2 * GX_NRINGS];  // the block's discard bytes and records, per ring
@@ -504,12 +535,12 @@ __device__ __forceinline__ void ring_count(uint32_t r, uint64_t recs) {
 // counts to the ring's.
 __device__ __forceinline__ void ring_chunk_close(const MapDev* m, uint32_t slot) {
   const uint32_t r = slot % GX_NRINGS;
-  const uint64_t left = g_rchunk[slot].left, pos = g_rchunk[slot].pos, recs = g_rchunk[slot].recs;
+  const uint64_t left = *lds(&g_rchunk[slot].left), pos = *lds(&g_rchunk[slot].pos), recs = *lds(&g_rchunk[slot].recs);
   if (lane_id() == (uint32_t)__builtin_ctzll(ballot(true))) {
     ring_discard(m, r, pos, left);
     ring_count(r, recs);
-    g_rchunk[slot].left = 0;
-    g_rchunk[slot].recs = 0;
+    *lds(&g_rchunk[slot].left) = 0;
+    *lds(&g_rchunk[slot].recs) = 0;
   }
 }
 __device__ __forceinline__ void ring_block_close(const MapDev* m, uint32_t r) {
@@ -567,10 +598,10 @@ __device__ __forceinline__ bool ring_block_take(const MapDev* m, uint32_t r, uin
 // this one is short.  Same results as ring_output while space lasts; near a
 // full ring a request may fail a little earlier (the unused parts of chunks
 // count as used until the drain).
+template <class Src>
 __device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t slot, uint32_t r,
-                                                       uint64_t chunk_bytes, uint64_t block_bytes, int kind,
-                                                       uint64_t dp, uint32_t size, uint64_t flags,
-                                                       const Stk& stk) {
+                                                       uint64_t chunk_bytes, uint64_t block_bytes, const Src& src,
+                                                       uint32_t size, uint64_t flags) {
   uint64_t res = 0;
   const bool want = flags == 0;
   if (!want) res = (uint64_t)-E_INVAL;
@@ -580,7 +611,7 @@ __device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t 
   const uint32_t need = 8 + ((size + 7) & ~7u);
   const uint32_t cnt = popc64(wm);
   const uint64_t total = (uint64_t)need * cnt;
-  uint64_t pos = g_rchunk[slot].pos, left = g_rchunk[slot].left, recs = g_rchunk[slot].recs;
+  uint64_t pos = *lds(&g_rchunk[slot].pos), left = *lds(&g_rchunk[slot].left), recs = *lds(&g_rchunk[slot].recs);
   if (total > left) {
     uint32_t ok = 0, lo = 0, hi = 0, glo = 0, ghi = 0;
     if (lane_id() == leader) {
@@ -596,7 +627,7 @@ __device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t 
     }
     ok = rdlane(ok, leader);
     if (!ok) {
-      if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos, 0, 0};
+      if (lane_id() == leader) chunk_store(slot, pos, 0, 0);
       return want ? (uint64_t)-E_AGAIN : res;
     }
     pos = ((uint64_t)rdlane(hi, leader) << 32) | rdlane(lo, leader);
@@ -604,10 +635,10 @@ __device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t 
     recs = 0;
   }
   if (want) {
-    ring_put(m, pos + (uint64_t)need * rank_in(wm), kind, dp, size, stk);
+    ring_put(m, pos + (uint64_t)need * rank_in(wm), src, size);
     res = 0;
   }
-  if (lane_id() == leader) g_rchunk[slot] = RingChunk{pos + total, left - total, recs + cnt};
+  if (lane_id() == leader) chunk_store(slot, pos + total, left - total, recs + cnt);
   return res;
 }
 
@@ -615,18 +646,31 @@ __device__ __forceinline__ uint64_t ring_output_group(const MapDev* m, uint32_t 
 // that differ in record size or ring (their arguments then vary by lane),
 // so the active lanes are served one (slot, size) group at a time; each
 // group's records are carved as one wave request.
-__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint32_t r,
-                                                         uint64_t chunk_bytes, uint64_t block_bytes, int kind,
-                                                         uint64_t dp, uint32_t size, uint64_t flags,
-                                                         const Stk& stk) {
+template <class Src>
+__device__ __forceinline__ uint64_t ring_output_src(const MapDev* m, uint32_t slot, uint32_t r, uint64_t chunk_bytes,
+                                                     uint64_t block_bytes, const Src& src, uint32_t size,
+                                                     uint64_t flags) {
   uint64_t res = 0;
   for (uint64_t todo = ballot(true); todo;) {
     const uint32_t l0 = (uint32_t)__builtin_ctzll(todo);
     const bool mine = slot == rdlane(slot, l0) && size == rdlane(size, l0);
     todo &= ~ballot(mine);
-    if (mine) res = ring_output_group(m, slot, r, chunk_bytes, block_bytes, kind, dp, size, flags, stk);
+    if (mine) res = ring_output_group(m, slot, r, chunk_bytes, block_bytes, src, size, flags);
   }
   return res;
+}
+__device__ __forceinline__ uint64_t ring_output_chunked(const MapDev* m, uint32_t slot, uint32_t r,
+                                                         uint64_t chunk_bytes, uint64_t block_bytes, int kind,
+                                                         uint64_t dp, uint32_t size, uint64_t flags,
+                                                         const Stk& stk) {
+  return ring_output_src(m, slot, r, chunk_bytes, block_bytes, RecSrc{kind, dp, stk}, size, flags);
+}
+// The record's words passed by value (a record in the private frame of a
+// compiled program: no stack memory is read).
+__device__ __forceinline__ uint64_t ring_output_words(const MapDev* m, uint32_t slot, uint32_t r,
+                                                       uint64_t chunk_bytes, uint64_t block_bytes, const RecVal& v,
+                                                       uint32_t size, uint64_t flags) {
+  return ring_output_src(m, slot, r, chunk_bytes, block_bytes, v, size, flags);
 }
 #endif
 
@@ -783,7 +827,11 @@ __device__ __forceinline__ T load_uniform(uint64_t addr) {
   typedef const __attribute__((address_space(4))) T cT;
   const uint64_t u = rfl64(addr);
   if (ballot(addr != u) == 0) return *(const cT*)u;
-  return *(const T*)addr;
+  // lanes apart: a global (not flat) vector load, consumed on this path, so
+  // that the scalar path above never waits for the wave's vector memory
+  uint64_t v = *(const GX_GLOBAL T*)addr;
+  __asm__ volatile("" : "+v"(v));
+  return (T)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -837,10 +885,13 @@ __device__ __forceinline__ void mirror_flush(const T* acc, uint32_t words, uint3
   }
 }
 
-// tagged cache, 4-way set associative: slot s holds the sum for word
-// tag[s] - 1 of the map's value area (0: free); a word claims the first free
-// way of its set and keeps it for the block's lifetime, so a word whose set
-// is full goes to the map directly
+// tagged cache, 4-way set associative: slot s*4 + w holds the partial sum
+// of the word its tag names in set s (tag 0: free); a word claims the first
+// free way of its set and keeps it for the block's lifetime, so a word whose
+// set is full goes to the map directly.  Two tag formats: 32-bit tags (the
+// word index + 1, one per slot), or 8-bit tags (the word index divided by
+// the set count, + 1; the set's four packed in one 32-bit word), which hold
+// 1.6x the slots in the same LDS when the quotient stays below 255.
 constexpr uint32_t kCacheWays = 4;
 
 // Set of a key (a word index) in a cache of ``sets`` 4-way sets: the index
@@ -851,10 +902,16 @@ __device__ __forceinline__ uint32_t cache_set(uint32_t key, uint32_t sets) {
   return key % sets;
 }
 
-template <typename TV>
+// Tag words of a cache of ``sets`` sets.
+template <bool TAG8>
+__device__ __forceinline__ uint32_t cache_tag_words(uint32_t sets) {
+  return TAG8 ? sets : sets * kCacheWays;
+}
+
+template <typename TV, bool TAG8>
 __device__ __forceinline__ void cache_init(uint32_t* tag, TV* val, uint32_t sets, uint32_t op) {
   for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
-    tag[i] = 0;
+    if (i < cache_tag_words<TAG8>(sets)) tag[i] = 0;
     val[i] = op_identity<TV>(op);
   }
 }
@@ -865,7 +922,8 @@ __device__ __forceinline__ void cache_init(uint32_t* tag, TV* val, uint32_t sets
 // 0 there only sends the lane to the compare-and-swap, which sees the truth.
 __device__ __forceinline__ int cache_way(uint32_t* tag, uint32_t base, uint32_t key) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  const u32x4 t4 = *(volatile u32x4*)&tag[base];
+  typedef volatile __attribute__((address_space(3))) u32x4 lds_u32x4;
+  const u32x4 t4 = *(lds_u32x4*)&tag[base];  // an LDS read, not a flat one
   const uint32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
   for (int w = 0; w < (int)kCacheWays; w++) {
@@ -882,89 +940,133 @@ __device__ __forceinline__ int cache_way(uint32_t* tag, uint32_t base, uint32_t 
   return -1;
 }
 
-template <typename T>
+// The same with 8-bit tags: t8 (1..255) in set s's tag word.  Ways fill in
+// order, so a set's free ways are its last ones; the lowest byte equal to
+// t8, or the lowest zero byte, is found with the zero-byte test on the
+// word (exact for the lowest such byte).  A claim swaps the whole word and
+// is retried when another lane changed it first; at most four claims ever
+// succeed on a set, so a lane tries at most five times.
+__device__ __forceinline__ int cache_way8(uint32_t* tag, uint32_t s, uint32_t t8) {
+  uint32_t cur = *lds(&tag[s]);
+  for (int tries = 0; tries < 5; tries++) {
+    const uint32_t x = cur ^ (t8 * 0x01010101u);
+    const uint32_t hit = (x - 0x01010101u) & ~x & 0x80808080u;
+    if (hit) return (int)(__builtin_ctz(hit) >> 3);
+    const uint32_t fr = (cur - 0x01010101u) & ~cur & 0x80808080u;
+    if (!fr) return -1;
+    const uint32_t w = __builtin_ctz(fr) >> 3;
+    uint32_t e = cur;
+    if (__hip_atomic_compare_exchange_strong(&tag[s], &e, cur | (t8 << (8 * w)), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return (int)w;
+    cur = e;
+  }
+  return -1;
+}
+
+// Slot of word index ``x`` (claimed if need be), or -1 when its set is full.
+template <bool TAG8>
+__device__ __forceinline__ int cache_slot(uint32_t* tag, uint32_t sets, uint32_t x) {
+  const uint32_t s = cache_set(x, sets);
+  const int w = TAG8 ? cache_way8(tag, s, x / sets + 1) : cache_way(tag, s * kCacheWays, x + 1);
+  return w < 0 ? -1 : (int)(s * kCacheWays) + w;
+}
+
+template <typename T, bool TAG8>
 __device__ __forceinline__ void cache_rmw(uint32_t* tag, T* val, uint32_t sets, uint8_t* data, uint64_t addr, T v,
                                           uint32_t op) {
-  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)) + 1;
-  const uint32_t base = cache_set(key - 1, sets) * kCacheWays;  // by word index
-  const int w = cache_way(tag, base, key);
-  if (w >= 0)
-    lds_rmw(&val[base + w], v, op);
+  const int k = cache_slot<TAG8>(tag, sets, (uint32_t)((addr - (uint64_t)(uintptr_t)data) / sizeof(T)));
+  if (k >= 0)
+    lds_rmw(&val[k], v, op);
   else
     global_rmw((T*)addr, v, op);
 }
 
 // 64-bit sums kept as 32-bit partial sums (twice the slots in the same LDS):
-// an addend of 2^32 or more goes to the map directly, and a partial sum that
-// wraps adds the lost 2^32 to the map at once, so map word + partial sums is
-// always the exact total.
+// only addends up to ``vmax`` are summed in LDS, where vmax times the most
+// updates a block can make (its events times the program's updates per
+// invocation) stays below 2^32, so no partial sum can wrap and the LDS add
+// needs no returned value; larger addends go to the map directly.
+template <bool TAG8>
 __device__ __forceinline__ void cache_add_narrow(uint32_t* tag, uint32_t* val, uint32_t sets, uint8_t* data,
-                                                 uint64_t addr, uint64_t v) {
-  if (v >> 32) {
+                                                 uint64_t addr, uint64_t v, uint32_t vmax) {
+  const int k = v <= vmax ? cache_slot<TAG8>(tag, sets, (uint32_t)((addr - (uint64_t)(uintptr_t)data) / 8)) : -1;
+  if (k < 0)
     global_rmw((uint64_t*)addr, v, 0u);
-    return;
-  }
-  const uint32_t key = (uint32_t)((addr - (uint64_t)(uintptr_t)data) / 8) + 1;
-  const uint32_t base = cache_set(key - 1, sets) * kCacheWays;  // by word index
-  const int w = cache_way(tag, base, key);
-  if (w < 0) {
-    global_rmw((uint64_t*)addr, v, 0u);
-    return;
-  }
-  const uint32_t old = __hip_atomic_fetch_add(&val[base + w], (uint32_t)v, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-  if ((uint32_t)(old + (uint32_t)v) < old) global_rmw((uint64_t*)addr, (uint64_t)1 << 32, 0u);
+  else
+    __hip_atomic_fetch_add(&val[k], (uint32_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Largest addend a block's narrow caches sum in LDS (see cache_add_narrow):
+// the block's waves take tiles t0, t0 + waves, ... of 64 events, and each
+// invocation makes at most ``per_inv`` updates.
+__device__ __forceinline__ uint32_t narrow_vmax(uint64_t n_events, uint64_t per_inv) {
+  const uint64_t nw = blockDim.x / 64u, waves = (uint64_t)gridDim.x * nw;
+  const uint64_t tiles = (n_events + 63) / 64;
+  const uint64_t most = (tiles + waves - 1) / waves * nw * 64u * per_inv;
+  return most ? (uint32_t)(0xffffffffull / most) : 0xffffffffu;
+}
+
+// Word index held by way w of set s, or -1 for a free way.
+template <bool TAG8>
+__device__ __forceinline__ int64_t cache_word(const uint32_t* tag, uint32_t sets, uint32_t s, uint32_t w) {
+  const uint32_t t = TAG8 ? (tag[s] >> (8 * w)) & 0xffu : tag[s * kCacheWays + w];
+  return t == 0 ? -1 : TAG8 ? (int64_t)(t - 1) * sets + s : (int64_t)t - 1;
 }
 
 // Consecutive threads flush one way of consecutive sets, which mostly hold
 // neighbouring words (the first keys of a region to arrive take way 0):
 // their device atomics then share cache lines.  T is the map word, TV the
 // slot.
-template <typename T, typename TV>
+template <typename T, typename TV, bool TAG8>
 __device__ __forceinline__ void cache_flush(const uint32_t* tag, const TV* val, uint32_t sets, uint32_t op,
                                             uint8_t* data) {
   const TV id = op_identity<TV>(op);
   for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
     const uint32_t w = i / sets, s = i - w * sets;
-    const uint32_t t = tag[s * kCacheWays + w];
+    const int64_t x = cache_word<TAG8>(tag, sets, s, w);
     const TV v = val[s * kCacheWays + w];
-    if (t && v != id) global_rmw((T*)data + (t - 1), (T)v, op);
+    if (x >= 0 && v != id) global_rmw((T*)data + x, (T)v, op);
   }
 }
 
-// The block's cache written out for the reduce kernel: tags [sets][nb][4],
-// then slots [sets][nb][4], this block's four ways of each set side by side.
-template <typename TV>
+// The block's cache written out for the reduce kernel: tags [sets][nb][4]
+// (32-bit tags) or [sets][nb] (8-bit tags, a set's four in one word), then
+// slots [sets][nb][4], this block's four ways of each set side by side.
+template <typename TV, bool TAG8>
 __device__ __forceinline__ void cache_spill(const uint32_t* tag, const TV* val, uint32_t sets, uint8_t* spill,
                                             uint32_t b, uint32_t nb) {
   uint32_t* st = (uint32_t*)spill;
-  TV* sv = (TV*)(spill + (uint64_t)sets * nb * kCacheWays * 4);
+  TV* sv = (TV*)(spill + (uint64_t)cache_tag_words<TAG8>(sets) * nb * 4);
   for (uint32_t i = threadIdx.x; i < sets * kCacheWays; i += blockDim.x) {
     const uint32_t s = i / kCacheWays, w = i - s * kCacheWays;
     const uint64_t at = ((uint64_t)s * nb + b) * kCacheWays + w;
-    gl(st)[at] = tag[i];
+    if (!TAG8) gl(st)[at] = tag[i];
+    else if (w == 0) gl(st)[(uint64_t)s * nb + b] = tag[s];
     gl(sv)[at] = val[i];
   }
 }
 
 // One cache set over all blocks of a launch (one reduce block per set):
-// every word of the set is summed in LDS - word key of set s is s + q * sets,
+// every word of the set is summed in LDS - word x of set s is s + q * sets,
 // so q indexes the LDS sums - and applied to the map with one device atomic.
-template <typename T, typename TV, uint32_t QMAX>
+template <typename T, typename TV, uint32_t QMAX, bool TAG8>
 __device__ __forceinline__ void cache_reduce(const uint8_t* spill, uint32_t sets, uint32_t s, uint32_t nb,
                                              uint32_t op, uint8_t* data, uint32_t words) {
   __shared__ T sum[QMAX];
   const uint32_t* st = (const uint32_t*)spill;
-  const TV* sv = (const TV*)(spill + (uint64_t)sets * nb * kCacheWays * 4);
+  const TV* sv = (const TV*)(spill + (uint64_t)cache_tag_words<TAG8>(sets) * nb * 4);
   const T id = op_identity<T>(op);
   for (uint32_t q = threadIdx.x; q < QMAX; q += blockDim.x) sum[q] = id;
   __syncthreads();
   const uint64_t base = (uint64_t)s * nb * kCacheWays;
   for (uint32_t j = threadIdx.x; j < nb * kCacheWays; j += blockDim.x) {
-    const uint32_t t = gl(st)[base + j];
+    // q + 1 for the word of this way: the 8-bit tag itself, or x / sets + 1
+    const uint32_t t = TAG8 ? (gl(st)[(uint64_t)s * nb + j / kCacheWays] >> (8 * (j % kCacheWays))) & 0xffu
+                            : gl(st)[base + j];
     if (!t) continue;
     const TV v = gl(sv)[base + j];
-    if (v != op_identity<TV>(op)) lds_rmw<T>(&sum[(t - 1) / sets], (T)v, op);
+    if (v != op_identity<TV>(op)) lds_rmw<T>(&sum[TAG8 ? t - 1 : (t - 1) / sets], (T)v, op);
   }
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < QMAX; q += blockDim.x) {
@@ -1136,9 +1238,9 @@ __device__ __forceinline__ void event_tile(Run& R, const RunArgs& A, uint64_t fi
 }
 
 // A wave's share of an event-parallel run: tiles t0, t0 + tstep, ...
-// (Loading the next tile's records, or a group of tiles, ahead of the
-// current one measured slower: the many resident waves already keep the
-// loads in flight, and the extra live registers cost more than they hid.)
+// (The interpreter loads one tile at a time: its flat accesses to the
+// stack and maps wait for every outstanding vector load, so a tile loaded
+// ahead would only be waited for sooner, and measured slower.)
 template <class Run>
 __device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0, uint64_t tstep, const Stk& stk) {
   uint64_t steps = 0;
@@ -1151,6 +1253,34 @@ __device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0
     if (live) c = load_record(A, i);
     const uint32_t rc = tile_run(R, A, live, c, stk, steps);
     if (live && A.rc) A.rc[i] = rc;
+  }
+}
+
+// The same with the next tile's records loaded while the current tile runs
+// (compiled programs: their tiles issue no flat accesses, so no wait inside
+// a tile holds the load back).  Two record sets take turns and every load
+// is unconditional (a lane past the end reads the last record and runs no
+// invocation), so that no register copy has to wait for a load.
+template <class Run>
+__device__ __forceinline__ void event_loop_ahead(Run& R, const RunArgs& A, uint64_t t0, uint64_t tstep,
+                                                 const Stk& stk) {
+  uint64_t steps = 0;
+  const uint64_t n = A.n_events, d = tstep * 64;
+  if (n == 0) return;
+  const uint64_t last = n - 1;
+  uint64_t i = t0 * 64 + lane_id();
+  Ctx a = load_record(A, i < last ? i : last), b;
+  // every lane takes the same trips: t is lane 0's event
+  for (uint64_t t = t0 * 64; t < n; t += 2 * d) {
+    b = load_record(A, i + d < last ? i + d : last);
+    uint32_t rc = tile_run(R, A, i < n, a, stk, steps);
+    if (i < n && A.rc) A.rc[i] = rc;
+    i += d;
+    if (t + d >= n) break;
+    a = load_record(A, i + d < last ? i + d : last);
+    rc = tile_run(R, A, i < n, b, stk, steps);
+    if (i < n && A.rc) A.rc[i] = rc;
+    i += d;
   }
 }
 

@@ -16,6 +16,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cerrno>
 #include <cstdio>
 #include <cstdlib>
@@ -50,6 +51,7 @@ struct Acc {
   int sc = -1;         // operand width: 2 (u32) or 3 (u64); -1 if the map takes no atomics
   uint32_t words = 0;  // mirror: words of the value area; cache: slots (4 per set)
   bool narrow = false; // cache of 64-bit sums kept as 32-bit partial sums
+  bool tag8 = false;   // cache with 8-bit tags (word index / sets + 1, four per 32-bit word)
   std::string word_type() const { return sc == 3 ? "uint64_t" : "uint32_t"; }
   std::string slot_type() const { return sc == 3 && !narrow ? "uint64_t" : "uint32_t"; }
 };
@@ -136,9 +138,15 @@ struct JMaps {
       Acc& a = acc[k];
       if (a.sc < 2 || a.kind) continue;
       a.narrow = a.op == 0x00 && a.sc == 3;
-      const uint64_t slot_bytes = 4 + (a.slot_type() == "uint64_t" ? 8 : 4);
-      uint64_t sets = share / (kCacheSlotsPerSet * slot_bytes);
-      sets -= sets % 2 == 0 && sets > 0;  // an odd count (the device maps keys to sets modulo it)
+      const uint64_t val_bytes = a.slot_type() == "uint64_t" ? 8 : 4;
+      // an odd set count (the device maps keys to sets modulo it)
+      auto odd = [](uint64_t n) { return n - (n % 2 == 0 && n > 0); };
+      // 8-bit tags when every word's quotient by the set count fits (the
+      // tags then take a quarter of the LDS); 32-bit tags otherwise
+      const uint64_t map_words = (uint64_t)m[k].second.max_entries * m[k].second.vstride / (a.sc == 3 ? 8 : 4);
+      uint64_t sets = odd(share / (kCacheSlotsPerSet * (val_bytes + 1)));
+      a.tag8 = sets >= 64 && (map_words + sets - 1) / sets <= 254;
+      if (!a.tag8) sets = odd(share / (kCacheSlotsPerSet * (val_bytes + 4)));
       if (sets >= 64) {
         a.kind = 2;
         a.words = (uint32_t)(sets * kCacheSlotsPerSet);
@@ -873,13 +881,15 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
         const std::string T = ac->word_type(), K = std::to_string(mk);
         const std::string ops = std::to_string(ac->op) + "u";
         const std::string sets = std::to_string(ac->words / kCacheSlotsPerSet) + "u";
+        const std::string tg = ac->tag8 ? "true" : "false";
         // the update of word a_ by x_ in the block's LDS accumulator
         const std::string lds =
             ac->kind == 1 ? "lds_rmw<" + T + ">(&g_acc" + K + "[(a_ - (uint64_t)(uintptr_t)M" + K + ".data) >> " +
                                 std::to_string(ac->sc) + "], (" + T + ")x_, " + ops + ");"
-            : ac->narrow ? "cache_add_narrow(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, a_, x_);"
-                         : "cache_rmw<" + T + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K + ".data, a_, (" +
-                               T + ")x_, " + ops + ");";
+            : ac->narrow ? "cache_add_narrow<" + tg + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K +
+                               ".data, a_, x_, nmax);"
+                         : "cache_rmw<" + T + ", " + tg + ">(g_tag" + K + ", g_val" + K + ", " + sets + ", M" + K +
+                               ".data, a_, (" + T + ")x_, " + ops + ");";
         // lanes of the wave that update one word are combined first (one
         // LDS atomic per distinct word instead of one per lane)
         const std::string fn = "auto acc_ = [&](uint64_t a_, uint64_t x_) { " + lds + " }; ";
@@ -1000,6 +1010,18 @@ void emit_uop(std::string& o, const Uop& u, uint32_t pc, const JMaps& J, const W
     case H_RET_EINVAL: o += "  r0 = (uint64_t)-22ll;\n"; break;
     case H_RINGBUF_OUTPUT: {
       const int k = J.index(u.imm);
+      const uint32_t size = (uint32_t)u.aux;
+      // a record in the private frame, word-aligned, of at most 64 bytes:
+      // its words go to the helper by value (no stack memory is read)
+      if (k >= 0 && J.ring[k] >= 0 && Fr.priv && (a8 & 1) == PK_STACK && fb >= 0 && fb % 8 == 0 && size <= 64) {
+        o += "  { RecVal rv_{};";
+        for (uint32_t j = 0; j < (size + 7) / 8; j++)
+          o += " rv_.w[" + std::to_string(j) + "] = f" + std::to_string(fb / 8 + j) + ";";
+        o += "\n    r0 = uni<UNI>(ring_output_words(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, " +
+             std::to_string(J.ring[k]) + "u, chunk[" + std::to_string(J.ring[k]) + "], bchunk[" +
+             std::to_string(J.ring[k]) + "], rv_, " + std::to_string(size) + "u, r4)); }\n";
+        break;
+      }
       o += "  " + spill_args((uint32_t)u.aux, 0) + "\n";
       if (k >= 0 && J.ring[k] >= 0)
         o += "  r0 = uni<UNI>(ring_output_chunked(" + M + ", wave * GX_NRINGS + " + std::to_string(J.ring[k]) + "u, " +
@@ -1057,7 +1079,7 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     const uint64_t words = (uint64_t)maps[k].second.max_entries * maps[k].second.vstride / (a.sc == 3 ? 8 : 4);
     if ((words + sets - 1) / sets > kReduceMax) spill = false;
     spill_off[k] = spill_block;
-    spill_block += (uint64_t)a.words * (4 + (a.slot_type() == "uint64_t" ? 8 : 4));
+    spill_block += (a.tag8 ? sets : a.words) * 4 + (uint64_t)a.words * (a.slot_type() == "uint64_t" ? 8 : 4);
     red_blocks += (uint32_t)sets;
   }
   if (!spill) spill_block = red_blocks = 0;
@@ -1079,7 +1101,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     if (a.kind == 1)
       o += "__shared__ " + T + " g_acc" + K + "[" + N + "];\n";
     else
-      o += "__shared__ __attribute__((aligned(16))) uint32_t g_tag" + K + "[" + N + "];\n__shared__ " + a.slot_type() +
+      o += "__shared__ __attribute__((aligned(16))) uint32_t g_tag" + K + "[" +
+           std::to_string(a.tag8 ? a.words / kCacheSlotsPerSet : a.words) + "];\n__shared__ " + a.slot_type() +
            " g_val" + K + "[" + N + "];\n";
   }
   Windows Wn = plan_windows(U, J);
@@ -1114,6 +1137,23 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   // the maps' descriptors, read from the map table once per run (they stay
   // in scalar registers instead of being reloaded for every event)
   for (size_t k = 0; k < maps.size(); k++) o += "  MapDev m" + std::to_string(k) + ";\n";
+  // narrow caches: updates per invocation (every site once without loops,
+  // else the verifier's instruction bound) and the addend bound it gives
+  uint64_t narrow_sites = 0;
+  bool loops = false;
+  for (uint32_t pc = 0; pc < U.size(); pc++) {
+    const uint32_t h = U[pc].w0 & 0xff;
+    if (h == H_LDIMM) {
+      pc++;
+      continue;
+    }
+    if (is_jump(h) && (uint32_t)U[pc].aux <= pc) loops = true;
+    const int mk = pc < J.mem_map.size() ? J.mem_map[pc] : -1;
+    if (h == H_ATOMIC_MAP && mk >= 0 && mk < (int)J.acc.size() && J.acc[mk].kind == 2 && J.acc[mk].narrow)
+      narrow_sites++;
+  }
+  const uint64_t per_inv = loops ? std::max<uint64_t>(P.max_insns, 1) : std::max<uint64_t>(narrow_sites, 1);
+  if (narrow_sites) o += "  uint32_t nmax = 0;  // largest addend the narrow caches sum in LDS\n";
   // combiners: a one-lane run's updates of a shared map word gather in
   // registers (kCombSlots words, replaced round robin) and reach the map as
   // one device atomic per word when replaced or at the end; only atomics
@@ -1199,9 +1239,10 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
         o += "      mirror_init<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
              "u);\n";
       else if (a.kind == 2)
-        o += "      cache_init<" + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+        o += "      cache_init<" + a.slot_type() + ", " + (a.tag8 ? "true" : "false") + ">(g_tag" + K + ", g_val" + K + ", " +
              std::to_string(a.words / kCacheSlotsPerSet) + "u, " + std::to_string(a.op) + "u);\n";
     }
+    if (narrow_sites) o += "      nmax = narrow_vmax(A.n_events, " + std::to_string(per_inv) + "ull);\n";
     o += "      __syncthreads();\n    }\n";
   }
   o += "  }\n  __device__ __forceinline__ void end(const RunArgs& A) {\n    (void)A;\n";
@@ -1241,17 +1282,18 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
     for (size_t k = 0; k < maps.size(); k++) {
       const Acc& a = J.acc[k];
       const std::string T = a.sc == 3 ? "uint64_t" : "uint32_t", K = std::to_string(k);
+      const std::string tg = a.tag8 ? "true" : "false";
       if (a.kind == 1)
         o += "      mirror_flush<" + T + ">(g_acc" + K + ", " + std::to_string(a.words) + "u, " + std::to_string(a.op) +
              "u, m" + K + ".data);\n";
       else if (a.kind == 2 && spill_block)
-        o += "      if (A.spill) cache_spill<" + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+        o += "      if (A.spill) cache_spill<" + a.slot_type() + ", " + tg + ">(g_tag" + K + ", g_val" + K + ", " +
              std::to_string(a.words / kCacheSlotsPerSet) + "u, A.spill + (uint64_t)gridDim.x * " +
              std::to_string(spill_off[k]) + "ull, blockIdx.x, gridDim.x);\n      else cache_flush<" + T + ", " +
-             a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words / kCacheSlotsPerSet) +
+             a.slot_type() + ", " + tg + ">(g_tag" + K + ", g_val" + K + ", " + std::to_string(a.words / kCacheSlotsPerSet) +
              "u, " + std::to_string(a.op) + "u, m" + K + ".data);\n";
       else if (a.kind == 2)
-        o += "      cache_flush<" + T + ", " + a.slot_type() + ">(g_tag" + K + ", g_val" + K + ", " +
+        o += "      cache_flush<" + T + ", " + a.slot_type() + ", " + tg + ">(g_tag" + K + ", g_val" + K + ", " +
              std::to_string(a.words / kCacheSlotsPerSet) + "u, " + std::to_string(a.op) + "u, m" + K + ".data);\n";
     }
     o += "    }\n";
@@ -1318,7 +1360,8 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
       const uint64_t words = (uint64_t)maps[k].second.max_entries * maps[k].second.vstride / (a.sc == 3 ? 8 : 4);
       const std::string S = std::to_string(sets) + "u", K = std::to_string(k);
       o += "  if (b < " + S + ") {\n    cache_reduce<" + a.word_type() + ", " + a.slot_type() + ", " +
-           std::to_string((words + sets - 1) / sets) + "u>(A.spill + (uint64_t)nb * " + std::to_string(spill_off[k]) +
+           std::to_string((words + sets - 1) / sets) + "u, " + (a.tag8 ? "true" : "false") +
+           ">(A.spill + (uint64_t)nb * " + std::to_string(spill_off[k]) +
            "ull, " + S + ", b, nb, " + std::to_string(a.op) + "u, gx_map" + K + "(A).data, " + std::to_string(words) +
            "u);\n    return;\n  }\n  b -= " + S + ";\n";
     }
@@ -1326,6 +1369,20 @@ std::string emit_prog(const JitProg& P, const std::string& ns, bool allow_acc, u
   }
   o += "}  // namespace " + ns + "\n}  // namespace gx\n\n";
   return o;
+}
+
+// Whether generated code uses the LDS frames: any mention of stk besides
+// the parameter declarations ("const Stk stk").
+bool reads_stack(const std::string& body) {
+  size_t uses = 0, decls = 0;
+  for (size_t at = body.find("stk"); at != std::string::npos; at = body.find("stk", at + 3)) {
+    const bool word = (at == 0 || !(std::isalnum((unsigned char)body[at - 1]) || body[at - 1] == '_')) &&
+                      (at + 3 >= body.size() || !(std::isalnum((unsigned char)body[at + 3]) || body[at + 3] == '_'));
+    if (!word) continue;
+    uses++;
+    if (at >= 10 && body.compare(at - 10, 10, "const Stk ") == 0) decls++;
+  }
+  return uses > decls;
 }
 
 int ring_count(const JitProg& P) {
@@ -1341,16 +1398,26 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
   // (decisions are rare; their map updates go to the map directly)
   const bool sched = P.kernel == 2;
   const uint32_t nw = sched ? 1u : jit_waves(P.stack_bytes, P.event_parallel);
-  const uint32_t lds = P.stack_bytes ? nw * 64u * P.stack_bytes : 16u;
+  uint32_t lds = P.stack_bytes ? nw * 64u * P.stack_bytes : 16u;
   const int nr = std::max(ring_count(P), 1);
+  const uint64_t ring_lds = (uint64_t)sizeof(uint64_t) * 3 * nw * nr;  // the waves' ring chunks
+  JitInfo ji;
+  std::string body = emit_prog(P, "p0", !sched, sched ? 0 : lds + ring_lds, &ji);
+  // An event-parallel program whose stack lives wholly in its private frame
+  // (no access and no helper argument reads stack memory: the generated
+  // code never touches stk) needs no LDS frames, and its accumulators take
+  // that LDS instead.
+  if (P.event_parallel && !sched && P.stack_bytes && !reads_stack(body)) {
+    lds = 16u;
+    body = emit_prog(P, "p0", true, lds + ring_lds, &ji);
+  }
   std::string o;
   o += "#define GX_LDS_BYTES " + std::to_string(lds) + "\n";
   o += guards_define();
   o += "#define GX_NRINGS " + std::to_string(nr) + "u\n";
   o += "#define GX_RING_SLOTS " + std::to_string(nw * nr) + "\n";
   o += "#include \"gx_dev.h\"\n\n";
-  JitInfo ji;
-  o += emit_prog(P, "p0", !sched, sched ? 0 : lds + (uint64_t)sizeof(uint64_t) * 3 * nw * nr, &ji);  // + the ring chunks
+  o += body;
   if (info) *info = ji;
   const std::string W = std::to_string(nw), T = std::to_string(64 * nw);
   const std::string head = "  const uint32_t wave = threadIdx.x >> 6;\n"
@@ -1372,7 +1439,8 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
          "  gx::sched_worker<true>(P, A, S, blockIdx.x, stk);\n  P.end(A);\n}\n\n";
   else if (P.event_parallel)
     o += "extern \"C\" __global__ void __launch_bounds__(" + T + ") gx_j_event_parallel(gx::RunArgs A) {\n" + head +
-         "  gx::event_loop(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
+         "  gx::" + std::string(env_int_jit("GX_EP_AHEAD", 1) ? "event_loop_ahead" : "event_loop") +
+         "(P, A, (uint64_t)blockIdx.x * " + W + "u + wave, (uint64_t)gridDim.x * " + W + "u, stk);\n"
          "  P.end(A);\n}\n\n" + reduce;
   else
     o += "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_seq(gx::RunArgs A, uint32_t lanes, "

@@ -34,6 +34,7 @@ struct JitProg {
   // its mode; 1, the instrumented vector add gx_j_app_vadd (event-parallel
   // memory hooks); 2, the block scheduler's workers gx_j_sched (HOOK_SCHED)
   int kernel = 0;
+  uint64_t max_insns = 0;  // the verifier's bound on instructions per invocation (0: unknown)
 };
 
 // HIP source of one program: its micro-ops written out as straight-line

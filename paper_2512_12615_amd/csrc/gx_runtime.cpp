@@ -682,8 +682,10 @@ struct StandIn {
   std::string log;
   int hook = 0;
   JitProg prog() const {
-    return JitProg{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel, hook == HOOK_WAVE_MEM,
-                   hook == HOOK_SIMT_MEM};
+    JitProg q{&U, v.stack_bytes, &maps, &v.mem_map, &v.ld_map, v.event_parallel, hook == HOOK_WAVE_MEM,
+              hook == HOOK_SIMT_MEM};
+    q.max_insns = v.max_insns;
+    return q;
   }
 };
 
@@ -1207,10 +1209,10 @@ int gx_jit_program(gx_rt* rt, int prog_fd, char* log, uint32_t log_size) {
     return 0;
   }
   JitInfo info;
-  const std::string src =
-      jit_source(JitProg{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
-                         p->hook == HOOK_WAVE_MEM, p->hook == HOOK_SIMT_MEM},
-                 &info);
+  JitProg jp{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
+             p->hook == HOOK_WAVE_MEM, p->hook == HOOK_SIMT_MEM};
+  jp.max_insns = p->v.max_insns;
+  const std::string src = jit_source(jp, &info);
   auto adopt = [&](const gx_rt::JitMod& jm) {
     p->jf_ep = jm.fe;
     p->jf_seq = jm.fs;
@@ -1444,6 +1446,7 @@ int jit_app_module(gx_rt* rt, ProgObj* p, int kind, hipModule_t* mod, hipFunctio
   JitProg jp{&p->uops, p->v.stack_bytes, &maps, &p->v.mem_map, &p->v.ld_map, p->v.event_parallel,
              p->hook == HOOK_WAVE_MEM, p->hook == HOOK_SIMT_MEM};
   jp.kernel = kind;
+  jp.max_insns = p->v.max_insns;
   JitInfo info;
   const std::string src = jit_source(jp, &info);
   auto adopt = [&](const gx_rt::JitMod& jm) {

@@ -209,11 +209,14 @@ def _shared_prog(op, width, entries, operand="and64 r1, 0xffff"):
 
 
 @pytest.mark.parametrize("op,width,entries", [("add", 8, 4096), ("or", 4, 1024), ("and", 8, 2048),
-                                              ("xor", 4, 4096), ("add", 8, 1 << 16), ("xor", 8, 1 << 18)])
+                                              ("xor", 4, 4096), ("add", 8, 1 << 16), ("xor", 8, 1 << 18),
+                                              ("add", 8, 1 << 21)])
 def test_jit_shared_map_lds_accumulation(rt, op, width, entries):
     """Shared-map atomics summed in LDS per block (whole-map mirror for small
-    maps, tagged cache with direct misses for large ones) give the oracle's
-    map exactly."""
+    maps, tagged cache with direct misses for large ones: 8-bit tags up to
+    2^18 words here, 32-bit tags for the 2^21-word map, whose word index
+    divided by the set count exceeds a byte) give the oracle's map
+    exactly."""
     _log(f"jit shared {op}{width} entries={entries}")
     pol = _shared_prog(op, width, entries)
     n = 300007
@@ -233,9 +236,9 @@ def test_jit_shared_map_lds_accumulation(rt, op, width, entries):
 
 @pytest.mark.parametrize("operand", ["rsh64 r1, 32", "mov64 r1, r1", "rsh64 r1, 31"])
 def test_jit_shared_add_partial_sums_wrap(rt, operand):
-    """64-bit sums cached as 32-bit partial sums: operands near 2^32 make the
-    partial sums wrap (the carry goes to the map), operands of 2^32 or more
-    go to the map directly, mixed ones take both paths."""
+    """64-bit sums cached as 32-bit partial sums: only addends small enough
+    that no partial sum can wrap are summed in LDS; operands near or above
+    2^32 go to the map directly, mixed ones take both paths."""
     _log(f"jit shared add64 operand={operand}")
     pol = _shared_prog("add", 8, 1 << 16, operand)
     n = 400009
@@ -246,6 +249,47 @@ def test_jit_shared_add_partial_sums_wrap(rt, operand):
     g = gpu_run(rt, pol, ev, jit=True)
     assert_same(g, oracle_run(pol, ev), pol.name)
     assert g.stats["vm_errors"] == 0
+
+
+RING_RECORD = """
+    ldxdw r6, [r1+0]
+    ldxdw r7, [r1+16]
+    mov64 r0, r6
+    and64 r0, 7
+    jne r0, 0, out
+    stxdw [r10-24], r7
+    stxdw [r10-16], r6
+    stxdw [r10-8], r7
+    lddw r1, map:ring
+    mov64 r2, r10
+    add64 r2, {off}
+    mov64 r3, {size}
+    mov64 r4, 0
+    call ringbuf_output
+    mov64 r0, r6
+    and64 r0, 3
+out:
+    exit
+"""
+
+
+@pytest.mark.parametrize("off,size", [(-24, 24), (-24, 12), (-16, 13), (-20, 12), (-13, 5)])
+def test_jit_ring_records_from_the_frame(rt, off, size):
+    """Ring records built in the private frame: word-aligned ones go to the
+    helper by value (whole words, or a last word cut to the record's size),
+    unaligned ones through the LDS frames; every payload byte as the
+    oracle's."""
+    _log(f"jit ring record off={off} size={size}")
+    text = RING_RECORD.format(off=off, size=size)
+    pol = W.Policy(f"ringrec{-off}_{size}", W.HOOK_MEM_ACCESS, text,
+                   [W.MapSpec("ring", W.MAP_RINGBUF, 0, 0, 1 << 22, 0)])
+    n = 64 * 311 + 17
+    ev = W.gen_mem_uniform(n, 131 + size)
+    ev["ts"] = W.splitmix(19, n)
+    g = gpu_run(rt, pol, ev, jit=True)
+    want = oracle_run(pol, ev)
+    assert len(want.rings[0]) > 1000
+    assert_same(g, want, pol.name)
 
 
 def test_jit_ring_partial_drains(rt):

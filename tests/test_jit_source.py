@@ -44,7 +44,8 @@ def test_source_structure(G):
     # its key lies in a frame word (private frame), so it is passed by value
     assert src.count("hash_lookup_k(") == 2 and src.count("hash_update(") == 1
     assert "saddr(stk, (uint32_t)" not in src  # no stack access left in LDS
-    assert src.count("ring_output_chunked(") == 1
+    # the ring record lies in the frame too: its words go to the helper by value
+    assert src.count("ring_output_words(") == 1 and "ring_output_chunked(" not in src
     labels = set(re.findall(r"^L(\d+):;", src, re.M))
     gotos = set(re.findall(r"goto L(\d+);", src))
     assert labels == gotos
@@ -84,6 +85,48 @@ def test_largest_frame_with_accumulators_compiles(G, entries):
     pol = W.Policy("big", W.HOOK_MEM_ACCESS, BIG_STACK_SHARED, [W.MapSpec("sh", W.MAP_ARRAY, 4, 8, entries, W.F_SHARED)])
     src = G.jit_source(pol.code, pol.hook, _shapes(pol), compile=True)
     assert "g_acc0" in src or "g_tag0" in src or "if (PRIV)" not in src
+
+
+UNALIGNED_RECORD = """
+    ldxdw r6, [r1+0]
+    stxdw [r10-16], r6
+    stxdw [r10-8], r6
+    lddw r1, map:ring
+    mov64 r2, r10
+    add64 r2, -12
+    mov64 r3, 12
+    mov64 r4, 0
+    call ringbuf_output
+    mov64 r0, 0
+    exit
+"""
+
+
+def test_frames_and_cache_layout(G):
+    """An event-parallel program whose stack never leaves its private frame
+    keeps no LDS frames (the latency histogram: its ring record goes to the
+    helper by value; the 512-byte frame above: its key goes by value), and
+    its histogram's cache takes 8-bit tags (word index / sets < 255, four
+    tags per 32-bit word); a record the helper must read from the stack (not
+    word-aligned) keeps the LDS frames, and a map too large for 8-bit tags
+    keeps 32-bit ones."""
+    pol = W.latency_hist_policy()
+    src = G.jit_source(pol.code, pol.hook, _shapes(pol))
+    assert "#define GX_LDS_BYTES 16\n" in src
+    body = src[src.index("uint64_t r10"):]
+    assert "cache_add_narrow<true>(" in src and not re.search(r"\bstk\b", body[:body.index("\n};\n")])
+    sets = int(re.search(r"g_tag0\[(\d+)\]", src).group(1))
+    assert int(re.search(r"g_val0\[(\d+)\]", src).group(1)) == 4 * sets and sets % 2 == 1
+    assert 4096 * 64 // sets < 255
+    big = W.Policy("big", W.HOOK_MEM_ACCESS, BIG_STACK_SHARED, [W.MapSpec("sh", W.MAP_ARRAY, 4, 8, 1 << 21, W.F_SHARED)])
+    src = G.jit_source(big.code, big.hook, _shapes(big), compile=True)
+    assert "#define GX_LDS_BYTES 16\n" in src
+    sets = int(re.search(r"g_val0\[(\d+)\]", src).group(1)) // 4
+    assert (1 << 21) // sets >= 255 and "cache_add_narrow<false>(" in src
+    assert int(re.search(r"g_tag0\[(\d+)\]", src).group(1)) == 4 * sets
+    una = W.Policy("una", W.HOOK_MEM_ACCESS, UNALIGNED_RECORD, [W.MapSpec("ring", W.MAP_RINGBUF, 0, 0, 1 << 16, 0)])
+    src = G.jit_source(una.code, una.hook, _shapes(una), compile=True)
+    assert "#define GX_LDS_BYTES 16\n" not in src and "ring_output_chunked(" in src
 
 
 def test_source_holds_no_map_addresses(G):
