@@ -1384,7 +1384,7 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t x, uint32_t j) {
   return ((uint64_t)rdlane((uint32_t)(x >> 32), j) << 32) | rdlane((uint32_t)x, j);
 }
 
-template <class Run>
+template <bool GATHER, class Run>
 __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q, uint32_t qstride,
                                            uint32_t qend_last, const Stk& stk, uint64_t& steps) {
   typedef const __attribute__((address_space(4))) uint32_t cu32;
@@ -1392,40 +1392,45 @@ __device__ __forceinline__ void stream_uni(Run& R, const RunArgs& A, uint32_t q,
   if (q >= A.n_queues) return;
   const uint32_t beg = ((const cu32*)A.qstart)[(uint64_t)q * qstride];
   const uint32_t end = q + 1 < A.n_queues ? ((const cu32*)A.qstart)[(uint64_t)(q + 1) * qstride] : qend_last;
+  if (beg >= end) return;
   const bool wide = A.record_size > 16;
-  const uint32_t l = lane_id();
+  const uint32_t l = lane_id(), w2 = wide ? 2u : 1u;
   Ctx nc{0, 0, 0};
   uint32_t ni = 0;
   // With the queue-ordered copy, lane l reads record k0 + l of it and its
   // index; without it (A.sorted null), lane l gathers event order[k0 + l]
   // from the input: the indices are read a block earlier than the records
-  // (ni2), so neither load waits inside the loop.
-  const bool gather = A.sorted == nullptr;
+  // (ni2), so neither load waits inside the loop.  Every load is
+  // unconditional (a lane past the queue's end reads its last event; a
+  // 16-byte record's third word is its second, cleared where it is used),
+  // so that no register copy of a load in flight waits for it.
+  constexpr bool gather = GATHER;  // A.sorted is null exactly when GATHER
+  const uint64_t last = end - 1;
   uint32_t ni2 = 0;
-  auto index_of = [&](uint64_t k) { return k < end ? ((const GX_GLOBAL uint32_t*)A.order)[k] : 0u; };
+  auto index_of = [&](uint64_t k) { return ((const GX_GLOBAL uint32_t*)A.order)[k < last ? k : last]; };
   auto fetch = [&](uint64_t k0) {  // lane l: record k0 + l
     const uint64_t k = k0 + l;
+    const GX_GLOBAL uint64_t* p;
     if (gather) {
       ni = ni2;
       ni2 = index_of(k + 64);
-      if (k < end) {
-        const GX_GLOBAL uint64_t* p = (const GX_GLOBAL uint64_t*)(A.events + (uint64_t)ni * A.record_size);
-        nc.c0 = p[0];
-        nc.c1 = p[1];
-        nc.c2 = wide ? p[2] : 0;
-      }
-    } else if (k < end) {
-      const GX_GLOBAL uint64_t* p = (const GX_GLOBAL uint64_t*)(A.sorted + (uint64_t)k * kSortedStride);
-      nc.c0 = p[0];
-      nc.c1 = p[1];
-      nc.c2 = wide ? p[2] : 0;
-      ni = ((const GX_GLOBAL uint32_t*)A.order)[k];
+      p = (const GX_GLOBAL uint64_t*)(A.events + (uint64_t)ni * A.record_size);
+    } else {
+      p = (const GX_GLOBAL uint64_t*)(A.sorted + (k < last ? k : last) * kSortedStride);
+      ni = index_of(k);
     }
+    nc.c0 = p[0];
+    nc.c1 = p[1];
+    nc.c2 = p[w2];
   };
   if (gather) ni2 = index_of((uint64_t)beg + l);
   fetch(beg);
   for (uint64_t k0 = beg; k0 < end; k0 += 64) {
-    const Ctx cc = nc;  // this block's records, one per lane
+    Ctx cc{nc.c0, nc.c1, wide ? nc.c2 : 0};  // this block's records, one per lane
+    // formed here, with every lane active: lane 0 reads them below by lane
+    // index inside a branch only it takes, so their computation must not
+    // move into that branch
+    __asm__ volatile("" : "+v"(cc.c0), "+v"(cc.c1), "+v"(cc.c2));
     const uint32_t ci = ni;
     fetch(k0 + 64);
     const uint32_t n = end - k0 < 64 ? (uint32_t)(end - k0) : 64u;

@@ -1451,7 +1451,7 @@ std::string jit_source(const JitProg& P, JitInfo* info) {
        "extern \"C\" __global__ void __launch_bounds__(64) gx_j_stream_uni(gx::RunArgs A, uint32_t qstride, "
        "uint32_t qend_last) {\n  gx::Stk stk{0, 0u, blockIdx.x * 64u + threadIdx.x};\n"
        "  gx::p0::Prog<false, true> P{0u};\n  P.begin(A);\n  uint64_t steps = 0;\n"
-       "  gx::stream_uni(P, A, blockIdx.x, qstride, qend_last, stk, steps);\n"
+       "  gx::stream_uni<true>(P, A, blockIdx.x, qstride, qend_last, stk, steps);\n"
        "  P.end(A);\n}\n";
   return o;
 }
@@ -1484,7 +1484,7 @@ std::string jit_set_source(const std::vector<JitProg>& progs) {
     if (ep)
       o += "        gx::event_tile(P, bd.A, (uint64_t)chunk * 64u, stk, steps);\n";
     else
-      o += "        gx::stream_uni(P, bd.A, chunk, bd.qstride, bd.qend_last, stku, steps);\n";
+      o += "        gx::stream_uni<false>(P, bd.A, chunk, bd.qstride, bd.qend_last, stku, steps);\n";
     o += "        P.end(bd.A);\n        break;\n      }\n";
   }
   o += "      default: break;\n    }\n  });\n}\n";
