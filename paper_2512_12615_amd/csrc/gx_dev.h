@@ -1256,31 +1256,36 @@ __device__ __forceinline__ void event_loop(Run& R, const RunArgs& A, uint64_t t0
   }
 }
 
-// The same with the next tile's records loaded while the current tile runs
-// (compiled programs: their tiles issue no flat accesses, so no wait inside
-// a tile holds the load back).  Two record sets take turns and every load
-// is unconditional (a lane past the end reads the last record and runs no
-// invocation), so that no register copy has to wait for a load.
-template <class Run>
+// The same with the records of the next AHEAD tiles loaded while the
+// current tile runs (compiled programs: their tiles issue no flat
+// accesses, so no wait inside a tile holds the loads back).  AHEAD + 1
+// record sets take turns (the loop body is unrolled over them) and every
+// load is unconditional (a lane past the end reads the last record and
+// runs no invocation), so that no register copy has to wait for a load.
+template <int AHEAD, class Run>
 __device__ __forceinline__ void event_loop_ahead(Run& R, const RunArgs& A, uint64_t t0, uint64_t tstep,
                                                  const Stk& stk) {
+  constexpr int K = AHEAD + 1;
   uint64_t steps = 0;
   const uint64_t n = A.n_events, d = tstep * 64;
   if (n == 0) return;
   const uint64_t last = n - 1;
-  uint64_t i = t0 * 64 + lane_id();
-  Ctx a = load_record(A, i < last ? i : last), b;
+  uint64_t i = t0 * 64 + lane_id();  // this lane's event of the current tile
+  Ctx set[K];
+#pragma unroll
+  for (int u = 0; u < AHEAD; u++) set[u] = load_record(A, i + u * d < last ? i + u * d : last);
   // every lane takes the same trips: t is lane 0's event
-  for (uint64_t t = t0 * 64; t < n; t += 2 * d) {
-    b = load_record(A, i + d < last ? i + d : last);
-    uint32_t rc = tile_run(R, A, i < n, a, stk, steps);
-    if (i < n && A.rc) A.rc[i] = rc;
-    i += d;
-    if (t + d >= n) break;
-    a = load_record(A, i + d < last ? i + d : last);
-    rc = tile_run(R, A, i < n, b, stk, steps);
-    if (i < n && A.rc) A.rc[i] = rc;
-    i += d;
+  for (uint64_t t = t0 * 64; t < n;) {
+#pragma unroll
+    for (int u = 0; u < K; u++) {
+      const uint64_t j = i + AHEAD * d;
+      set[(u + AHEAD) % K] = load_record(A, j < last ? j : last);
+      const uint32_t rc = tile_run(R, A, i < n, set[u], stk, steps);
+      if (i < n && A.rc) A.rc[i] = rc;
+      i += d;
+      t += d;
+      if (t >= n) break;
+    }
   }
 }
 
