@@ -1585,9 +1585,18 @@ __device__ __forceinline__ void sched_worker(Run& R, const RunArgs& A, const Sch
         const uint32_t size = first(v + 1) - first(v);
         rem = taken < size ? size - taken : 0;
       }
-      const uint64_t m = ballot(rem > 0);
-      if (m) {
-        const uint32_t f = (uint32_t)__builtin_ctzll(m);
+      if (ballot(rem > 0)) {
+        // the candidate with the most units left (the nearest among
+        // equals): thieves spread over the slow workers instead of all
+        // claiming from the first one they find
+        uint64_t lo = ((uint64_t)rem << 6) | (63u - l), hi = lo;
+        minmax_step<0x111, 0xf>(lo, hi);  // row_shr:1
+        minmax_step<0x112, 0xf>(lo, hi);  // row_shr:2
+        minmax_step<0x114, 0xf>(lo, hi);  // row_shr:4
+        minmax_step<0x118, 0xf>(lo, hi);  // row_shr:8
+        minmax_step<0x142, 0xa>(lo, hi);  // row_bcast:15 into rows 1 and 3
+        minmax_step<0x143, 0xc>(lo, hi);  // row_bcast:31 into rows 2 and 3
+        const uint32_t f = 63u - (rdlane((uint32_t)hi, 63) & 63u);
         victim = rdlane(v, f);
         left = rdlane(rem, f);
       }
