@@ -47,6 +47,24 @@ def test_jit_latency_hist(rt, n):
     assert g.stats["ring_drops"] == 0 and g.stats["vm_errors"] == 0
 
 
+@pytest.mark.parametrize("ahead", [0, 1, 3, 7])
+def test_jit_tiles_loaded_ahead(rt, monkeypatch, ahead):
+    """The event-parallel kernel with the records of 0 (one tile at a
+    time), 1, 3 and 7 tiles loaded ahead of the running one: every depth
+    unrolls the tile loop differently, and runs that end inside an unrolled
+    round or leave waves without tiles must still give the oracle's rc,
+    maps and ring records."""
+    monkeypatch.setenv("GX_EP_AHEAD", str(ahead))
+    for n in (64 * 4099 + 37, 64 * 3 + 1):
+        _log(f"jit latency_hist ahead={ahead} n={n}")
+        pol = W.latency_hist_policy()
+        ev = W.gen_timing(n, 1202 + n)
+        init = [(1, b"\0\0\0\0", np.uint64(W.p99_threshold(ev["lat"])).tobytes())]
+        g = gpu_run(rt, pol, ev, init, jit=True)
+        assert_same(g, oracle_run(pol, ev, init), f"latency_hist ahead={ahead} n={n}")
+        assert g.stats["ring_drops"] == 0 and g.stats["vm_errors"] == 0
+
+
 @pytest.mark.parametrize("n,streams", [(1, 1), (777, 8), (1 << 16, 1024)])
 def test_jit_stride_prefetch(rt, n, streams):
     _log(f"jit stride_prefetch n={n} streams={streams}")
