@@ -375,6 +375,26 @@ int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_by
 int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
                               uint64_t* n_records);
 
+/* The drain of gx_drain_ringbuf_view in two halves, so that the copy to
+ * the host overlaps the caller's next launches (section 5.3's host side
+ * draining the ring while the device keeps producing).  _start waits for
+ * the runtime's launches, reads the ring's position and queues, on a copy
+ * stream of the runtime, the copy of the committed range into the ring's
+ * pinned staging buffer and then the move of the ring's tail past it; it
+ * returns 0 without waiting for them.  Until _finish: launches of
+ * gx_run_batch that may write this ring wait on the device for the copy
+ * before their VM kernel (their partition kernels do not); the other
+ * launching entry points wait for it on the host; gx_drain_ringbuf,
+ * gx_drain_ringbuf_view and a second _start on the ring return -EBUSY.
+ * When the range needs a host pass (records some writer did not count, a
+ * cut-back head) _start drains it synchronously instead.  _finish waits
+ * for the copy and returns what gx_drain_ringbuf_view would have: *view
+ * (valid until the next drain of this ring), *view_bytes, *n_records and
+ * the kept bytes; -EINVAL without a started drain. */
+int gx_drain_ringbuf_start(gx_rt* rt, int ring_fd);
+int64_t gx_drain_ringbuf_finish(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
+                                uint64_t* n_records);
+
 /* Position of a ring: *head = bytes reserved since the ring was created
  * (records, their padding and discard records), *tail = bytes drained.
  * Both only grow; head - tail is the backlog a drain would read, and

@@ -68,6 +68,14 @@ struct MapObj {
   size_t data_bytes = 0, slot_bytes = 0;
   uint8_t* h_pin = nullptr;  // ring: pinned staging for drains
   size_t pin_cap = 0;
+  // ring: a drain started by gx_drain_ringbuf_start, whose copy and the
+  // ring's new control words are queued on the runtime's copy stream and
+  // done at drain_ev; launches that write the ring wait for that event
+  hipEvent_t drain_ev = nullptr;
+  bool drain_pending = false;
+  uint64_t* ctrl_pin = nullptr;  // pinned source of the new control words
+  uint64_t pend_bytes = 0, pend_kept = 0, pend_recs = 0;
+  bool pend_counted = false;  // the drain's bytes are already in the runtime's counters
   // host tier (F_HOST): the pinned host allocations behind h.data / h.slots
   uint8_t* host_data = nullptr;
   uint8_t* host_slots = nullptr;
@@ -243,6 +251,7 @@ void exec_free(Exec& x) {
 struct gx_rt {
   int dev = 0;
   hipStream_t internal = nullptr;
+  hipStream_t copy = nullptr;  // started drains (created on first use)
   // compiled modules by generated source (instances of one program with
   // same-shaped maps share one); guarded for concurrent gx_jit_program calls
   struct JitMod {
@@ -335,8 +344,31 @@ void free_map(MapObj& m) {
   else if (m.h.slots) (void)hipFree(m.h.slots);
   if (m.h.ctrl) (void)hipFree(m.h.ctrl);
   if (m.d_desc) (void)hipFree(m.d_desc);
+  if (m.drain_ev) {
+    (void)hipEventSynchronize(m.drain_ev);  // a started drain still copying
+    (void)hipEventDestroy(m.drain_ev);
+  }
   if (m.h_pin) (void)hipHostFree(m.h_pin);
+  if (m.ctrl_pin) (void)hipHostFree(m.ctrl_pin);
   m = MapObj{};
+}
+
+// Launches on stream s that may write the program's rings wait for the
+// copies of those rings' started drains (the copies read the ring's
+// committed range and then move its tail).
+void wait_drains(gx_rt* rt, const ProgObj* p, hipStream_t s) {
+  for (int fd : p->fds) {
+    const MapObj& m = rt->maps[fd];
+    if (m.drain_pending && m.drain_ev) (void)hipStreamWaitEvent(s, m.drain_ev, 0);
+  }
+}
+
+// Entry points without that stream ordering wait on the host for every
+// started drain's copy before they launch.
+int drain_barrier(gx_rt* rt) {
+  for (const MapObj& m : rt->maps)
+    if (m.drain_pending && m.drain_ev && hipEventSynchronize(m.drain_ev) != hipSuccess) return -EIO;
+  return 0;
 }
 
 void note_stream(gx_rt* rt, hipStream_t s) {
@@ -613,6 +645,7 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
   if (rt->profile) pe = prof_pair(rt);
   if (p->v.event_parallel) {
     A.step_limit = per_event;
+    wait_drains(rt, p, s);
     if (pe.first) (void)hipEventRecord(pe.first, s);
     if (p->jf_ep) {
       const uint64_t need = jit_spill_bytes(p, n_events, k.blocks);
@@ -654,6 +687,8 @@ int run_one(gx_rt* rt, ProgObj* p, const void* d_events, uint64_t n_events, uint
       A.sorted = gather ? nullptr : X.d_sorted;
       A.qstart = X.d_counts;
       A.n_queues = L;
+      // the partition above may run while a started drain still copies
+      wait_drains(rt, p, s);
       if (pe.first) (void)hipEventRecord(pe.first, s);
       if (p->jf_seq) {
         e = launch_jit(p, A, 1, k.lanes, nt, (uint32_t)n_events, 0, nullptr, s);
@@ -832,6 +867,7 @@ void gx_close(gx_rt* rt) {
   for (void* p : {(void*)rt->d_err, (void*)rt->d_stage})
     if (p) (void)hipFree(p);
   if (rt->internal) (void)hipStreamDestroy(rt->internal);
+  if (rt->copy) (void)hipStreamDestroy(rt->copy);
   delete rt;
 }
 
@@ -1865,6 +1901,7 @@ int gx_run_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stream) {
   int r = check_batches(rt, descs, n);
   if (r) return r;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
   if (rt->snap) lk.lock();
   return run_batches_impl(rt, descs, n, (hipStream_t)stream);
@@ -1879,6 +1916,7 @@ int gx_run_batch_noalloc(gx_rt* rt, int prog_fd, const void* d_events, uint64_t 
   if (!d_events) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
   if (rt->snap) lk.lock();
   return run_noalloc(rt, p, d_events, n_events, d_rc, (hipStream_t)stream, knobs_of(p));
@@ -2027,6 +2065,7 @@ int gx_graph_launch(gx_graph* G, void* stream) {
   if (!G) return -EINVAL;
   gx_rt* rt = G->rt;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   hipStream_t s = (hipStream_t)stream;
   std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
   if (rt->snap) lk.lock();
@@ -2051,6 +2090,7 @@ void gx_graph_destroy(gx_graph* G) {
 int64_t gx_drain_ringbuf(gx_rt* rt, int ring_fd, void* host_buf, uint64_t buf_bytes, uint64_t* n_records) {
   MapObj* m = get_map(rt, ring_fd);
   if (!m || m->h.type != MAP_RINGBUF || (!host_buf && buf_bytes)) return -EINVAL;
+  if (m->drain_pending) return -EBUSY;  // a started drain is not finished
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
   uint64_t ctrl[kRingCount + 2 * kRingCountSlots];
@@ -2120,6 +2160,7 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
                               uint64_t* n_records) {
   MapObj* m = get_map(rt, ring_fd);
   if (!m || m->h.type != MAP_RINGBUF || !view || !view_bytes) return -EINVAL;
+  if (m->drain_pending) return -EBUSY;  // a started drain is not finished
   DevGuard g(rt->dev);
   if (wait_all(rt)) return -EIO;
   uint64_t ctrl[kRingCount + 2 * kRingCountSlots];
@@ -2183,6 +2224,89 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
   rt->stats.bytes_drained += kept;
   if (n_records) *n_records = nrec;
   return (int64_t)kept;
+}
+
+int gx_drain_ringbuf_start(gx_rt* rt, int ring_fd) {
+  MapObj* m = get_map(rt, ring_fd);
+  if (!m || m->h.type != MAP_RINGBUF) return -EINVAL;
+  if (m->drain_pending) return -EBUSY;
+  DevGuard g(rt->dev);
+  if (wait_all(rt)) return -EIO;
+  uint64_t ctrl[kRingCount + 2 * kRingCountSlots];
+  if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;
+  const uint64_t head = ctrl[0], tail = ctrl[1], cap = (uint64_t)m->h.slot_mask + 1, avail = head - tail;
+  uint64_t disc = 0, recs = 0;
+  for (uint32_t k = 0; k < kRingCountSlots; k++) {
+    disc += ctrl[kRingCount + 2 * k];
+    recs += ctrl[kRingCount + 2 * k + 1];
+  }
+  if (ctrl[3] != 0 || ctrl[kRingUnknown] || disc > avail || avail == 0) {
+    // a range the host must walk, a head to cut back, or nothing: drained
+    // here and now, as gx_drain_ringbuf_view does
+    const void* v = nullptr;
+    uint64_t vb = 0, n = 0;
+    const int64_t kept = gx_drain_ringbuf_view(rt, ring_fd, &v, &vb, &n);
+    if (kept < 0) return (int)kept;
+    m->pend_bytes = vb;
+    m->pend_kept = (uint64_t)kept;
+    m->pend_recs = n;
+    m->pend_counted = true;
+    m->drain_pending = true;
+    return 0;
+  }
+  if (!rt->copy && hipStreamCreateWithFlags(&rt->copy, hipStreamNonBlocking) != hipSuccess) {
+    rt->copy = nullptr;
+    return -EIO;
+  }
+  if (!m->drain_ev && hipEventCreateWithFlags(&m->drain_ev, hipEventDisableTiming) != hipSuccess) {
+    m->drain_ev = nullptr;
+    return -EIO;
+  }
+  if (!m->ctrl_pin && hipHostMalloc((void**)&m->ctrl_pin, sizeof ctrl, hipHostMallocDefault) != hipSuccess) {
+    m->ctrl_pin = nullptr;
+    return -ENOMEM;
+  }
+  if (m->pin_cap < avail) {
+    if (m->h_pin) (void)hipHostFree(m->h_pin);
+    m->h_pin = nullptr;
+    m->pin_cap = 0;
+    if (hipHostMalloc((void**)&m->h_pin, avail, hipHostMallocDefault) != hipSuccess) return -ENOMEM;
+    m->pin_cap = avail;
+  }
+  // the committed range, then the ring's new control words (tail moved
+  // past the range, the device's counts cleared), in order on the copy
+  // stream
+  const uint64_t t0 = tail & (cap - 1), first = std::min(avail, cap - t0);
+  std::memset(m->ctrl_pin, 0, sizeof ctrl);
+  m->ctrl_pin[0] = head;
+  m->ctrl_pin[1] = tail + avail;
+  m->ctrl_pin[2] = ctrl[2];
+  if (hipMemcpyAsync(m->h_pin, m->h.data + t0, first, hipMemcpyDeviceToHost, rt->copy) != hipSuccess ||
+      (first < avail && hipMemcpyAsync(m->h_pin + first, m->h.data, avail - first, hipMemcpyDeviceToHost,
+                                       rt->copy) != hipSuccess) ||
+      hipMemcpyAsync(m->h.ctrl, m->ctrl_pin, sizeof ctrl, hipMemcpyHostToDevice, rt->copy) != hipSuccess ||
+      hipEventRecord(m->drain_ev, rt->copy) != hipSuccess)
+    return -EIO;
+  m->pend_bytes = avail;
+  m->pend_kept = avail - disc;
+  m->pend_recs = recs;
+  m->pend_counted = false;
+  m->drain_pending = true;
+  return 0;
+}
+
+int64_t gx_drain_ringbuf_finish(gx_rt* rt, int ring_fd, const void** view, uint64_t* view_bytes,
+                                uint64_t* n_records) {
+  MapObj* m = get_map(rt, ring_fd);
+  if (!m || m->h.type != MAP_RINGBUF || !view || !view_bytes || !m->drain_pending) return -EINVAL;
+  DevGuard g(rt->dev);
+  if (m->drain_ev && hipEventSynchronize(m->drain_ev) != hipSuccess) return -EIO;
+  m->drain_pending = false;
+  *view = m->pend_bytes ? m->h_pin : nullptr;
+  *view_bytes = m->pend_bytes;
+  if (n_records) *n_records = m->pend_recs;
+  if (!m->pend_counted) rt->stats.bytes_drained += m->pend_kept;
+  return (int64_t)m->pend_kept;
 }
 
 }  // extern "C"
@@ -2336,6 +2460,7 @@ int gx_run_app_vadd(gx_rt* rt, int prog_fd, const double* d_a, const double* d_b
   hipStream_t s = (hipStream_t)stream;
   const AppArgs P{d_a, d_b, d_c, n, stride, ~0ull / n};
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   if (prog_fd < 0) {
     hipError_t e = launch_app_plain(P, rt->n_cu, s);
     return e == hipSuccess ? 0 : to_errno(e);
@@ -2388,6 +2513,7 @@ int gx_run_sched(gx_rt* rt, int prog_fd, const uint32_t* d_cost, uint32_t n_unit
   }
   hipStream_t s = (hipStream_t)stream;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   std::unique_lock<std::mutex> lk(rt->enq_mu, std::defer_lock);
   if (rt->snap) lk.lock();
   Exec* Xp = exec_for(rt, s);
@@ -2439,6 +2565,7 @@ int gx_ringbuf_pos(gx_rt* rt, int ring_fd, uint64_t* head, uint64_t* tail) {
   MapObj* m = get_map(rt, ring_fd);
   if (!m || m->h.type != MAP_RINGBUF || !head || !tail) return -EINVAL;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   if (wait_all(rt)) return -EIO;
   uint64_t ctrl[4];
   if (hipMemcpy(ctrl, m->h.ctrl, sizeof ctrl, hipMemcpyDeviceToHost) != hipSuccess) return -EIO;

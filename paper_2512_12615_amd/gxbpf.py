@@ -43,7 +43,7 @@ class Batch(C.Structure):
 
 EXPORTS = ["gx_open", "gx_close", "gx_create_map", "gx_map_update", "gx_map_lookup", "gx_map_delete",
            "gx_map_dump", "gx_map_clear", "gx_load_program", "gx_prog_info_get", "gx_verify", "gx_run_batch", "gx_run_batch_noalloc", "gx_run_app_vadd", "gx_run_sched",
-           "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
+           "gx_run_batches", "gx_autotune_batches", "gx_drain_ringbuf_view", "gx_drain_ringbuf_start", "gx_drain_ringbuf_finish", "gx_graph_create", "gx_graph_launch", "gx_graph_destroy", "gx_autotune", "gx_jit_program", "gx_jit_program_set", "gx_jit_source",
            "gx_jit_set_source", "gx_drain_ringbuf", "gx_ringbuf_pos", "gx_snapshot_start", "gx_snapshot_read",
            "gx_snapshot_flush", "gx_snapshot_stop", "gx_stats_get", "gx_profile_enable", "gx_profile_read",
            "gx_server_create", "gx_server_submit", "gx_server_submit_borrowed", "gx_server_poll",
@@ -108,6 +108,10 @@ def lib():
     L.gx_autotune_batches.argtypes = [vp, C.POINTER(Batch), u32, vp, C.POINTER(Tune)]
     L.gx_drain_ringbuf_view.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(u64), C.POINTER(u64)]
     L.gx_drain_ringbuf_view.restype = C.c_int64
+    L.gx_drain_ringbuf_start.argtypes = [vp, C.c_int]
+    L.gx_drain_ringbuf_start.restype = C.c_int
+    L.gx_drain_ringbuf_finish.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(u64), C.POINTER(u64)]
+    L.gx_drain_ringbuf_finish.restype = C.c_int64
     L.gx_graph_launch.argtypes = [vp, vp]
     L.gx_graph_destroy.argtypes = [vp]
     L.gx_graph_destroy.restype = None
@@ -403,6 +407,21 @@ class Runtime:
         view, vb, n = C.c_void_p(), C.c_uint64(0), C.c_uint64(0)
         kept = _check(lib().gx_drain_ringbuf_view(self._h, fd, C.byref(view), C.byref(vb), C.byref(n)),
                       "gx_drain_ringbuf_view")
+        if not vb.value:
+            return np.empty(0, np.uint8), kept, n.value
+        return np.ctypeslib.as_array(C.cast(view, C.POINTER(C.c_uint8)), shape=(vb.value,)), kept, n.value
+
+    def drain_ringbuf_start(self, fd):
+        """First half of drain_ringbuf_view (gx_drain_ringbuf_start): the
+        copy to the host is queued and overlaps the next launches."""
+        _check(lib().gx_drain_ringbuf_start(self._h, fd), "gx_drain_ringbuf_start")
+
+    def drain_ringbuf_finish(self, fd):
+        """Second half (gx_drain_ringbuf_finish): (view, kept_bytes,
+        n_records) as drain_ringbuf_view returns them."""
+        view, vb, n = C.c_void_p(), C.c_uint64(0), C.c_uint64(0)
+        kept = _check(lib().gx_drain_ringbuf_finish(self._h, fd, C.byref(view), C.byref(vb), C.byref(n)),
+                      "gx_drain_ringbuf_finish")
         if not vb.value:
             return np.empty(0, np.uint8), kept, n.value
         return np.ctypeslib.as_array(C.cast(view, C.POINTER(C.c_uint8)), shape=(vb.value,)), kept, n.value
