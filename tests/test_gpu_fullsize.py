@@ -49,9 +49,10 @@ def _records32(payloads):
 
 def test_stride_prefetch_compiled_at_bench_size(rt, monkeypatch):
     """2^24 events over 1024 streams, two rotated batches on persisting
-    maps, compiled one-queue kernel in the tuned launch shape; a view drain
-    after the first launch and a copying drain after the second (the 64 MiB
-    ring wraps during the second).  Return codes, the whole hash map and
+    maps, compiled one-queue kernel in the tuned launch shape; as in the
+    benchmark, the first launch's drain is started after it and finished
+    after the second launch is queued, then a copying drain follows the
+    second (the 64 MiB ring wraps during the second).  Return codes, the whole hash map and
     the ring multisets equal the oracle's."""
     import torch
     from oracle import oracle as O
@@ -61,8 +62,8 @@ def test_stride_prefetch_compiled_at_bench_size(rt, monkeypatch):
     hosts = [W.gen_mem_stride(n, 1001 + 7 * b) for b in range(2)]
     fds, prog = setup(rt, pol, jit=True)
     dev = [to_device(h) for h in hosts]
-    rc = torch.empty(n, dtype=torch.int32, device="cuda")
-    tune = rt.autotune(prog, dev[0], n_events=n, record_size=24, rc=rc)
+    rcs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    tune = rt.autotune(prog, dev[0], n_events=n, record_size=24, rc=rcs[0])
     _log(f"stride full size: tuned shape {tune}")
     o = O.Oracle()
     o.set_tracking(False)
@@ -70,18 +71,21 @@ def test_stride_prefetch_compiled_at_bench_size(rt, monkeypatch):
         o.create_map(m.type, m.key_size, m.value_size, m.max_entries, m.flags)
     ring_fd = fds[1]
     cap = pol.maps[1].max_entries
-    for b in range(2):
-        rt.run_batch(prog, dev[b], n_events=n, record_size=24, rc=rc)
-        torch.cuda.synchronize()
-        if b == 0:
-            view, kept, nrec = rt.drain_ringbuf_view(ring_fd)
-            got = _payloads(view.tobytes())
-        else:
-            buf, nrec = rt.drain_ringbuf(ring_fd)
-            got = _payloads(buf)
+    # the benchmark's sequence: the first batch's drain is started after
+    # its launch and finished after the second batch is queued (whose VM
+    # kernel waits for the copy); the second batch takes a copying drain,
+    # where the 64 MiB ring wraps
+    rt.run_batch(prog, dev[0], n_events=n, record_size=24, rc=rcs[0])
+    rt.drain_ringbuf_start(ring_fd)
+    rt.run_batch(prog, dev[1], n_events=n, record_size=24, rc=rcs[1])
+    view, kept, nrec0 = rt.drain_ringbuf_finish(ring_fd)
+    got0 = _payloads(view.tobytes())
+    torch.cuda.synchronize()
+    buf, nrec1 = rt.drain_ringbuf(ring_fd)
+    for b, got, nrec in ((0, got0, nrec0), (1, _payloads(buf), nrec1)):
         assert len(got) == nrec
         want_rc = o.run(pol.code, pol.hook, hosts[b])
-        g_rc = rc.cpu().numpy().view(np.uint32)
+        g_rc = rcs[b].cpu().numpy().view(np.uint32)
         bad = np.nonzero(g_rc != want_rc)[0]
         assert len(bad) == 0, f"batch {b}: rc differs at {bad[:8]}"
         want = o.drain(1)
