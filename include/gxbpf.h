@@ -384,7 +384,9 @@ int64_t gx_drain_ringbuf_view(gx_rt* rt, int ring_fd, const void** view, uint64_
  * returns 0 without waiting for them.  Until _finish: launches of
  * gx_run_batch that may write this ring wait on the device for the copy
  * before their VM kernel (their partition kernels do not); the other
- * launching entry points wait for it on the host; gx_drain_ringbuf,
+ * launching entry points and the autotuners wait for it on the host (a
+ * server's own launches do not: rings of served programs are drained by
+ * their callers after the requests complete); gx_drain_ringbuf,
  * gx_drain_ringbuf_view and a second _start on the ring return -EBUSY.
  * When the range needs a host pass (records some writer did not count, a
  * cut-back head) _start drains it synchronously instead.  _finish waits

@@ -1150,6 +1150,7 @@ int gx_autotune(gx_rt* rt, int prog_fd, const void* d_events, uint64_t n_events,
   if (!p || record_size != p->record_size || p->hook == HOOK_SCHED || !d_events || n_events == 0) return -EINVAL;
   if (n_events >= (1ull << 32)) return -E2BIG;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   hipStream_t s = (hipStream_t)stream;
   // candidate shapes
   std::vector<Knobs> cand;
@@ -1927,6 +1928,7 @@ int gx_autotune_batches(gx_rt* rt, const gx_batch* descs, uint32_t n, void* stre
   if (r) return r;
   if (!n) return -EINVAL;
   DevGuard g(rt->dev);
+  if (drain_barrier(rt)) return -EIO;  // started drains finish copying first
   hipStream_t s = (hipStream_t)stream;
   const uint32_t def = (uint32_t)std::min(32, std::max(1, env_int("GX_BATCH_WAVES_PER_CU", 8)));
   std::vector<uint32_t> cand{def};
